@@ -1,0 +1,6 @@
+"""Seeded synthetic electron-event inputs (shared by tests and the benchmark)."""
+from .synth import (WORKLOADS, C4_TRUE_ABERRATIONS, LAMBDA_300KV, EventData, Workload, simulate,
+                    random_csr, with_pileup, shuffle_within_frames, probe_spectrum)
+
+__all__ = ["WORKLOADS", "C4_TRUE_ABERRATIONS", "LAMBDA_300KV", "EventData", "Workload", "simulate",
+           "random_csr", "with_pileup", "shuffle_within_frames", "probe_spectrum"]
