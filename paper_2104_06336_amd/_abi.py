@@ -1,0 +1,103 @@
+"""ctypes declarations of include/stem4d.h and the library loader."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libstem4d.so")
+
+STEM_FFT_FP32, STEM_DFT_BF16_SPLIT, STEM_DFT_FP16_SPLIT = 0, 1, 2
+STEM_G_RECOMPUTE, STEM_G_STORE = 0, 1
+STEM_SSB_ACCUMULATE, STEM_SSB_FINALIZE, STEM_SSB_REFOCUS, STEM_SSB_ONESHOT = 0, 1, 2, 3
+
+STEM_REGION_D, STEM_REGION_G, STEM_REGION_T, STEM_REGION_KC = 0, 1, 2, 3
+
+STATUS_BITS = {1: "EINVAL", 2: "ERANGE", 4: "EOFFSETS", 8: "EOVERFLOW", 16: "EWORKSPACE", 32: "EHIP",
+               64: "ESTATE"}
+
+
+class StemError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        self.code = int(code)
+        names = [n for b, n in STATUS_BITS.items() if self.code & b] or [str(self.code)]
+        super().__init__(f"{what}: {'|'.join(names)}")
+
+
+class Det(ctypes.Structure):
+    _fields_ = [("W", ctypes.c_int32), ("H", ctypes.c_int32), ("cx", ctypes.c_int32), ("cy", ctypes.c_int32),
+                ("bin", ctypes.c_int32)]
+
+
+class Scan(ctypes.Structure):
+    _fields_ = [("ny", ctypes.c_int32), ("nx", ctypes.c_int32), ("step", ctypes.c_double)]
+
+
+class Optics(ctypes.Structure):
+    _fields_ = [("lam", ctypes.c_double), ("r_bf", ctypes.c_double), ("dk", ctypes.c_double),
+                ("c", ctypes.c_double * 8)]
+
+    @classmethod
+    def from_values(cls, lam, r_bf, dk, c=(0.0,) * 8):
+        return cls(float(lam), float(r_bf), float(dk), (ctypes.c_double * 8)(*[float(v) for v in c]))
+
+
+class Dpc(ctypes.Structure):
+    _fields_ = [("mu", ctypes.c_double), ("lam1", ctypes.c_double), ("lam2", ctypes.c_double),
+                ("n_iter", ctypes.c_int32)]
+
+
+class Ssb(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("normalize", ctypes.c_int32), ("g_mode", ctypes.c_int32),
+                ("d_bits", ctypes.c_int32)]
+
+
+_LIB = None
+
+_SIGS = {
+    "stem_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "stem_version": (ctypes.c_int, []),
+    "eer_load_csr": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                    ctypes.c_int64, ctypes.POINTER(Det), ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_void_p]),
+    "com_dpc_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Scan)]),
+    "com_dpc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                               ctypes.POINTER(Det), ctypes.POINTER(Scan), ctypes.POINTER(Optics),
+                               ctypes.POINTER(Dpc), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                               ctypes.c_void_p]),
+    "ssb_num_pixels": (ctypes.c_int, [ctypes.POINTER(Det), ctypes.POINTER(Optics)]),
+    "ssb_state_bytes": (ctypes.c_size_t, [ctypes.POINTER(Det), ctypes.POINTER(Scan), ctypes.POINTER(Optics),
+                                          ctypes.POINTER(Ssb)]),
+    "ssb_reconstruct": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                       ctypes.POINTER(Det), ctypes.POINTER(Scan), ctypes.POINTER(Optics),
+                                       ctypes.POINTER(Ssb), ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p]),
+    "ssb_state_region": (ctypes.c_int, [ctypes.POINTER(Det), ctypes.POINTER(Scan), ctypes.POINTER(Optics),
+                                        ctypes.POINTER(Ssb), ctypes.c_int, ctypes.POINTER(ctypes.c_size_t),
+                                        ctypes.POINTER(ctypes.c_size_t)]),
+    "ssb_backward": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Det), ctypes.POINTER(Scan),
+                                    ctypes.POINTER(Optics), ctypes.POINTER(Ssb), ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_void_p]),
+}
+
+
+def lib():
+    """Load libstem4d.so (built by build_lib.build()); raises if it is missing."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libstem4d.so not found at {LIB_PATH}: build it with "
+                               "`python -m paper_2104_06336_amd.build_lib` (there is no CPU fallback)")
+        h = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(h, name)
+            f.restype = res
+            f.argtypes = args
+        _LIB = h
+    return _LIB
+
+
+def strerror(code: int) -> str:
+    return lib().stem_strerror(code).decode()

@@ -1,0 +1,51 @@
+// Internal launchers shared between the translation units of the stem4d library.
+#pragma once
+
+#include "common.h"
+#include "geom.h"
+
+namespace stem {
+
+// ---- eer.hip ---------------------------------------------------------------------------------
+int launch_com(const int32_t* idx, const int64_t* off, int64_t frame0, int64_t n_frames,
+               const stem_det& det, int64_t nplane, double* com64, float* com32, int32_t* counts,
+               int32_t* status, hipStream_t stream);
+int launch_geometry(const stem_det& det, double r2, RowRun* rows, double2* kc, hipStream_t stream);
+int launch_bin(const int32_t* idx, const int64_t* off, int64_t frame0, int64_t n_frames,
+               const stem_det& det, const RowRun* rows, int n_k, int64_t F, void* D, int d_bits,
+               int32_t* status, hipStream_t stream);
+
+// ---- fft2.hip: batched row FFTs of length n (power of two, 32..1024) --------------------------
+enum RowIn { IN_C64 = 0, IN_C64_SUM = 1, IN_F32_PAIR = 2, IN_F64_PAIR = 3 };
+enum RowOut { OUT_T_C64 = 0, OUT_ROW_C64 = 1, OUT_ROW_RE = 2, OUT_ROW_IM = 3, OUT_T_RE = 4, OUT_T_IM = 5 };
+
+struct RowFftArgs {
+  int64_t nrows;
+  // inputs
+  const float2* in_c;      // IN_C64 / IN_C64_SUM: row r at in_c + r*n (+ p*part_stride)
+  int64_t part_stride;
+  int32_t nparts;
+  const float* in_f0;      // IN_F32_PAIR: re = in_f0[r*n + j]*s0, im = in_f1[...]*s1 (in_f1 may be null)
+  const float* in_f1;
+  const double* in_d0;     // IN_F64_PAIR
+  const double* in_d1;
+  float s0, s1;
+  // outputs
+  float2* out_c;           // OUT_T_*: element (r, m) at out[m*out_stride + r]; OUT_ROW_*: out[r*n + m]
+  float* out_f;
+  int64_t out_stride;
+  float2 osc;              // complex factor applied to every output value
+};
+
+int launch_row_fft(int n, bool inverse, RowIn in, RowOut out, const RowFftArgs& a, hipStream_t stream);
+
+// DPC per-frequency gradient descent on the packed spectrum C = FFT2(gx + i gy), row-major
+// [my][mx]; writes Phi (row-major).
+int launch_dpc_update(const float2* C, float2* Phi, int ny, int nx, double step, const stem_dpc& p,
+                      hipStream_t stream);
+
+// ---- ssb.hip ---------------------------------------------------------------------------------
+size_t ssb_layout(const stem_det& det, const stem_scan& scan, const stem_optics& optics,
+                  const stem_ssb& ssb, int n_k, struct SsbLayout* lay);
+
+}  // namespace stem

@@ -1,0 +1,279 @@
+"""GPU parity of the HIP path against the FP64 oracle (small sizes: full element-by-element).
+
+Integer work (counts, binned cube, G(K, 0)) is compared bit for bit; FP32 outputs by
+relative L2 against the oracle with the tolerance 1e-5.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_2104_06336_amd as stem
+from gen import C4_TRUE_ABERRATIONS, WORKLOADS, random_csr, shuffle_within_frames, simulate, with_pileup
+from oracle import eer as oeer
+from oracle import ssb as ossb
+
+from helpers import (gpu_com, gpu_ssb, oracle_dpc, oracle_ssb, rel_l2, state_D, state_G_half, state_kc,
+                     structs, to_device)
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+SMALL = WORKLOADS["small"]
+# 576x576 detector binned 8x on a 64x64 scan (the large workloads' pixel set, oracle-sized)
+MID = WORKLOADS["scan1024"].replace(name="mid: scan 64x64, 576 detector binned 8x", scan=(64, 64))
+# non-square scan, binning 2 of a 64x64 detector
+RECT = SMALL.replace(name="rect: scan 32x64, binned 2x", scan=(32, 64), bin=2, mean_e=30.0)
+ABERR = SMALL.replace(name="small aberrated", aberr=C4_TRUE_ABERRATIONS)
+
+CASES = {"small": SMALL, "mid": MID, "rect": RECT, "aberr": ABERR}
+_DATA = {}
+
+
+def data(name):
+    if name not in _DATA:
+        wl = CASES[name]
+        d = simulate(wl)
+        idx, off = d.numpy()
+        _DATA[name] = (wl, idx, off)
+    return _DATA[name]
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    print(f"\n[gpu] {request.node.name}", flush=True)
+
+
+# ----------------------------------------------------------------------------------------------
+# centre of mass and DPC
+
+
+@pytest.mark.parametrize("name", ["small", "mid", "rect"])
+def test_com_bit_exact(gpu, name):
+    wl, idx, off = data(name)
+    d_idx, d_off = to_device(idx, off)
+    g = gpu_com(d_idx, d_off, wl)
+    H, W = wl.det
+    cx, cy, sx, sy, n = oeer.com(idx, off, W, H)
+    assert g["status"] == 0
+    assert np.array_equal(g["counts"], n)
+    assert np.array_equal(g["com64"][0], cx) and np.array_equal(g["com64"][1], cy)
+    assert np.array_equal(g["com32"][0], cx.astype(np.float32))
+    assert np.array_equal(g["com32"][1], cy.astype(np.float32))
+
+
+def test_com_chunks_and_edge_frames(gpu):
+    """Empty frames, a 300-event pile-up, unsorted frames; four chunks equal one call."""
+    rng = np.random.default_rng(11)
+    wl = SMALL.replace(scan=(32, 33))  # F = 1056: ragged last block of frames
+    idx, off = random_csr(rng, wl.n_frames, 64, 64, mean=20.0, p_empty=0.3)
+    idx, off = with_pileup(idx, off, 17, 64 * 31 + 5, 300)
+    idx = shuffle_within_frames(rng, idx, off)
+    d_idx, d_off = to_device(idx, off)
+    det, scan, optics = structs(wl)
+    F = wl.n_frames
+    com64 = torch.zeros(2 * F, dtype=torch.float64, device="cuda")
+    st = stem.status_tensor()
+    for f0 in range(0, F, 300):
+        stem.com_dpc(d_idx, d_off, f0, min(300, F - f0), det, scan, com64=com64, d_status=st)
+    cx, cy, *_ = oeer.com(idx, off, 64, 64)
+    c = com64.cpu().numpy().reshape(2, F)
+    assert int(st.item()) == 0
+    assert np.array_equal(c[0], cx) and np.array_equal(c[1], cy)
+
+
+@pytest.mark.parametrize("name", ["small", "mid", "rect"])
+@pytest.mark.parametrize("reg", [(0.0, 0.0, 10), (1.0, 0.05, 25)])
+def test_dpc_phase_parity(gpu, name, reg):
+    wl, idx, off = data(name)
+    d_idx, d_off = to_device(idx, off)
+    lam1, lam2, L = reg
+    g = gpu_com(d_idx, d_off, wl, phase=True, dpc_params=stem.Dpc(0.5, lam1, lam2, L))
+    ref = oracle_dpc(idx, off, wl, lam1=lam1, lam2=lam2, n_iter=L)
+    assert g["status"] == 0
+    assert rel_l2(g["phase"], ref) <= TOL
+
+
+# ----------------------------------------------------------------------------------------------
+# binning, scan transform, sideband sum, phase
+
+
+@pytest.mark.parametrize("name", ["small", "mid", "rect"])
+def test_binning_and_scan_transform(gpu, name):
+    wl, idx, off = data(name)
+    d_idx, d_off = to_device(idx, off)
+    st, out = gpu_ssb(d_idx, d_off, wl)
+    ref = oracle_ssb(idx, off, wl)
+    assert out["status"] == 0
+    assert np.array_equal(state_kc(st), ref["kc"])
+    assert np.array_equal(state_D(st, wl), ref["D"])
+    nh = wl.scan[1] // 2 + 1
+    G = state_G_half(st, wl)
+    Gr = ref["G"][:, :, :nh]
+    assert rel_l2(G, Gr) <= TOL
+    # G(K, Q=0) is the summed pattern, exactly (P6)
+    assert np.array_equal(G[:, 0, 0].real.astype(np.float64), ref["D"].sum(axis=1).astype(np.float64))
+    assert np.all(G[:, 0, 0].imag == 0)
+
+
+@pytest.mark.parametrize("name", ["small", "mid", "rect", "aberr"])
+def test_ssb_phase_parity(gpu, name):
+    wl, idx, off = data(name)
+    d_idx, d_off = to_device(idx, off)
+    c = wl.aberr
+    theta = None
+    if name == "aberr":
+        det, _, optics = structs(wl)
+        theta = np.random.default_rng(3).uniform(-0.3, 0.3, size=stem.ssb_num_pixels(det, optics))
+    st, out = gpu_ssb(d_idx, d_off, wl, c=c, theta=theta)
+    ref = oracle_ssb(idx, off, wl, c=c, theta=None if theta is None else theta.astype(np.float32))
+    assert out["status"] == 0
+    assert rel_l2(out["T"], ref["T"]) <= TOL
+    assert rel_l2(out["phi"], ref["phi"]) <= TOL
+    assert out["T"][0, 0] == 0
+
+
+def test_ssb_normalized_parity(gpu):
+    wl, idx, off = data("small")
+    d_idx, d_off = to_device(idx, off)
+    st, out = gpu_ssb(d_idx, d_off, wl, normalize=1)
+    ref = oracle_ssb(idx, off, wl, normalize=True)
+    assert rel_l2(out["T"], ref["T"]) <= TOL
+    assert rel_l2(out["phi"], ref["phi"]) <= TOL
+
+
+def test_refocus_matches_fresh_reconstruction(gpu):
+    """Interactive refocus (Sec. IV): only Eq. 3 and the phase are recomputed from stored G."""
+    wl, idx, off = data("aberr")
+    d_idx, d_off = to_device(idx, off)
+    st, out0 = gpu_ssb(d_idx, d_off, wl, c=(0.0,) * 8)
+    F = wl.n_frames
+    phase = torch.zeros(F, dtype=torch.float32, device="cuda")
+    T = torch.zeros(F, dtype=torch.complex64, device="cuda")
+    st.refocus(c=wl.aberr, phase=phase, T=T)
+    ref = oracle_ssb(idx, off, wl, c=wl.aberr)
+    assert rel_l2(T.cpu().numpy().reshape(wl.scan), ref["T"]) <= TOL
+    assert rel_l2(phase.cpu().numpy().reshape(wl.scan), ref["phi"]) <= TOL
+
+
+def test_chunked_accumulate_equals_oneshot(gpu):
+    wl, idx, off = data("mid")
+    d_idx, d_off = to_device(idx, off)
+    _, one = gpu_ssb(d_idx, d_off, wl)
+    _, chk = gpu_ssb(d_idx, d_off, wl, chunk_rows=16)
+    _, odd = gpu_ssb(d_idx, d_off, wl, chunk_rows=24)  # ragged last chunk
+    assert rel_l2(chk["phi"], one["phi"]) <= 1e-6
+    assert rel_l2(odd["phi"], one["phi"]) <= 1e-6
+
+
+def test_uint16_cube_and_overflow(gpu):
+    """A pile-up of 300 events in one bin does not fit uint8: STEM_EOVERFLOW, never clamped
+    silently; the uint16 cube holds it and matches the oracle."""
+    wl, idx, off = data("small")
+    H, W = wl.det
+    idx2, off2 = with_pileup(idx, off, 100, (H // 2) * W + W // 2, 300)
+    d_idx, d_off = to_device(idx2, off2)
+    st8, out8 = gpu_ssb(d_idx, d_off, wl, d_bits=8)
+    assert out8["status"] & 8
+    st16, out16 = gpu_ssb(d_idx, d_off, wl, d_bits=16)
+    assert out16["status"] == 0
+    ref = oracle_ssb(idx2, off2, wl)
+    assert np.array_equal(state_D(st16, wl), ref["D"])
+    assert rel_l2(out16["phi"], ref["phi"]) <= TOL
+
+
+def test_ingest_copy_and_validation(gpu):
+    """eer_load_csr: chunked host->device copy, then the device-side checks."""
+    wl, idx, off = data("small")
+    det, scan, optics = structs(wl)
+    F = wl.n_frames
+    d_idx = torch.zeros(len(idx), dtype=torch.int32, device="cuda")
+    d_off = torch.zeros(F + 1, dtype=torch.int64, device="cuda")
+    st = stem.status_tensor()
+    h_idx = torch.from_numpy(idx).pin_memory()
+    h_off = torch.from_numpy(off).pin_memory()
+    for f0 in range(0, F, 256):
+        nf = min(256, F - f0)
+        e0, e1 = int(off[f0]), int(off[f0 + nf])
+        stem.eer_load_csr(h_idx[e0:e1], h_off[f0:f0 + nf + 1], f0, nf, e1 - e0, det, d_idx, d_off, d_status=st)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    assert np.array_equal(d_idx.cpu().numpy(), idx) and np.array_equal(d_off.cpu().numpy(), off)
+    # out-of-range index -> ERANGE (validate-only path)
+    bad = idx.copy()
+    bad[5] = W_H = wl.det[0] * wl.det[1]
+    b_idx, b_off = to_device(bad, off)
+    st.zero_()
+    stem.eer_load_csr(None, None, 0, F, len(bad), det, b_idx, b_off, d_status=st)
+    assert int(st.item()) == 2
+    # decreasing offsets -> EOFFSETS
+    off_bad = off.copy()
+    off_bad[10] = off_bad[11] + 1
+    b_idx, b_off = to_device(idx, off_bad)
+    st.zero_()
+    stem.eer_load_csr(None, None, 0, F, len(idx), det, b_idx, b_off, d_status=st)
+    assert int(st.item()) & 4
+    # offsets pointing past the event array -> EOFFSETS, never followed
+    off_big = off.copy()
+    off_big[-1] = len(idx) + 1000
+    b_idx, b_off = to_device(idx, off_big)
+    st.zero_()
+    stem.eer_load_csr(None, None, 0, F, len(idx), det, b_idx, b_off, d_status=st)
+    assert int(st.item()) & 4
+    # COM and binning skip (and report) out-of-range indices without faulting
+    b_idx, b_off = to_device(bad, off)
+    g = gpu_com(b_idx, b_off, wl)
+    assert g["status"] == 2
+    assert W_H > 0
+
+
+# ----------------------------------------------------------------------------------------------
+# adjoint
+
+
+def test_adjoint_matches_oracle_gradient(gpu):
+    wl, idx, off = data("aberr")
+    d_idx, d_off = to_device(idx, off)
+    rng = np.random.default_rng(7)
+    c = np.array(C4_TRUE_ABERRATIONS) * (1 + rng.uniform(-0.5, 0.5, size=8))
+    st, out = gpu_ssb(d_idx, d_off, wl, c=c)
+    phi = torch.from_numpy(out["phi"]).cuda()
+    gbar = (-(2.0 / phi.numel()) * (phi - phi.mean())).contiguous().view(-1)
+    dc, dth = st.backward(gbar, c=c)
+    ref = oracle_ssb(idx, off, wl, c=c)
+    gbar_o = ossb.neg_var_grad(ref["phi"])
+    dco, dtho = ossb.ssb_adjoint(ref["G"], ref["kc"], gbar_o, wl.step, wl.dk, wl.lam, wl.r_bf, c)
+    dc = dc.cpu().numpy()
+    assert np.max(np.abs(dc - dco)) <= 1e-3 * np.max(np.abs(dco))
+    assert rel_l2(dth.cpu().numpy(), dtho) <= 1e-3
+
+
+def test_autograd_function_and_finite_differences(gpu):
+    """SSBPhase: torch.autograd gradient of -Var(phi) equals central differences of the
+    GPU forward (rel <= 1e-3) for every coefficient."""
+    wl, idx, off = data("aberr")
+    d_idx, d_off = to_device(idx, off)
+    det, scan, optics = structs(wl)
+    st = stem.SsbState(det, scan, optics)
+    st.accumulate(d_idx, d_off, 0, wl.n_frames)
+    rng = np.random.default_rng(8)
+    c0 = np.array(C4_TRUE_ABERRATIONS) * (1 + rng.uniform(-0.5, 0.5, size=8))
+    c = torch.tensor(c0, dtype=torch.float64, requires_grad=True)
+
+    def loss_of(cc):
+        phi = stem.SSBPhase.apply(cc, None, st)
+        return -phi.double().var(unbiased=False)
+
+    L = loss_of(c)
+    L.backward()
+    g = c.grad.numpy()
+    for j in range(8):
+        h = 2e-3 * abs(c0[j])
+        cp, cm = c0.copy(), c0.copy()
+        cp[j] += h
+        cm[j] -= h
+        with torch.no_grad():
+            lp = float(loss_of(torch.tensor(cp)).double())
+            lm = float(loss_of(torch.tensor(cm)).double())
+        fd = (lp - lm) / (2 * h)
+        assert abs(g[j] - fd) <= 1e-3 * max(abs(fd), 2e-2 * np.max(np.abs(g)))
