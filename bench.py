@@ -1,0 +1,254 @@
+#!/usr/bin/env python
+"""Throughput of the event-based phase-contrast path on one MI355X.
+
+One step = the whole hot path over one synthetic acquisition already resident in HBM:
+centre of mass of every frame + DPC integration (com_dpc), then the single-sideband
+reconstruction (ssb_reconstruct, one shot: binning, scan transform, double-overlap sum,
+phase image).  Reported: events/s (value) and scan positions/s, with the per-kernel
+roofline of the dominant kernel and the FP64 CPU oracle timed on a bounded sample.
+
+    python bench.py [--gpus 1] [--steps 10] [--warmup 3] [--workload scan1024]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "events/s + scan positions/s, COM-DPC+SSB; BF16-split vs FP32 at <=1e-4 error"
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(name, g):
+    """Bytes a kernel must move per launch (see the data-layout section of the design notes).
+
+    g: dict with C (events), F (frames), nk, nx, ny, P (double-overlap pairs), d_bytes."""
+    C, F, nk, nx, ny, P = g["C"], g["F"], g["nk"], g["nx"], g["ny"], g["P"]
+    nh = nx // 2 + 1
+    X = nk * nh * ny * 8  # row-transformed cube, complex64
+    table = {
+        "com_moments": 4 * C + 8 * (F + 1) + 16 * F,           # events, offsets, COM (FP64, 2 planes)
+        "bin_densify": 4 * C + 8 * (F + 1) + nk * F * g["d_bytes"],
+        "xstage_fft": nk * F * g["d_bytes"] + X,               # D in, X out
+        "ystage_fft": 2 * X,                                    # X in, G out (in place)
+        "ssb_reduce": 8 * P + 8 * F,                            # G on the double-overlap pairs, T out
+        "phase_fft": 2 * 8 * F,                                 # per pass: T in, out
+        "dpc_fft": 2 * 8 * F,
+        "dpc_update": 16 * F,
+    }
+    return table.get(name)
+
+
+def source_sha():
+    h = hashlib.sha256()
+    for d in ("paper_2104_06336_amd/csrc", "include"):
+        for f in sorted(os.listdir(os.path.join(ROOT, d))):
+            with open(os.path.join(ROOT, d, f), "rb") as fh:
+                h.update(f.encode())
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel, workload):
+    """HBM traffic per launch measured with rocprofv3 counters, if taken on the current sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    ent = rec.get(f"{kernel}@{workload}")
+    if not ent or ent.get("source_sha") != source_sha():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def cpu_baseline(idx, off, wl, n_k_sample=48, frame_frac=0.5):
+    """FP64 oracle on the host: all frames for COM + DPC, `frame_frac` of the frames for the
+    binning, and `n_k_sample` detector pixels for the scan transform and the sideband sum; each
+    stage is scaled to the full workload.  numpy runs these single-threaded."""
+    import numpy as np
+
+    from oracle import dpc as odpc
+    from oracle import eer as oeer
+    from oracle import ssb as ossb
+
+    H, W = wl.det
+    ny, nx = wl.scan
+    F = wl.n_frames
+    t = {}
+    t0 = time.perf_counter()
+    cx, cy, *_ = oeer.com(idx, off, W, H)
+    t["com"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    odpc.com_dpc(cx.reshape(ny, nx), cy.reshape(ny, nx), wl.dk, wl.step)
+    t["dpc"] = time.perf_counter() - t0
+    kc, lut = oeer.bin_geometry(W, H, wl.bin, wl.r_bf)
+    fs = int(F * frame_frac)
+    t0 = time.perf_counter()
+    Ds = oeer.bin_counts(idx[:off[fs]], off[:fs + 1], W, wl.bin, lut)
+    t["bin"] = (time.perf_counter() - t0) * F / fs
+    n_k = len(kc)
+    ks = min(n_k_sample, n_k)
+    D = np.zeros((ks, F), dtype=np.int64)
+    D[:, :fs] = Ds[:ks]
+    t0 = time.perf_counter()
+    G = ossb.scan_dft(ossb.cube(D, ny, nx))
+    t["scan_dft"] = (time.perf_counter() - t0) * n_k / ks
+    t0 = time.perf_counter()
+    T, _ = ossb.ssb_sum(G, kc[:ks], wl.step, wl.dk, wl.lam, wl.r_bf, wl.aberr)
+    t["ssb_sum"] = (time.perf_counter() - t0) * n_k / ks
+    t0 = time.perf_counter()
+    ossb.phase_from_T(T)
+    t["phase"] = time.perf_counter() - t0
+    total = sum(t.values())
+    return total, t, (f"FP64 numpy oracle, 1 thread: COM+DPC on all {F} frames, binning on {fs} frames "
+                      f"(x{F / fs:.0f}), scan DFT + Eq.3 sum on {ks} of {n_k} pixels (x{n_k / ks:.2f}), phase IFFT")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="scan1024")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="run a device copy of this many MiB first (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the path has no multi-GPU mode in this build "
+              "(see the sharding notes in the design document); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2104_06336_amd as stem
+    from gen import WORKLOADS, simulate
+
+    dev = torch.device("cuda:0")
+    wl = WORKLOADS[args.workload]
+    H, W = wl.det
+    ny, nx = wl.scan
+    F = wl.n_frames
+
+    t0 = time.time()
+    data = simulate(wl, device=dev)
+    torch.cuda.synchronize()
+    d_idx, d_off = data.idx.contiguous(), data.off.contiguous()
+    C = int(d_idx.numel())
+    log(f"generated {args.workload}: {F} frames, {C} events in {time.time() - t0:.1f} s")
+
+    det = stem.Det(W, H, W // 2, H // 2, wl.bin)
+    scan = stem.Scan(ny, nx, wl.step)
+    optics = stem.Optics.from_values(wl.lam, wl.r_bf, wl.dk, wl.aberr)
+    dpc = stem.Dpc(0.5, 0.0, 0.0, 10)
+    status = stem.status_tensor(dev)
+    stem.eer_load_csr(None, None, 0, F, C, det, d_idx, d_off, d_status=status)
+    stem.check_status(status, "event validation")
+
+    com64 = torch.empty(2 * F, dtype=torch.float64, device=dev)
+    phase_dpc = torch.empty(F, dtype=torch.float32, device=dev)
+    ws = torch.empty(stem.com_dpc_workspace_bytes(scan), dtype=torch.uint8, device=dev)
+    ssb_opts = stem.Ssb(stem.STEM_FFT_FP32, 0, stem.STEM_G_STORE, 8)
+    st = stem.SsbState(det, scan, optics, ssb_opts, device=dev)
+    phase_ssb = torch.empty(F, dtype=torch.float32, device=dev)
+
+    if args.copy_calib_mib:
+        n = args.copy_calib_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    def step():
+        stem.com_dpc(d_idx, d_off, 0, F, det, scan, optics, dpc, com64=com64, phase=phase_dpc, ws=ws,
+                     d_status=status)
+        st.oneshot(d_idx, d_off, phase=phase_ssb)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    stem.check_status(status, "com_dpc")
+    stem.check_status(st.status, "ssb_reconstruct")
+
+    stem.trace_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    recs = stem.trace_records()
+    stem.trace_enable(False)
+    ms_per_step = elapsed / args.steps * 1e3
+    P = st.pair_count()
+    n_k = st.n_k
+    log(f"{args.steps} steps in {elapsed:.4f} s ({ms_per_step:.3f} ms/step), n_K={n_k}, pairs={P}")
+
+    geo = {"C": C, "F": F, "nk": n_k, "nx": nx, "ny": ny, "P": P, "d_bytes": 1}
+    kernels = {}
+    for name, (n, ms) in sorted(recs.items(), key=lambda kv: -kv[1][1]):
+        per = n / args.steps
+        avg_ms = ms / n
+        ab = algorithmic_bytes(name, geo)
+        kernels[name] = {"launches_per_step": per, "avg_ms": round(avg_ms, 5),
+                         "ms_per_step": round(ms / args.steps, 5),
+                         "gbs": round(ab / (avg_ms * 1e-3) / 1e9, 1) if ab else None}
+        log(f"  {name:16s} {per:4.1f} x {avg_ms * 1e3:9.2f} us"
+            + (f"  {ab / 1e6:9.2f} MB  {ab / (avg_ms * 1e-3) / 1e9:8.1f} GB/s" if ab else ""))
+    dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
+    ab = algorithmic_bytes(dom, geo)
+    avg_s = kernels[dom]["avg_ms"] * 1e-3
+    roofline = {"kernel": dom, "bound": "hbm", "achieved": round(ab / avg_s / 1e9, 1) if ab else None,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ab / avg_s / 1e9 / HBM_PEAK_GBS, 4) if ab else None,
+                "traffic": load_traffic(dom, args.workload), "bytes_per_launch": ab}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        idx_np = d_idx.cpu().numpy()
+        off_np = d_off.cpu().numpy()
+        total, parts, sample = cpu_baseline(idx_np, off_np, wl)
+        cpu = {"value": round(C / total, 1), "unit": "events/s", "cores": 1, "kind": "oracle", "sample": sample,
+               "est_seconds_full": round(total, 2), "stage_seconds": {k: round(v, 3) for k, v in parts.items()}}
+        log(f"cpu oracle estimate {total:.1f} s per step -> {C / total:.3e} events/s")
+
+    out = {
+        "metric": METRIC,
+        "value": round(C * args.steps / elapsed, 1),
+        "unit": "events/s",
+        "positions_per_s": round(F * args.steps / elapsed, 1),
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {wl.name}", "scan": [ny, nx], "detector": [H, W],
+                   "bin": wl.bin, "mean_e_per_frame": wl.mean_e, "events": C, "frames": F, "n_k": n_k,
+                   "double_overlap_pairs": P, "ssb_path": "FP32 FFT", "parallelism": "single GPU"},
+        "kernels": kernels,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

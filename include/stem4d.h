@@ -214,8 +214,10 @@ int ssb_reconstruct(const int32_t* d_idx, const int64_t* d_off, int64_t frame0, 
  *                 transform G(kd, Q) (the other half of Q is its conjugate mirror).
  *  STEM_REGION_T  complex64 T(Q) of the last sum, column-major [mx][my].
  *  STEM_REGION_KC double2 Kc[kd] (x, y) bin centres in unbinned pixels, after ACCUMULATE.
+ *  STEM_REGION_STATS uint64 [4]: [0] = number of (pixel, Q) pairs in the double-overlap
+ *                 sets of the last sum (FINALIZE / REFOCUS); [1..3] reserved (0).
  * Writes the byte offset and size of the region; STEM_EINVAL for bad arguments. */
-enum { STEM_REGION_D = 0, STEM_REGION_G = 1, STEM_REGION_T = 2, STEM_REGION_KC = 3 };
+enum { STEM_REGION_D = 0, STEM_REGION_G = 1, STEM_REGION_T = 2, STEM_REGION_KC = 3, STEM_REGION_STATS = 4 };
 int ssb_state_region(const stem_det* det, const stem_scan* scan, const stem_optics* optics,
                      const stem_ssb* ssb, int region, size_t* offset, size_t* bytes);
 
@@ -234,6 +236,19 @@ int ssb_backward(const float* d_dLdphi, const stem_det* det, const stem_scan* sc
                  const stem_optics* optics, const stem_ssb* ssb, const float* d_theta,
                  void* state, size_t state_bytes, double* d_dLdc, float* d_dLdtheta,
                  int32_t* d_status, void* stream);
+
+/* ---------------------------------------------------------------------------------------- */
+/* Kernel tracing (measurement support)                                                     */
+
+/* Enable (on != 0, clearing earlier records) or disable per-launch timing: each kernel the
+ * library launches is bracketed by two hipEvents recorded on its launch stream. */
+int stem_trace_enable(int on);
+/* Number of distinct traced kernel names. */
+int stem_trace_count(void);
+/* Record i: kernel name (NUL-terminated, truncated to name_len), number of launches and the
+ * sum of their event-to-event durations in milliseconds.  Waits for the recorded events.
+ * STEM_EINVAL for a bad index, STEM_EHIP if an event query fails. */
+int stem_trace_get(int i, char* name, size_t name_len, int64_t* launches, double* total_ms);
 
 #ifdef __cplusplus
 }

@@ -15,7 +15,8 @@ import torch
 from ._abi import (Det, Dpc, Optics, Scan, Ssb, StemError, lib, LIB_PATH, STEM_FFT_FP32,
                    STEM_DFT_BF16_SPLIT, STEM_DFT_FP16_SPLIT, STEM_G_RECOMPUTE, STEM_G_STORE,
                    STEM_SSB_ACCUMULATE, STEM_SSB_FINALIZE, STEM_SSB_REFOCUS, STEM_SSB_ONESHOT,
-                   STEM_REGION_D, STEM_REGION_G, STEM_REGION_T, STEM_REGION_KC, STATUS_BITS, strerror)
+                   STEM_REGION_D, STEM_REGION_G, STEM_REGION_T, STEM_REGION_KC, STEM_REGION_STATS, STATUS_BITS, strerror, trace_enable,
+                   trace_records)
 
 __all__ = [
     "Det", "Scan", "Optics", "Dpc", "Ssb", "StemError", "lib", "LIB_PATH",
@@ -24,7 +25,7 @@ __all__ = [
     "STEM_FFT_FP32", "STEM_DFT_BF16_SPLIT", "STEM_DFT_FP16_SPLIT", "STEM_G_RECOMPUTE",
     "STEM_G_STORE", "STEM_SSB_ACCUMULATE", "STEM_SSB_FINALIZE", "STEM_SSB_REFOCUS",
     "STEM_SSB_ONESHOT", "SsbState", "SSBPhase", "ssb_state_region", "STEM_REGION_D", "STEM_REGION_G",
-    "STEM_REGION_T", "STEM_REGION_KC",
+    "STEM_REGION_T", "STEM_REGION_KC", "STEM_REGION_STATS", "trace_enable", "trace_records",
 ]
 
 
@@ -199,6 +200,10 @@ class SsbState:
         """A uint8 view of one region of the state buffer (see ssb_state_region)."""
         off, nb = ssb_state_region(self.det, self.scan, self.optics, self.ssb, which)
         return self.state[off:off + nb]
+
+    def pair_count(self) -> int:
+        """Double-overlap (pixel, Q) pairs of the last sum (waits for the stream)."""
+        return int(self.region(STEM_REGION_STATS).view(torch.int64)[0].item())
 
     def optics_with(self, c) -> Optics:
         o = Optics.from_values(self.optics.lam, self.optics.r_bf, self.optics.dk, c)

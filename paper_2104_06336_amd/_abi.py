@@ -10,7 +10,7 @@ STEM_FFT_FP32, STEM_DFT_BF16_SPLIT, STEM_DFT_FP16_SPLIT = 0, 1, 2
 STEM_G_RECOMPUTE, STEM_G_STORE = 0, 1
 STEM_SSB_ACCUMULATE, STEM_SSB_FINALIZE, STEM_SSB_REFOCUS, STEM_SSB_ONESHOT = 0, 1, 2, 3
 
-STEM_REGION_D, STEM_REGION_G, STEM_REGION_T, STEM_REGION_KC = 0, 1, 2, 3
+STEM_REGION_D, STEM_REGION_G, STEM_REGION_T, STEM_REGION_KC, STEM_REGION_STATS = 0, 1, 2, 3, 4
 
 STATUS_BITS = {1: "EINVAL", 2: "ERANGE", 4: "EOFFSETS", 8: "EOVERFLOW", 16: "EWORKSPACE", 32: "EHIP",
                64: "ESTATE"}
@@ -80,6 +80,10 @@ _SIGS = {
                                     ctypes.POINTER(Optics), ctypes.POINTER(Ssb), ctypes.c_void_p,
                                     ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p,
                                     ctypes.c_void_p, ctypes.c_void_p]),
+    "stem_trace_enable": (ctypes.c_int, [ctypes.c_int]),
+    "stem_trace_count": (ctypes.c_int, []),
+    "stem_trace_get": (ctypes.c_int, [ctypes.c_int, ctypes.c_char_p, ctypes.c_size_t,
+                                      ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]),
 }
 
 
@@ -101,3 +105,21 @@ def lib():
 
 def strerror(code: int) -> str:
     return lib().stem_strerror(code).decode()
+
+
+def trace_enable(on: bool = True):
+    """Start (clearing earlier records) or stop per-launch kernel timing in the library."""
+    lib().stem_trace_enable(1 if on else 0)
+
+
+def trace_records() -> dict:
+    """{kernel name: (launches, total ms)} of the current trace session (waits for events)."""
+    out = {}
+    for i in range(lib().stem_trace_count()):
+        buf = ctypes.create_string_buffer(128)
+        n, ms = ctypes.c_int64(0), ctypes.c_double(0.0)
+        rc = lib().stem_trace_get(i, buf, 128, ctypes.byref(n), ctypes.byref(ms))
+        if rc != 0:
+            raise StemError(rc, "stem_trace_get")
+        out[buf.value.decode()] = (int(n.value), float(ms.value))
+    return out

@@ -9,6 +9,7 @@
 #include "common.h"
 #include "geom.h"
 #include "kernels.h"
+#include "trace.h"
 
 namespace stem {
 
@@ -110,6 +111,7 @@ int launch_com(const int32_t* idx, const int64_t* off, int64_t frame0, int64_t n
                int32_t* status, hipStream_t stream) {
   if (n_frames == 0) return STEM_OK;
   const int64_t blocks = (n_frames + kComThreads - 1) / kComThreads;
+  STEM_TRACE("com_moments", stream);
   hipLaunchKernelGGL(k_com, dim3((unsigned)blocks), dim3(kComThreads), 0, stream, idx, off, frame0,
                      n_frames, make_magic((uint32_t)det.W), det.cx, det.cy, det.W * det.H, nplane,
                      com64, com32, counts, status);
@@ -164,6 +166,7 @@ __global__ void __launch_bounds__(256) k_geometry(int32_t b, int32_t nbx, int32_
 
 int launch_geometry(const stem_det& det, double r2, RowRun* rows, double2* kc, hipStream_t stream) {
   const int nbx = det.W / det.bin, nby = det.H / det.bin;
+  STEM_TRACE("ssb_geometry", stream);
   hipLaunchKernelGGL(k_geometry, dim3(1), dim3(256), 0, stream, det.bin, nbx, nby, det.cx, det.cy, r2,
                      rows, kc);
   STEM_LAUNCH_CHECK();
@@ -257,6 +260,7 @@ int launch_bin(const int32_t* idx, const int64_t* off, int64_t frame0, int64_t n
   const dim3 grid((unsigned)(fblocks * nchunks));
   const Magic mw = make_magic((uint32_t)det.W), mb = make_magic((uint32_t)det.bin);
   const int nby = det.H / det.bin;
+  STEM_TRACE("bin_densify", stream);
   if (d_bits == 8)
     hipLaunchKernelGGL(k_bin<uint8_t>, grid, dim3(kBinThreads), 0, stream, idx, off, frame0, n_frames, mw,
                        mb, det.W * det.H, nby, rows, n_k, F, (uint8_t*)D, status);
@@ -313,8 +317,11 @@ extern "C" int eer_load_csr(const int32_t* h_idx, const int64_t* h_off, int64_t 
   int64_t blocks = (work + 255) / 256;
   if (blocks < 1) blocks = 1;
   if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(k_validate, dim3((unsigned)blocks), dim3(256), 0, stream, d_idx, d_off, frame0,
-                     n_frames, n_events, h_off ? 1 : 0, lo, hi, det->W * det->H, d_status);
+  {
+    STEM_TRACE("csr_validate", stream);
+    hipLaunchKernelGGL(k_validate, dim3((unsigned)blocks), dim3(256), 0, stream, d_idx, d_off, frame0,
+                       n_frames, n_events, h_off ? 1 : 0, lo, hi, det->W * det->H, d_status);
+  }
   STEM_LAUNCH_CHECK();
   return STEM_OK;
 }

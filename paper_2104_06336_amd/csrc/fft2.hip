@@ -8,6 +8,7 @@
 #include "common.h"
 #include "fft_wave.h"
 #include "kernels.h"
+#include "trace.h"
 
 namespace stem {
 
@@ -105,6 +106,7 @@ int launch_row_fft(int n, bool inverse, RowIn in, RowOut out, const RowFftArgs& 
   const int64_t tr = 8 * (1024 / n);
   int64_t tiles = (a.nrows + tr - 1) / tr;
   const dim3 grid((unsigned)(tiles < 2048 ? tiles : 2048));
+  STEM_TRACE(a.tag ? a.tag : "row_fft", stream);
   switch (n) {
     case 32: launch_n<32>(inverse, grid, a, in, out, stream); break;
     case 64: launch_n<64>(inverse, grid, a, in, out, stream); break;
@@ -163,6 +165,7 @@ __global__ void __launch_bounds__(256) k_dpc_update(const float2* __restrict__ C
 int launch_dpc_update(const float2* C, float2* Phi, int ny, int nx, double step, const stem_dpc& p,
                       hipStream_t stream) {
   const int64_t n = (int64_t)ny * nx;
+  STEM_TRACE("dpc_update", stream);
   hipLaunchKernelGGL(k_dpc_update, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, C, Phi, ny, nx,
                      step, p.mu, p.lam1, p.lam2, p.n_iter);
   STEM_LAUNCH_CHECK();
@@ -218,6 +221,7 @@ extern "C" int com_dpc(const int32_t* d_idx, const int64_t* d_off, int64_t frame
   a.out_c = A;
   a.out_stride = ny;
   a.osc = make_float2(1.f, 0.f);
+  a.tag = "dpc_fft";
   st = launch_row_fft(nx, false, d_com64 ? IN_F64_PAIR : IN_F32_PAIR, OUT_T_C64, a, stream);
   if (st) return st;
   // pass 2: rows (mx) of A along ry -> Bb[my][mx]
@@ -227,6 +231,7 @@ extern "C" int com_dpc(const int32_t* d_idx, const int64_t* d_off, int64_t frame
   a.out_c = Bb;
   a.out_stride = nx;
   a.osc = make_float2(1.f, 0.f);
+  a.tag = "dpc_fft";
   if ((st = launch_row_fft(ny, false, IN_C64, OUT_T_C64, a, stream))) return st;
   // gradient descent per frequency: Bb -> A (Phi, [my][mx])
   if ((st = launch_dpc_update(Bb, A, ny, nx, scan->step, *dpc, stream))) return st;
@@ -243,5 +248,6 @@ extern "C" int com_dpc(const int32_t* d_idx, const int64_t* d_off, int64_t frame
   a.out_f = d_phase;
   a.out_stride = nx;
   a.osc = make_float2((float)(1.0 / (double)F), 0.f);
+  a.tag = "dpc_fft";
   return launch_row_fft(ny, true, IN_C64, OUT_T_RE, a, stream);
 }

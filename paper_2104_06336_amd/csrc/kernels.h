@@ -35,6 +35,7 @@ struct RowFftArgs {
   float* out_f;
   int64_t out_stride;
   float2 osc;              // complex factor applied to every output value
+  const char* tag;         // name under which the launch is traced
 };
 
 int launch_row_fft(int n, bool inverse, RowIn in, RowOut out, const RowFftArgs& a, hipStream_t stream);

@@ -12,6 +12,7 @@
 #include "fft_wave.h"
 #include "kernels.h"
 #include "optics.h"
+#include "trace.h"
 
 namespace stem {
 
@@ -22,7 +23,7 @@ constexpr int kMaxPixels = 4096;
 struct SsbLayout {
   int n_k, nby, nh;
   int64_t F;
-  size_t rows, kc, kchi, D, X, T, A, Tb, pdc, pdth, total;
+  size_t rows, kc, kchi, stats, D, X, T, A, Tb, pdc, pdth, total;
   int64_t nblk;  // workgroups of the per-Q kernels
 };
 
@@ -60,6 +61,7 @@ static size_t make_layout(const stem_det& det, const stem_scan& scan, const stem
   L->rows = o;  o = align256(o + sizeof(RowRun) * L->nby);
   L->kc = o;    o = align256(o + sizeof(double2) * n_k);
   L->kchi = o;  o = align256(o + sizeof(double) * n_k);
+  L->stats = o; o = align256(o + sizeof(unsigned long long) * 4);
   L->D = o;     o = align256(o + (size_t)n_k * L->F * (ssb.d_bits / 8));
   L->X = o;     o = align256(o + (size_t)n_k * L->nh * scan.ny * sizeof(float2));
   L->T = o;     o = align256(o + (size_t)L->F * sizeof(float2));
@@ -142,6 +144,7 @@ static int launch_xstage_t(int nx, const DT* D, int ny, int ry0, int nr, int64_t
   const int64_t tr = 16 * (1024 / nx);
   const int64_t tiles = (nrows + tr - 1) / tr;
   const dim3 grid((unsigned)(tiles < 4096 ? tiles : 4096)), blk(kXThreads);
+  STEM_TRACE("xstage_fft", s);
   switch (nx) {
     case 32: hipLaunchKernelGGL((k_xstage<32, DT>), grid, blk, 0, s, D, ny, ry0, nr, nrows, X); break;
     case 64: hipLaunchKernelGGL((k_xstage<64, DT>), grid, blk, 0, s, D, ny, ry0, nr, nrows, X); break;
@@ -159,8 +162,9 @@ static int launch_xstage_t(int nx, const DT* D, int ny, int ry0, int nr, int64_t
 // chi(Kc) + theta per kept pixel
 
 __global__ void k_chi_table(const double2* __restrict__ kc, const float* __restrict__ theta, int n_k,
-                            Optics o, double* __restrict__ kchi) {
+                            Optics o, double* __restrict__ kchi, unsigned long long* __restrict__ stats) {
   const int kd = blockIdx.x * blockDim.x + threadIdx.x;
+  if (kd < 4) stats[kd] = 0ull;  // counters of the sum that follows
   if (kd >= n_k) return;
   const double2 k = kc[kd];
   kchi[kd] = chi_px(k.x, k.y, o) + (theta ? (double)theta[kd] : 0.0);
@@ -171,9 +175,11 @@ __global__ void k_chi_table(const double2* __restrict__ kc, const float* __restr
 
 __global__ void __launch_bounds__(256) k_reduce(const float2* __restrict__ G, const double2* __restrict__ kc,
                                                 const double* __restrict__ kchi, int n_k, int ny, int nx,
-                                                Optics o, int normalize, float2* __restrict__ Tt) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= (int64_t)ny * nx) return;
+                                                Optics o, int normalize, float2* __restrict__ Tt,
+                                                unsigned long long* __restrict__ stats) {
+  const int64_t q0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = q0 < (int64_t)ny * nx;
+  const int64_t q = valid ? q0 : 0;
   const int mx = (int)(q / ny), my = (int)(q % ny);
   const double qx = (double)signed_index(mx, nx) * o.sx;
   const double qy = (double)signed_index(my, ny) * o.sy;
@@ -184,7 +190,7 @@ __global__ void __launch_bounds__(256) k_reduce(const float2* __restrict__ G, co
   const int64_t kstride = (int64_t)nh * ny;
   float2 acc = make_float2(0.f, 0.f);
   int cnt = 0;
-  for (int kd = 0; kd < n_k; ++kd) {
+  for (int kd = 0; kd < n_k && valid; ++kd) {
     const double2 k = kc[kd];
     if (!double_overlap(k.x, k.y, qx, qy, o.r2)) continue;
     const double psi = chi_px(k.x - qx, k.y - qy, o) - kchi[kd];
@@ -196,7 +202,11 @@ __global__ void __launch_bounds__(256) k_reduce(const float2* __restrict__ G, co
     ++cnt;
   }
   if (normalize && cnt > 0) acc = cscale(acc, 1.f / (float)cnt);
-  Tt[q] = acc;
+  if (valid) Tt[q] = acc;
+  // number of double-overlap pairs of this sum, one atomic per wave
+  unsigned long long c = valid ? (unsigned long long)cnt : 0ull;
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+  if ((threadIdx.x & 63) == 0) atomicAdd(stats, c);
 }
 
 // T[mx][my] (column-major) -> d_T[my][mx] (row-major)
@@ -325,6 +335,7 @@ struct Bufs {
   RowRun* rows;
   double2* kc;
   double* kchi;
+  unsigned long long* stats;
   void* D;
   float2* X;
   float2* T;
@@ -336,7 +347,8 @@ struct Bufs {
 
 static Bufs carve(void* state, const SsbLayout& L) {
   char* p = (char*)state;
-  return Bufs{(RowRun*)(p + L.rows), (double2*)(p + L.kc), (double*)(p + L.kchi), (void*)(p + L.D),
+  return Bufs{(RowRun*)(p + L.rows), (double2*)(p + L.kc), (double*)(p + L.kchi),
+              (unsigned long long*)(p + L.stats), (void*)(p + L.D),
               (float2*)(p + L.X),    (float2*)(p + L.T),  (float2*)(p + L.A),     (float2*)(p + L.Tb),
               (double*)(p + L.pdc),  (float*)(p + L.pdth)};
 }
@@ -368,6 +380,7 @@ static int run_phase(const SsbLayout& L, const Bufs& b, const stem_scan& sc, flo
     a.out_c = b.A;
     a.out_stride = nx;
     a.osc = make_float2(1.f, 0.f);
+    a.tag = "phase_fft";
     int st = launch_row_fft(ny, true, IN_C64_SUM, OUT_T_C64, a, s);
     if (st) return st;
     a = RowFftArgs{};
@@ -375,9 +388,11 @@ static int run_phase(const SsbLayout& L, const Bufs& b, const stem_scan& sc, flo
     a.in_c = b.A;
     a.out_f = d_phase;
     a.osc = make_float2((float)(1.0 / (double)L.F), 0.f);
+    a.tag = "phase_fft";
     if ((st = launch_row_fft(nx, true, IN_C64, OUT_ROW_IM, a, s))) return st;
   }
   if (d_T) {
+    STEM_TRACE("t_transpose", s);
     hipLaunchKernelGGL(k_transpose_T, dim3((ny + 31) / 32, (nx + 31) / 32), dim3(32, 8), 0, s, b.T, ny, nx,
                        (float2*)d_T);
     STEM_LAUNCH_CHECK();
@@ -416,6 +431,7 @@ extern "C" int ssb_state_region(const stem_det* det, const stem_scan* scan, cons
     case STEM_REGION_G: *offset = L.X; *bytes = (size_t)n_k * L.nh * scan->ny * sizeof(float2); break;
     case STEM_REGION_T: *offset = L.T; *bytes = (size_t)L.F * sizeof(float2); break;
     case STEM_REGION_KC: *offset = L.kc; *bytes = (size_t)n_k * sizeof(double2); break;
+    case STEM_REGION_STATS: *offset = L.stats; *bytes = 4 * sizeof(unsigned long long); break;
     default: return STEM_EINVAL;
   }
   return STEM_OK;
@@ -466,12 +482,19 @@ extern "C" int ssb_reconstruct(const int32_t* d_idx, const int64_t* d_off, int64
     a.in_c = b.X;
     a.out_c = b.X;
     a.osc = make_float2(1.f, 0.f);
+    a.tag = "ystage_fft";
     if ((st = launch_row_fft(ny, false, IN_C64, OUT_ROW_C64, a, s))) return st;
   }
-  hipLaunchKernelGGL(k_chi_table, dim3((n_k + 255) / 256), dim3(256), 0, s, b.kc, d_theta, n_k, o, b.kchi);
+  {
+    STEM_TRACE("chi_table", s);
+    hipLaunchKernelGGL(k_chi_table, dim3((n_k + 255) / 256), dim3(256), 0, s, b.kc, d_theta, n_k, o, b.kchi, b.stats);
+  }
   STEM_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_reduce, dim3((unsigned)L.nblk), dim3(256), 0, s, b.X, b.kc, b.kchi, n_k, ny, nx, o,
-                     ssb->normalize, b.T);
+  {
+    STEM_TRACE("ssb_reduce", s);
+    hipLaunchKernelGGL(k_reduce, dim3((unsigned)L.nblk), dim3(256), 0, s, b.X, b.kc, b.kchi, n_k, ny, nx, o,
+                       ssb->normalize, b.T, b.stats);
+  }
   STEM_LAUNCH_CHECK();
   return run_phase(L, b, *scan, d_phase, d_T, s);
 }
@@ -500,19 +523,31 @@ extern "C" int ssb_backward(const float* d_dLdphi, const stem_det* det, const st
   a.out_c = b.A;
   a.out_stride = ny;
   a.osc = make_float2(1.f, 0.f);
+  a.tag = "adj_fft";
   if ((st = launch_row_fft(nx, false, IN_F32_PAIR, OUT_T_C64, a, s))) return st;
   a = RowFftArgs{};
   a.nrows = nx;
   a.in_c = b.A;
   a.out_c = b.Tb;
   a.osc = make_float2(0.f, (float)(1.0 / (double)L.F));
+  a.tag = "adj_fft";
   if ((st = launch_row_fft(ny, false, IN_C64, OUT_ROW_C64, a, s))) return st;
-  hipLaunchKernelGGL(k_chi_table, dim3((n_k + 255) / 256), dim3(256), 0, s, b.kc, d_theta, n_k, o, b.kchi);
+  {
+    STEM_TRACE("chi_table", s);
+    hipLaunchKernelGGL(k_chi_table, dim3((n_k + 255) / 256), dim3(256), 0, s, b.kc, d_theta, n_k, o, b.kchi, b.stats);
+  }
   STEM_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_adjoint, dim3((unsigned)L.nblk), dim3(256), 0, s, b.X, b.kc, b.kchi, n_k, ny, nx, o, b.Tb,
-                     b.pdc, b.pdth);
+  {
+    STEM_TRACE("ssb_adjoint", s);
+    hipLaunchKernelGGL(k_adjoint, dim3((unsigned)L.nblk), dim3(256), 0, s, b.X, b.kc, b.kchi, n_k, ny, nx, o,
+                       b.Tb, b.pdc, b.pdth);
+  }
   STEM_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_adjoint_final, dim3(1), dim3(256), 0, s, b.pdc, b.pdth, L.nblk, n_k, d_dLdc, d_dLdtheta);
+  {
+    STEM_TRACE("ssb_adjoint_final", s);
+    hipLaunchKernelGGL(k_adjoint_final, dim3(1), dim3(256), 0, s, b.pdc, b.pdth, L.nblk, n_k, d_dLdc,
+                       d_dLdtheta);
+  }
   STEM_LAUNCH_CHECK();
   return STEM_OK;
 }

@@ -244,13 +244,16 @@ def test_adjoint_matches_oracle_gradient(gpu):
     gbar_o = ossb.neg_var_grad(ref["phi"])
     dco, dtho = ossb.ssb_adjoint(ref["G"], ref["kc"], gbar_o, wl.step, wl.dk, wl.lam, wl.r_bf, c)
     dc = dc.cpu().numpy()
-    assert np.max(np.abs(dc - dco)) <= 1e-3 * np.max(np.abs(dco))
-    assert rel_l2(dth.cpu().numpy(), dtho) <= 1e-3
+    # every component, including those 1000x below the largest, to 1e-4 of its own size
+    assert np.all(np.abs(dc - dco) <= 1e-4 * np.abs(dco) + 1e-7 * np.max(np.abs(dco)))
+    assert rel_l2(dth.cpu().numpy(), dtho) <= 1e-4
 
 
 def test_autograd_function_and_finite_differences(gpu):
     """SSBPhase: torch.autograd gradient of -Var(phi) equals central differences of the
-    GPU forward (rel <= 1e-3) for every coefficient."""
+    GPU forward (rel <= 1e-3) for the coefficients that carry at least 10% of the largest
+    gradient.  (Smaller components sit below the FP32 forward's finite-difference noise;
+    they are checked component by component against the FP64 oracle gradient above.)"""
     wl, idx, off = data("aberr")
     d_idx, d_off = to_device(idx, off)
     det, scan, optics = structs(wl)
@@ -268,6 +271,8 @@ def test_autograd_function_and_finite_differences(gpu):
     L.backward()
     g = c.grad.numpy()
     for j in range(8):
+        if abs(g[j]) < 0.1 * np.max(np.abs(g)):
+            continue
         h = 2e-3 * abs(c0[j])
         cp, cm = c0.copy(), c0.copy()
         cp[j] += h
@@ -276,4 +281,4 @@ def test_autograd_function_and_finite_differences(gpu):
             lp = float(loss_of(torch.tensor(cp)).double())
             lm = float(loss_of(torch.tensor(cm)).double())
         fd = (lp - lm) / (2 * h)
-        assert abs(g[j] - fd) <= 1e-3 * max(abs(fd), 2e-2 * np.max(np.abs(g)))
+        assert abs(g[j] - fd) <= 1e-3 * abs(fd)
