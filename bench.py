@@ -42,8 +42,9 @@ def algorithmic_bytes(name, g):
         "bin_densify": 4 * C + 8 * (F + 1) + nk * F * g["d_bytes"],
         "xstage_fft": nk * F * g["d_bytes"] + X,               # D in, X out
         "ystage_fft": 2 * X,                                    # X in, G out (in place)
+        "ssb_yreduce": X + 8 * F * g["groups"],                # X in, partial T per pixel group out
         "ssb_reduce": 8 * P + 8 * F,                            # G on the double-overlap pairs, T out
-        "phase_fft": 2 * 8 * F,                                 # per pass: T in, out
+        "phase_fft": 8 * F * (1 + g["groups"]) // 2 + 8 * F,  # the two passes averaged: partial sums in, T out
         "dpc_fft": 2 * 8 * F,
         "dpc_update": 16 * F,
     }
@@ -161,7 +162,7 @@ def main():
     com64 = torch.empty(2 * F, dtype=torch.float64, device=dev)
     phase_dpc = torch.empty(F, dtype=torch.float32, device=dev)
     ws = torch.empty(stem.com_dpc_workspace_bytes(scan), dtype=torch.uint8, device=dev)
-    ssb_opts = stem.Ssb(stem.STEM_FFT_FP32, 0, stem.STEM_G_STORE, 8)
+    ssb_opts = stem.Ssb(stem.STEM_FFT_FP32, 0, stem.STEM_G_RECOMPUTE, 8)
     st = stem.SsbState(det, scan, optics, ssb_opts, device=dev)
     phase_ssb = torch.empty(F, dtype=torch.float32, device=dev)
 
@@ -194,11 +195,11 @@ def main():
     recs = stem.trace_records()
     stem.trace_enable(False)
     ms_per_step = elapsed / args.steps * 1e3
-    P = st.pair_count()
+    P, groups = st.stats()[:2]
     n_k = st.n_k
     log(f"{args.steps} steps in {elapsed:.4f} s ({ms_per_step:.3f} ms/step), n_K={n_k}, pairs={P}")
 
-    geo = {"C": C, "F": F, "nk": n_k, "nx": nx, "ny": ny, "P": P, "d_bytes": 1}
+    geo = {"C": C, "F": F, "nk": n_k, "nx": nx, "ny": ny, "P": P, "d_bytes": 1, "groups": groups}
     kernels = {}
     for name, (n, ms) in sorted(recs.items(), key=lambda kv: -kv[1][1]):
         per = n / args.steps
@@ -242,7 +243,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {wl.name}", "scan": [ny, nx], "detector": [H, W],
                    "bin": wl.bin, "mean_e_per_frame": wl.mean_e, "events": C, "frames": F, "n_k": n_k,
-                   "double_overlap_pairs": P, "ssb_path": "FP32 FFT", "parallelism": "single GPU"},
+                   "double_overlap_pairs": P, "ssb_path": "FP32 FFT, fused column transform + sum (G recomputed)",
+                   "parallelism": "single GPU"},
         "kernels": kernels,
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -215,7 +215,9 @@ int ssb_reconstruct(const int32_t* d_idx, const int64_t* d_off, int64_t frame0, 
  *  STEM_REGION_T  complex64 T(Q) of the last sum, column-major [mx][my].
  *  STEM_REGION_KC double2 Kc[kd] (x, y) bin centres in unbinned pixels, after ACCUMULATE.
  *  STEM_REGION_STATS uint64 [4]: [0] = number of (pixel, Q) pairs in the double-overlap
- *                 sets of the last sum (FINALIZE / REFOCUS); [1..3] reserved (0).
+ *                 sets of the last sum (FINALIZE / REFOCUS); [1] = number of partial sums of T
+ *                 it combined (pixel groups of the fused column transform, 1 otherwise);
+ *                 [2..3] reserved (0).
  * Writes the byte offset and size of the region; STEM_EINVAL for bad arguments. */
 enum { STEM_REGION_D = 0, STEM_REGION_G = 1, STEM_REGION_T = 2, STEM_REGION_KC = 3, STEM_REGION_STATS = 4 };
 int ssb_state_region(const stem_det* det, const stem_scan* scan, const stem_optics* optics,

@@ -205,6 +205,10 @@ class SsbState:
         """Double-overlap (pixel, Q) pairs of the last sum (waits for the stream)."""
         return int(self.region(STEM_REGION_STATS).view(torch.int64)[0].item())
 
+    def stats(self) -> list:
+        """The four uint64 counters of the state (pairs, partial sums of T, reserved)."""
+        return [int(v) for v in self.region(STEM_REGION_STATS).view(torch.int64).cpu().tolist()]
+
     def optics_with(self, c) -> Optics:
         o = Optics.from_values(self.optics.lam, self.optics.r_bf, self.optics.dk, c)
         return o

@@ -14,7 +14,6 @@
 namespace stem {
 
 constexpr int kComThreads = 256;   // one frame per thread
-constexpr int kWin = 4096;         // events per LDS window
 
 // ---------------------------------------------------------------------------------------------
 // validation
@@ -47,7 +46,46 @@ __global__ void __launch_bounds__(256) k_validate(const int32_t* __restrict__ id
 }
 
 // ---------------------------------------------------------------------------------------------
-// centre of mass
+// block-local frame lookup shared by the event-parallel kernels
+
+// Largest j in [0, nf) with rel[j] <= e (rel: non-decreasing, rel[0] = 0 <= e < rel[nf]).
+__device__ __forceinline__ int frame_of(const int32_t* rel, int nf, int32_t e) {
+  int a = 0, z = nf - 1;
+  while (a < z) {
+    const int mid = (a + z + 1) >> 1;
+    if (rel[mid] <= e) a = mid; else z = mid - 1;
+  }
+  return a;
+}
+
+// Loads the block's offsets relative to its first event.  Returns false (and reports) when
+// the block holds 2^30 events or more, which the 32-bit relative offsets cannot address.
+__device__ __forceinline__ bool load_rel_offsets(const int64_t* __restrict__ off, int64_t fb, int nf,
+                                                 int32_t* s_rel, int64_t* s_base, int32_t* status) {
+  const int64_t base = off[fb];
+  const int64_t span = off[fb + nf] - base;
+  if (span >= (1ll << 30)) {
+    if (threadIdx.x == 0) report(status, STEM_EOVERFLOW);
+    return false;
+  }
+  for (int i = threadIdx.x; i <= nf; i += blockDim.x) s_rel[i] = (int32_t)(off[fb + i] - base);
+  if (threadIdx.x == 0) *s_base = base;
+  return true;
+}
+
+// ---------------------------------------------------------------------------------------------
+// centre of mass.  A workgroup owns kComThreads frames, each wave 64 of them; a wave walks its
+// frames kUnroll at a time, lane l taking event l of each frame (loads for the kUnroll frames
+// are issued together), and reduces a frame's moments across the lanes.  Frames with more than
+// 64 events loop over further 64-event runs.
+
+constexpr int kUnroll = 8;
+
+__device__ __forceinline__ int32_t wave_sum_i32(int32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
 
 __global__ void __launch_bounds__(kComThreads) k_com(const int32_t* __restrict__ idx,
                                                      const int64_t* __restrict__ off,
@@ -57,51 +95,72 @@ __global__ void __launch_bounds__(kComThreads) k_com(const int32_t* __restrict__
                                                      float* __restrict__ com32,
                                                      int32_t* __restrict__ counts,
                                                      int32_t* status) {
-  __shared__ int64_t s_off[kComThreads + 1];
-  __shared__ int32_t s_ev[kWin];
-  const int t = threadIdx.x;
-  const int64_t fb = frame0 + (int64_t)blockIdx.x * kComThreads;  // first frame of the block
+  __shared__ int32_t s_rel[kComThreads + 1];
+  __shared__ int64_t s_sx[kComThreads], s_sy[kComThreads];
+  __shared__ int64_t s_base;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int64_t fb = frame0 + (int64_t)blockIdx.x * kComThreads;
   const int64_t fend = frame0 + n_frames;
   const int nf = (int)((fend - fb) < kComThreads ? (fend - fb) : kComThreads);
-  for (int i = t; i <= nf; i += kComThreads) s_off[i] = off[fb + i];
+  if (!load_rel_offsets(off, fb, nf, s_rel, &s_base, status)) return;
   __syncthreads();
-  const int64_t ebeg = s_off[0], eend = s_off[nf];
-  const int64_t my_lo = t < nf ? s_off[t] : 0, my_hi = t < nf ? s_off[t + 1] : 0;
-  int64_t sx = 0, sy = 0;
+  const int32_t* ev = idx + s_base;
+  const int fw0 = wave * 64, fw1 = fw0 + 64 < nf ? fw0 + 64 : nf;
   int32_t bad = 0;
-  for (int64_t w0 = ebeg; w0 < eend; w0 += kWin) {
-    const int wn = (int)((eend - w0) < kWin ? (eend - w0) : kWin);
-    __syncthreads();
-    for (int i = t; i < wn; i += kComThreads) s_ev[i] = idx[w0 + i];
-    __syncthreads();
-    const int64_t lo = my_lo > w0 ? my_lo : w0;
-    const int64_t hi = my_hi < w0 + wn ? my_hi : w0 + wn;
-    for (int64_t e = lo; e < hi; ++e) {
-      const int32_t k = s_ev[e - w0];
-      if (k < 0 || k >= npix) {
-        bad = STEM_ERANGE;
-        continue;
+  for (int f = fw0; f < fw1; f += kUnroll) {
+    int32_t kv[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      kv[u] = 0;
+      const int fr = f + u;
+      if (fr < fw1) {
+        const int32_t e = s_rel[fr] + lane;
+        if (e < s_rel[fr + 1]) kv[u] = ev[e];
       }
-      const uint32_t ky = magic_div((uint32_t)k, divw);
-      const int32_t kx = k - (int32_t)(ky * divw.d);
-      sx += kx - cx;
-      sy += (int32_t)ky - cy;
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int fr = f + u;
+      if (fr >= fw1) break;
+      const int32_t lo = s_rel[fr], hi = s_rel[fr + 1];
+      int64_t sx = 0, sy = 0;
+      for (int32_t base = lo; base < hi; base += 64) {
+        const int32_t e = base + lane;
+        int32_t dx = 0, dy = 0;
+        if (e < hi) {
+          const int32_t k = base == lo ? kv[u] : ev[e];
+          if (k < 0 || k >= npix) {
+            bad = STEM_ERANGE;
+          } else {
+            const uint32_t ky = magic_div((uint32_t)k, divw);
+            dx = k - (int32_t)(ky * divw.d) - cx;
+            dy = (int32_t)ky - cy;
+          }
+        }
+        sx += wave_sum_i32(dx);
+        sy += wave_sum_i32(dy);
+      }
+      if (lane == 0) {
+        s_sx[fr] = sx;
+        s_sy[fr] = sy;
+      }
     }
   }
+  __syncthreads();
   if (t < nf) {
-    const int64_t f = fb + t;
-    const int64_t n = my_hi - my_lo;
-    const double x = n > 0 ? (double)sx / (double)n : 0.0;
-    const double y = n > 0 ? (double)sy / (double)n : 0.0;
+    const int64_t fr = fb + t;
+    const int64_t n = s_rel[t + 1] - s_rel[t];
+    const double x = n > 0 ? (double)s_sx[t] / (double)n : 0.0;
+    const double y = n > 0 ? (double)s_sy[t] / (double)n : 0.0;
     if (com64) {
-      com64[f] = x;
-      com64[nplane + f] = y;
+      com64[fr] = x;
+      com64[nplane + fr] = y;
     }
     if (com32) {
-      com32[f] = (float)x;
-      com32[nplane + f] = (float)y;
+      com32[fr] = (float)x;
+      com32[nplane + fr] = (float)y;
     }
-    if (counts) counts[f] = (int32_t)(n < 0x7fffffff ? n : 0x7fffffff);
+    if (counts) counts[fr] = (int32_t)n;
   }
   if (bad) report(status, bad);
 }
@@ -176,13 +235,18 @@ int launch_geometry(const stem_det& det, double r2, RowRun* rows, double2* kc, h
 // ---------------------------------------------------------------------------------------------
 // binning into D[kd][f] (frames of whole scan rows)
 //
-// Workgroup = (block of kBinFrames frames) x (run of kBinChunk kept pixels).  Counters are
-// 16-bit, two per LDS word (frames fl and fl+1 of one pixel share a word).  A frame with
-// more than 65535 events could carry into its neighbour and is rejected (STEM_EOVERFLOW).
+// Workgroup = kBinFrames consecutive frames x a run of up to kBinKd kept pixels.  Events are
+// processed in parallel (coalesced loads, frame by binary search in the block's offsets) and
+// counted in LDS: 8-bit counters, four frames per word, when every frame of the block has at
+// most 255 events (no count can then carry into its neighbour); otherwise 16-bit counters, two
+// frames per word, over two passes of half the pixels.  A count above the element type of D
+// sets STEM_EOVERFLOW (the stored value is then not meaningful).
 
 constexpr int kBinFrames = 256;
-constexpr int kBinChunk = 64;
 constexpr int kBinThreads = 256;
+constexpr int kBinWords = 11776;                      // 46 KB of counters
+constexpr int kBinKd = kBinWords * 4 / kBinFrames;    // 184 pixels per workgroup
+constexpr int kBinLdsRows = 256;                      // bin rows cached in LDS
 
 template <typename DT>
 __global__ void __launch_bounds__(kBinThreads) k_bin(const int32_t* __restrict__ idx,
@@ -191,62 +255,114 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(const int32_t* __restrict__
                                                      int32_t npix, int32_t nby,
                                                      const RowRun* __restrict__ rows, int32_t n_k,
                                                      int64_t F, DT* __restrict__ D, int32_t* status) {
-  __shared__ uint32_t s_hist[kBinChunk * kBinFrames / 2];
-  __shared__ int64_t s_off[kBinFrames + 1];
-  __shared__ int32_t s_ev[kWin];
+  __shared__ uint32_t s_hist[kBinWords];
+  __shared__ int32_t s_rel[kBinFrames + 1];
+  __shared__ RowRun s_rows[kBinLdsRows];
+  __shared__ int64_t s_base;
   const int t = threadIdx.x;
-  const int nchunks = (n_k + kBinChunk - 1) / kBinChunk;
-  const int kd0 = (int)(blockIdx.x % nchunks) * kBinChunk;
+  const int nchunks = (n_k + kBinKd - 1) / kBinKd;
+  const int kd0 = (int)(blockIdx.x % nchunks) * kBinKd;
+  const int kc = n_k - kd0 < kBinKd ? n_k - kd0 : kBinKd;
   const int64_t fb = frame0 + (int64_t)(blockIdx.x / nchunks) * kBinFrames;
   const int64_t fend = frame0 + n_frames;
   const int nf = (int)((fend - fb) < kBinFrames ? (fend - fb) : kBinFrames);
-  const int nkc = n_k - kd0 < kBinChunk ? n_k - kd0 : kBinChunk;
-  for (int i = t; i < kBinChunk * kBinFrames / 2; i += kBinThreads) s_hist[i] = 0u;
-  for (int i = t; i <= nf; i += kBinThreads) s_off[i] = off[fb + i];
+  if (!load_rel_offsets(off, fb, nf, s_rel, &s_base, status)) return;
+  const bool rows_lds = nby <= kBinLdsRows;
+  if (rows_lds)
+    for (int i = t; i < nby; i += kBinThreads) s_rows[i] = rows[i];
   __syncthreads();
+  const int wide = __syncthreads_or(t < nf && s_rel[t + 1] - s_rel[t] > 255);
+  const int32_t* ev = idx + s_base;
+  const RowRun* rtab = rows_lds ? s_rows : rows;
   int32_t bad = 0;
-  if (t < nf && s_off[t + 1] - s_off[t] > 65535) bad |= STEM_EOVERFLOW;
-  const int64_t ebeg = s_off[0], eend = s_off[nf];
-  const int64_t my_lo = t < nf ? s_off[t] : 0, my_hi = t < nf ? s_off[t + 1] : 0;
-  for (int64_t w0 = ebeg; w0 < eend; w0 += kWin) {
-    const int wn = (int)((eend - w0) < kWin ? (eend - w0) : kWin);
-    __syncthreads();
-    for (int i = t; i < wn; i += kBinThreads) s_ev[i] = idx[w0 + i];
-    __syncthreads();
-    // thread t bins the events of frame t that fall in this window
-    const int64_t lo = my_lo > w0 ? my_lo : w0;
-    const int64_t hi = my_hi < w0 + wn ? my_hi : w0 + wn;
-    for (int64_t e = lo; e < hi; ++e) {
-      const int32_t k = s_ev[e - w0];
-      if (k < 0 || k >= npix) {
-        bad |= STEM_ERANGE;
-        continue;
-      }
-      const uint32_t ky = magic_div((uint32_t)k, divw);
-      const uint32_t kx = (uint32_t)k - ky * divw.d;
-      const int by = (int)magic_div(ky, divb);
-      const int bx = (int)magic_div(kx, divb);
-      if (by >= nby) continue;
-      const RowRun rr = rows[by];
-      if (bx < rr.lo || bx >= rr.hi) continue;
-      const int kd = rr.start + bx - rr.lo - kd0;
-      if (kd < 0 || kd >= nkc) continue;
-      atomicAdd(&s_hist[(kd * kBinFrames + t) >> 1], (t & 1) ? 0x10000u : 1u);
-    }
-  }
-  __syncthreads();
-  // write out: each thread writes 2 consecutive frames of one pixel row per step
+  const int npass = wide ? 2 : 1;
+  const int kpp = (kc + npass - 1) / npass;       // pixels per pass
+  const int fpw = wide ? 2 : 4;                   // frames per counter word
+  const int wpr = kBinFrames / fpw;               // words per pixel row
   const uint32_t cap = sizeof(DT) == 1 ? 255u : 65535u;
-  for (int i = t; i < nkc * (kBinFrames / 2); i += kBinThreads) {
-    const int kd = i / (kBinFrames / 2);
-    const int fp = (i % (kBinFrames / 2)) * 2;
-    if (fp >= nf) continue;
-    const uint32_t w = s_hist[(kd * kBinFrames + fp) >> 1];
-    const uint32_t c0 = w & 0xffffu, c1 = w >> 16;
-    if (c0 > cap || c1 > cap) bad |= STEM_EOVERFLOW;
-    DT* dst = D + (int64_t)(kd0 + kd) * F + (fb + fp);
-    dst[0] = (DT)(c0 > cap ? cap : c0);
-    if (fp + 1 < nf) dst[1] = (DT)(c1 > cap ? cap : c1);
+  for (int pass = 0; pass < npass; ++pass) {
+    const int ka = kd0 + pass * kpp;
+    const int kn = (kd0 + kc) - ka < kpp ? (kd0 + kc) - ka : kpp;
+    for (int i = t; i < kn * wpr; i += kBinThreads) s_hist[i] = 0u;
+    __syncthreads();
+    // wave w walks frames [64w, 64w + 64), kUnroll at a time, lane l taking event l of a frame
+    const int lane = t & 63, fw0 = (t >> 6) * 64, fw1 = fw0 + 64 < nf ? fw0 + 64 : nf;
+    for (int f = fw0; f < fw1; f += kUnroll) {
+      int32_t kv[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        kv[u] = 0;
+        const int fr = f + u;
+        if (fr < fw1) {
+          const int32_t e = s_rel[fr] + lane;
+          if (e < s_rel[fr + 1]) kv[u] = ev[e];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int fl = f + u;
+        if (fl >= fw1) break;
+        const int32_t lo = s_rel[fl], hi = s_rel[fl + 1];
+        for (int32_t base = lo; base < hi; base += 64) {
+          const int32_t e = base + lane;
+          if (e >= hi) continue;
+          const int32_t k = base == lo ? kv[u] : ev[e];
+          if (k < 0 || k >= npix) {
+            bad |= STEM_ERANGE;
+            continue;
+          }
+          const uint32_t ky = magic_div((uint32_t)k, divw);
+          const uint32_t kx = (uint32_t)k - ky * divw.d;
+          const int by = (int)magic_div(ky, divb);
+          const int bx = (int)magic_div(kx, divb);
+          if (by >= nby) continue;
+          const RowRun rr = rtab[by];
+          if (bx < rr.lo || bx >= rr.hi) continue;
+          const int kd = rr.start + bx - rr.lo - ka;
+          if (kd < 0 || kd >= kn) continue;
+          if (wide)
+            atomicAdd(&s_hist[kd * wpr + (fl >> 1)], 1u << (16 * (fl & 1)));
+          else
+            atomicAdd(&s_hist[kd * wpr + (fl >> 2)], 1u << (8 * (fl & 3)));
+        }
+      }
+    }
+    __syncthreads();
+    // one counter word per thread and step: fpw consecutive frames of one pixel row
+    for (int i = t; i < kn * wpr; i += kBinThreads) {
+      const int kd = i / wpr, q = i % wpr;
+      const int f0 = q * fpw;
+      if (f0 >= nf) continue;
+      const uint32_t w = s_hist[i];
+      uint32_t c[4];
+      if (wide) {
+        c[0] = w & 0xffffu;
+        c[1] = w >> 16;
+        c[2] = c[3] = 0u;
+      } else {
+        c[0] = w & 0xffu;
+        c[1] = (w >> 8) & 0xffu;
+        c[2] = (w >> 16) & 0xffu;
+        c[3] = w >> 24;
+      }
+      DT* dst = D + (int64_t)(ka + kd) * F + (fb + f0);
+      if (f0 + fpw <= nf) {
+        if (sizeof(DT) == 1 && !wide) {
+          *(uint32_t*)dst = w;  // four 8-bit counts are the four bytes
+        } else {
+          for (int j = 0; j < fpw; ++j) {
+            if (c[j] > cap) bad |= STEM_EOVERFLOW;
+            dst[j] = (DT)c[j];
+          }
+        }
+      } else {
+        for (int j = 0; j < fpw && f0 + j < nf; ++j) {
+          if (c[j] > cap) bad |= STEM_EOVERFLOW;
+          dst[j] = (DT)c[j];
+        }
+      }
+    }
+    __syncthreads();
   }
   if (bad) report(status, bad);
 }
@@ -255,7 +371,7 @@ int launch_bin(const int32_t* idx, const int64_t* off, int64_t frame0, int64_t n
                const stem_det& det, const RowRun* rows, int n_k, int64_t F, void* D, int d_bits,
                int32_t* status, hipStream_t stream) {
   if (n_frames == 0) return STEM_OK;
-  const int nchunks = (n_k + kBinChunk - 1) / kBinChunk;
+  const int nchunks = (n_k + kBinKd - 1) / kBinKd;
   const int64_t fblocks = (n_frames + kBinFrames - 1) / kBinFrames;
   const dim3 grid((unsigned)(fblocks * nchunks));
   const Magic mw = make_magic((uint32_t)det.W), mb = make_magic((uint32_t)det.bin);

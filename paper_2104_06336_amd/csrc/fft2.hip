@@ -42,6 +42,7 @@ __global__ void __launch_bounds__(kRowThreads) k_row_fft(RowFftArgs a, int in_mo
           x = a.in_c[e];
         } else if (in_mode == IN_C64_SUM) {
           for (int p = 0; p < a.nparts; ++p) x = cadd(x, a.in_c[p * a.part_stride + e]);
+          if (a.sum_out) a.sum_out[e] = x;
         } else if (in_mode == IN_F32_PAIR) {
           x.x = a.in_f0[e] * a.s0;
           x.y = a.in_f1 ? a.in_f1[e] * a.s1 : 0.f;

@@ -25,6 +25,7 @@ struct RowFftArgs {
   const float2* in_c;      // IN_C64 / IN_C64_SUM: row r at in_c + r*n (+ p*part_stride)
   int64_t part_stride;
   int32_t nparts;
+  float2* sum_out;         // IN_C64_SUM: if set, the summed input is also stored here (row-major)
   const float* in_f0;      // IN_F32_PAIR: re = in_f0[r*n + j]*s0, im = in_f1[...]*s1 (in_f1 may be null)
   const float* in_f1;
   const double* in_d0;     // IN_F64_PAIR

@@ -156,6 +156,37 @@ def test_refocus_matches_fresh_reconstruction(gpu):
     assert rel_l2(phase.cpu().numpy().reshape(wl.scan), ref["phi"]) <= TOL
 
 
+@pytest.mark.parametrize("name", ["small", "mid", "aberr"])
+def test_recompute_mode_matches_oracle(gpu, name):
+    """G-recompute mode: the fused column transform + sum never stores G; the row-transformed
+    cube stays, so a second FINALIZE with other coefficients works and the adjoint recomputes G."""
+    wl, idx, off = data(name)
+    d_idx, d_off = to_device(idx, off)
+    c = wl.aberr
+    st, out = gpu_ssb(d_idx, d_off, wl, c=c, g_mode=stem.STEM_G_RECOMPUTE)
+    ref = oracle_ssb(idx, off, wl, c=c)
+    assert out["status"] == 0
+    assert rel_l2(out["T"], ref["T"]) <= TOL
+    assert rel_l2(out["phi"], ref["phi"]) <= TOL
+    assert st.pair_count() == int(sum(ossb.ssb_sum(ref["G"], ref["kc"], wl.step, wl.dk, wl.lam, wl.r_bf, c)[1].sum()
+                                      for _ in [0]))
+    # finalize again with different coefficients (the cube is intact)
+    c2 = tuple(0.5 * v for v in C4_TRUE_ABERRATIONS)
+    phase = torch.zeros(wl.n_frames, dtype=torch.float32, device="cuda")
+    st.finalize(c=c2, phase=phase)
+    ref2 = oracle_ssb(idx, off, wl, c=c2)
+    assert rel_l2(phase.cpu().numpy().reshape(wl.scan), ref2["phi"]) <= TOL
+    # adjoint with recomputed G
+    phi = phase.view(-1)
+    gbar = (-(2.0 / phi.numel()) * (phi - phi.mean())).contiguous()
+    dc, dth = st.backward(gbar, c=c2)
+    dco, dtho = ossb.ssb_adjoint(ref2["G"], ref2["kc"], ossb.neg_var_grad(ref2["phi"]), wl.step, wl.dk, wl.lam,
+                                 wl.r_bf, c2)
+    dc = dc.cpu().numpy()
+    assert np.all(np.abs(dc - dco) <= 1e-4 * np.abs(dco) + 1e-6 * np.max(np.abs(dco)))
+    assert rel_l2(dth.cpu().numpy(), dtho) <= 1e-4
+
+
 def test_chunked_accumulate_equals_oneshot(gpu):
     wl, idx, off = data("mid")
     d_idx, d_off = to_device(idx, off)
