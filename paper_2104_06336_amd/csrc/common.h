@@ -26,6 +26,21 @@ __device__ __forceinline__ float2 cmul_mi(float2 a) { return make_float2(a.y, -a
 __device__ __forceinline__ float2 cmul_pi(float2 a) { return make_float2(-a.y, a.x); }
 
 // ---------------------------------------------------------------------------------------------
+// sum over the 64 lanes of a wave with DPP lane moves (all lanes must be active); the total is
+// returned to every lane (read from lane 63).  quad_perm [1,0,3,2] and [2,3,0,1] give quad sums,
+// row_half_mirror and row_mirror row (16-lane) sums, row_bcast15 / row_bcast31 carry rows 0 and
+// 2 into 1 and 3, then rows 0-1 into 2-3.
+__device__ __forceinline__ int wave_sum_dpp(int v) {
+  v += __builtin_amdgcn_update_dpp(0, v, 0xb1, 0xf, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x4e, 0xf, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x141, 0xf, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x140, 0xf, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);
+  return __builtin_amdgcn_readlane(v, 63);
+}
+
+// ---------------------------------------------------------------------------------------------
 // status reporting: device-side error bits are OR-ed into the caller's status word
 
 __device__ __forceinline__ void report(int32_t* status, int32_t bits) {

@@ -48,16 +48,6 @@ __global__ void __launch_bounds__(256) k_validate(const int32_t* __restrict__ id
 // ---------------------------------------------------------------------------------------------
 // block-local frame lookup shared by the event-parallel kernels
 
-// Largest j in [0, nf) with rel[j] <= e (rel: non-decreasing, rel[0] = 0 <= e < rel[nf]).
-__device__ __forceinline__ int frame_of(const int32_t* rel, int nf, int32_t e) {
-  int a = 0, z = nf - 1;
-  while (a < z) {
-    const int mid = (a + z + 1) >> 1;
-    if (rel[mid] <= e) a = mid; else z = mid - 1;
-  }
-  return a;
-}
-
 // Loads the block's offsets relative to its first event.  Returns false (and reports) when
 // the block holds 2^30 events or more, which the 32-bit relative offsets cannot address.
 __device__ __forceinline__ bool load_rel_offsets(const int64_t* __restrict__ off, int64_t fb, int nf,
@@ -74,18 +64,33 @@ __device__ __forceinline__ bool load_rel_offsets(const int64_t* __restrict__ off
 }
 
 // ---------------------------------------------------------------------------------------------
-// centre of mass.  A workgroup owns kComThreads frames, each wave 64 of them; a wave walks its
-// frames kUnroll at a time, lane l taking event l of each frame (loads for the kUnroll frames
-// are issued together), and reduces a frame's moments across the lanes.  Frames with more than
-// 64 events loop over further 64-event runs.
+// Thread-per-frame walk over a frame's events: a scalar head up to 16-byte alignment, then
+// 16-byte vector loads (four events each, four loads issued together), then a scalar tail.
+// f(k) is applied to every event index in order.
 
-constexpr int kUnroll = 8;
-
-__device__ __forceinline__ int32_t wave_sum_i32(int32_t v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
+template <typename Fn>
+__device__ __forceinline__ void for_each_event(const int32_t* __restrict__ ev, int64_t lo, int64_t hi, Fn f) {
+  int64_t e = lo;
+  for (; e < hi && (((uintptr_t)(ev + e)) & 15); ++e) f(ev[e]);
+  for (; e + 16 <= hi; e += 16) {
+    const int4 q0 = *(const int4*)(ev + e);
+    const int4 q1 = *(const int4*)(ev + e + 4);
+    const int4 q2 = *(const int4*)(ev + e + 8);
+    const int4 q3 = *(const int4*)(ev + e + 12);
+    f(q0.x); f(q0.y); f(q0.z); f(q0.w);
+    f(q1.x); f(q1.y); f(q1.z); f(q1.w);
+    f(q2.x); f(q2.y); f(q2.z); f(q2.w);
+    f(q3.x); f(q3.y); f(q3.z); f(q3.w);
+  }
+  for (; e + 4 <= hi; e += 4) {
+    const int4 q = *(const int4*)(ev + e);
+    f(q.x); f(q.y); f(q.z); f(q.w);
+  }
+  for (; e < hi; ++e) f(ev[e]);
 }
+
+// ---------------------------------------------------------------------------------------------
+// centre of mass: one thread per frame
 
 __global__ void __launch_bounds__(kComThreads) k_com(const int32_t* __restrict__ idx,
                                                      const int64_t* __restrict__ off,
@@ -95,73 +100,32 @@ __global__ void __launch_bounds__(kComThreads) k_com(const int32_t* __restrict__
                                                      float* __restrict__ com32,
                                                      int32_t* __restrict__ counts,
                                                      int32_t* status) {
-  __shared__ int32_t s_rel[kComThreads + 1];
-  __shared__ int64_t s_sx[kComThreads], s_sy[kComThreads];
-  __shared__ int64_t s_base;
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int64_t fb = frame0 + (int64_t)blockIdx.x * kComThreads;
-  const int64_t fend = frame0 + n_frames;
-  const int nf = (int)((fend - fb) < kComThreads ? (fend - fb) : kComThreads);
-  if (!load_rel_offsets(off, fb, nf, s_rel, &s_base, status)) return;
-  __syncthreads();
-  const int32_t* ev = idx + s_base;
-  const int fw0 = wave * 64, fw1 = fw0 + 64 < nf ? fw0 + 64 : nf;
+  const int64_t fr = frame0 + (int64_t)blockIdx.x * kComThreads + threadIdx.x;
+  if (fr >= frame0 + n_frames) return;
+  const int64_t lo = off[fr], hi = off[fr + 1];
+  int64_t sx = 0, sy = 0;
   int32_t bad = 0;
-  for (int f = fw0; f < fw1; f += kUnroll) {
-    int32_t kv[kUnroll];
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      kv[u] = 0;
-      const int fr = f + u;
-      if (fr < fw1) {
-        const int32_t e = s_rel[fr] + lane;
-        if (e < s_rel[fr + 1]) kv[u] = ev[e];
-      }
+  for_each_event(idx, lo, hi, [&](int32_t k) {
+    if (k < 0 || k >= npix) {
+      bad = STEM_ERANGE;
+      return;
     }
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      const int fr = f + u;
-      if (fr >= fw1) break;
-      const int32_t lo = s_rel[fr], hi = s_rel[fr + 1];
-      int64_t sx = 0, sy = 0;
-      for (int32_t base = lo; base < hi; base += 64) {
-        const int32_t e = base + lane;
-        int32_t dx = 0, dy = 0;
-        if (e < hi) {
-          const int32_t k = base == lo ? kv[u] : ev[e];
-          if (k < 0 || k >= npix) {
-            bad = STEM_ERANGE;
-          } else {
-            const uint32_t ky = magic_div((uint32_t)k, divw);
-            dx = k - (int32_t)(ky * divw.d) - cx;
-            dy = (int32_t)ky - cy;
-          }
-        }
-        sx += wave_sum_i32(dx);
-        sy += wave_sum_i32(dy);
-      }
-      if (lane == 0) {
-        s_sx[fr] = sx;
-        s_sy[fr] = sy;
-      }
-    }
+    const uint32_t ky = magic_div((uint32_t)k, divw);
+    sx += k - (int32_t)(ky * divw.d) - cx;
+    sy += (int32_t)ky - cy;
+  });
+  const int64_t n = hi - lo;
+  const double x = n > 0 ? (double)sx / (double)n : 0.0;
+  const double y = n > 0 ? (double)sy / (double)n : 0.0;
+  if (com64) {
+    com64[fr] = x;
+    com64[nplane + fr] = y;
   }
-  __syncthreads();
-  if (t < nf) {
-    const int64_t fr = fb + t;
-    const int64_t n = s_rel[t + 1] - s_rel[t];
-    const double x = n > 0 ? (double)s_sx[t] / (double)n : 0.0;
-    const double y = n > 0 ? (double)s_sy[t] / (double)n : 0.0;
-    if (com64) {
-      com64[fr] = x;
-      com64[nplane + fr] = y;
-    }
-    if (com32) {
-      com32[fr] = (float)x;
-      com32[nplane + fr] = (float)y;
-    }
-    if (counts) counts[fr] = (int32_t)n;
+  if (com32) {
+    com32[fr] = (float)x;
+    com32[nplane + fr] = (float)y;
   }
+  if (counts) counts[fr] = (int32_t)(n < 0x7fffffff ? n : 0x7fffffff);
   if (bad) report(status, bad);
 }
 
@@ -245,7 +209,9 @@ int launch_geometry(const stem_det& det, double r2, RowRun* rows, double2* kc, h
 constexpr int kBinFrames = 256;
 constexpr int kBinThreads = 256;
 constexpr int kBinWords = 11776;                      // 46 KB of counters
-constexpr int kBinKd = kBinWords * 4 / kBinFrames;    // 184 pixels per workgroup
+// pixel rows of counters are kBinFrames/4 (+1 padding) words apart, so that the events of one
+// frame (same column, different pixels) fall into different LDS banks
+constexpr int kBinKd = kBinWords / (kBinFrames / 4 + 1);  // 181 pixels per workgroup
 constexpr int kBinLdsRows = 256;                      // bin rows cached in LDS
 
 template <typename DT>
@@ -279,53 +245,33 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(const int32_t* __restrict__
   const int kpp = (kc + npass - 1) / npass;       // pixels per pass
   const int fpw = wide ? 2 : 4;                   // frames per counter word
   const int wpr = kBinFrames / fpw;               // words per pixel row
+  const int wps = wpr + 1;                        // row stride in words (padded)
   const uint32_t cap = sizeof(DT) == 1 ? 255u : 65535u;
   for (int pass = 0; pass < npass; ++pass) {
     const int ka = kd0 + pass * kpp;
     const int kn = (kd0 + kc) - ka < kpp ? (kd0 + kc) - ka : kpp;
-    for (int i = t; i < kn * wpr; i += kBinThreads) s_hist[i] = 0u;
+    for (int i = t; i < kn * wps; i += kBinThreads) s_hist[i] = 0u;
     __syncthreads();
-    // wave w walks frames [64w, 64w + 64), kUnroll at a time, lane l taking event l of a frame
-    const int lane = t & 63, fw0 = (t >> 6) * 64, fw1 = fw0 + 64 < nf ? fw0 + 64 : nf;
-    for (int f = fw0; f < fw1; f += kUnroll) {
-      int32_t kv[kUnroll];
-#pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        kv[u] = 0;
-        const int fr = f + u;
-        if (fr < fw1) {
-          const int32_t e = s_rel[fr] + lane;
-          if (e < s_rel[fr + 1]) kv[u] = ev[e];
+    // thread t walks the events of frame t
+    if (t < nf) {
+      const int shift = wide ? 16 * (t & 1) : 8 * (t & 3);
+      const int col = wide ? (t >> 1) : (t >> 2);
+      for_each_event(ev, s_rel[t], s_rel[t + 1], [&](int32_t k) {
+        if (k < 0 || k >= npix) {
+          bad |= STEM_ERANGE;
+          return;
         }
-      }
-#pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        const int fl = f + u;
-        if (fl >= fw1) break;
-        const int32_t lo = s_rel[fl], hi = s_rel[fl + 1];
-        for (int32_t base = lo; base < hi; base += 64) {
-          const int32_t e = base + lane;
-          if (e >= hi) continue;
-          const int32_t k = base == lo ? kv[u] : ev[e];
-          if (k < 0 || k >= npix) {
-            bad |= STEM_ERANGE;
-            continue;
-          }
-          const uint32_t ky = magic_div((uint32_t)k, divw);
-          const uint32_t kx = (uint32_t)k - ky * divw.d;
-          const int by = (int)magic_div(ky, divb);
-          const int bx = (int)magic_div(kx, divb);
-          if (by >= nby) continue;
-          const RowRun rr = rtab[by];
-          if (bx < rr.lo || bx >= rr.hi) continue;
-          const int kd = rr.start + bx - rr.lo - ka;
-          if (kd < 0 || kd >= kn) continue;
-          if (wide)
-            atomicAdd(&s_hist[kd * wpr + (fl >> 1)], 1u << (16 * (fl & 1)));
-          else
-            atomicAdd(&s_hist[kd * wpr + (fl >> 2)], 1u << (8 * (fl & 3)));
-        }
-      }
+        const uint32_t ky = magic_div((uint32_t)k, divw);
+        const uint32_t kx = (uint32_t)k - ky * divw.d;
+        const int by = (int)magic_div(ky, divb);
+        const int bx = (int)magic_div(kx, divb);
+        if (by >= nby) return;
+        const RowRun rr = rtab[by];
+        if (bx < rr.lo || bx >= rr.hi) return;
+        const int kd = rr.start + bx - rr.lo - ka;
+        if (kd < 0 || kd >= kn) return;
+        atomicAdd(&s_hist[kd * wps + col], 1u << shift);
+      });
     }
     __syncthreads();
     // one counter word per thread and step: fpw consecutive frames of one pixel row
@@ -333,7 +279,7 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(const int32_t* __restrict__
       const int kd = i / wpr, q = i % wpr;
       const int f0 = q * fpw;
       if (f0 >= nf) continue;
-      const uint32_t w = s_hist[i];
+      const uint32_t w = s_hist[kd * wps + q];
       uint32_t c[4];
       if (wide) {
         c[0] = w & 0xffffu;

@@ -21,7 +21,7 @@ __global__ void __launch_bounds__(kRowThreads) k_row_fft(RowFftArgs a, int in_mo
   __shared__ float2 s_buf[8 * kWaveStride];
   constexpr int B = 1024 / N;
   constexpr int TR = 8 * B;  // rows per tile
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   fill_twiddles(s_tw, threadIdx.x, kRowThreads);
   __syncthreads();
   float2* buf = s_buf + wave * kWaveStride;

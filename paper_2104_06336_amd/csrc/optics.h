@@ -13,6 +13,8 @@ struct Optics {
   //   + p30 wx^3 + p21 wx^2 wy + p12 wx wy^2 + p03 wy^3 + p4 (wx^2 + wy^2)^2
   double lk;
   double p20, p02, p11, p30, p21, p12, p03, p4;
+  // float screening of the double-overlap test: thresholds r2 -/+ a bound on the float error
+  float sxf, syf, r2lo, r2hi;
 };
 
 // Monomial coefficients of chi (2 pi / lam times the expansion of the eight terms).
@@ -64,6 +66,22 @@ __device__ __forceinline__ double chi_px(double kx_px, double ky_px, const Optic
   return x;
 }
 
+// Thresholds of the float screening.  With |K| <= r, |Q| <= qmax and M = r + qmax, the float
+// evaluation of (Kx -/+ Qx)^2 + (Ky -/+ Qy)^2 (K rounded once to float, Q = i * float(s) rounded
+// twice, then the difference, the squares and the sum) differs from the exact value by less than
+// 20 eps M^2 (eps = 2^-24); the margin is 32 eps M^2 plus 8 eps r^2 for the rounding of the
+// thresholds themselves, so a float result outside [r2lo, r2hi] decides the double test.
+inline void optics_screen(Optics& o, int ny, int nx) {
+  const double eps = 1.0 / 16777216.0;
+  const double qx = 0.5 * nx * o.sx, qy = 0.5 * ny * o.sy;
+  const double M = o.r + __builtin_sqrt(qx * qx + qy * qy);
+  const double margin = 32.0 * eps * M * M + 8.0 * eps * o.r2 + 1e-30;
+  o.sxf = (float)o.sx;
+  o.syf = (float)o.sy;
+  o.r2lo = (float)(o.r2 - margin);
+  o.r2hi = (float)(o.r2 + margin);
+}
+
 // Signed scan-frequency index (numpy fftfreq order: n/2 -> -n/2).
 __device__ __forceinline__ int signed_index(int m, int n) { return m < (n + 1) / 2 ? m : m - n; }
 
@@ -77,6 +95,100 @@ __device__ __forceinline__ bool double_overlap(double kx, double ky, double qx, 
   const double ux = kx + qx, uy = ky + qy;
   const double u2 = ux * ux + uy * uy;
   return (k2 < r2) && (d2 < r2) && (u2 >= r2);
+}
+
+// Double-overlap membership of a kept pixel K (|K| < r holds for every kept pixel by the same
+// predicate) for the frequency with signed indices (ix, iy): decided in float when both float
+// distances clear r^2 by the error margin, otherwise by the reference double evaluation.
+__device__ __forceinline__ bool overlap_screened(double kx, double ky, float kxf, float kyf, int ix, int iy,
+                                                 const Optics& o) {
+  const float qxf = (float)ix * o.sxf, qyf = (float)iy * o.syf;
+  const float dx = kxf - qxf, dy = kyf - qyf;
+  const float d2 = dx * dx + dy * dy;
+  const float ux = kxf + qxf, uy = kyf + qyf;
+  const float u2 = ux * ux + uy * uy;
+  if (d2 > o.r2hi || u2 < o.r2lo) return false;
+  if (d2 < o.r2lo && u2 > o.r2hi) return true;
+  return double_overlap(kx, ky, (double)ix * o.sx, (double)iy * o.sy, o.r2);
+}
+
+// ---------------------------------------------------------------------------------------------
+// The double-overlap set of one pixel K along one scan-frequency column.  For a fixed column
+// (fixed Qx, signed index ix) and Qy = iy*sy increasing with iy, the rounded distance
+// fl(fl(dx^2) + fl(dy^2)) with dy = fl(Ky - Qy) is non-increasing and then non-decreasing in iy
+// (IEEE rounding is monotone), so {iy : |K - Q|^2 < r^2} is one interval [a0, a1] and
+// {iy : |K + Q|^2 < r^2} another, [b0, b1]; the set is [a0, a1] minus [b0, b1] (|K| < r holds
+// for every kept pixel).  The bounds come from a square-root estimate corrected by the exact
+// double test of `double_overlap`, so membership equals that test for every iy.
+
+// |K - Q|^2 < r^2 (sgn = -1) or |K + Q|^2 < r^2 (sgn = +1), evaluated as the reference does
+__device__ __forceinline__ bool near_disk(double kx, double ky, double qx, double qy, double r2, int sgn) {
+#pragma clang fp contract(off)
+  const double dx = sgn < 0 ? kx - qx : kx + qx;
+  const double dy = sgn < 0 ? ky - qy : ky + qy;
+  return dx * dx + dy * dy < r2;
+}
+
+// Interval of iy in [lo, hi] (inclusive) where near_disk holds along the column Qx = qx; empty
+// when lo_out > hi_out.  ny: number of frequencies (iy in [-ny/2, ny/2)).
+__device__ __forceinline__ void disk_interval(double kx, double ky, double qx, double sy, double r, double r2, int sgn,
+                                              int ny, int& lo_out, int& hi_out) {
+  const int imin = -ny / 2, imax = ny / 2 - 1;
+  // centre: Qy = -sgn*... (K - Q: Qy = Ky; K + Q: Qy = -Ky)
+  const double cy = sgn < 0 ? ky : -ky;
+  const double dxv = sgn < 0 ? kx - qx : kx + qx;
+  const double h2 = r2 - dxv * dxv;
+  lo_out = 1;
+  hi_out = 0;
+  if (!(h2 > -1e-9 * r2)) return;  // |dx| well beyond r: empty (the exact test is checked at the centre)
+  const double h = sqrt(h2 > 0.0 ? h2 : 0.0);
+  int c0 = (int)floor(cy / sy);
+  if (c0 < imin) c0 = imin;
+  if (c0 > imax) c0 = imax;
+  // the minimum of the V lies at c0 or a neighbour (c0 = floor(cy/sy) may be off by one after
+  // rounding); if the test fails at all three the set is empty
+  int c = c0;
+  if (!near_disk(kx, ky, qx, (double)c * sy, r2, sgn)) {
+    c = c0 + 1;
+    if (c > imax || !near_disk(kx, ky, qx, (double)c * sy, r2, sgn)) {
+      c = c0 - 1;
+      if (c < imin || !near_disk(kx, ky, qx, (double)c * sy, r2, sgn)) return;
+    }
+  }
+  // upper end: estimate, then walk to the exact boundary
+  int u = (int)floor((cy + h) / sy);
+  if (u < c) u = c;
+  if (u > imax) u = imax;
+  while (u > c && !near_disk(kx, ky, qx, (double)u * sy, r2, sgn)) --u;
+  while (u < imax && near_disk(kx, ky, qx, (double)(u + 1) * sy, r2, sgn)) ++u;
+  int l = (int)ceil((cy - h) / sy);
+  if (l > c) l = c;
+  if (l < imin) l = imin;
+  while (l < c && !near_disk(kx, ky, qx, (double)l * sy, r2, sgn)) ++l;
+  while (l > imin && near_disk(kx, ky, qx, (double)(l - 1) * sy, r2, sgn)) --l;
+  lo_out = l;
+  hi_out = u;
+}
+
+// chi along one column as a polynomial in wy = lam*dk*(Ky - Qy) for fixed wx = lam*dk*(Kx - Qx):
+// chi = h0 + wy (h1 + wy (h2 + wy (h3 + wy h4)))
+struct ChiCol {
+  double h0, h1, h2, h3, h4;
+};
+
+__device__ __forceinline__ ChiCol chi_column(double wx, const Optics& o) {
+  const double xx = wx * wx;
+  ChiCol c;
+  c.h0 = xx * (o.p20 + wx * o.p30 + xx * o.p4);
+  c.h1 = wx * (o.p11 + wx * o.p21);
+  c.h2 = o.p02 + wx * o.p12 + 2.0 * o.p4 * xx;
+  c.h3 = o.p03;
+  c.h4 = o.p4;
+  return c;
+}
+
+__device__ __forceinline__ double chi_eval(const ChiCol& c, double wy) {
+  return c.h0 + wy * (c.h1 + wy * (c.h2 + wy * (c.h3 + wy * c.h4)));
 }
 
 // exp(i psi): psi is reduced in double to r in [-pi/4, pi/4] plus a quadrant (r = psi - q pi/2,

@@ -100,7 +100,7 @@ __global__ void __launch_bounds__(kXThreads) k_xstage(const DT* __restrict__ D, 
   constexpr int TR = 16 * B;  // real rows per tile
   constexpr int NH = N / 2 + 1;
   constexpr int ROWB = N * (int)sizeof(DT);  // bytes per row of D
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   fill_twiddles(s_tw, threadIdx.x, kXThreads);
   __syncthreads();
   float2* buf = s_buf + wave * kXWaveStride;
@@ -224,8 +224,9 @@ __global__ void __launch_bounds__(256) k_reduce(const float2* __restrict__ G, co
   const bool valid = q0 < (int64_t)ny * nx;
   const int64_t q = valid ? q0 : 0;
   const int mx = (int)(q / ny), my = (int)(q % ny);
-  const double qx = (double)signed_index(mx, nx) * o.sx;
-  const double qy = (double)signed_index(my, ny) * o.sy;
+  const int ix = signed_index(mx, nx), iy = signed_index(my, ny);
+  const double qx = (double)ix * o.sx;
+  const double qy = (double)iy * o.sy;
   const bool mir = mx > nx / 2;
   const int gmx = mir ? nx - mx : mx, gmy = mir ? (ny - my) % ny : my;
   const int nh = nx / 2 + 1;
@@ -242,7 +243,7 @@ __global__ void __launch_bounds__(256) k_reduce(const float2* __restrict__ G, co
       const double kx = kc[kd].x;
       if (kx - qx >= o.r) break;
       if (qx - kx >= o.r) continue;
-      if (!double_overlap(kx, ky, qx, qy, o.r2)) continue;
+      if (!overlap_screened(kx, ky, (float)kx, (float)ky, ix, iy, o)) continue;
       const double psi = chi_poly(kx - qx, ky - qy, o) - kchi[kd];
       float2 g = gcol[kd * kstride];
       if (mir) g = cconj(g);
@@ -274,6 +275,39 @@ __global__ void __launch_bounds__(256) k_reduce(const float2* __restrict__ G, co
 
 constexpr int kYThreads = 256;
 
+// Registers of a lane grouped by column: register i holds the frequency (my, c0 + b) of
+// fft_out_index.  With NB = NY/RL >= 64 the column of register i does not depend on the lane
+// (slot = that column offset b); otherwise a slot is the group i/RL, whose column depends on the
+// lane.  Per slot the double-overlap sets of the column (and of its mirror) are computed once.
+template <int NY>
+struct Slots {
+  static constexpr int RL = fft_last_radix<NY>();
+  static constexpr int NB = NY / RL;
+  static constexpr bool uniform_col = NB >= kWave;
+  static constexpr int slot_of(int i) { return uniform_col ? (kWave * (i / RL)) / NB : i / RL; }
+  static constexpr int count = slot_of(15) + 1;
+};
+
+// Double-overlap sets of pixel K along column ix: iy in [a0, a1] but not in [b0, b1].
+struct ColSet {
+  int a0, a1, b0, b1;
+  __device__ __forceinline__ bool has(int iy) const { return iy >= a0 && iy <= a1 && !(iy >= b0 && iy <= b1); }
+  __device__ __forceinline__ bool empty() const { return a0 > a1; }
+};
+
+__device__ __forceinline__ ColSet col_set(double kx, double ky, int ix, int ny, const Optics& o) {
+  const double qx = (double)ix * o.sx;
+  ColSet cs;
+  disk_interval(kx, ky, qx, o.sy, o.r, o.r2, -1, ny, cs.a0, cs.a1);
+  if (cs.a0 > cs.a1) {
+    cs.b0 = 1;
+    cs.b1 = 0;
+    return cs;
+  }
+  disk_interval(kx, ky, qx, o.sy, o.r, o.r2, +1, ny, cs.b0, cs.b1);
+  return cs;
+}
+
 template <int NY>
 __global__ void __launch_bounds__(kYThreads) k_yreduce(float2* __restrict__ X, const double2* __restrict__ kc,
                                                        const double* __restrict__ kchi, int n_k, int nx,
@@ -283,7 +317,8 @@ __global__ void __launch_bounds__(kYThreads) k_yreduce(float2* __restrict__ X, c
   __shared__ float2 s_tw[1024];
   __shared__ float2 s_buf[4 * kXWaveStride];
   constexpr int B = 1024 / NY;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  using SL = Slots<NY>;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nc = nx / 2 + 1;
   const int ncs = (nc + B - 1) / B;                       // column sets
   const int g = blockIdx.x % ngroups;
@@ -294,11 +329,6 @@ __global__ void __launch_bounds__(kYThreads) k_yreduce(float2* __restrict__ X, c
   float2* buf = s_buf + wave * kXWaveStride;
   const int c0 = cs * B;
   const int kd_a = (int)((int64_t)n_k * g / ngroups), kd_b = (int)((int64_t)n_k * (g + 1) / ngroups);
-  // column tested by this lane in the pixel-skip test (B columns per wave)
-  const int ct = c0 + lane % B;
-  const bool ct_ok = ct < nc;
-  const double ctx = (double)signed_index(ct, nx) * o.sx;
-  const bool ct_m = ct_ok && ct > 0 && 2 * ct < nx;
   float2 accd[16], accm[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) accd[i] = accm[i] = make_float2(0.f, 0.f);
@@ -306,10 +336,25 @@ __global__ void __launch_bounds__(kYThreads) k_yreduce(float2* __restrict__ X, c
   const int64_t kstride = (int64_t)nc * NY;
   for (int kd = kd_a; kd < kd_b; ++kd) {
     const double2 k = kc[kd];
-    // some column with |Kx - Qx| < r or |Kx + Qx| < r (with store_g every column is transformed,
-    // so that the stored G is complete)
-    const bool near = ct_ok && (fabs(k.x - ctx) < o.r || (ct_m && fabs(k.x + ctx) < o.r));
-    if (!store_g && !__ballot(near)) continue;
+    // double-overlap sets of this pixel for the lane's columns (direct and mirrored)
+    ColSet sd[SL::count], sm[SL::count];
+    bool any = false;
+#pragma unroll
+    for (int sl = 0; sl < SL::count; ++sl) {
+      int b0, m0;
+      fft_out_index<NY>(lane, sl * (16 / SL::count), b0, m0);
+      int c = c0 + b0;
+      asm volatile("" : "+v"(c));
+      sd[sl] = ColSet{1, 0, 1, 0};
+      sm[sl] = ColSet{1, 0, 1, 0};
+      if (c < nc) {
+        sd[sl] = col_set(k.x, k.y, signed_index(c, nx), NY, o);
+        if (c > 0 && 2 * c < nx) sm[sl] = col_set(k.x, k.y, signed_index(nx - c, nx), NY, o);
+      }
+      any = any || !sd[sl].empty() || !sm[sl].empty();
+    }
+    // with store_g every pixel is transformed, so that the stored G is complete
+    if (!store_g && !__ballot(any)) continue;
     float2 v[16];
     const float2* xcol = X + kd * kstride + (int64_t)c0 * NY;
 #pragma unroll
@@ -330,29 +375,32 @@ __global__ void __launch_bounds__(kYThreads) k_yreduce(float2* __restrict__ X, c
     }
     const double kch = kchi[kd];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      int b, m;
-      fft_out_index<NY>(lane, i, b, m);
-      int c = c0 + b;
-      // keep the frequency arithmetic inside the pixel loop: hoisted out of it, the 16 registers'
-      // frequencies would stay live across the loop and cost occupancy
-      asm volatile("" : "+v"(c), "+v"(m));
-      if (c >= nc) continue;
-      const double qx = (double)signed_index(c, nx) * o.sx;
-      const double qy = (double)signed_index(m, NY) * o.sy;
-      // direct frequency Q = (my, c)
-      if (fabs(k.y - qy) < o.r && fabs(k.x - qx) < o.r && double_overlap(k.x, k.y, qx, qy, o.r2)) {
-        const float2 e = expi_reduced(chi_poly(k.x - qx, k.y - qy, o) - kch);
-        accd[i].x += v[i].x * e.x - v[i].y * e.y;
-        accd[i].y += v[i].x * e.y + v[i].y * e.x;
-        ++cnt;
-      }
-      // mirrored frequency (-my, -c), G(-Q) = conj G(Q)
-      if (c > 0 && 2 * c < nx) {
-        const double qxm = (double)signed_index(nx - c, nx) * o.sx;
-        const double qym = (double)signed_index((NY - m) & (NY - 1), NY) * o.sy;
-        if (fabs(k.y - qym) < o.r && fabs(k.x - qxm) < o.r && double_overlap(k.x, k.y, qxm, qym, o.r2)) {
-          const float2 e = expi_reduced(chi_poly(k.x - qxm, k.y - qym, o) - kch);
+    for (int sl = 0; sl < SL::count; ++sl) {
+      int b0, m0;
+      fft_out_index<NY>(lane, sl * (16 / SL::count), b0, m0);
+      const int c = c0 + b0;
+      const ChiCol chd = chi_column(o.lk * (k.x - (double)signed_index(c, nx) * o.sx), o);
+      const ChiCol chm = chi_column(o.lk * (k.x - (double)signed_index(nx - c, nx) * o.sx), o);
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        if (SL::slot_of(i) != sl) continue;
+        int b, m;
+        fft_out_index<NY>(lane, i, b, m);
+        // keep the per-register frequency arithmetic inside the pixel loop: hoisted out of it, the
+        // 16 registers' frequencies stay live across the loop and cost occupancy
+        asm volatile("" : "+v"(m));
+        const int iy = signed_index(m, NY);
+        if (sd[sl].has(iy)) {
+          const double wy = o.lk * (k.y - (double)iy * o.sy);
+          const float2 e = expi_reduced(chi_eval(chd, wy) - kch);
+          accd[i].x += v[i].x * e.x - v[i].y * e.y;
+          accd[i].y += v[i].x * e.y + v[i].y * e.x;
+          ++cnt;
+        }
+        const int jy = signed_index((NY - m) & (NY - 1), NY);
+        if (sm[sl].has(jy)) {
+          const double wy = o.lk * (k.y - (double)jy * o.sy);
+          const float2 e = expi_reduced(chi_eval(chm, wy) - kch);
           accm[i].x += v[i].x * e.x + v[i].y * e.y;
           accm[i].y += v[i].x * e.y - v[i].y * e.x;
           ++cnt;
@@ -370,9 +418,9 @@ __global__ void __launch_bounds__(kYThreads) k_yreduce(float2* __restrict__ X, c
     pg[(int64_t)c * NY + m] = accd[i];
     if (c > 0 && 2 * c < nx) pg[(int64_t)(nx - c) * NY + ((NY - m) & (NY - 1))] = accm[i];
   }
-  unsigned long long c = cnt;
-  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
-  if (lane == 0) atomicAdd(stats, c);
+  unsigned long long cc = cnt;
+  for (int off = 32; off > 0; off >>= 1) cc += __shfl_xor(cc, off);
+  if (lane == 0) atomicAdd(stats, cc);
 }
 
 // Fused column transform + adjoint of Eq. 3 (G recomputed, never stored).  Same work split as
@@ -388,7 +436,7 @@ __global__ void __launch_bounds__(kYThreads) k_yadjoint(const float2* __restrict
   __shared__ float2 s_tw[1024];
   __shared__ float2 s_buf[4 * kXWaveStride];
   constexpr int B = 1024 / NY;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nc = nx / 2 + 1;
   const int ncs = (nc + B - 1) / B;
   const int g = blockIdx.x % ngroups;
@@ -447,6 +495,7 @@ __global__ void __launch_bounds__(kYThreads) k_yadjoint(const float2* __restrict
       wave_fft<NY>(v, buf, s_tw, lane);
     }
     const double kch = kchi[kd];
+    const float kxf = (float)k.x, kyf = (float)k.y;
     double bk[8];
     chi_basis(k.x, k.y, o, bk);
     float wsum = 0.f;
@@ -458,16 +507,17 @@ __global__ void __launch_bounds__(kYThreads) k_yadjoint(const float2* __restrict
       asm volatile("" : "+v"(c), "+v"(m));  // see k_yreduce
       if (c >= nc) continue;
       for (int side = 0; side < 2; ++side) {
-        double qx, qy;
+        int ix, iy;
         if (side == 0) {
-          qx = (double)signed_index(c, nx) * o.sx;
-          qy = (double)signed_index(m, NY) * o.sy;
+          ix = signed_index(c, nx);
+          iy = signed_index(m, NY);
         } else {
           if (!(c > 0 && 2 * c < nx)) break;
-          qx = (double)signed_index(nx - c, nx) * o.sx;
-          qy = (double)signed_index((NY - m) & (NY - 1), NY) * o.sy;
+          ix = signed_index(nx - c, nx);
+          iy = signed_index((NY - m) & (NY - 1), NY);
         }
-        if (!(fabs(k.y - qy) < o.r && fabs(k.x - qx) < o.r && double_overlap(k.x, k.y, qx, qy, o.r2))) continue;
+        if (!overlap_screened(k.x, k.y, kxf, kyf, ix, iy, o)) continue;
+        const double qx = (double)ix * o.sx, qy = (double)iy * o.sy;
         double bm[8];
         chi_basis(k.x - qx, k.y - qy, o, bm);
         double chim = 0.0;
@@ -604,6 +654,7 @@ static Optics make_optics(const stem_optics& op, const stem_scan& sc) {
   o.sx = 1.0 / (((double)sc.nx * sc.step) * op.dk);
   o.sy = 1.0 / (((double)sc.ny * sc.step) * op.dk);
   optics_poly(o);
+  optics_screen(o, sc.ny, sc.nx);
   return o;
 }
 
