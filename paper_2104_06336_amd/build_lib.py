@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libstem4d.so")
-SOURCES = ["eer.hip", "fft2.hip", "ssb.hip", "dft_mfma.hip", "trace.hip"]
+SOURCES = ["eer.hip", "fft2.hip", "ssb.hip", "ssb_bf16.hip", "ssb_fp16.hip", "trace.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
@@ -44,7 +44,7 @@ def build(verbose: bool = False) -> str:
     """Compile every HIP source for gfx950 and link the shared library; returns its path."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
-    with concurrent.futures.ThreadPoolExecutor(max_workers=min(4, len(srcs))) as ex:
+    with concurrent.futures.ThreadPoolExecutor(max_workers=min(6, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]

@@ -10,14 +10,13 @@
 // The other half of the Q plane (mx > Nx/2) uses G(K, Q) = conj G(K, -Q) of the real input.
 #include "common.h"
 #include "fft_wave.h"
+#include "ssb_fused.h"
 #include "kernels.h"
 #include "optics.h"
 #include "trace.h"
 
 namespace stem {
 
-constexpr int kXThreads = 512;
-constexpr int kXWaveStride = kFftLds + 4;
 constexpr int kMaxPixels = 4096;
 
 struct SsbLayout {
@@ -86,113 +85,40 @@ static size_t make_layout(const stem_det& det, const stem_scan& scan, const stem
 }
 
 // ---------------------------------------------------------------------------------------------
-// x-stage: rows (kd, ry) with ry in [ry0, ry0 + nr) of D, two real rows per complex FFT.
-// Tile = 16B real rows (B = 1024/N); each of the 8 waves transforms B row pairs; the
-// workgroup then splits the pairs and writes X[kd][m][ry] for m in [0, N/2] in runs of
-// consecutive ry.
+// precision dispatch of the scan-DFT launchers
 
-template <int N, typename DT>
-__global__ void __launch_bounds__(kXThreads) k_xstage(const DT* __restrict__ D, int ny, int ry0, int nr,
-                                                      int64_t nrows, int pair_store, float2* __restrict__ X) {
-  __shared__ float2 s_tw[1024];
-  __shared__ float2 s_buf[8 * kXWaveStride];
-  constexpr int B = 1024 / N;
-  constexpr int TR = 16 * B;  // real rows per tile
-  constexpr int NH = N / 2 + 1;
-  constexpr int ROWB = N * (int)sizeof(DT);  // bytes per row of D
-  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  fill_twiddles(s_tw, threadIdx.x, kXThreads);
-  __syncthreads();
-  float2* buf = s_buf + wave * kXWaveStride;
-  const int64_t ntiles = (nrows + TR - 1) / TR;
-  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const int64_t r0 = tile * TR + wave * 2 * B;  // first real row of this wave
-    // stage the wave's 2B rows of D in its LDS buffer with 16-byte loads
-    {
-      uint4* raw = (uint4*)buf;
-      constexpr int CH = 2 * B * ROWB / 16;  // 16-byte chunks
-#pragma unroll
-      for (int c = lane; c < CH; c += kWave) {
-        const int j = c * 16 / ROWB, col = c * 16 % ROWB;
-        const int64_t r = r0 + j;
-        uint4 v = make_uint4(0u, 0u, 0u, 0u);
-        if (r < nrows) {
-          const int64_t kd = r / nr, ry = ry0 + r % nr;
-          v = *(const uint4*)((const char*)D + (kd * ny + ry) * ROWB + col);
-        }
-        raw[c] = v;
-      }
-    }
-    wave_lds_sync();
-    float2 v[16];
-    {
-      const DT* rows = (const DT*)buf;
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        int b, n;
-        fft_in_index<N>(lane, i, b, n);
-        v[i] = make_float2((float)rows[(2 * b) * N + n], (float)rows[(2 * b + 1) * N + n]);
-      }
-    }
-    wave_lds_sync();
-    wave_fft<N>(v, buf, s_tw, lane);
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      int b, m;
-      fft_out_index<N>(lane, i, b, m);
-      buf[fft_pad(b * N + m)] = v[i];
-    }
-    __syncthreads();
-    // split each complex transform z = a + i b of rows (2p, 2p+1) into the two half spectra
-    // A(m) = (z(m) + conj z(-m))/2, B(m) = (z(m) - conj z(-m))/(2i); write them at adjacent ry
-    for (int u = threadIdx.x; u < NH * (TR / 2); u += kXThreads) {
-      const int m = u / (TR / 2), pr = u % (TR / 2);
-      const int w = pr / B, b = pr % B;
-      const float2* wb = s_buf + w * kXWaveStride;
-      const float2 z = wb[fft_pad(b * N + m)];
-      const float2 zc = cconj(wb[fft_pad(b * N + ((N - m) & (N - 1)))]);
-      const float2 va = cscale(cadd(z, zc), 0.5f);
-      const float2 vb = cscale(cmul_mi(csub(z, zc)), 0.5f);
-      const int64_t rho = tile * TR + 2 * pr;
-      if (pair_store && rho + 1 < nrows) {
-        const int64_t kd = rho / nr, ry = ry0 + rho % nr;
-        *(float4*)(X + (kd * NH + m) * ny + ry) = make_float4(va.x, va.y, vb.x, vb.y);
-      } else {
-        if (rho < nrows) {
-          const int64_t kd = rho / nr, ry = ry0 + rho % nr;
-          X[(kd * NH + m) * ny + ry] = va;
-        }
-        if (rho + 1 < nrows) {
-          const int64_t kd = (rho + 1) / nr, ry = ry0 + (rho + 1) % nr;
-          X[(kd * NH + m) * ny + ry] = vb;
-        }
-      }
-    }
-    __syncthreads();
+template <typename DT>
+static int launch_xstage_t(int prec, int nx, const DT* D, int ny, int ry0, int nr, int64_t nrows, float2* X,
+                           hipStream_t s) {
+  switch (prec) {
+    case STEM_DFT_BF16_SPLIT: return launch_xstage_p<STEM_DFT_BF16_SPLIT, DT>(nx, D, ny, ry0, nr, nrows, X, s);
+    case STEM_DFT_FP16_SPLIT: return launch_xstage_p<STEM_DFT_FP16_SPLIT, DT>(nx, D, ny, ry0, nr, nrows, X, s);
+    default: return launch_xstage_p<STEM_FFT_FP32, DT>(nx, D, ny, ry0, nr, nrows, X, s);
   }
 }
 
-template <typename DT>
-static int launch_xstage_t(int nx, const DT* D, int ny, int ry0, int nr, int64_t nrows, float2* X,
-                           hipStream_t s) {
-  const int64_t tr = 16 * (1024 / nx);
-  // rows 2p, 2p+1 of a tile share a pixel and sit at adjacent, 16-byte aligned ry when the
-  // chunk starts on an even row and holds an even number of rows per pixel
-  const int pair_store = (nr % 2 == 0) && (ry0 % 2 == 0);
-  const int64_t tiles = (nrows + tr - 1) / tr;
-  const dim3 grid((unsigned)(tiles < 4096 ? tiles : 4096)), blk(kXThreads);
-  STEM_TRACE("xstage_fft", s);
-  switch (nx) {
-    case 32: hipLaunchKernelGGL((k_xstage<32, DT>), grid, blk, 0, s, D, ny, ry0, nr, nrows, pair_store, X); break;
-    case 64: hipLaunchKernelGGL((k_xstage<64, DT>), grid, blk, 0, s, D, ny, ry0, nr, nrows, pair_store, X); break;
-    case 128: hipLaunchKernelGGL((k_xstage<128, DT>), grid, blk, 0, s, D, ny, ry0, nr, nrows, pair_store, X); break;
-    case 256: hipLaunchKernelGGL((k_xstage<256, DT>), grid, blk, 0, s, D, ny, ry0, nr, nrows, pair_store, X); break;
-    case 512: hipLaunchKernelGGL((k_xstage<512, DT>), grid, blk, 0, s, D, ny, ry0, nr, nrows, pair_store, X); break;
-    case 1024: hipLaunchKernelGGL((k_xstage<1024, DT>), grid, blk, 0, s, D, ny, ry0, nr, nrows, pair_store, X); break;
-    default: return STEM_EINVAL;
+static int launch_yreduce(int prec, int ny, float2* X, const double2* kc, const double* kchi, int n_k, int nx,
+                          int ngroups, const Optics& o, int store_g, float2* part, unsigned long long* stats,
+                          hipStream_t s) {
+  switch (prec) {
+    case STEM_DFT_BF16_SPLIT:
+      return launch_yreduce_p<STEM_DFT_BF16_SPLIT>(ny, X, kc, kchi, n_k, nx, ngroups, o, store_g, part, stats, s);
+    case STEM_DFT_FP16_SPLIT:
+      return launch_yreduce_p<STEM_DFT_FP16_SPLIT>(ny, X, kc, kchi, n_k, nx, ngroups, o, store_g, part, stats, s);
+    default: return launch_yreduce_p<STEM_FFT_FP32>(ny, X, kc, kchi, n_k, nx, ngroups, o, store_g, part, stats, s);
   }
-  STEM_LAUNCH_CHECK();
-  return STEM_OK;
+}
+
+static int launch_yadjoint(int prec, int ny, const float2* X, const double2* kc, const double* kchi, int n_k,
+                           int nx, int ngroups, const Optics& o, int g_stored, const float2* Tbt, double* pdc,
+                           float* pdth, hipStream_t s) {
+  switch (prec) {
+    case STEM_DFT_BF16_SPLIT:
+      return launch_yadjoint_p<STEM_DFT_BF16_SPLIT>(ny, X, kc, kchi, n_k, nx, ngroups, o, g_stored, Tbt, pdc, pdth, s);
+    case STEM_DFT_FP16_SPLIT:
+      return launch_yadjoint_p<STEM_DFT_FP16_SPLIT>(ny, X, kc, kchi, n_k, nx, ngroups, o, g_stored, Tbt, pdc, pdth, s);
+    default: return launch_yadjoint_p<STEM_FFT_FP32>(ny, X, kc, kchi, n_k, nx, ngroups, o, g_stored, Tbt, pdc, pdth, s);
+  }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -259,329 +185,6 @@ __global__ void __launch_bounds__(256) k_reduce(const float2* __restrict__ G, co
   unsigned long long c = valid ? (unsigned long long)cnt : 0ull;
   for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
   if ((threadIdx.x & 63) == 0) atomicAdd(stats, c);
-}
-
-// ---------------------------------------------------------------------------------------------
-// Fused column transform + Eq. 3 (the path that never stores G).  A wave owns B = 1024/NY
-// consecutive half-spectrum columns c (Qx = c*sx) and a group of kept pixels.  For each pixel it
-// loads the row-transformed columns X[kd][c][0..NY), FFTs them along ry in registers (giving
-// G(kd, (my, c)) for every my), and adds every double-overlap term to its accumulators: the
-// direct frequency Q = (my, c) with G, and for 0 < c < Nx/2 the mirrored frequency
-// (-my, -c) with conj G.  A pixel is skipped without loading when neither Qx nor -Qx of any of
-// its columns lies within r of Kx (then |Kx - Qx| >= r rules out |K - Q| < r for every my).
-// The wave writes its partial T for its columns into part[g] (column-major [mx][my]); the phase
-// pass sums the groups in a fixed order.  With store_g the transformed columns are also written
-// back in place (X becomes G) for later refocusing.
-
-constexpr int kYThreads = 256;
-
-// Registers of a lane grouped by column: register i holds the frequency (my, c0 + b) of
-// fft_out_index.  With NB = NY/RL >= 64 the column of register i does not depend on the lane
-// (slot = that column offset b); otherwise a slot is the group i/RL, whose column depends on the
-// lane.  Per slot the double-overlap sets of the column (and of its mirror) are computed once.
-template <int NY>
-struct Slots {
-  static constexpr int RL = fft_last_radix<NY>();
-  static constexpr int NB = NY / RL;
-  static constexpr bool uniform_col = NB >= kWave;
-  static constexpr int slot_of(int i) { return uniform_col ? (kWave * (i / RL)) / NB : i / RL; }
-  static constexpr int count = slot_of(15) + 1;
-};
-
-// Double-overlap sets of pixel K along column ix: iy in [a0, a1] but not in [b0, b1].
-struct ColSet {
-  int a0, a1, b0, b1;
-  __device__ __forceinline__ bool has(int iy) const { return iy >= a0 && iy <= a1 && !(iy >= b0 && iy <= b1); }
-  __device__ __forceinline__ bool empty() const { return a0 > a1; }
-};
-
-__device__ __forceinline__ ColSet col_set(double kx, double ky, int ix, int ny, const Optics& o) {
-  const double qx = (double)ix * o.sx;
-  ColSet cs;
-  disk_interval(kx, ky, qx, o.sy, o.r, o.r2, -1, ny, cs.a0, cs.a1);
-  if (cs.a0 > cs.a1) {
-    cs.b0 = 1;
-    cs.b1 = 0;
-    return cs;
-  }
-  disk_interval(kx, ky, qx, o.sy, o.r, o.r2, +1, ny, cs.b0, cs.b1);
-  return cs;
-}
-
-template <int NY>
-__global__ void __launch_bounds__(kYThreads) k_yreduce(float2* __restrict__ X, const double2* __restrict__ kc,
-                                                       const double* __restrict__ kchi, int n_k, int nx,
-                                                       int ngroups, Optics o, int store_g,
-                                                       float2* __restrict__ part,
-                                                       unsigned long long* __restrict__ stats) {
-  __shared__ float2 s_tw[1024];
-  __shared__ float2 s_buf[4 * kXWaveStride];
-  constexpr int B = 1024 / NY;
-  using SL = Slots<NY>;
-  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int nc = nx / 2 + 1;
-  const int ncs = (nc + B - 1) / B;                       // column sets
-  const int g = blockIdx.x % ngroups;
-  const int cs = (blockIdx.x / ngroups) * 4 + wave;       // this wave's column set
-  fill_twiddles(s_tw, threadIdx.x, kYThreads);
-  __syncthreads();
-  if (cs >= ncs) return;
-  float2* buf = s_buf + wave * kXWaveStride;
-  const int c0 = cs * B;
-  const int kd_a = (int)((int64_t)n_k * g / ngroups), kd_b = (int)((int64_t)n_k * (g + 1) / ngroups);
-  float2 accd[16], accm[16];
-#pragma unroll
-  for (int i = 0; i < 16; ++i) accd[i] = accm[i] = make_float2(0.f, 0.f);
-  unsigned cnt = 0;
-  const int64_t kstride = (int64_t)nc * NY;
-  for (int kd = kd_a; kd < kd_b; ++kd) {
-    const double2 k = kc[kd];
-    // double-overlap sets of this pixel for the lane's columns (direct and mirrored)
-    ColSet sd[SL::count], sm[SL::count];
-    bool any = false;
-#pragma unroll
-    for (int sl = 0; sl < SL::count; ++sl) {
-      int b0, m0;
-      fft_out_index<NY>(lane, sl * (16 / SL::count), b0, m0);
-      int c = c0 + b0;
-      asm volatile("" : "+v"(c));
-      sd[sl] = ColSet{1, 0, 1, 0};
-      sm[sl] = ColSet{1, 0, 1, 0};
-      if (c < nc) {
-        sd[sl] = col_set(k.x, k.y, signed_index(c, nx), NY, o);
-        if (c > 0 && 2 * c < nx) sm[sl] = col_set(k.x, k.y, signed_index(nx - c, nx), NY, o);
-      }
-      any = any || !sd[sl].empty() || !sm[sl].empty();
-    }
-    // with store_g every pixel is transformed, so that the stored G is complete
-    if (!store_g && !__ballot(any)) continue;
-    float2 v[16];
-    const float2* xcol = X + kd * kstride + (int64_t)c0 * NY;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      int b, n;
-      fft_in_index<NY>(lane, i, b, n);
-      v[i] = (c0 + b < nc) ? xcol[(int64_t)b * NY + n] : make_float2(0.f, 0.f);
-    }
-    wave_fft<NY>(v, buf, s_tw, lane);
-    if (store_g) {
-      float2* gcol = X + kd * kstride + (int64_t)c0 * NY;
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        int b, m;
-        fft_out_index<NY>(lane, i, b, m);
-        if (c0 + b < nc) gcol[(int64_t)b * NY + m] = v[i];
-      }
-    }
-    const double kch = kchi[kd];
-#pragma unroll
-    for (int sl = 0; sl < SL::count; ++sl) {
-      int b0, m0;
-      fft_out_index<NY>(lane, sl * (16 / SL::count), b0, m0);
-      const int c = c0 + b0;
-      const ChiCol chd = chi_column(o.lk * (k.x - (double)signed_index(c, nx) * o.sx), o);
-      const ChiCol chm = chi_column(o.lk * (k.x - (double)signed_index(nx - c, nx) * o.sx), o);
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        if (SL::slot_of(i) != sl) continue;
-        int b, m;
-        fft_out_index<NY>(lane, i, b, m);
-        // keep the per-register frequency arithmetic inside the pixel loop: hoisted out of it, the
-        // 16 registers' frequencies stay live across the loop and cost occupancy
-        asm volatile("" : "+v"(m));
-        const int iy = signed_index(m, NY);
-        if (sd[sl].has(iy)) {
-          const double wy = o.lk * (k.y - (double)iy * o.sy);
-          const float2 e = expi_reduced(chi_eval(chd, wy) - kch);
-          accd[i].x += v[i].x * e.x - v[i].y * e.y;
-          accd[i].y += v[i].x * e.y + v[i].y * e.x;
-          ++cnt;
-        }
-        const int jy = signed_index((NY - m) & (NY - 1), NY);
-        if (sm[sl].has(jy)) {
-          const double wy = o.lk * (k.y - (double)jy * o.sy);
-          const float2 e = expi_reduced(chi_eval(chm, wy) - kch);
-          accm[i].x += v[i].x * e.x + v[i].y * e.y;
-          accm[i].y += v[i].x * e.y - v[i].y * e.x;
-          ++cnt;
-        }
-      }
-    }
-  }
-  float2* pg = part + (int64_t)g * nx * NY;
-#pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    int b, m;
-    fft_out_index<NY>(lane, i, b, m);
-    const int c = c0 + b;
-    if (c >= nc) continue;
-    pg[(int64_t)c * NY + m] = accd[i];
-    if (c > 0 && 2 * c < nx) pg[(int64_t)(nx - c) * NY + ((NY - m) & (NY - 1))] = accm[i];
-  }
-  unsigned long long cc = cnt;
-  for (int off = 32; off > 0; off >>= 1) cc += __shfl_xor(cc, off);
-  if (lane == 0) atomicAdd(stats, cc);
-}
-
-// Fused column transform + adjoint of Eq. 3 (G recomputed, never stored).  Same work split as
-// k_yreduce.  For every double-overlap pair, z = G e^{i psi} (conj G for mirrored frequencies),
-// w = Re(conj(Tbar(Q)) i z); dL/dc_j gains w (B_j(K - Q) - B_j(K)) and dL/dtheta[kd] loses w.
-// Partials: pdc[wave][8] (FP64), pdth[column set][kd] (FP32; one writer per entry).
-template <int NY>
-__global__ void __launch_bounds__(kYThreads) k_yadjoint(const float2* __restrict__ X, const double2* __restrict__ kc,
-                                                        const double* __restrict__ kchi, int n_k, int nx,
-                                                        int ngroups, Optics o, int g_stored,
-                                                        const float2* __restrict__ Tbt, double* __restrict__ pdc,
-                                                        float* __restrict__ pdth) {
-  __shared__ float2 s_tw[1024];
-  __shared__ float2 s_buf[4 * kXWaveStride];
-  constexpr int B = 1024 / NY;
-  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int nc = nx / 2 + 1;
-  const int ncs = (nc + B - 1) / B;
-  const int g = blockIdx.x % ngroups;
-  const int cs = (blockIdx.x / ngroups) * 4 + wave;
-  const int64_t wid = (int64_t)blockIdx.x * 4 + wave;
-  fill_twiddles(s_tw, threadIdx.x, kYThreads);
-  __syncthreads();
-  if (cs >= ncs) {
-    if (lane < 8) pdc[wid * 8 + lane] = 0.0;
-    return;
-  }
-  float2* buf = s_buf + wave * kXWaveStride;
-  const int c0 = cs * B;
-  const int kd_a = (int)((int64_t)n_k * g / ngroups), kd_b = (int)((int64_t)n_k * (g + 1) / ngroups);
-  const int ct = c0 + lane % B;
-  const bool ct_ok = ct < nc;
-  const double ctx = (double)signed_index(ct, nx) * o.sx;
-  const bool ct_m = ct_ok && ct > 0 && 2 * ct < nx;
-  float2 tbd[16], tbm[16];
-#pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    int b, m;
-    fft_out_index<NY>(lane, i, b, m);
-    const int c = c0 + b;
-    tbd[i] = c < nc ? Tbt[(int64_t)c * NY + m] : make_float2(0.f, 0.f);
-    tbm[i] = (c < nc && c > 0 && 2 * c < nx) ? Tbt[(int64_t)(nx - c) * NY + ((NY - m) & (NY - 1))]
-                                              : make_float2(0.f, 0.f);
-  }
-  double dc[8];
-#pragma unroll
-  for (int j = 0; j < 8; ++j) dc[j] = 0.0;
-  const int64_t kstride = (int64_t)nc * NY;
-  for (int kd = kd_a; kd < kd_b; ++kd) {
-    const double2 k = kc[kd];
-    const bool near = ct_ok && (fabs(k.x - ctx) < o.r || (ct_m && fabs(k.x + ctx) < o.r));
-    if (!__ballot(near)) {
-      if (lane == 0) pdth[(int64_t)cs * n_k + kd] = 0.f;
-      continue;
-    }
-    float2 v[16];
-    const float2* xcol = X + kd * kstride + (int64_t)c0 * NY;
-    if (g_stored) {
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        int b, m;
-        fft_out_index<NY>(lane, i, b, m);
-        v[i] = (c0 + b < nc) ? xcol[(int64_t)b * NY + m] : make_float2(0.f, 0.f);
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        int b, n;
-        fft_in_index<NY>(lane, i, b, n);
-        v[i] = (c0 + b < nc) ? xcol[(int64_t)b * NY + n] : make_float2(0.f, 0.f);
-      }
-      wave_fft<NY>(v, buf, s_tw, lane);
-    }
-    const double kch = kchi[kd];
-    const float kxf = (float)k.x, kyf = (float)k.y;
-    double bk[8];
-    chi_basis(k.x, k.y, o, bk);
-    float wsum = 0.f;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      int b, m;
-      fft_out_index<NY>(lane, i, b, m);
-      int c = c0 + b;
-      asm volatile("" : "+v"(c), "+v"(m));  // see k_yreduce
-      if (c >= nc) continue;
-      for (int side = 0; side < 2; ++side) {
-        int ix, iy;
-        if (side == 0) {
-          ix = signed_index(c, nx);
-          iy = signed_index(m, NY);
-        } else {
-          if (!(c > 0 && 2 * c < nx)) break;
-          ix = signed_index(nx - c, nx);
-          iy = signed_index((NY - m) & (NY - 1), NY);
-        }
-        if (!overlap_screened(k.x, k.y, kxf, kyf, ix, iy, o)) continue;
-        const double qx = (double)ix * o.sx, qy = (double)iy * o.sy;
-        double bm[8];
-        chi_basis(k.x - qx, k.y - qy, o, bm);
-        double chim = 0.0;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) chim += o.c[j] * bm[j];
-        const float2 e = expi_reduced(chim - kch);
-        const float2 gq = side ? cconj(v[i]) : v[i];
-        const float2 z = make_float2(gq.x * e.x - gq.y * e.y, gq.x * e.y + gq.y * e.x);
-        const float2 tb = side ? tbm[i] : tbd[i];
-        const float w = tb.x * (-z.y) + tb.y * z.x;
-        wsum += w;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) dc[j] += (double)w * (bm[j] - bk[j]);
-      }
-    }
-    for (int off = 32; off > 0; off >>= 1) wsum += __shfl_xor(wsum, off);
-    if (lane == 0) pdth[(int64_t)cs * n_k + kd] = -wsum;
-  }
-#pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    double v = dc[j];
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    if (lane == 0) pdc[wid * 8 + j] = v;
-  }
-}
-
-static int launch_yadjoint(int ny, const float2* X, const double2* kc, const double* kchi, int n_k, int nx,
-                           int ngroups, const Optics& o, int g_stored, const float2* Tbt, double* pdc,
-                           float* pdth, hipStream_t s) {
-  const int B = 1024 / ny;
-  const int ncs = (nx / 2 + 1 + B - 1) / B;
-  const dim3 grid((unsigned)(((ncs + 3) / 4) * ngroups)), blk(kYThreads);
-  STEM_TRACE("ssb_yadjoint", s);
-  switch (ny) {
-    case 32: hipLaunchKernelGGL((k_yadjoint<32>), grid, blk, 0, s, X, kc, kchi, n_k, nx, ngroups, o, g_stored, Tbt, pdc, pdth); break;
-    case 64: hipLaunchKernelGGL((k_yadjoint<64>), grid, blk, 0, s, X, kc, kchi, n_k, nx, ngroups, o, g_stored, Tbt, pdc, pdth); break;
-    case 128: hipLaunchKernelGGL((k_yadjoint<128>), grid, blk, 0, s, X, kc, kchi, n_k, nx, ngroups, o, g_stored, Tbt, pdc, pdth); break;
-    case 256: hipLaunchKernelGGL((k_yadjoint<256>), grid, blk, 0, s, X, kc, kchi, n_k, nx, ngroups, o, g_stored, Tbt, pdc, pdth); break;
-    case 512: hipLaunchKernelGGL((k_yadjoint<512>), grid, blk, 0, s, X, kc, kchi, n_k, nx, ngroups, o, g_stored, Tbt, pdc, pdth); break;
-    case 1024: hipLaunchKernelGGL((k_yadjoint<1024>), grid, blk, 0, s, X, kc, kchi, n_k, nx, ngroups, o, g_stored, Tbt, pdc, pdth); break;
-    default: return STEM_EINVAL;
-  }
-  STEM_LAUNCH_CHECK();
-  return STEM_OK;
-}
-
-static int launch_yreduce(int ny, float2* X, const double2* kc, const double* kchi, int n_k, int nx,
-                          int ngroups, const Optics& o, int store_g, float2* part,
-                          unsigned long long* stats, hipStream_t s) {
-  const int B = 1024 / ny;
-  const int ncs = (nx / 2 + 1 + B - 1) / B;
-  const dim3 grid((unsigned)(((ncs + 3) / 4) * ngroups)), blk(kYThreads);
-  STEM_TRACE("ssb_yreduce", s);
-  switch (ny) {
-    case 32: hipLaunchKernelGGL((k_yreduce<32>), grid, blk, 0, s, X, kc, kchi, n_k, nx, ngroups, o, store_g, part, stats); break;
-    case 64: hipLaunchKernelGGL((k_yreduce<64>), grid, blk, 0, s, X, kc, kchi, n_k, nx, ngroups, o, store_g, part, stats); break;
-    case 128: hipLaunchKernelGGL((k_yreduce<128>), grid, blk, 0, s, X, kc, kchi, n_k, nx, ngroups, o, store_g, part, stats); break;
-    case 256: hipLaunchKernelGGL((k_yreduce<256>), grid, blk, 0, s, X, kc, kchi, n_k, nx, ngroups, o, store_g, part, stats); break;
-    case 512: hipLaunchKernelGGL((k_yreduce<512>), grid, blk, 0, s, X, kc, kchi, n_k, nx, ngroups, o, store_g, part, stats); break;
-    case 1024: hipLaunchKernelGGL((k_yreduce<1024>), grid, blk, 0, s, X, kc, kchi, n_k, nx, ngroups, o, store_g, part, stats); break;
-    default: return STEM_EINVAL;
-  }
-  STEM_LAUNCH_CHECK();
-  return STEM_OK;
 }
 
 // number of pixel groups of the fused sum: about 4096 waves, at most n_k, partial sums <= 64 MB
@@ -687,7 +290,9 @@ static int check_common(const stem_det* det, const stem_scan* scan, const stem_o
   if (!is_pow2_in(scan->ny, 32, 1024) || !is_pow2_in(scan->nx, 32, 1024) || !(scan->step > 0))
     return STEM_EINVAL;
   if (ssb->d_bits != 8 && ssb->d_bits != 16) return STEM_EINVAL;
-  if (ssb->precision != STEM_FFT_FP32) return STEM_EINVAL;
+  if (ssb->precision != STEM_FFT_FP32 && ssb->precision != STEM_DFT_BF16_SPLIT &&
+      ssb->precision != STEM_DFT_FP16_SPLIT)
+    return STEM_EINVAL;
   if (ssb->g_mode != STEM_G_STORE && ssb->g_mode != STEM_G_RECOMPUTE) return STEM_EINVAL;
   const int n = count_pixels(*det, optics->r_bf * optics->r_bf);
   if (n <= 0 || n > kMaxPixels) return STEM_EINVAL;
@@ -817,9 +422,9 @@ extern "C" int ssb_reconstruct(const int32_t* d_idx, const int64_t* d_off, int64
     const int ry0 = (int)(frame0 / nx), nr = (int)(n_frames / nx);
     const int64_t nrows = (int64_t)n_k * nr;
     if (ssb->d_bits == 8)
-      st = launch_xstage_t<uint8_t>(nx, (const uint8_t*)b.D, ny, ry0, nr, nrows, b.X, s);
+      st = launch_xstage_t<uint8_t>(ssb->precision, nx, (const uint8_t*)b.D, ny, ry0, nr, nrows, b.X, s);
     else
-      st = launch_xstage_t<uint16_t>(nx, (const uint16_t*)b.D, ny, ry0, nr, nrows, b.X, s);
+      st = launch_xstage_t<uint16_t>(ssb->precision, nx, (const uint16_t*)b.D, ny, ry0, nr, nrows, b.X, s);
     if (st) return st;
     if (mode == STEM_SSB_ACCUMULATE) return STEM_OK;
   }
@@ -828,6 +433,15 @@ extern "C" int ssb_reconstruct(const int32_t* d_idx, const int64_t* d_off, int64
   if (mode == STEM_SSB_REFOCUS) {
     // Eq. 3 again from the stored G
     if ((st = run_reduce_stored(L, b, ny, nx, o, ssb->normalize, s))) return st;
+    return run_phase(L, b, *scan, b.T, 1, d_phase, d_T, s);
+  }
+  if (ssb->normalize && ssb->precision != STEM_FFT_FP32) {
+    // split precision: the fused kernel transforms X -> G in place (its partial sums are not
+    // used); the counters are reset before the per-Q normalised sum
+    if ((st = launch_yreduce(ssb->precision, ny, b.X, b.kc, b.kchi, n_k, nx, L.groups, o, 1, b.part, b.stats, s)))
+      return st;
+    if ((st = run_chi_table(b, d_theta, n_k, o, 1, s))) return st;
+    if ((st = run_reduce_stored(L, b, ny, nx, o, 1, s))) return st;
     return run_phase(L, b, *scan, b.T, 1, d_phase, d_T, s);
   }
   if (ssb->normalize) {
@@ -843,8 +457,8 @@ extern "C" int ssb_reconstruct(const int32_t* d_idx, const int64_t* d_off, int64
     if ((st = run_reduce_stored(L, b, ny, nx, o, 1, s))) return st;
     return run_phase(L, b, *scan, b.T, 1, d_phase, d_T, s);
   }
-  if ((st = launch_yreduce(ny, b.X, b.kc, b.kchi, n_k, nx, L.groups, o, ssb->g_mode == STEM_G_STORE, b.part,
-                           b.stats, s)))
+  if ((st = launch_yreduce(ssb->precision, ny, b.X, b.kc, b.kchi, n_k, nx, L.groups, o, ssb->g_mode == STEM_G_STORE,
+                           b.part, b.stats, s)))
     return st;
   return run_phase(L, b, *scan, b.part, L.groups, d_phase, d_T, s);
 }
@@ -883,8 +497,8 @@ extern "C" int ssb_backward(const float* d_dLdphi, const stem_det* det, const st
   a.tag = "adj_fft";
   if ((st = launch_row_fft(ny, false, IN_C64, OUT_ROW_C64, a, s))) return st;
   if ((st = run_chi_table(b, d_theta, n_k, o, L.groups, s))) return st;
-  if ((st = launch_yadjoint(ny, b.X, b.kc, b.kchi, n_k, nx, L.groups, o, ssb->g_mode == STEM_G_STORE, b.Tb, b.pdc,
-                            b.pdth, s)))
+  if ((st = launch_yadjoint(ssb->precision, ny, b.X, b.kc, b.kchi, n_k, nx, L.groups, o, ssb->g_mode == STEM_G_STORE,
+                            b.Tb, b.pdc, b.pdth, s)))
     return st;
   {
     STEM_TRACE("ssb_adjoint_final", s);

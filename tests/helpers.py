@@ -80,9 +80,9 @@ def oracle_ssb(idx, off, wl, c=(0.0,) * 8, theta=None, normalize=False, direct=F
 
 
 def gpu_ssb(d_idx, d_off, wl, c=(0.0,) * 8, theta=None, normalize=0, g_mode=stem.STEM_G_STORE, d_bits=8,
-            chunk_rows=None):
+            chunk_rows=None, precision=stem.STEM_FFT_FP32):
     det, scan, optics = structs(wl, c)
-    ssb = stem.Ssb(stem.STEM_FFT_FP32, normalize, g_mode, d_bits)
+    ssb = stem.Ssb(precision, normalize, g_mode, d_bits)
     st = stem.SsbState(det, scan, optics, ssb, device=d_idx.device)
     F = wl.n_frames
     ny, nx = wl.scan

@@ -1,0 +1,138 @@
+"""Split-precision matrix-core scan DFT (BF16 and FP16, twiddles and non-integer data split
+into hi + lo parts, FP32 accumulation) against the FP64 oracle.
+
+Every output of the transform and of the sum that follows it (G, T, phi, the adjoint) is
+compared by relative L2 error with the bound 1e-4; binning stays bit-exact, and G(K, Q=0),
+whose DFT weights are all exactly one, equals the summed pattern exactly.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_2104_06336_amd as stem
+from gen import C4_TRUE_ABERRATIONS, with_pileup
+from oracle import ssb as ossb
+
+from helpers import gpu_ssb, oracle_ssb, rel_l2, state_D, state_G_half, structs, to_device
+from test_gpu_parity import data
+
+pytestmark = pytest.mark.gpu
+
+TOL_SPLIT = 1e-4
+SPLIT = [stem.STEM_DFT_BF16_SPLIT, stem.STEM_DFT_FP16_SPLIT]
+IDS = ["bf16", "fp16"]
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    print(f"\n[gpu] {request.node.name}", flush=True)
+
+
+@pytest.mark.parametrize("prec", SPLIT, ids=IDS)
+@pytest.mark.parametrize("name", ["small", "mid", "rect"])
+def test_split_transform_per_output(gpu, name, prec):
+    wl, idx, off = data(name)
+    d_idx, d_off = to_device(idx, off)
+    st, out = gpu_ssb(d_idx, d_off, wl, precision=prec)
+    ref = oracle_ssb(idx, off, wl)
+    assert out["status"] == 0
+    assert np.array_equal(state_D(st, wl), ref["D"])
+    nh = wl.scan[1] // 2 + 1
+    G = state_G_half(st, wl)
+    errs = {"G": rel_l2(G, ref["G"][:, :, :nh]), "T": rel_l2(out["T"], ref["T"]),
+            "phi": rel_l2(out["phi"], ref["phi"])}
+    print(f"[split] {name} prec={prec} rel_l2 {errs}", flush=True)
+    for k, e in errs.items():
+        assert e <= TOL_SPLIT, k
+    # G(K, 0) is the summed pattern, exactly (P6)
+    assert np.array_equal(G[:, 0, 0].real.astype(np.float64), ref["D"].sum(axis=1).astype(np.float64))
+    assert np.all(G[:, 0, 0].imag == 0)
+    assert out["T"][0, 0] == 0
+
+
+@pytest.mark.parametrize("prec", SPLIT, ids=IDS)
+@pytest.mark.parametrize("g_mode", [stem.STEM_G_RECOMPUTE, stem.STEM_G_STORE], ids=["recompute", "store"])
+def test_split_aberrated_phase(gpu, g_mode, prec):
+    wl, idx, off = data("aberr")
+    d_idx, d_off = to_device(idx, off)
+    det, _, optics = structs(wl)
+    theta = np.random.default_rng(3).uniform(-0.3, 0.3, size=stem.ssb_num_pixels(det, optics))
+    st, out = gpu_ssb(d_idx, d_off, wl, c=wl.aberr, theta=theta, g_mode=g_mode, precision=prec)
+    ref = oracle_ssb(idx, off, wl, c=wl.aberr, theta=theta.astype(np.float32))
+    assert out["status"] == 0
+    assert rel_l2(out["T"], ref["T"]) <= TOL_SPLIT
+    assert rel_l2(out["phi"], ref["phi"]) <= TOL_SPLIT
+    # the double-overlap set does not depend on the transform's precision
+    npair = int(ossb.ssb_sum(ref["G"], ref["kc"], wl.step, wl.dk, wl.lam, wl.r_bf, wl.aberr)[1].sum())
+    assert st.pair_count() == npair
+
+
+@pytest.mark.parametrize("prec", SPLIT, ids=IDS)
+def test_split_refocus(gpu, prec):
+    wl, idx, off = data("aberr")
+    d_idx, d_off = to_device(idx, off)
+    st, _ = gpu_ssb(d_idx, d_off, wl, c=(0.0,) * 8, precision=prec)
+    F = wl.n_frames
+    phase = torch.zeros(F, dtype=torch.float32, device="cuda")
+    T = torch.zeros(F, dtype=torch.complex64, device="cuda")
+    st.refocus(c=wl.aberr, phase=phase, T=T)
+    ref = oracle_ssb(idx, off, wl, c=wl.aberr)
+    assert rel_l2(T.cpu().numpy().reshape(wl.scan), ref["T"]) <= TOL_SPLIT
+    assert rel_l2(phase.cpu().numpy().reshape(wl.scan), ref["phi"]) <= TOL_SPLIT
+
+
+@pytest.mark.parametrize("prec", SPLIT, ids=IDS)
+def test_split_uint16_cube(gpu, prec):
+    """Counts above 255 are not exact in BF16: the uint16 cube takes the split-data path."""
+    wl, idx, off = data("small")
+    H, W = wl.det
+    idx2, off2 = with_pileup(idx, off, 100, (H // 2) * W + W // 2, 300)
+    d_idx, d_off = to_device(idx2, off2)
+    st, out = gpu_ssb(d_idx, d_off, wl, d_bits=16, precision=prec)
+    assert out["status"] == 0
+    ref = oracle_ssb(idx2, off2, wl)
+    assert np.array_equal(state_D(st, wl), ref["D"])
+    G = state_G_half(st, wl)
+    assert rel_l2(G, ref["G"][:, :, :wl.scan[1] // 2 + 1]) <= TOL_SPLIT
+    assert rel_l2(out["phi"], ref["phi"]) <= TOL_SPLIT
+
+
+@pytest.mark.parametrize("prec", SPLIT, ids=IDS)
+def test_split_normalized(gpu, prec):
+    wl, idx, off = data("small")
+    d_idx, d_off = to_device(idx, off)
+    st, out = gpu_ssb(d_idx, d_off, wl, normalize=1, precision=prec)
+    ref = oracle_ssb(idx, off, wl, normalize=True)
+    assert rel_l2(out["T"], ref["T"]) <= TOL_SPLIT
+    assert rel_l2(out["phi"], ref["phi"]) <= TOL_SPLIT
+    npair = int(ossb.ssb_sum(ref["G"], ref["kc"], wl.step, wl.dk, wl.lam, wl.r_bf, (0.0,) * 8)[1].sum())
+    assert st.pair_count() == npair
+
+
+@pytest.mark.parametrize("prec", SPLIT, ids=IDS)
+def test_split_chunked_accumulate(gpu, prec):
+    wl, idx, off = data("mid")
+    d_idx, d_off = to_device(idx, off)
+    _, one = gpu_ssb(d_idx, d_off, wl, precision=prec)
+    _, odd = gpu_ssb(d_idx, d_off, wl, chunk_rows=24, precision=prec)  # ragged last chunk
+    assert rel_l2(odd["phi"], one["phi"]) <= 1e-5
+
+
+@pytest.mark.parametrize("prec", SPLIT, ids=IDS)
+@pytest.mark.parametrize("g_mode", [stem.STEM_G_RECOMPUTE, stem.STEM_G_STORE], ids=["recompute", "store"])
+def test_split_adjoint(gpu, g_mode, prec):
+    wl, idx, off = data("aberr")
+    d_idx, d_off = to_device(idx, off)
+    rng = np.random.default_rng(7)
+    c = np.array(C4_TRUE_ABERRATIONS) * (1 + rng.uniform(-0.5, 0.5, size=8))
+    st, out = gpu_ssb(d_idx, d_off, wl, c=c, g_mode=g_mode, precision=prec)
+    phi = torch.from_numpy(out["phi"]).cuda()
+    gbar = (-(2.0 / phi.numel()) * (phi - phi.mean())).contiguous().view(-1)
+    dc, dth = st.backward(gbar, c=c)
+    ref = oracle_ssb(idx, off, wl, c=c)
+    dco, dtho = ossb.ssb_adjoint(ref["G"], ref["kc"], ossb.neg_var_grad(ref["phi"]), wl.step, wl.dk, wl.lam,
+                                 wl.r_bf, c)
+    dc = dc.cpu().numpy()
+    print(f"[split] adjoint prec={prec} rel per comp {np.abs(dc - dco) / np.abs(dco)}", flush=True)
+    assert rel_l2(dc, dco) <= TOL_SPLIT
+    assert rel_l2(dth.cpu().numpy(), dtho) <= TOL_SPLIT
