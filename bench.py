@@ -124,6 +124,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="scan1024")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-split", action="store_true", help="skip the split-precision scan-DFT variants")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run a device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
@@ -162,8 +163,6 @@ def main():
     com64 = torch.empty(2 * F, dtype=torch.float64, device=dev)
     phase_dpc = torch.empty(F, dtype=torch.float32, device=dev)
     ws = torch.empty(stem.com_dpc_workspace_bytes(scan), dtype=torch.uint8, device=dev)
-    ssb_opts = stem.Ssb(stem.STEM_FFT_FP32, 0, stem.STEM_G_RECOMPUTE, 8)
-    st = stem.SsbState(det, scan, optics, ssb_opts, device=dev)
     phase_ssb = torch.empty(F, dtype=torch.float32, device=dev)
 
     if args.copy_calib_mib:
@@ -174,29 +173,37 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    def step():
-        stem.com_dpc(d_idx, d_off, 0, F, det, scan, optics, dpc, com64=com64, phase=phase_dpc, ws=ws,
-                     d_status=status)
-        st.oneshot(d_idx, d_off, phase=phase_ssb)
+    def run(precision, steps, warmup):
+        """Times `steps` whole steps with the given scan-DFT precision; returns
+        (elapsed s, kernel trace, SSB phase, SsbState)."""
+        st = stem.SsbState(det, scan, optics, stem.Ssb(precision, 0, stem.STEM_G_RECOMPUTE, 8), device=dev)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    stem.check_status(status, "com_dpc")
-    stem.check_status(st.status, "ssb_reconstruct")
+        def step():
+            stem.com_dpc(d_idx, d_off, 0, F, det, scan, optics, dpc, com64=com64, phase=phase_dpc, ws=ws,
+                         d_status=status)
+            st.oneshot(d_idx, d_off, phase=phase_ssb)
 
-    stem.trace_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    recs = stem.trace_records()
-    stem.trace_enable(False)
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        stem.check_status(status, "com_dpc")
+        stem.check_status(st.status, "ssb_reconstruct")
+        stem.trace_enable(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        recs = stem.trace_records()
+        stem.trace_enable(False)
+        return elapsed, recs, phase_ssb.clone(), st
+
+    elapsed, recs, phi32, st = run(stem.STEM_FFT_FP32, args.steps, args.warmup)
     ms_per_step = elapsed / args.steps * 1e3
     P, groups = st.stats()[:2]
     n_k = st.n_k
+    del st
     log(f"{args.steps} steps in {elapsed:.4f} s ({ms_per_step:.3f} ms/step), n_K={n_k}, pairs={P}")
 
     geo = {"C": C, "F": F, "nk": n_k, "nx": nx, "ny": ny, "P": P, "d_bytes": 1, "groups": groups}
@@ -217,6 +224,29 @@ def main():
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ab / avg_s / 1e9 / HBM_PEAK_GBS, 4) if ab else None,
                 "traffic": load_traffic(dom, args.workload), "bytes_per_launch": ab}
+
+    def ssb_ms(r):
+        return sum(ms for name, (n, ms) in r.items() if not name.startswith(("com_", "dpc_"))) / args.steps
+
+    ssb32 = ssb_ms(recs)
+    variants = {}
+    if not args.no_split:
+        for label, prec in (("bf16_split", stem.STEM_DFT_BF16_SPLIT), ("fp16_split", stem.STEM_DFT_FP16_SPLIT)):
+            el, rv, phi, st = run(prec, args.steps, args.warmup)
+            del st
+            d = float((phi.double() - phi32.double()).norm() / phi32.double().norm())
+            sm = ssb_ms(rv)
+            variants[label] = {
+                "ms_per_step": round(el / args.steps * 1e3, 4),
+                "value": round(C * args.steps / el, 1),
+                "speedup_vs_fp32_step": round(elapsed / el, 3),
+                "ssb_ms": round(sm, 4),
+                "speedup_vs_fp32_ssb": round(ssb32 / sm, 3),
+                "phi_rel_l2_vs_fp32_path": float(f"{d:.3e}"),
+                "kernels_us": {k: round(ms / n * 1e3, 2) for k, (n, ms) in rv.items()},
+            }
+            log(f"{label}: {el / args.steps * 1e3:.3f} ms/step (SSB {sm:.3f} ms vs FP32 {ssb32:.3f} ms), "
+                f"phi vs FP32 path rel L2 {d:.2e}")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -246,6 +276,8 @@ def main():
                    "double_overlap_pairs": P, "ssb_path": "FP32 FFT, fused column transform + sum (G recomputed)",
                    "parallelism": "single GPU"},
         "kernels": kernels,
+        "ssb_ms_fp32": round(ssb32, 4),
+        "precision_variants": variants,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -4,8 +4,9 @@
 //  k_com            : per-frame count and exact integer first moments -> centre of mass.
 //  k_bin            : per-frame binned, cropped counts into the dense cube D[kd][f].
 //
-// Frame blocks: a workgroup owns a run of consecutive frames; their events are one
-// contiguous CSR slice, streamed into LDS with coalesced loads in windows of kWin events.
+// Frame blocks: a workgroup owns a run of consecutive frames; their events are one contiguous
+// CSR slice, read with coalesced 16-byte loads: staged in LDS for the per-frame sums of k_com,
+// streamed with an LDS map event -> frame for the counts of k_bin.
 #include "common.h"
 #include "geom.h"
 #include "kernels.h"
@@ -13,7 +14,7 @@
 
 namespace stem {
 
-constexpr int kComThreads = 256;   // one frame per thread
+constexpr int kComThreads = 256;   // = kComFrames: thread t finishes frame t
 
 // ---------------------------------------------------------------------------------------------
 // validation
@@ -64,33 +65,67 @@ __device__ __forceinline__ bool load_rel_offsets(const int64_t* __restrict__ off
 }
 
 // ---------------------------------------------------------------------------------------------
-// Thread-per-frame walk over a frame's events: a scalar head up to 16-byte alignment, then
-// 16-byte vector loads (four events each, four loads issued together), then a scalar tail.
-// f(k) is applied to every event index in order.
+// Staging of a workgroup's events in LDS: the events [a0, a0 + n) (absolute indices) are copied
+// with 16-byte loads from the 16-byte aligned position at or below a0; s[sh + j] then holds event
+// a0 + j (sh < 4 is returned).  Groups not wholly inside [a0, a0 + n) are copied element by
+// element, so nothing outside the window is read.
 
-template <typename Fn>
-__device__ __forceinline__ void for_each_event(const int32_t* __restrict__ ev, int64_t lo, int64_t hi, Fn f) {
-  int64_t e = lo;
-  for (; e < hi && (((uintptr_t)(ev + e)) & 15); ++e) f(ev[e]);
-  for (; e + 16 <= hi; e += 16) {
-    const int4 q0 = *(const int4*)(ev + e);
-    const int4 q1 = *(const int4*)(ev + e + 4);
-    const int4 q2 = *(const int4*)(ev + e + 8);
-    const int4 q3 = *(const int4*)(ev + e + 12);
-    f(q0.x); f(q0.y); f(q0.z); f(q0.w);
-    f(q1.x); f(q1.y); f(q1.z); f(q1.w);
-    f(q2.x); f(q2.y); f(q2.z); f(q2.w);
-    f(q3.x); f(q3.y); f(q3.z); f(q3.w);
+// Group c of four events starting at the absolute index e (16-byte aligned): k[j] = idx[e + j],
+// ok[j] = e + j in [a0, aend); the whole group is one 16-byte load when it lies inside.
+__device__ __forceinline__ void load_group(const int32_t* __restrict__ idx, int64_t e, int64_t a0, int64_t aend,
+                                           int32_t* k, bool* ok) {
+  if (e >= a0 && e + 4 <= aend) {
+    const int4 v = *(const int4*)(idx + e);
+    k[0] = v.x;
+    k[1] = v.y;
+    k[2] = v.z;
+    k[3] = v.w;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) ok[j] = true;
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      ok[j] = e + j >= a0 && e + j < aend;
+      k[j] = ok[j] ? idx[e + j] : 0;
+    }
   }
-  for (; e + 4 <= hi; e += 4) {
-    const int4 q = *(const int4*)(ev + e);
-    f(q.x); f(q.y); f(q.z); f(q.w);
+}
+
+// Staging of a workgroup's events in LDS: the events [a0, a0 + n) (absolute indices) are copied
+// from the 16-byte aligned position at or below a0; s[sh + j] then holds event a0 + j (sh < 4 is
+// returned).  Each thread issues kStageUnroll loads before its LDS stores, so that many loads are
+// in flight; nothing outside the window is read.
+constexpr int kStageUnroll = 8;
+
+__device__ __forceinline__ int stage_events(const int32_t* __restrict__ idx, int64_t a0, int n, int32_t* s) {
+  const int sh = (int)((((uintptr_t)(idx + a0)) & 15) >> 2);
+  const int64_t al = a0 - sh, aend = a0 + n;
+  const int nchunk = (n + sh + 3) >> 2;
+  const int step = blockDim.x * kStageUnroll;
+  for (int c0 = threadIdx.x; c0 < nchunk; c0 += step) {
+    int32_t k[kStageUnroll][4];
+    bool ok[kStageUnroll][4];
+#pragma unroll
+    for (int u = 0; u < kStageUnroll; ++u) {
+      const int c = c0 + u * blockDim.x;
+      if (c < nchunk) load_group(idx, al + 4 * (int64_t)c, a0, aend, k[u], ok[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < kStageUnroll; ++u) {
+      const int c = c0 + u * blockDim.x;
+      if (c < nchunk) *(int4*)&s[4 * c] = make_int4(k[u][0], k[u][1], k[u][2], k[u][3]);
+    }
   }
-  for (; e < hi; ++e) f(ev[e]);
+  return sh;
 }
 
 // ---------------------------------------------------------------------------------------------
-// centre of mass: one thread per frame
+// centre of mass: a workgroup owns kComFrames consecutive frames.  Their events are staged in
+// LDS in windows of kComWin (coalesced 16-byte loads); thread t then sums the events of frame t
+// from LDS with four independent accumulators (int32 within a window, int64 across windows).
+
+constexpr int kComFrames = 256;
+constexpr int kComWin = 12288;
 
 __global__ void __launch_bounds__(kComThreads) k_com(const int32_t* __restrict__ idx,
                                                      const int64_t* __restrict__ off,
@@ -100,32 +135,62 @@ __global__ void __launch_bounds__(kComThreads) k_com(const int32_t* __restrict__
                                                      float* __restrict__ com32,
                                                      int32_t* __restrict__ counts,
                                                      int32_t* status) {
-  const int64_t fr = frame0 + (int64_t)blockIdx.x * kComThreads + threadIdx.x;
-  if (fr >= frame0 + n_frames) return;
-  const int64_t lo = off[fr], hi = off[fr + 1];
+  __shared__ int32_t s_ev[kComWin + 8];
+  __shared__ int32_t s_rel[kComFrames + 1];
+  __shared__ int64_t s_base;
+  const int t = threadIdx.x;
+  const int64_t fb = frame0 + (int64_t)blockIdx.x * kComFrames;
+  const int64_t left = frame0 + n_frames - fb;
+  const int nf = (int)(left < kComFrames ? left : kComFrames);
+  if (!load_rel_offsets(off, fb, nf, s_rel, &s_base, status)) return;
+  __syncthreads();
+  const int span = s_rel[nf];
+  const int lo_t = t < nf ? s_rel[t] : 0, hi_t = t < nf ? s_rel[t + 1] : 0;
   int64_t sx = 0, sy = 0;
   int32_t bad = 0;
-  for_each_event(idx, lo, hi, [&](int32_t k) {
-    if (k < 0 || k >= npix) {
-      bad = STEM_ERANGE;
-      return;
+  for (int w0 = 0; w0 < span; w0 += kComWin) {
+    const int wn = span - w0 < kComWin ? span - w0 : kComWin;
+    __syncthreads();
+    const int sh = stage_events(idx, s_base + w0, wn, s_ev);
+    __syncthreads();
+    const int lo = (lo_t > w0 ? lo_t : w0) - w0 + sh;
+    const int hi = (hi_t < w0 + wn ? hi_t : w0 + wn) - w0 + sh;
+    int32_t ax[4] = {0, 0, 0, 0}, ay[4] = {0, 0, 0, 0};
+    uint32_t nbad = 0;
+    // out-of-range indices are counted (and reported) and contribute nothing; no branches
+    auto add = [&](int j, int32_t k) {
+      const bool in = (uint32_t)k < (uint32_t)npix;
+      nbad += in ? 0u : 1u;
+      const uint32_t kk = in ? (uint32_t)k : 0u;
+      const uint32_t ky = magic_div(kk, divw);
+      ax[j] += in ? (int32_t)(kk - ky * divw.d) - cx : 0;
+      ay[j] += in ? (int32_t)ky - cy : 0;
+    };
+    int e = lo;
+    for (; e + 4 <= hi; e += 4) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) add(j, s_ev[e + j]);
     }
-    const uint32_t ky = magic_div((uint32_t)k, divw);
-    sx += k - (int32_t)(ky * divw.d) - cx;
-    sy += (int32_t)ky - cy;
-  });
-  const int64_t n = hi - lo;
-  const double x = n > 0 ? (double)sx / (double)n : 0.0;
-  const double y = n > 0 ? (double)sy / (double)n : 0.0;
-  if (com64) {
-    com64[fr] = x;
-    com64[nplane + fr] = y;
+    for (; e < hi; ++e) add(0, s_ev[e]);
+    if (nbad) bad = STEM_ERANGE;
+    sx += (int64_t)ax[0] + ax[1] + ax[2] + ax[3];
+    sy += (int64_t)ay[0] + ay[1] + ay[2] + ay[3];
   }
-  if (com32) {
-    com32[fr] = (float)x;
-    com32[nplane + fr] = (float)y;
+  if (t < nf) {
+    const int64_t fr = fb + t;
+    const int64_t n = hi_t - lo_t;
+    const double x = n > 0 ? (double)sx / (double)n : 0.0;
+    const double y = n > 0 ? (double)sy / (double)n : 0.0;
+    if (com64) {
+      com64[fr] = x;
+      com64[nplane + fr] = y;
+    }
+    if (com32) {
+      com32[fr] = (float)x;
+      com32[nplane + fr] = (float)y;
+    }
+    if (counts) counts[fr] = (int32_t)n;
   }
-  if (counts) counts[fr] = (int32_t)(n < 0x7fffffff ? n : 0x7fffffff);
   if (bad) report(status, bad);
 }
 
@@ -133,7 +198,7 @@ int launch_com(const int32_t* idx, const int64_t* off, int64_t frame0, int64_t n
                const stem_det& det, int64_t nplane, double* com64, float* com32, int32_t* counts,
                int32_t* status, hipStream_t stream) {
   if (n_frames == 0) return STEM_OK;
-  const int64_t blocks = (n_frames + kComThreads - 1) / kComThreads;
+  const int64_t blocks = (n_frames + kComFrames - 1) / kComFrames;
   STEM_TRACE("com_moments", stream);
   hipLaunchKernelGGL(k_com, dim3((unsigned)blocks), dim3(kComThreads), 0, stream, idx, off, frame0,
                      n_frames, make_magic((uint32_t)det.W), det.cx, det.cy, det.W * det.H, nplane,
@@ -187,11 +252,29 @@ __global__ void __launch_bounds__(256) k_geometry(int32_t b, int32_t nbx, int32_
   }
 }
 
-int launch_geometry(const stem_det& det, double r2, RowRun* rows, double2* kc, hipStream_t stream) {
+// ---------------------------------------------------------------------------------------------
+// pixel -> kept bin lookup: lut[ky*W + kx] = kd of the bin holding the pixel, -1 if that bin is
+// dropped (its centre outside the disk)
+
+__global__ void __launch_bounds__(256) k_pixel_lut(const RowRun* __restrict__ rows, int32_t W, int32_t H, int32_t b,
+                                                   int16_t* __restrict__ lut) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= (int64_t)W * H) return;
+  const int ky = (int)(p / W), kx = (int)(p % W);
+  const RowRun rr = rows[ky / b];
+  const int bx = kx / b;
+  lut[p] = (int16_t)(bx >= rr.lo && bx < rr.hi ? rr.start + bx - rr.lo : -1);
+}
+
+int launch_geometry(const stem_det& det, double r2, RowRun* rows, double2* kc, int16_t* lut, hipStream_t stream) {
   const int nbx = det.W / det.bin, nby = det.H / det.bin;
   STEM_TRACE("ssb_geometry", stream);
   hipLaunchKernelGGL(k_geometry, dim3(1), dim3(256), 0, stream, det.bin, nbx, nby, det.cx, det.cy, r2,
                      rows, kc);
+  STEM_LAUNCH_CHECK();
+  const int64_t npix = (int64_t)det.W * det.H;
+  hipLaunchKernelGGL(k_pixel_lut, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, stream, rows, det.W, det.H,
+                     det.bin, lut);
   STEM_LAUNCH_CHECK();
   return STEM_OK;
 }
@@ -199,12 +282,14 @@ int launch_geometry(const stem_det& det, double r2, RowRun* rows, double2* kc, h
 // ---------------------------------------------------------------------------------------------
 // binning into D[kd][f] (frames of whole scan rows)
 //
-// Workgroup = kBinFrames consecutive frames x a run of up to kBinKd kept pixels.  Events are
-// processed in parallel (coalesced loads, frame by binary search in the block's offsets) and
-// counted in LDS: 8-bit counters, four frames per word, when every frame of the block has at
-// most 255 events (no count can then carry into its neighbour); otherwise 16-bit counters, two
-// frames per word, over two passes of half the pixels.  A count above the element type of D
-// sets STEM_EOVERFLOW (the stored value is then not meaningful).
+// Workgroup = kBinFrames consecutive frames x a run of up to kBinKd kept pixels.  The block's
+// events are streamed in windows of kBinWin: first each thread writes its frame number into an
+// LDS byte map over the window's events, then the events are read with coalesced 16-byte loads
+// (four per lane), their frames read from the map as one word and their pixels mapped by the
+// lookup table.  Counts live in LDS: 8-bit counters, four frames per word, when every frame of
+// the block has at most 255 events (no count can then carry into its neighbour); otherwise
+// 16-bit counters, two frames per word, over two passes of half the pixels.  A count above the
+// element type of D sets STEM_EOVERFLOW (the stored value is then not meaningful).
 
 constexpr int kBinFrames = 256;
 constexpr int kBinThreads = 256;
@@ -212,20 +297,20 @@ constexpr int kBinWords = 11776;                      // 46 KB of counters
 // pixel rows of counters are kBinFrames/4 (+1 padding) words apart, so that the events of one
 // frame (same column, different pixels) fall into different LDS banks
 constexpr int kBinKd = kBinWords / (kBinFrames / 4 + 1);  // 181 pixels per workgroup
-constexpr int kBinLdsRows = 256;                      // bin rows cached in LDS
+constexpr int kBinWin = 4096;                         // events per window of the frame map
 
 template <typename DT>
 __global__ void __launch_bounds__(kBinThreads) k_bin(const int32_t* __restrict__ idx,
                                                      const int64_t* __restrict__ off, int64_t frame0,
-                                                     int64_t n_frames, Magic divw, Magic divb,
-                                                     int32_t npix, int32_t nby,
-                                                     const RowRun* __restrict__ rows, int32_t n_k,
+                                                     int64_t n_frames, int32_t npix,
+                                                     const int16_t* __restrict__ lut, int32_t n_k,
                                                      int64_t F, DT* __restrict__ D, int32_t* status) {
   __shared__ uint32_t s_hist[kBinWords];
+  __shared__ uint32_t s_map[(kBinWin + 16) / 4];
   __shared__ int32_t s_rel[kBinFrames + 1];
-  __shared__ RowRun s_rows[kBinLdsRows];
   __shared__ int64_t s_base;
   const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6, nw = kBinThreads / 64;
   const int nchunks = (n_k + kBinKd - 1) / kBinKd;
   const int kd0 = (int)(blockIdx.x % nchunks) * kBinKd;
   const int kc = n_k - kd0 < kBinKd ? n_k - kd0 : kBinKd;
@@ -233,48 +318,87 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(const int32_t* __restrict__
   const int64_t fend = frame0 + n_frames;
   const int nf = (int)((fend - fb) < kBinFrames ? (fend - fb) : kBinFrames);
   if (!load_rel_offsets(off, fb, nf, s_rel, &s_base, status)) return;
-  const bool rows_lds = nby <= kBinLdsRows;
-  if (rows_lds)
-    for (int i = t; i < nby; i += kBinThreads) s_rows[i] = rows[i];
   __syncthreads();
   const int wide = __syncthreads_or(t < nf && s_rel[t + 1] - s_rel[t] > 255);
-  const int32_t* ev = idx + s_base;
-  const RowRun* rtab = rows_lds ? s_rows : rows;
+  const int span = s_rel[nf];
+  const int lo_t = t < nf ? s_rel[t] : 0, hi_t = t < nf ? s_rel[t + 1] : 0;
+  uint8_t* map = (uint8_t*)s_map;
   int32_t bad = 0;
   const int npass = wide ? 2 : 1;
   const int kpp = (kc + npass - 1) / npass;       // pixels per pass
-  const int fpw = wide ? 2 : 4;                   // frames per counter word
-  const int wpr = kBinFrames / fpw;               // words per pixel row
+  const int wpr = wide ? kBinFrames / 2 : kBinFrames / 4;  // words per pixel row
   const int wps = wpr + 1;                        // row stride in words (padded)
   const uint32_t cap = sizeof(DT) == 1 ? 255u : 65535u;
   for (int pass = 0; pass < npass; ++pass) {
     const int ka = kd0 + pass * kpp;
     const int kn = (kd0 + kc) - ka < kpp ? (kd0 + kc) - ka : kpp;
     for (int i = t; i < kn * wps; i += kBinThreads) s_hist[i] = 0u;
-    __syncthreads();
-    // thread t walks the events of frame t
-    if (t < nf) {
-      const int shift = wide ? 16 * (t & 1) : 8 * (t & 3);
-      const int col = wide ? (t >> 1) : (t >> 2);
-      for_each_event(ev, s_rel[t], s_rel[t + 1], [&](int32_t k) {
-        if (k < 0 || k >= npix) {
-          bad |= STEM_ERANGE;
-          return;
+    for (int w0 = 0; w0 < span; w0 += kBinWin) {
+      const int wn = span - w0 < kBinWin ? span - w0 : kBinWin;
+      const int64_t a0 = s_base + w0;
+      const int sh = (int)((((uintptr_t)(idx + a0)) & 15) >> 2);  // map[sh + j] <-> event a0 + j
+      __syncthreads();
+      {
+        // frame t's events of this window: map entries [lo, hi)
+        const int lo = (lo_t > w0 ? lo_t : w0) - w0 + sh;
+        const int hi = (hi_t < w0 + wn ? hi_t : w0 + wn) - w0 + sh;
+        int j = lo;
+        for (; j < hi && (j & 3); ++j) map[j] = (uint8_t)t;
+        const uint32_t word = (uint32_t)(t & 0xff) * 0x01010101u;
+        for (; j + 4 <= hi; j += 4) s_map[j >> 2] = word;
+        for (; j < hi; ++j) map[j] = (uint8_t)t;
+      }
+      __syncthreads();
+      const int64_t al = a0 - sh, aend = a0 + wn;
+      const int ng = (wn + sh + 3) >> 2;  // groups of four events in this window
+      constexpr int U = 4;                // groups per lane in flight
+      for (int g0 = lane + 64 * wave; g0 < ng; g0 += U * 64 * nw) {
+        int32_t k[U][4];
+        bool ok[U][4];
+        uint32_t fr4[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int g = g0 + u * 64 * nw;
+          if (g < ng) {
+            load_group(idx, al + 4 * (int64_t)g, a0, aend, k[u], ok[u]);
+            fr4[u] = s_map[g];
+          } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              ok[u][q] = false;
+              k[u][q] = 0;
+            }
+            fr4[u] = 0u;
+          }
         }
-        const uint32_t ky = magic_div((uint32_t)k, divw);
-        const uint32_t kx = (uint32_t)k - ky * divw.d;
-        const int by = (int)magic_div(ky, divb);
-        const int bx = (int)magic_div(kx, divb);
-        if (by >= nby) return;
-        const RowRun rr = rtab[by];
-        if (bx < rr.lo || bx >= rr.hi) return;
-        const int kd = rr.start + bx - rr.lo - ka;
-        if (kd < 0 || kd >= kn) return;
-        atomicAdd(&s_hist[kd * wps + col], 1u << shift);
-      });
+        // the table lookups are issued together; out-of-range indices look up pixel 0 and are
+        // dropped (and reported)
+        int kd[U][4];
+        bool in[U][4];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            in[u][q] = (uint32_t)k[u][q] < (uint32_t)npix;
+            if (ok[u][q] && !in[u][q]) bad |= STEM_ERANGE;
+            kd[u][q] = (int)lut[in[u][q] ? k[u][q] : 0] - ka;
+          }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            // a dropped bin (-1), or a pixel of another chunk or pass, is not counted here
+            if (!(ok[u][q] && in[u][q] && (uint32_t)kd[u][q] < (uint32_t)kn)) continue;
+            const int f = (int)((fr4[u] >> (8 * q)) & 0xffu);
+            const int shift = wide ? 16 * (f & 1) : 8 * (f & 3);
+            const int col = wide ? (f >> 1) : (f >> 2);
+            atomicAdd(&s_hist[kd[u][q] * wps + col], 1u << shift);
+          }
+      }
     }
     __syncthreads();
     // one counter word per thread and step: fpw consecutive frames of one pixel row
+    const int fpw = wide ? 2 : 4;
     for (int i = t; i < kn * wpr; i += kBinThreads) {
       const int kd = i / wpr, q = i % wpr;
       const int f0 = q * fpw;
@@ -314,21 +438,19 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(const int32_t* __restrict__
 }
 
 int launch_bin(const int32_t* idx, const int64_t* off, int64_t frame0, int64_t n_frames,
-               const stem_det& det, const RowRun* rows, int n_k, int64_t F, void* D, int d_bits,
+               const stem_det& det, const int16_t* lut, int n_k, int64_t F, void* D, int d_bits,
                int32_t* status, hipStream_t stream) {
   if (n_frames == 0) return STEM_OK;
   const int nchunks = (n_k + kBinKd - 1) / kBinKd;
   const int64_t fblocks = (n_frames + kBinFrames - 1) / kBinFrames;
   const dim3 grid((unsigned)(fblocks * nchunks));
-  const Magic mw = make_magic((uint32_t)det.W), mb = make_magic((uint32_t)det.bin);
-  const int nby = det.H / det.bin;
   STEM_TRACE("bin_densify", stream);
   if (d_bits == 8)
-    hipLaunchKernelGGL(k_bin<uint8_t>, grid, dim3(kBinThreads), 0, stream, idx, off, frame0, n_frames, mw,
-                       mb, det.W * det.H, nby, rows, n_k, F, (uint8_t*)D, status);
+    hipLaunchKernelGGL(k_bin<uint8_t>, grid, dim3(kBinThreads), 0, stream, idx, off, frame0, n_frames,
+                       det.W * det.H, lut, n_k, F, (uint8_t*)D, status);
   else
     hipLaunchKernelGGL(k_bin<uint16_t>, grid, dim3(kBinThreads), 0, stream, idx, off, frame0, n_frames,
-                       mw, mb, det.W * det.H, nby, rows, n_k, F, (uint16_t*)D, status);
+                       det.W * det.H, lut, n_k, F, (uint16_t*)D, status);
   STEM_LAUNCH_CHECK();
   return STEM_OK;
 }

@@ -1,10 +1,11 @@
 // Batched row FFTs (power-of-two lengths 32..1024) and the centre-of-mass DPC path
 // (Eq. 4 and the regularised Fourier gradient descent of Sec. V).
 //
-// k_row_fft: a workgroup of 8 waves; each wave transforms B = 1024/N rows at a time with the
-// wavefront FFT of fft_wave.h.  Row-major outputs are stored straight from registers;
-// transposed outputs (element (r, m) -> out[m*stride + r]) are first staged in the waves' LDS
-// buffers so that the workgroup writes runs of 8B consecutive rows per frequency.
+// k_row_fft: a workgroup of W = 8 waves (4 when there are too few rows to give every CU a
+// workgroup); each wave transforms B = 1024/N rows at a time with the wavefront FFT of
+// fft_wave.h.  Row-major outputs are stored straight from registers; transposed outputs
+// (element (r, m) -> out[m*stride + r]) are first staged in the waves' LDS buffers so that the
+// workgroup writes runs of W B consecutive rows per frequency.
 #include "common.h"
 #include "fft_wave.h"
 #include "kernels.h"
@@ -12,15 +13,15 @@
 
 namespace stem {
 
-constexpr int kRowThreads = 512;
 constexpr int kWaveStride = kFftLds + 4;  // float2 per wave buffer; the +4 staggers LDS banks
 
-template <int N, bool INV>
-__global__ void __launch_bounds__(kRowThreads) k_row_fft(RowFftArgs a, int in_mode, int out_mode) {
+template <int N, bool INV, int W>
+__global__ void __launch_bounds__(64 * W) k_row_fft(RowFftArgs a, int in_mode, int out_mode) {
+  constexpr int kRowThreads = 64 * W;
   __shared__ float2 s_tw[1024];
-  __shared__ float2 s_buf[8 * kWaveStride];
+  __shared__ float2 s_buf[W * kWaveStride];
   constexpr int B = 1024 / N;
-  constexpr int TR = 8 * B;  // rows per tile
+  constexpr int TR = W * B;  // rows per tile
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   fill_twiddles(s_tw, threadIdx.x, kRowThreads);
   __syncthreads();
@@ -30,28 +31,52 @@ __global__ void __launch_bounds__(kRowThreads) k_row_fft(RowFftArgs a, int in_mo
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int64_t r0 = tile * TR + wave * B;
     float2 v[16];
+    if (in_mode == IN_C64_SUM) {
+      // partial sums in a fixed order; the 16 loads of one partial are issued together
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      int b, n;
-      fft_in_index<N>(lane, i, b, n);
-      const int64_t r = r0 + b;
-      float2 x = make_float2(0.f, 0.f);
-      if (r < a.nrows) {
-        const int64_t e = r * N + n;
-        if (in_mode == IN_C64) {
-          x = a.in_c[e];
-        } else if (in_mode == IN_C64_SUM) {
-          for (int p = 0; p < a.nparts; ++p) x = cadd(x, a.in_c[p * a.part_stride + e]);
-          if (a.sum_out) a.sum_out[e] = x;
-        } else if (in_mode == IN_F32_PAIR) {
-          x.x = a.in_f0[e] * a.s0;
-          x.y = a.in_f1 ? a.in_f1[e] * a.s1 : 0.f;
-        } else {
-          x.x = (float)(a.in_d0[e] * (double)a.s0);
-          x.y = a.in_d1 ? (float)(a.in_d1[e] * (double)a.s1) : 0.f;
+      for (int i = 0; i < 16; ++i) v[i] = make_float2(0.f, 0.f);
+      for (int p = 0; p < a.nparts; ++p) {
+        const float2* src = a.in_c + (int64_t)p * a.part_stride;
+        float2 t[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          int b, n;
+          fft_in_index<N>(lane, i, b, n);
+          const int64_t r = r0 + b;
+          t[i] = r < a.nrows ? src[r * N + n] : make_float2(0.f, 0.f);
         }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) v[i] = cadd(v[i], t[i]);
       }
-      v[i] = INV ? cconj(x) : x;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        int b, n;
+        fft_in_index<N>(lane, i, b, n);
+        const int64_t r = r0 + b;
+        if (a.sum_out && r < a.nrows) a.sum_out[r * N + n] = v[i];
+        if (INV) v[i] = cconj(v[i]);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        int b, n;
+        fft_in_index<N>(lane, i, b, n);
+        const int64_t r = r0 + b;
+        float2 x = make_float2(0.f, 0.f);
+        if (r < a.nrows) {
+          const int64_t e = r * N + n;
+          if (in_mode == IN_C64) {
+            x = a.in_c[e];
+          } else if (in_mode == IN_F32_PAIR) {
+            x.x = a.in_f0[e] * a.s0;
+            x.y = a.in_f1 ? a.in_f1[e] * a.s1 : 0.f;
+          } else {
+            x.x = (float)(a.in_d0[e] * (double)a.s0);
+            x.y = a.in_d1 ? (float)(a.in_d1[e] * (double)a.s1) : 0.f;
+          }
+        }
+        v[i] = INV ? cconj(x) : x;
+      }
     }
     wave_fft<N>(v, buf, s_tw, lane);
 #pragma unroll
@@ -94,27 +119,36 @@ __global__ void __launch_bounds__(kRowThreads) k_row_fft(RowFftArgs a, int in_mo
   }
 }
 
-template <int N>
-static void launch_n(bool inv, dim3 grid, const RowFftArgs& a, int in, int out, hipStream_t s) {
+template <int N, int W>
+static void launch_nw(bool inv, const RowFftArgs& a, int in, int out, hipStream_t s) {
+  const int64_t tr = W * (1024 / N);
+  const int64_t tiles = (a.nrows + tr - 1) / tr;
+  const dim3 grid((unsigned)(tiles < 2048 ? tiles : 2048));
   if (inv)
-    hipLaunchKernelGGL((k_row_fft<N, true>), grid, dim3(kRowThreads), 0, s, a, in, out);
+    hipLaunchKernelGGL((k_row_fft<N, true, W>), grid, dim3(64 * W), 0, s, a, in, out);
   else
-    hipLaunchKernelGGL((k_row_fft<N, false>), grid, dim3(kRowThreads), 0, s, a, in, out);
+    hipLaunchKernelGGL((k_row_fft<N, false, W>), grid, dim3(64 * W), 0, s, a, in, out);
+}
+
+template <int N>
+static void launch_n(bool inv, const RowFftArgs& a, int in, int out, hipStream_t s) {
+  // fewer than two 8-wave tiles per CU: 4-wave workgroups spread the rows over more CUs
+  if (a.nrows < 2 * 256 * 8 * (1024 / N))
+    launch_nw<N, 4>(inv, a, in, out, s);
+  else
+    launch_nw<N, 8>(inv, a, in, out, s);
 }
 
 int launch_row_fft(int n, bool inverse, RowIn in, RowOut out, const RowFftArgs& a, hipStream_t stream) {
   if (a.nrows <= 0) return STEM_OK;
-  const int64_t tr = 8 * (1024 / n);
-  int64_t tiles = (a.nrows + tr - 1) / tr;
-  const dim3 grid((unsigned)(tiles < 2048 ? tiles : 2048));
   STEM_TRACE(a.tag ? a.tag : "row_fft", stream);
   switch (n) {
-    case 32: launch_n<32>(inverse, grid, a, in, out, stream); break;
-    case 64: launch_n<64>(inverse, grid, a, in, out, stream); break;
-    case 128: launch_n<128>(inverse, grid, a, in, out, stream); break;
-    case 256: launch_n<256>(inverse, grid, a, in, out, stream); break;
-    case 512: launch_n<512>(inverse, grid, a, in, out, stream); break;
-    case 1024: launch_n<1024>(inverse, grid, a, in, out, stream); break;
+    case 32: launch_n<32>(inverse, a, in, out, stream); break;
+    case 64: launch_n<64>(inverse, a, in, out, stream); break;
+    case 128: launch_n<128>(inverse, a, in, out, stream); break;
+    case 256: launch_n<256>(inverse, a, in, out, stream); break;
+    case 512: launch_n<512>(inverse, a, in, out, stream); break;
+    case 1024: launch_n<1024>(inverse, a, in, out, stream); break;
     default: return STEM_EINVAL;
   }
   STEM_LAUNCH_CHECK();
@@ -150,14 +184,15 @@ __global__ void __launch_bounds__(256) k_dpc_update(const float2* __restrict__ C
                     !((nx % 2 == 0) && mx == nx / 2);
   double pr = 0.0, pi = 0.0;
   if (live) {
+    const double md = mu / d;  // the step size over the regularised denominator, fixed per frequency
     for (int l = 0; l < n_iter; ++l) {
       // residuals G - D Phi with D = i q:  i q (pr + i pi) = -q pi + i q pr
       const double rxr = gxr + qx * pi, rxi = gxi - qx * pr;
       const double ryr = gyr + qy * pi, ryi = gyi - qy * pr;
       // conj(D) r = -i q r = q ri - i q rr
       const double ur = qx * rxi + qy * ryi, ui = -(qx * rxr + qy * ryr);
-      pr += mu * ur / d;
-      pi += mu * ui / d;
+      pr += md * ur;
+      pi += md * ui;
     }
   }
   Phi[e] = make_float2((float)pr, (float)pi);

@@ -22,7 +22,7 @@ constexpr int kMaxPixels = 4096;
 struct SsbLayout {
   int n_k, nby, nh;
   int64_t F;
-  size_t rows, kc, kchi, stats, D, X, T, A, Tb, pdc, pdth, part, total;
+  size_t rows, kc, kchi, cst, lut, stats, D, X, T, A, Tb, pdc, pdth, part, total;
   int groups;  // pixel groups of the fused column transform + sum
   int ncs;     // column sets (B = 1024/Ny half-spectrum columns each)
   int64_t nwy; // waves of the fused kernels
@@ -65,6 +65,8 @@ static size_t make_layout(const stem_det& det, const stem_scan& scan, const stem
   L->rows = o;  o = align256(o + sizeof(RowRun) * L->nby);
   L->kc = o;    o = align256(o + sizeof(double2) * n_k);
   L->kchi = o;  o = align256(o + sizeof(double) * n_k);
+  L->cst = o;   o = align256(o + sizeof(int4) * n_k * L->nh);
+  L->lut = o;   o = align256(o + sizeof(int16_t) * (size_t)det.W * det.H);
   L->stats = o; o = align256(o + sizeof(unsigned long long) * 4);
   L->D = o;     o = align256(o + (size_t)n_k * L->F * (ssb.d_bits / 8));
   L->X = o;     o = align256(o + (size_t)n_k * L->nh * scan.ny * sizeof(float2));
@@ -97,27 +99,60 @@ static int launch_xstage_t(int prec, int nx, const DT* D, int ny, int ry0, int n
   }
 }
 
-static int launch_yreduce(int prec, int ny, float2* X, const double2* kc, const double* kchi, int n_k, int nx,
-                          int ngroups, const Optics& o, int store_g, float2* part, unsigned long long* stats,
-                          hipStream_t s) {
+// double-overlap intervals of every (pixel, half-spectrum column) and of its mirror
+__global__ void __launch_bounds__(256) k_colsets(const double2* __restrict__ kc, int n_k, int nx, int ny, Optics o,
+                                                 int4* __restrict__ cst) {
+  const int nc = nx / 2 + 1;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n_k * nc) return;
+  const int kd = (int)(t / nc), c = (int)(t % nc);
+  const double2 k = kc[kd];
+  const ColSet d = col_set(k.x, k.y, signed_index(c, nx), ny, o);
+  ColSet m{1, 0, 1, 0};
+  if (c > 0 && 2 * c < nx) m = col_set(k.x, k.y, signed_index(nx - c, nx), ny, o);
+  auto pk = [](int lo, int hi) { return (int)(((uint32_t)lo & 0xffffu) | ((uint32_t)hi << 16)); };
+  cst[t] = make_int4(pk(d.a0, d.a1), pk(d.b0, d.b1), pk(m.a0, m.a1), pk(m.b0, m.b1));
+}
+
+// the interval table, then the fused column sum
+static int launch_yreduce(int prec, int ny, float2* X, const double2* kc, const double* kchi, int4* cst, int n_k,
+                          int nx, int ngroups, const Optics& o, int store_g, float2* part,
+                          unsigned long long* stats, hipStream_t s) {
+  {
+    STEM_TRACE("ssb_colsets", s);
+    const int64_t n = (int64_t)n_k * (nx / 2 + 1);
+    hipLaunchKernelGGL(k_colsets, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, kc, n_k, nx, ny, o, cst);
+    STEM_LAUNCH_CHECK();
+  }
   switch (prec) {
     case STEM_DFT_BF16_SPLIT:
-      return launch_yreduce_p<STEM_DFT_BF16_SPLIT>(ny, X, kc, kchi, n_k, nx, ngroups, o, store_g, part, stats, s);
+      return launch_yreduce_p<STEM_DFT_BF16_SPLIT>(ny, X, kc, kchi, cst, n_k, nx, ngroups, o, store_g, part, stats, s);
     case STEM_DFT_FP16_SPLIT:
-      return launch_yreduce_p<STEM_DFT_FP16_SPLIT>(ny, X, kc, kchi, n_k, nx, ngroups, o, store_g, part, stats, s);
-    default: return launch_yreduce_p<STEM_FFT_FP32>(ny, X, kc, kchi, n_k, nx, ngroups, o, store_g, part, stats, s);
+      return launch_yreduce_p<STEM_DFT_FP16_SPLIT>(ny, X, kc, kchi, cst, n_k, nx, ngroups, o, store_g, part, stats, s);
+    default:
+      return launch_yreduce_p<STEM_FFT_FP32>(ny, X, kc, kchi, cst, n_k, nx, ngroups, o, store_g, part, stats, s);
   }
 }
 
-static int launch_yadjoint(int prec, int ny, const float2* X, const double2* kc, const double* kchi, int n_k,
-                           int nx, int ngroups, const Optics& o, int g_stored, const float2* Tbt, double* pdc,
-                           float* pdth, hipStream_t s) {
+static int launch_yadjoint(int prec, int ny, const float2* X, const double2* kc, const double* kchi, int4* cst,
+                           int n_k, int nx, int ngroups, const Optics& o, int g_stored, const float2* Tbt,
+                           double* pdc, float* pdth, hipStream_t s) {
+  {
+    STEM_TRACE("ssb_colsets", s);
+    const int64_t n = (int64_t)n_k * (nx / 2 + 1);
+    hipLaunchKernelGGL(k_colsets, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, kc, n_k, nx, ny, o, cst);
+    STEM_LAUNCH_CHECK();
+  }
   switch (prec) {
     case STEM_DFT_BF16_SPLIT:
-      return launch_yadjoint_p<STEM_DFT_BF16_SPLIT>(ny, X, kc, kchi, n_k, nx, ngroups, o, g_stored, Tbt, pdc, pdth, s);
+      return launch_yadjoint_p<STEM_DFT_BF16_SPLIT>(ny, X, kc, kchi, cst, n_k, nx, ngroups, o, g_stored, Tbt, pdc,
+                                                    pdth, s);
     case STEM_DFT_FP16_SPLIT:
-      return launch_yadjoint_p<STEM_DFT_FP16_SPLIT>(ny, X, kc, kchi, n_k, nx, ngroups, o, g_stored, Tbt, pdc, pdth, s);
-    default: return launch_yadjoint_p<STEM_FFT_FP32>(ny, X, kc, kchi, n_k, nx, ngroups, o, g_stored, Tbt, pdc, pdth, s);
+      return launch_yadjoint_p<STEM_DFT_FP16_SPLIT>(ny, X, kc, kchi, cst, n_k, nx, ngroups, o, g_stored, Tbt, pdc,
+                                                    pdth, s);
+    default:
+      return launch_yadjoint_p<STEM_FFT_FP32>(ny, X, kc, kchi, cst, n_k, nx, ngroups, o, g_stored, Tbt, pdc, pdth,
+                                              s);
   }
 }
 
@@ -265,6 +300,8 @@ struct Bufs {
   RowRun* rows;
   double2* kc;
   double* kchi;
+  int4* cst;
+  int16_t* lut;
   unsigned long long* stats;
   void* D;
   float2* X;
@@ -278,7 +315,8 @@ struct Bufs {
 
 static Bufs carve(void* state, const SsbLayout& L) {
   char* p = (char*)state;
-  return Bufs{(RowRun*)(p + L.rows), (double2*)(p + L.kc), (double*)(p + L.kchi),
+  return Bufs{(RowRun*)(p + L.rows), (double2*)(p + L.kc), (double*)(p + L.kchi), (int4*)(p + L.cst),
+              (int16_t*)(p + L.lut),
               (unsigned long long*)(p + L.stats), (void*)(p + L.D),
               (float2*)(p + L.X),    (float2*)(p + L.T),  (float2*)(p + L.A),     (float2*)(p + L.Tb),
               (double*)(p + L.pdc),  (float*)(p + L.pdth), (float2*)(p + L.part)};
@@ -416,8 +454,8 @@ extern "C" int ssb_reconstruct(const int32_t* d_idx, const int64_t* d_off, int64
     if (!d_idx || !d_off) return STEM_EINVAL;
     if (frame0 < 0 || n_frames <= 0 || frame0 % nx || n_frames % nx || frame0 + n_frames > L.F)
       return STEM_EINVAL;
-    if ((st = launch_geometry(*det, o.r2, b.rows, b.kc, s))) return st;
-    if ((st = launch_bin(d_idx, d_off, frame0, n_frames, *det, b.rows, n_k, L.F, b.D, ssb->d_bits, d_status, s)))
+    if ((st = launch_geometry(*det, o.r2, b.rows, b.kc, b.lut, s))) return st;
+    if ((st = launch_bin(d_idx, d_off, frame0, n_frames, *det, b.lut, n_k, L.F, b.D, ssb->d_bits, d_status, s)))
       return st;
     const int ry0 = (int)(frame0 / nx), nr = (int)(n_frames / nx);
     const int64_t nrows = (int64_t)n_k * nr;
@@ -438,7 +476,7 @@ extern "C" int ssb_reconstruct(const int32_t* d_idx, const int64_t* d_off, int64
   if (ssb->normalize && ssb->precision != STEM_FFT_FP32) {
     // split precision: the fused kernel transforms X -> G in place (its partial sums are not
     // used); the counters are reset before the per-Q normalised sum
-    if ((st = launch_yreduce(ssb->precision, ny, b.X, b.kc, b.kchi, n_k, nx, L.groups, o, 1, b.part, b.stats, s)))
+    if ((st = launch_yreduce(ssb->precision, ny, b.X, b.kc, b.kchi, b.cst, n_k, nx, L.groups, o, 1, b.part, b.stats, s)))
       return st;
     if ((st = run_chi_table(b, d_theta, n_k, o, 1, s))) return st;
     if ((st = run_reduce_stored(L, b, ny, nx, o, 1, s))) return st;
@@ -457,7 +495,7 @@ extern "C" int ssb_reconstruct(const int32_t* d_idx, const int64_t* d_off, int64
     if ((st = run_reduce_stored(L, b, ny, nx, o, 1, s))) return st;
     return run_phase(L, b, *scan, b.T, 1, d_phase, d_T, s);
   }
-  if ((st = launch_yreduce(ssb->precision, ny, b.X, b.kc, b.kchi, n_k, nx, L.groups, o, ssb->g_mode == STEM_G_STORE,
+  if ((st = launch_yreduce(ssb->precision, ny, b.X, b.kc, b.kchi, b.cst, n_k, nx, L.groups, o, ssb->g_mode == STEM_G_STORE,
                            b.part, b.stats, s)))
     return st;
   return run_phase(L, b, *scan, b.part, L.groups, d_phase, d_T, s);
@@ -497,7 +535,7 @@ extern "C" int ssb_backward(const float* d_dLdphi, const stem_det* det, const st
   a.tag = "adj_fft";
   if ((st = launch_row_fft(ny, false, IN_C64, OUT_ROW_C64, a, s))) return st;
   if ((st = run_chi_table(b, d_theta, n_k, o, L.groups, s))) return st;
-  if ((st = launch_yadjoint(ssb->precision, ny, b.X, b.kc, b.kchi, n_k, nx, L.groups, o, ssb->g_mode == STEM_G_STORE,
+  if ((st = launch_yadjoint(ssb->precision, ny, b.X, b.kc, b.kchi, b.cst, n_k, nx, L.groups, o, ssb->g_mode == STEM_G_STORE,
                             b.Tb, b.pdc, b.pdth, s)))
     return st;
   {

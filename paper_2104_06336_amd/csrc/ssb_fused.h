@@ -14,7 +14,6 @@
 
 namespace stem {
 
-constexpr int kXThreads = 512;
 constexpr int kXWaveStride = kFftLds + 4;
 constexpr int kYThreads = 256;
 
@@ -33,6 +32,10 @@ struct XfFft {
   static constexpr bool kUniformCol = NB >= kWave;
   static constexpr int slot_of(int i) { return kUniformCol ? (kWave * (i / RL)) / NB : i / RL; }
   static constexpr int kSlots = slot_of(15) + 1;
+  // x-stage workgroup: 8 waves, each with an LDS buffer for the FFT exchanges
+  static constexpr int kXWaves = 8;
+  static constexpr int kXStride = kXWaveStride;
+  static __device__ __forceinline__ int pad(int i) { return fft_pad(i); }
   static __device__ __forceinline__ void in(int lane, int i, int& b, int& n) { fft_in_index<N>(lane, i, b, n); }
   static __device__ __forceinline__ void out(int lane, int i, int& b, int& m) { fft_out_index<N>(lane, i, b, m); }
   static __device__ __forceinline__ void fill(uint4*, const float2*, int, int) {}
@@ -48,6 +51,12 @@ struct XfMfma {
   static constexpr bool kMfma = true;
   static constexpr int slot_of(int) { return 0; }  // all 16 registers of a lane share its column
   static constexpr int kSlots = 1;
+  // x-stage workgroup: 16 waves (one workgroup per CU holds the operand tables once); the
+  // staging buffer pads one element per 32, so that a lane's outputs (32 apart) hit distinct
+  // banks, and the wave stride (8 mod 32 elements) spreads the waves' rows over the banks
+  static constexpr int kXWaves = 16;
+  static constexpr int kXStride = 1064;
+  static __device__ __forceinline__ int pad(int i) { return i + (i >> 5); }
   static __device__ __forceinline__ void in(int lane, int i, int& b, int& n) { MfmaIndex<N>::in(lane, i, b, n); }
   static __device__ __forceinline__ void out(int lane, int i, int& b, int& m) { MfmaIndex<N>::out(lane, i, b, m); }
   static __device__ __forceinline__ void fill(uint4* tab, const float2* tw, int tid, int nthreads) {
@@ -84,30 +93,31 @@ static int with_n(int n, F&& f) {
 }
 
 // ---------------------------------------------------------------------------------------------
-// x-stage: rows (kd, ry) with ry in [ry0, ry0 + nr) of D, two real rows per complex FFT.
-// Tile = 16B real rows (B = 1024/N); each of the 8 waves transforms B row pairs; the
-// workgroup then splits the pairs and writes X[kd][m][ry] for m in [0, N/2] in runs of
-// consecutive ry.
+// x-stage: rows (kd, ry) with ry in [ry0, ry0 + nr) of D, two real rows per complex transform.
+// Tile = 2 W B real rows (B = 1024/N, W waves per workgroup); each wave transforms B row
+// pairs; the workgroup then splits the pairs and writes X[kd][m][ry] for m in [0, N/2] in runs
+// of consecutive ry.
 
 template <typename XF, typename DT>
-__global__ void __launch_bounds__(kXThreads) k_xstage(const DT* __restrict__ D, int ny, int ry0, int nr,
+__global__ void __launch_bounds__(64 * XF::kXWaves) k_xstage(const DT* __restrict__ D, int ny, int ry0, int nr,
                                                       int64_t nrows, int pair_store, float2* __restrict__ X) {
   constexpr int N = XF::N;
   // counts below 256 are exact in the split formats and need no low part
   constexpr bool kExact = std::is_same<DT, uint8_t>::value;
   __shared__ float2 s_tw[1024];
-  __shared__ float2 s_buf[8 * kXWaveStride];
+  constexpr int kThreads = 64 * XF::kXWaves;
+  __shared__ float2 s_buf[XF::kXWaves * XF::kXStride];
   __shared__ uint4 s_tab[XF::kMfma ? kMfmaTab : 1];
   constexpr int B = 1024 / N;
-  constexpr int TR = 16 * B;  // real rows per tile
+  constexpr int TR = 2 * XF::kXWaves * B;  // real rows per tile
   constexpr int NH = N / 2 + 1;
   constexpr int ROWB = N * (int)sizeof(DT);  // bytes per row of D
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  fill_twiddles(s_tw, threadIdx.x, kXThreads);
+  fill_twiddles(s_tw, threadIdx.x, kThreads);
   __syncthreads();
-  XF::fill(s_tab, s_tw, threadIdx.x, kXThreads);
+  XF::fill(s_tab, s_tw, threadIdx.x, kThreads);
   if (XF::kMfma) __syncthreads();
-  float2* buf = s_buf + wave * kXWaveStride;
+  float2* buf = s_buf + wave * XF::kXStride;
   const int64_t ntiles = (nrows + TR - 1) / TR;
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int64_t r0 = tile * TR + wave * 2 * B;  // first real row of this wave
@@ -144,17 +154,17 @@ __global__ void __launch_bounds__(kXThreads) k_xstage(const DT* __restrict__ D, 
     for (int i = 0; i < 16; ++i) {
       int b, m;
       XF::out(lane, i, b, m);
-      buf[fft_pad(b * N + m)] = v[i];
+      buf[XF::pad(b * N + m)] = v[i];
     }
     __syncthreads();
     // split each complex transform z = a + i b of rows (2p, 2p+1) into the two half spectra
     // A(m) = (z(m) + conj z(-m))/2, B(m) = (z(m) - conj z(-m))/(2i); write them at adjacent ry
-    for (int u = threadIdx.x; u < NH * (TR / 2); u += kXThreads) {
+    for (int u = threadIdx.x; u < NH * (TR / 2); u += kThreads) {
       const int m = u / (TR / 2), pr = u % (TR / 2);
       const int w = pr / B, b = pr % B;
-      const float2* wb = s_buf + w * kXWaveStride;
-      const float2 z = wb[fft_pad(b * N + m)];
-      const float2 zc = cconj(wb[fft_pad(b * N + ((N - m) & (N - 1)))]);
+      const float2* wb = s_buf + w * XF::kXStride;
+      const float2 z = wb[XF::pad(b * N + m)];
+      const float2 zc = cconj(wb[XF::pad(b * N + ((N - m) & (N - 1)))]);
       const float2 va = cscale(cadd(z, zc), 0.5f);
       const float2 vb = cscale(cmul_mi(csub(z, zc)), 0.5f);
       const int64_t rho = tile * TR + 2 * pr;
@@ -208,9 +218,19 @@ __device__ __forceinline__ ColSet col_set(double kx, double ky, int ix, int ny, 
   return cs;
 }
 
+// The sets of one pixel for a half-spectrum column c (direct) and for -c (mirror) depend only on
+// the geometry; they are tabulated once per reconstruction (k_colsets), 16 bytes per (pixel,
+// column): (a0, a1, b0, b1) direct and mirrored as int16 (|iy| <= 512).
+__device__ __forceinline__ void load_colsets(const int4* __restrict__ cst, int64_t i, ColSet& d, ColSet& m) {
+  const int4 r = cst[i];
+  d = ColSet{(int)(short)(r.x & 0xffff), r.x >> 16, (int)(short)(r.y & 0xffff), r.y >> 16};
+  m = ColSet{(int)(short)(r.z & 0xffff), r.z >> 16, (int)(short)(r.w & 0xffff), r.w >> 16};
+}
+
 template <typename XF>
-__global__ void __launch_bounds__(kYThreads) k_yreduce(float2* __restrict__ X, const double2* __restrict__ kc,
-                                                       const double* __restrict__ kchi, int n_k, int nx,
+__global__ void __launch_bounds__(kYThreads, 2) k_yreduce(float2* __restrict__ X, const double2* __restrict__ kc,
+                                                       const double* __restrict__ kchi,
+                                                       const int4* __restrict__ cst, int n_k, int nx,
                                                        int ngroups, Optics o, int store_g,
                                                        float2* __restrict__ part,
                                                        unsigned long long* __restrict__ stats) {
@@ -248,14 +268,10 @@ __global__ void __launch_bounds__(kYThreads) k_yreduce(float2* __restrict__ X, c
     for (int sl = 0; sl < SL::kSlots; ++sl) {
       int b0, m0;
       XF::out(lane, sl * kSlotStride, b0, m0);
-      int c = c0 + b0;
-      asm volatile("" : "+v"(c));
+      const int c = c0 + b0;
       sd[sl] = ColSet{1, 0, 1, 0};
       sm[sl] = ColSet{1, 0, 1, 0};
-      if (c < nc) {
-        sd[sl] = col_set(k.x, k.y, signed_index(c, nx), NY, o);
-        if (c > 0 && 2 * c < nx) sm[sl] = col_set(k.x, k.y, signed_index(nx - c, nx), NY, o);
-      }
+      if (c < nc) load_colsets(cst, (int64_t)kd * nc + c, sd[sl], sm[sl]);
       any = any || !sd[sl].empty() || !sm[sl].empty();
     }
     // with store_g every pixel is transformed, so that the stored G is complete
@@ -333,8 +349,9 @@ __global__ void __launch_bounds__(kYThreads) k_yreduce(float2* __restrict__ X, c
 // w = Re(conj(Tbar(Q)) i z); dL/dc_j gains w (B_j(K - Q) - B_j(K)) and dL/dtheta[kd] loses w.
 // Partials: pdc[wave][8] (FP64), pdth[column set][kd] (FP32; one writer per entry).
 template <typename XF>
-__global__ void __launch_bounds__(kYThreads) k_yadjoint(const float2* __restrict__ X, const double2* __restrict__ kc,
-                                                        const double* __restrict__ kchi, int n_k, int nx,
+__global__ void __launch_bounds__(kYThreads, 2) k_yadjoint(const float2* __restrict__ X, const double2* __restrict__ kc,
+                                                        const double* __restrict__ kchi,
+                                                        const int4* __restrict__ cst, int n_k, int nx,
                                                         int ngroups, Optics o, int g_stored,
                                                         const float2* __restrict__ Tbt, double* __restrict__ pdc,
                                                         float* __restrict__ pdth) {
@@ -360,10 +377,7 @@ __global__ void __launch_bounds__(kYThreads) k_yadjoint(const float2* __restrict
   float2* buf = s_buf + wave * kXWaveStride;
   const int c0 = cs * B;
   const int kd_a = (int)((int64_t)n_k * g / ngroups), kd_b = (int)((int64_t)n_k * (g + 1) / ngroups);
-  const int ct = c0 + lane % B;
-  const bool ct_ok = ct < nc;
-  const double ctx = (double)signed_index(ct, nx) * o.sx;
-  const bool ct_m = ct_ok && ct > 0 && 2 * ct < nx;
+  constexpr int kSlotStride = 16 / XF::kSlots;
   float2 tbd[16], tbm[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
@@ -380,8 +394,19 @@ __global__ void __launch_bounds__(kYThreads) k_yadjoint(const float2* __restrict
   const int64_t kstride = (int64_t)nc * NY;
   for (int kd = kd_a; kd < kd_b; ++kd) {
     const double2 k = kc[kd];
-    const bool near = ct_ok && (fabs(k.x - ctx) < o.r || (ct_m && fabs(k.x + ctx) < o.r));
-    if (!__ballot(near)) {
+    ColSet sd[XF::kSlots], sm[XF::kSlots];
+    bool any = false;
+#pragma unroll
+    for (int sl = 0; sl < XF::kSlots; ++sl) {
+      int b0, m0;
+      XF::out(lane, sl * kSlotStride, b0, m0);
+      const int c = c0 + b0;
+      sd[sl] = ColSet{1, 0, 1, 0};
+      sm[sl] = ColSet{1, 0, 1, 0};
+      if (c < nc) load_colsets(cst, (int64_t)kd * nc + c, sd[sl], sm[sl]);
+      any = any || !sd[sl].empty() || !sm[sl].empty();
+    }
+    if (!__ballot(any)) {
       if (lane == 0) pdth[(int64_t)cs * n_k + kd] = 0.f;
       continue;
     }
@@ -404,7 +429,6 @@ __global__ void __launch_bounds__(kYThreads) k_yadjoint(const float2* __restrict
       XF::template run<false>(v, buf, s_tw, s_tab, lane);
     }
     const double kch = kchi[kd];
-    const float kxf = (float)k.x, kyf = (float)k.y;
     double bk[8];
     chi_basis(k.x, k.y, o, bk);
     float wsum = 0.f;
@@ -415,17 +439,18 @@ __global__ void __launch_bounds__(kYThreads) k_yadjoint(const float2* __restrict
       int c = c0 + b;
       asm volatile("" : "+v"(c), "+v"(m));  // see k_yreduce
       if (c >= nc) continue;
+      const int sl = XF::slot_of(i);
       for (int side = 0; side < 2; ++side) {
         int ix, iy;
         if (side == 0) {
           ix = signed_index(c, nx);
           iy = signed_index(m, NY);
+          if (!sd[sl].has(iy)) continue;
         } else {
-          if (!(c > 0 && 2 * c < nx)) break;
           ix = signed_index(nx - c, nx);
           iy = signed_index((NY - m) & (NY - 1), NY);
+          if (!sm[sl].has(iy)) continue;  // empty unless 0 < c < Nx/2
         }
-        if (!overlap_screened(k.x, k.y, kxf, kyf, ix, iy, o)) continue;
         const double qx = (double)ix * o.sx, qy = (double)iy * o.sy;
         double bm[8];
         chi_basis(k.x - qx, k.y - qy, o, bm);
@@ -458,15 +483,15 @@ __global__ void __launch_bounds__(kYThreads) k_yadjoint(const float2* __restrict
 
 template <int PREC, typename DT>
 int launch_xstage_p(int nx, const DT* D, int ny, int ry0, int nr, int64_t nrows, float2* X, hipStream_t s) {
-  const int64_t tr = 16 * (1024 / nx);
   // rows 2p, 2p+1 of a tile share a pixel and sit at adjacent, 16-byte aligned ry when the
   // chunk starts on an even row and holds an even number of rows per pixel
   const int pair_store = (nr % 2 == 0) && (ry0 % 2 == 0);
-  const int64_t tiles = (nrows + tr - 1) / tr;
-  const dim3 grid((unsigned)(tiles < 4096 ? tiles : 4096)), blk(kXThreads);
   STEM_TRACE(PREC == STEM_FFT_FP32 ? "xstage_fft" : "xstage_mfma", s);
   const int st = with_n(nx, [&](auto nc) {
     using XF = typename XfSel<decltype(nc)::value, PREC>::type;
+    const int64_t tr = 2 * XF::kXWaves * (1024 / nx);
+    const int64_t tiles = (nrows + tr - 1) / tr;
+    const dim3 grid((unsigned)(tiles < 4096 ? tiles : 4096)), blk(64 * XF::kXWaves);
     hipLaunchKernelGGL((k_xstage<XF, DT>), grid, blk, 0, s, D, ny, ry0, nr, nrows, pair_store, X);
   });
   if (st) return st;
@@ -475,7 +500,8 @@ int launch_xstage_p(int nx, const DT* D, int ny, int ry0, int nr, int64_t nrows,
 }
 
 template <int PREC>
-int launch_yreduce_p(int ny, float2* X, const double2* kc, const double* kchi, int n_k, int nx, int ngroups, const Optics& o,
+int launch_yreduce_p(int ny, float2* X, const double2* kc, const double* kchi, const int4* cst, int n_k, int nx,
+                     int ngroups, const Optics& o,
                      int store_g, float2* part, unsigned long long* stats, hipStream_t s) {
   const int B = 1024 / ny;
   const int ncs = (nx / 2 + 1 + B - 1) / B;
@@ -483,7 +509,8 @@ int launch_yreduce_p(int ny, float2* X, const double2* kc, const double* kchi, i
   STEM_TRACE(PREC == STEM_FFT_FP32 ? "ssb_yreduce" : "ssb_yreduce_mfma", s);
   const int st = with_n(ny, [&](auto nc) {
     using XF = typename XfSel<decltype(nc)::value, PREC>::type;
-    hipLaunchKernelGGL((k_yreduce<XF>), grid, blk, 0, s, X, kc, kchi, n_k, nx, ngroups, o, store_g, part, stats);
+    hipLaunchKernelGGL((k_yreduce<XF>), grid, blk, 0, s, X, kc, kchi, cst, n_k, nx, ngroups, o, store_g, part,
+                       stats);
   });
   if (st) return st;
   STEM_LAUNCH_CHECK();
@@ -491,7 +518,8 @@ int launch_yreduce_p(int ny, float2* X, const double2* kc, const double* kchi, i
 }
 
 template <int PREC>
-int launch_yadjoint_p(int ny, const float2* X, const double2* kc, const double* kchi, int n_k, int nx, int ngroups,
+int launch_yadjoint_p(int ny, const float2* X, const double2* kc, const double* kchi, const int4* cst, int n_k,
+                      int nx, int ngroups,
                       const Optics& o, int g_stored, const float2* Tbt, double* pdc, float* pdth, hipStream_t s) {
   const int B = 1024 / ny;
   const int ncs = (nx / 2 + 1 + B - 1) / B;
@@ -499,8 +527,8 @@ int launch_yadjoint_p(int ny, const float2* X, const double2* kc, const double* 
   STEM_TRACE(PREC == STEM_FFT_FP32 ? "ssb_yadjoint" : "ssb_yadjoint_mfma", s);
   const int st = with_n(ny, [&](auto nc) {
     using XF = typename XfSel<decltype(nc)::value, PREC>::type;
-    hipLaunchKernelGGL((k_yadjoint<XF>), grid, blk, 0, s, X, kc, kchi, n_k, nx, ngroups, o, g_stored, Tbt, pdc,
-                       pdth);
+    hipLaunchKernelGGL((k_yadjoint<XF>), grid, blk, 0, s, X, kc, kchi, cst, n_k, nx, ngroups, o, g_stored, Tbt,
+                       pdc, pdth);
   });
   if (st) return st;
   STEM_LAUNCH_CHECK();
@@ -509,15 +537,15 @@ int launch_yadjoint_p(int ny, const float2* X, const double2* kc, const double* 
 
 extern template int launch_xstage_p<STEM_DFT_BF16_SPLIT, uint8_t>(int, const uint8_t*, int, int, int, int64_t, float2*, hipStream_t);
 extern template int launch_xstage_p<STEM_DFT_BF16_SPLIT, uint16_t>(int, const uint16_t*, int, int, int, int64_t, float2*, hipStream_t);
-extern template int launch_yreduce_p<STEM_DFT_BF16_SPLIT>(int, float2*, const double2*, const double*, int, int, int,
+extern template int launch_yreduce_p<STEM_DFT_BF16_SPLIT>(int, float2*, const double2*, const double*, const int4*, int, int, int,
                                             const Optics&, int, float2*, unsigned long long*, hipStream_t);
-extern template int launch_yadjoint_p<STEM_DFT_BF16_SPLIT>(int, const float2*, const double2*, const double*, int, int, int,
+extern template int launch_yadjoint_p<STEM_DFT_BF16_SPLIT>(int, const float2*, const double2*, const double*, const int4*, int, int, int,
                                              const Optics&, int, const float2*, double*, float*, hipStream_t);
 extern template int launch_xstage_p<STEM_DFT_FP16_SPLIT, uint8_t>(int, const uint8_t*, int, int, int, int64_t, float2*, hipStream_t);
 extern template int launch_xstage_p<STEM_DFT_FP16_SPLIT, uint16_t>(int, const uint16_t*, int, int, int, int64_t, float2*, hipStream_t);
-extern template int launch_yreduce_p<STEM_DFT_FP16_SPLIT>(int, float2*, const double2*, const double*, int, int, int,
+extern template int launch_yreduce_p<STEM_DFT_FP16_SPLIT>(int, float2*, const double2*, const double*, const int4*, int, int, int,
                                             const Optics&, int, float2*, unsigned long long*, hipStream_t);
-extern template int launch_yadjoint_p<STEM_DFT_FP16_SPLIT>(int, const float2*, const double2*, const double*, int, int, int,
+extern template int launch_yadjoint_p<STEM_DFT_FP16_SPLIT>(int, const float2*, const double2*, const double*, const int4*, int, int, int,
                                              const Optics&, int, const float2*, double*, float*, hipStream_t);
 
 }  // namespace stem

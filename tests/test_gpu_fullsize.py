@@ -1,0 +1,253 @@
+"""Parity at the full workload sizes, in the configuration the benchmark times.
+
+scan256      65,536 frames, 576x576 detector binned 4x (707 pixels), 100 e-/frame
+scan1024     1,048,576 frames, binned 8x (176 pixels), 40 e-/frame; also the split precisions
+aberrated512 262,144 frames, binned 6x (314 pixels), 60 e-/frame, true aberrations; adjoint
+
+The FP64 oracle is cheap enough here to compare every output element by element: COM and
+counts and the binned cube bit for bit, G, T, phi and the DPC phase by relative L2 (1e-5
+FP32, 1e-4 split precision), the adjoint against the oracle gradient and central differences.
+"""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2104_06336_amd as stem
+from gen import WORKLOADS, simulate
+from oracle import dpc as odpc
+from oracle import eer as oeer
+from oracle import ssb as ossb
+
+from helpers import gpu_ssb, rel_l2, state_D, state_G_half, structs
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+TOL_SPLIT = 1e-4
+_CACHE = {}
+
+
+def log(msg):
+    print(f"[full] {msg}", flush=True)
+
+
+def case(name):
+    """(wl, device CSR, host CSR, oracle dict) of one workload, generated once per session."""
+    if name in _CACHE:
+        return _CACHE[name]
+    wl = WORKLOADS[name]
+    t0 = time.time()
+    data = simulate(wl, device="cuda")
+    torch.cuda.synchronize()
+    d_idx, d_off = data.idx.contiguous(), data.off.contiguous()
+    idx, off = d_idx.cpu().numpy(), d_off.cpu().numpy()
+    log(f"{name}: {wl.n_frames} frames, {len(idx)} events generated in {time.time() - t0:.1f} s")
+    _CACHE[name] = (wl, d_idx, d_off, idx, off, {})
+    return _CACHE[name]
+
+
+def oracle(name, key):
+    wl, _, _, idx, off, ref = case(name)
+    if key in ref:
+        return ref[key]
+    H, W = wl.det
+    ny, nx = wl.scan
+    t0 = time.time()
+    if key == "com":
+        ref[key] = oeer.com(idx, off, W, H)
+    elif key == "dpc":
+        cx, cy = oracle(name, "com")[:2]
+        ref[key] = odpc.com_dpc(cx.reshape(ny, nx), cy.reshape(ny, nx), wl.dk, wl.step)
+    elif key == "geom":
+        ref[key] = oeer.bin_geometry(W, H, wl.bin, wl.r_bf)
+    elif key == "D":
+        ref[key] = oeer.bin_counts(idx, off, W, wl.bin, oracle(name, "geom")[1])
+    elif key == "G":
+        ref[key] = ossb.scan_dft(ossb.cube(oracle(name, "D"), ny, nx))
+    elif key == "T":
+        kc = oracle(name, "geom")[0]
+        ref[key] = ossb.ssb_sum(oracle(name, "G"), kc, wl.step, wl.dk, wl.lam, wl.r_bf, wl.aberr)
+    elif key == "phi":
+        ref[key] = ossb.phase_from_T(oracle(name, "T")[0])
+    log(f"{name}: oracle {key} in {time.time() - t0:.1f} s")
+    return ref[key]
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    print(f"\n[gpu] {request.node.name}", flush=True)
+
+
+def g_half_error(st, wl, G):
+    """rel L2 of the stored half spectrum against the oracle's, one pixel at a time."""
+    nh = wl.scan[1] // 2 + 1
+    Gg = state_G_half(st, wl)
+    num = den = 0.0
+    for kd in range(G.shape[0]):
+        r = G[kd, :, :nh]
+        num += float(np.sum(np.abs(Gg[kd] - r) ** 2))
+        den += float(np.sum(np.abs(r) ** 2))
+    return np.sqrt(num / den), Gg
+
+
+@pytest.mark.parametrize("name", ["scan256", "scan1024", "aberrated512"])
+def test_full_com_dpc(gpu, name):
+    wl, d_idx, d_off, idx, off, _ = case(name)
+    det, scan, optics = structs(wl)
+    F = wl.n_frames
+    com64 = torch.zeros(2 * F, dtype=torch.float64, device="cuda")
+    com32 = torch.zeros(2 * F, dtype=torch.float32, device="cuda")
+    counts = torch.zeros(F, dtype=torch.int32, device="cuda")
+    phase = torch.zeros(F, dtype=torch.float32, device="cuda")
+    ws = torch.empty(stem.com_dpc_workspace_bytes(scan), dtype=torch.uint8, device="cuda")
+    status = stem.status_tensor()
+    stem.com_dpc(d_idx, d_off, 0, F, det, scan, optics, stem.Dpc(0.5, 0.0, 0.0, 10), com64=com64, com32=com32,
+                 counts=counts, phase=phase, ws=ws, d_status=status)
+    torch.cuda.synchronize()
+    assert int(status.item()) == 0
+    cx, cy, sx, sy, n = oracle(name, "com")
+    c64 = com64.cpu().numpy().reshape(2, F)
+    assert np.array_equal(counts.cpu().numpy(), n)
+    assert np.array_equal(c64[0], cx) and np.array_equal(c64[1], cy)
+    assert np.array_equal(com32.cpu().numpy().reshape(2, F), c64.astype(np.float32))
+    err = rel_l2(phase.cpu().numpy().reshape(wl.scan), oracle(name, "dpc"))
+    log(f"{name}: DPC phase rel L2 {err:.2e}")
+    assert err <= TOL
+
+
+@pytest.mark.parametrize("name", ["scan256", "scan1024", "aberrated512"])
+def test_full_binning_transform_and_sum(gpu, name):
+    """Stored-G mode: binned cube bit-exact, G, T and phi against the oracle."""
+    wl, d_idx, d_off, idx, off, _ = case(name)
+    st, out = gpu_ssb(d_idx, d_off, wl, c=wl.aberr)
+    assert out["status"] == 0
+    assert np.array_equal(state_D(st, wl), oracle(name, "D"))
+    G = oracle(name, "G")
+    eg, Gg = g_half_error(st, wl, G)
+    assert np.array_equal(Gg[:, 0, 0].real.astype(np.float64), oracle(name, "D").sum(axis=1).astype(np.float64))
+    T, npair = oracle(name, "T")
+    et, ep = rel_l2(out["T"], T), rel_l2(out["phi"], oracle(name, "phi"))
+    log(f"{name}: FP32 rel L2 G {eg:.2e} T {et:.2e} phi {ep:.2e}")
+    assert eg <= TOL and et <= TOL and ep <= TOL
+    assert st.pair_count() == int(npair.sum())
+
+
+@pytest.mark.parametrize("name", ["scan256", "scan1024", "aberrated512"])
+def test_full_recompute_mode(gpu, name):
+    """The benchmark's mode: G recomputed in the fused column kernel, never stored."""
+    wl, d_idx, d_off, idx, off, _ = case(name)
+    st, out = gpu_ssb(d_idx, d_off, wl, c=wl.aberr, g_mode=stem.STEM_G_RECOMPUTE)
+    assert out["status"] == 0
+    et, ep = rel_l2(out["T"], oracle(name, "T")[0]), rel_l2(out["phi"], oracle(name, "phi"))
+    log(f"{name}: recompute rel L2 T {et:.2e} phi {ep:.2e}")
+    assert et <= TOL and ep <= TOL
+
+
+@pytest.mark.parametrize("prec", [stem.STEM_DFT_BF16_SPLIT, stem.STEM_DFT_FP16_SPLIT], ids=["bf16", "fp16"])
+def test_full_split_precision(gpu, prec):
+    """The split-precision scan DFT at 1024x1024: per-output error against the FP64 oracle."""
+    name = "scan1024"
+    wl, d_idx, d_off, idx, off, _ = case(name)
+    st, out = gpu_ssb(d_idx, d_off, wl, c=wl.aberr, precision=prec)
+    assert out["status"] == 0
+    eg, Gg = g_half_error(st, wl, oracle(name, "G"))
+    assert np.array_equal(Gg[:, 0, 0].real.astype(np.float64), oracle(name, "D").sum(axis=1).astype(np.float64))
+    et, ep = rel_l2(out["T"], oracle(name, "T")[0]), rel_l2(out["phi"], oracle(name, "phi"))
+    log(f"{name}: split prec={prec} rel L2 G {eg:.2e} T {et:.2e} phi {ep:.2e}")
+    assert eg <= TOL_SPLIT and et <= TOL_SPLIT and ep <= TOL_SPLIT
+    del st
+    _, out2 = gpu_ssb(d_idx, d_off, wl, c=wl.aberr, g_mode=stem.STEM_G_RECOMPUTE, precision=prec)
+    assert rel_l2(out2["phi"], oracle(name, "phi")) <= TOL_SPLIT
+
+
+def test_full_adjoint(gpu):
+    """Differentiation workload: 8 coefficients at seeded +-50% perturbations of the true set;
+    the adjoint against the FP64 oracle gradient, and autograd against central differences of
+    the GPU forward for the components that carry at least 10% of the largest."""
+    name = "aberrated512"
+    wl, d_idx, d_off, idx, off, _ = case(name)
+    rng = np.random.default_rng(11)
+    c0 = np.array(wl.aberr) * (1 + rng.uniform(-0.5, 0.5, size=8))
+    det, scan, optics = structs(wl, c0)
+    st = stem.SsbState(det, scan, optics, stem.Ssb(stem.STEM_FFT_FP32, 0, stem.STEM_G_RECOMPUTE, 8))
+    st.accumulate(d_idx, d_off, 0, wl.n_frames)
+    c = torch.tensor(c0, dtype=torch.float64, requires_grad=True)
+
+    def loss_of(cc):
+        phi = stem.SSBPhase.apply(cc, None, st)
+        return -phi.double().var(unbiased=False), phi
+
+    L, phi = loss_of(c)
+    L.backward()
+    g = c.grad.numpy()
+    kc = oracle(name, "geom")[0]
+    G = oracle(name, "G")
+    T, _ = ossb.ssb_sum(G, kc, wl.step, wl.dk, wl.lam, wl.r_bf, c0)
+    phio = ossb.phase_from_T(T)
+    assert rel_l2(phi.detach().cpu().numpy().reshape(wl.scan), phio) <= TOL
+    dco, _ = ossb.ssb_adjoint(G, kc, ossb.neg_var_grad(phio), wl.step, wl.dk, wl.lam, wl.r_bf, c0)
+    log(f"{name}: dL/dc gpu {g} oracle {dco}")
+    assert np.all(np.abs(g - dco) <= 1e-4 * np.abs(dco) + 1e-6 * np.max(np.abs(dco)))
+    for j in range(8):
+        if abs(g[j]) < 0.1 * np.max(np.abs(g)):
+            continue
+        h = 2e-3 * abs(c0[j])
+        cp, cm = c0.copy(), c0.copy()
+        cp[j] += h
+        cm[j] -= h
+        with torch.no_grad():
+            lp = float(loss_of(torch.tensor(cp))[0])
+            lm = float(loss_of(torch.tensor(cm))[0])
+        fd = (lp - lm) / (2 * h)
+        log(f"{name}: c[{j}] autograd {g[j]:.6e} central difference {fd:.6e}")
+        assert abs(g[j] - fd) <= 1e-3 * abs(fd)
+
+
+def test_full_streamed_ingest_scan1024(gpu):
+    """The large-area acquisition arrives as 16 chunks of 64 scan rows from pinned host memory:
+    each chunk is copied and validated (eer_load_csr), its COM taken and its rows binned and
+    row-transformed (ACCUMULATE); after the last chunk the DPC integration and the SSB
+    finalisation run.  Everything equals the one-shot results bit for bit."""
+    name = "scan1024"
+    wl, d_idx, d_off, idx, off, _ = case(name)
+    det, scan, optics = structs(wl, wl.aberr)
+    ny, nx = wl.scan
+    F = wl.n_frames
+    s_idx = torch.zeros_like(d_idx)
+    s_off = torch.zeros_like(d_off)
+    h_idx = torch.from_numpy(idx).pin_memory()
+    h_off = torch.from_numpy(off).pin_memory()
+    status = stem.status_tensor()
+    com64 = torch.zeros(2 * F, dtype=torch.float64, device="cuda")
+    phase_dpc = torch.zeros(F, dtype=torch.float32, device="cuda")
+    ws = torch.empty(stem.com_dpc_workspace_bytes(scan), dtype=torch.uint8, device="cuda")
+    dpc = stem.Dpc(0.5, 0.0, 0.0, 10)
+    st = stem.SsbState(det, scan, optics, stem.Ssb(stem.STEM_FFT_FP32, 0, stem.STEM_G_RECOMPUTE, 8))
+    rows = 64
+    for r0 in range(0, ny, rows):
+        f0, nf = r0 * nx, rows * nx
+        e0, e1 = int(off[f0]), int(off[f0 + nf])
+        stem.eer_load_csr(h_idx[e0:e1], h_off[f0:f0 + nf + 1], f0, nf, e1 - e0, det, s_idx, s_off, d_status=status)
+        last = r0 + rows >= ny
+        stem.com_dpc(s_idx, s_off, f0, nf, det, scan, optics, dpc, com64=com64, phase=phase_dpc if last else None,
+                     ws=ws, d_status=status)
+        st.accumulate(s_idx, s_off, f0, nf)
+    phase_ssb = torch.zeros(F, dtype=torch.float32, device="cuda")
+    st.finalize(phase=phase_ssb)
+    torch.cuda.synchronize()
+    assert int(status.item()) == 0 and int(st.status.item()) == 0
+    assert torch.equal(s_idx, d_idx) and torch.equal(s_off, d_off)
+    # one shot on the resident arrays
+    com1 = torch.zeros_like(com64)
+    ph1 = torch.zeros_like(phase_dpc)
+    stem.com_dpc(d_idx, d_off, 0, F, det, scan, optics, dpc, com64=com1, phase=ph1, ws=ws)
+    st1 = stem.SsbState(det, scan, optics, stem.Ssb(stem.STEM_FFT_FP32, 0, stem.STEM_G_RECOMPUTE, 8))
+    phs1 = torch.zeros_like(phase_ssb)
+    st1.oneshot(d_idx, d_off, phase=phs1)
+    torch.cuda.synchronize()
+    assert torch.equal(com64, com1)
+    assert torch.equal(phase_dpc, ph1)
+    assert torch.equal(phase_ssb, phs1)
+    assert rel_l2(phase_ssb.cpu().numpy().reshape(wl.scan), oracle(name, "phi")) <= TOL
