@@ -65,11 +65,6 @@ __device__ __forceinline__ bool load_rel_offsets(const int64_t* __restrict__ off
 }
 
 // ---------------------------------------------------------------------------------------------
-// Staging of a workgroup's events in LDS: the events [a0, a0 + n) (absolute indices) are copied
-// with 16-byte loads from the 16-byte aligned position at or below a0; s[sh + j] then holds event
-// a0 + j (sh < 4 is returned).  Groups not wholly inside [a0, a0 + n) are copied element by
-// element, so nothing outside the window is read.
-
 // Group c of four events starting at the absolute index e (16-byte aligned): k[j] = idx[e + j],
 // ok[j] = e + j in [a0, aend); the whole group is one 16-byte load when it lies inside.
 __device__ __forceinline__ void load_group(const int32_t* __restrict__ idx, int64_t e, int64_t a0, int64_t aend,
@@ -282,7 +277,8 @@ int launch_geometry(const stem_det& det, double r2, RowRun* rows, double2* kc, i
 // ---------------------------------------------------------------------------------------------
 // binning into D[kd][f] (frames of whole scan rows)
 //
-// Workgroup = kBinFrames consecutive frames x a run of up to kBinKd kept pixels.  The block's
+// Workgroup = kBinFrames consecutive frames x a run of up to kBinKd kept pixels (small
+// workgroups: several per CU hide the latency of their load, count and write-out phases).  The block's
 // events are streamed in windows of kBinWin: first each thread writes its frame number into an
 // LDS byte map over the window's events, then the events are read with coalesced 16-byte loads
 // (four per lane), their frames read from the map as one word and their pixels mapped by the
@@ -291,9 +287,9 @@ int launch_geometry(const stem_det& det, double r2, RowRun* rows, double2* kc, i
 // 16-bit counters, two frames per word, over two passes of half the pixels.  A count above the
 // element type of D sets STEM_EOVERFLOW (the stored value is then not meaningful).
 
-constexpr int kBinFrames = 256;
+constexpr int kBinFrames = 128;
 constexpr int kBinThreads = 256;
-constexpr int kBinWords = 11776;                      // 46 KB of counters
+constexpr int kBinWords = 5976;                       // 23 KB of counters
 // pixel rows of counters are kBinFrames/4 (+1 padding) words apart, so that the events of one
 // frame (same column, different pixels) fall into different LDS banks
 constexpr int kBinKd = kBinWords / (kBinFrames / 4 + 1);  // 181 pixels per workgroup
