@@ -25,15 +25,19 @@ MID = WORKLOADS["scan1024"].replace(name="mid: scan 64x64, 576 detector binned 8
 # non-square scan, binning 2 of a 64x64 detector
 RECT = SMALL.replace(name="rect: scan 32x64, binned 2x", scan=(32, 64), bin=2, mean_e=30.0)
 ABERR = SMALL.replace(name="small aberrated", aberr=C4_TRUE_ABERRATIONS)
+# other transform lengths: 128 (FFT radix plan 16.8, matrix-core blocks of 4) and 512 x 256
+# (plans 16.16.2 / 16.16, blocks of 16 and 8), aberrated
+N128 = SMALL.replace(name="scan 128x128", scan=(128, 128), aberr=C4_TRUE_ABERRATIONS)
+N512 = SMALL.replace(name="scan 512x256, binned 2x", scan=(512, 256), bin=2, mean_e=10.0)
 
-CASES = {"small": SMALL, "mid": MID, "rect": RECT, "aberr": ABERR}
+CASES = {"small": SMALL, "mid": MID, "rect": RECT, "aberr": ABERR, "n128": N128, "n512": N512}
 _DATA = {}
 
 
 def data(name):
     if name not in _DATA:
         wl = CASES[name]
-        d = simulate(wl)
+        d = simulate(wl, device="cuda" if wl.n_frames > 8192 else "cpu")
         idx, off = d.numpy()
         _DATA[name] = (wl, idx, off)
     return _DATA[name]
@@ -48,7 +52,7 @@ def _announce(request):
 # centre of mass and DPC
 
 
-@pytest.mark.parametrize("name", ["small", "mid", "rect"])
+@pytest.mark.parametrize("name", ["small", "mid", "rect", "n512"])
 def test_com_bit_exact(gpu, name):
     wl, idx, off = data(name)
     d_idx, d_off = to_device(idx, off)
@@ -98,7 +102,7 @@ def test_dpc_phase_parity(gpu, name, reg):
 # binning, scan transform, sideband sum, phase
 
 
-@pytest.mark.parametrize("name", ["small", "mid", "rect"])
+@pytest.mark.parametrize("name", ["small", "mid", "rect", "n128", "n512"])
 def test_binning_and_scan_transform(gpu, name):
     wl, idx, off = data(name)
     d_idx, d_off = to_device(idx, off)
@@ -116,7 +120,7 @@ def test_binning_and_scan_transform(gpu, name):
     assert np.all(G[:, 0, 0].imag == 0)
 
 
-@pytest.mark.parametrize("name", ["small", "mid", "rect", "aberr"])
+@pytest.mark.parametrize("name", ["small", "mid", "rect", "aberr", "n128", "n512"])
 def test_ssb_phase_parity(gpu, name):
     wl, idx, off = data(name)
     d_idx, d_off = to_device(idx, off)

@@ -29,12 +29,12 @@ def _announce(request):
 
 
 @pytest.mark.parametrize("prec", SPLIT, ids=IDS)
-@pytest.mark.parametrize("name", ["small", "mid", "rect"])
+@pytest.mark.parametrize("name", ["small", "mid", "rect", "n128", "n512"])
 def test_split_transform_per_output(gpu, name, prec):
     wl, idx, off = data(name)
     d_idx, d_off = to_device(idx, off)
-    st, out = gpu_ssb(d_idx, d_off, wl, precision=prec)
-    ref = oracle_ssb(idx, off, wl)
+    st, out = gpu_ssb(d_idx, d_off, wl, c=wl.aberr, precision=prec)
+    ref = oracle_ssb(idx, off, wl, c=wl.aberr)
     assert out["status"] == 0
     assert np.array_equal(state_D(st, wl), ref["D"])
     nh = wl.scan[1] // 2 + 1
