@@ -120,6 +120,7 @@ def main():
     ap.add_argument("--workload", default="scan1024")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-split", action="store_true", help="skip the split-precision scan-DFT variants")
+    ap.add_argument("--no-extras", action="store_true", help="skip the refocus and adjoint timings")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run a device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
@@ -132,7 +133,7 @@ def main():
     import torch
 
     import paper_2104_06336_amd as stem
-    from gen import WORKLOADS, simulate
+    from gen import C4_TRUE_ABERRATIONS, WORKLOADS, simulate
 
     dev = torch.device("cuda:0")
     wl = WORKLOADS[args.workload]
@@ -261,6 +262,63 @@ def main():
             log(f"{label}: {el / args.steps * 1e3:.3f} ms/step (SSB {sm:.3f} ms vs FP32 {ssb32:.3f} ms), "
                 f"phi vs FP32 path rel L2 {d:.2e}")
 
+    # interactive refocus (stored G): Eq. 3 and the phase only, with new coefficients
+    extras = {}
+    if not args.no_extras:
+        st = stem.SsbState(det, scan, optics, stem.Ssb(stem.STEM_FFT_FP32, 0, stem.STEM_G_STORE, 8), device=dev)
+        st.oneshot(d_idx, d_off, phase=phase_ssb)
+        c_new = tuple(0.5 * v for v in C4_TRUE_ABERRATIONS)
+        for _ in range(args.warmup):
+            st.refocus(c=c_new, phase=phase_ssb)
+        torch.cuda.synchronize()
+        stem.trace_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            st.refocus(c=c_new, phase=phase_ssb)
+        torch.cuda.synchronize()
+        el_r = time.perf_counter() - t0
+        rr = stem.trace_records()
+        stem.trace_enable(False)
+        del st
+        extras["refocus"] = {"workload": "scan1024, stored G, aberrated coefficients",
+                             "ms": round(el_r / args.steps * 1e3, 4),
+                             "kernels_us": {k: round(ms / n * 1e3, 2) for k, (n, ms) in rr.items()}}
+        log(f"refocus: {el_r / args.steps * 1e3:.3f} ms")
+        # differentiation workload: forward + adjoint of -Var(phi) w.r.t. the 8 coefficients
+        wl4 = WORKLOADS["aberrated512"]
+        d4 = simulate(wl4, device=dev)
+        torch.cuda.synchronize()
+        H4, W4 = wl4.det
+        det4 = stem.Det(W4, H4, W4 // 2, H4 // 2, wl4.bin)
+        scan4 = stem.Scan(wl4.scan[0], wl4.scan[1], wl4.step)
+        c4 = tuple(v * (1 + 0.25 * (-1) ** j) for j, v in enumerate(wl4.aberr))
+        opt4 = stem.Optics.from_values(wl4.lam, wl4.r_bf, wl4.dk, c4)
+        st = stem.SsbState(det4, scan4, opt4, stem.Ssb(stem.STEM_FFT_FP32, 0, stem.STEM_G_RECOMPUTE, 8), device=dev)
+        st.accumulate(d4.idx, d4.off, 0, wl4.n_frames)
+        ph4 = torch.empty(wl4.n_frames, dtype=torch.float32, device=dev)
+
+        def fb():
+            st.finalize(phase=ph4)
+            gbar = (-(2.0 / ph4.numel()) * (ph4 - ph4.mean())).contiguous()
+            return st.backward(gbar)
+
+        for _ in range(args.warmup):
+            fb()
+        torch.cuda.synchronize()
+        stem.trace_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fb()
+        torch.cuda.synchronize()
+        el_a = time.perf_counter() - t0
+        ra = stem.trace_records()
+        stem.trace_enable(False)
+        del st, d4
+        extras["adjoint"] = {"workload": f"aberrated512: {wl4.name}", "n_k": int(stem.ssb_num_pixels(det4, opt4)),
+                             "forward_plus_backward_ms": round(el_a / args.steps * 1e3, 4),
+                             "kernels_us": {k: round(ms / n * 1e3, 2) for k, (n, ms) in ra.items()}}
+        log(f"aberrated512 forward + adjoint: {el_a / args.steps * 1e3:.3f} ms")
+
     cpu = None
     if not args.no_cpu_baseline:
         idx_np = d_idx.cpu().numpy()
@@ -292,6 +350,7 @@ def main():
         "kernels": kernels,
         "ssb_ms_fp32": round(ssb32, 4),
         "precision_variants": variants,
+        **extras,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -251,32 +251,39 @@ __global__ void k_transpose_T(const float2* __restrict__ Tt, int ny, int nx, flo
 }
 
 // ---------------------------------------------------------------------------------------------
-// sums the adjoint partials in a fixed order: dL/dc over waves, dL/dtheta over column sets
+// sums the adjoint partials in a fixed order: dL/dc over waves (workgroup 0), dL/dtheta over
+// column sets (one thread per pixel, eight independent loads in flight)
 
 __global__ void __launch_bounds__(256) k_adjoint_final(const double* __restrict__ pdc, int64_t npdc,
                                                        const float* __restrict__ pdth, int64_t npdth, int n_k,
                                                        double* __restrict__ dLdc, float* __restrict__ dLdth) {
-  __shared__ double s[256][8];
-  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (int64_t b = threadIdx.x; b < npdc; b += blockDim.x)
+  if (blockIdx.x == 0) {
+    __shared__ double s[256][8];
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int64_t b = threadIdx.x; b < npdc; b += blockDim.x)
 #pragma unroll
-    for (int j = 0; j < 8; ++j) acc[j] += pdc[b * 8 + j];
+      for (int j = 0; j < 8; ++j) acc[j] += pdc[b * 8 + j];
 #pragma unroll
-  for (int j = 0; j < 8; ++j) s[threadIdx.x][j] = acc[j];
-  __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
-    if (threadIdx.x < h)
-#pragma unroll
-      for (int j = 0; j < 8; ++j) s[threadIdx.x][j] += s[threadIdx.x + h][j];
+    for (int j = 0; j < 8; ++j) s[threadIdx.x][j] = acc[j];
     __syncthreads();
-  }
-  if (threadIdx.x < 8) dLdc[threadIdx.x] = s[0][threadIdx.x];
-  if (dLdth)
-    for (int kd = threadIdx.x; kd < n_k; kd += blockDim.x) {
-      double a = 0.0;
-      for (int64_t b = 0; b < npdth; ++b) a += (double)pdth[b * n_k + kd];
-      dLdth[kd] = (float)a;
+    for (int h = 128; h > 0; h >>= 1) {
+      if (threadIdx.x < h)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) s[threadIdx.x][j] += s[threadIdx.x + h][j];
+      __syncthreads();
     }
+    if (threadIdx.x < 8) dLdc[threadIdx.x] = s[0][threadIdx.x];
+    return;
+  }
+  const int kd = (blockIdx.x - 1) * blockDim.x + threadIdx.x;
+  if (!dLdth || kd >= n_k) return;
+  double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int64_t b = 0;
+  for (; b + 8 <= npdth; b += 8)
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] += (double)pdth[(b + u) * n_k + kd];
+  for (; b < npdth; ++b) a[0] += (double)pdth[b * n_k + kd];
+  dLdth[kd] = (float)(((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7])));
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -540,8 +547,8 @@ extern "C" int ssb_backward(const float* d_dLdphi, const stem_det* det, const st
     return st;
   {
     STEM_TRACE("ssb_adjoint_final", s);
-    hipLaunchKernelGGL(k_adjoint_final, dim3(1), dim3(256), 0, s, b.pdc, L.nwy, b.pdth, (int64_t)L.ncs, n_k, d_dLdc,
-                       d_dLdtheta);
+    hipLaunchKernelGGL(k_adjoint_final, dim3(1 + (n_k + 255) / 256), dim3(256), 0, s, b.pdc, L.nwy, b.pdth,
+                       (int64_t)L.ncs, n_k, d_dLdc, d_dLdtheta);
   }
   STEM_LAUNCH_CHECK();
   return STEM_OK;
