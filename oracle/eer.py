@@ -140,3 +140,42 @@ def bin_dense(rho: np.ndarray, b: int, lut: np.ndarray) -> np.ndarray:
             if lut[by, bx] >= 0:
                 D[lut[by, bx]] = blocks[:, by, bx]
     return D
+
+
+def radial_sum(idx: np.ndarray, off: np.ndarray, W: int, H: int, r_in, r_out, cx: int | None = None,
+               cy: int | None = None) -> np.ndarray:
+    """Virtual annular detectors from events (Table 1 'radial sum', Sec. III).
+
+    For each annulus j and frame f: the number of events of f whose pixel lies at squared
+    distance d2 = (kx - cx)^2 + (ky - cy)^2 from the zero-frequency pixel with
+    r_in[j]^2 <= d2 < r_out[j]^2 (d2 is an exact integer, the radii squared in float64).
+    Cost O(C) from events, against O((r_out^2 - r_in^2) F) from dense frames.
+
+    Returns int64 [n_det, F].
+    """
+    cx = W // 2 if cx is None else cx
+    cy = H // 2 if cy is None else cy
+    k = np.asarray(idx, dtype=np.int64)
+    d2 = (k % W - cx) ** 2 + (k // W - cy) ** 2
+    f = frame_of_event(off)
+    F = len(off) - 1
+    out = np.zeros((len(r_in), F), dtype=np.int64)
+    for j, (a, b) in enumerate(zip(r_in, r_out)):
+        a2, b2 = float(a) * float(a), float(b) * float(b)
+        inside = (d2 >= a2) & (d2 < b2)
+        out[j] = np.bincount(f[inside], minlength=F)
+    return out
+
+
+def sum_frames(idx: np.ndarray, off: np.ndarray, W: int, H: int, frame0: int = 0,
+               n_frames: int | None = None) -> np.ndarray:
+    """Sum of the frames [frame0, frame0 + n_frames) (Table 1 'sum all frames'): the
+    position-averaged diffraction pattern (PACBED) up to the factor 1/n_frames, or, over frames
+    in vacuum, the average probe.  Each event adds one count to its pixel.
+
+    Returns int64 [H, W].
+    """
+    F = len(off) - 1
+    n_frames = F - frame0 if n_frames is None else n_frames
+    k = np.asarray(idx[off[frame0]:off[frame0 + n_frames]], dtype=np.int64)
+    return np.bincount(k, minlength=W * H).reshape(H, W)

@@ -156,3 +156,65 @@ def test_generator_counts_are_poisson_and_inside_detector():
     for f in range(0, len(n), 97):
         seg = idx[off[f]:off[f + 1]]
         assert (np.diff(seg) >= 0).all()
+
+
+# ----------------------------------------------------------------------------------------------
+# virtual detectors: radial sums and frame sums (Table 1)
+
+
+def test_radial_sum_and_frame_sum_hand_example():
+    g = _read_golden("eer_hand.txt")
+    W, H = int(g["W"][0]), int(g["H"][0])
+    idx = np.array(g["idx"], dtype=np.int32)
+    off = np.array(g["off"], dtype=np.int64)
+    rs = eer.radial_sum(idx, off, W, H, g["radial_in"], g["radial_out"])
+    assert rs[0].tolist() == [int(v) for v in g["radial_A"]]
+    assert rs[1].tolist() == [int(v) for v in g["radial_B"]]
+    assert eer.sum_frames(idx, off, W, H).ravel().tolist() == [int(v) for v in g["sum"]]
+
+
+def test_radial_sum_brute_force_dense():
+    """Pixel loops over dense frames (the dense-format column of Table 1)."""
+    rng = np.random.default_rng(21)
+    W, H = 11, 9
+    idx, off = random_csr(rng, 30, W, H, 12.0)
+    rho = eer.dense_frames(idx, off, W, H)
+    cx, cy = W // 2, H // 2
+    r_in, r_out = [0.0, 1.0, 2.5, 3.0], [1.0, 2.5, 3.0, 100.0]
+    got = eer.radial_sum(idx, off, W, H, r_in, r_out)
+    for j, (a, b) in enumerate(zip(r_in, r_out)):
+        for f in range(len(off) - 1):
+            tot = 0
+            for ky in range(H):
+                for kx in range(W):
+                    d2 = (kx - cx) ** 2 + (ky - cy) ** 2
+                    if a * a <= d2 < b * b:
+                        tot += int(rho[f, ky, kx])
+            assert got[j, f] == tot
+
+
+def test_radial_sum_special_cases():
+    rng = np.random.default_rng(22)
+    W, H = 16, 16
+    idx, off = random_csr(rng, 50, W, H, 20.0)
+    # the whole detector: every event, N_f
+    assert np.array_equal(eer.radial_sum(idx, off, W, H, [0.0], [1e9])[0], eer.frame_counts(off))
+    # additivity of adjacent annuli
+    a = eer.radial_sum(idx, off, W, H, [1.0, 3.5], [3.5, 6.0])
+    b = eer.radial_sum(idx, off, W, H, [1.0], [6.0])
+    assert np.array_equal(a.sum(axis=0), b[0])
+    # an empty annulus
+    assert not eer.radial_sum(idx, off, W, H, [2.0], [2.0]).any()
+
+
+def test_frame_sum_brute_force_and_ranges():
+    rng = np.random.default_rng(23)
+    W, H = 10, 7
+    idx, off = random_csr(rng, 40, W, H, 9.0)
+    rho = eer.dense_frames(idx, off, W, H)
+    assert np.array_equal(eer.sum_frames(idx, off, W, H), rho.sum(axis=0))
+    assert np.array_equal(eer.sum_frames(idx, off, W, H, 5, 20), rho[5:25].sum(axis=0))
+    assert eer.sum_frames(idx, off, W, H, 5, 20).sum() == off[25] - off[5]
+    left = eer.sum_frames(idx, off, W, H, 0, 17)
+    right = eer.sum_frames(idx, off, W, H, 17, 23)
+    assert np.array_equal(left + right, eer.sum_frames(idx, off, W, H))
