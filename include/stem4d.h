@@ -161,6 +161,38 @@ int com_dpc(const int32_t* d_idx, const int64_t* d_off, int64_t frame0, int64_t 
             float* d_phase, void* ws, size_t ws_bytes, int32_t* d_status, void* stream);
 
 /* ---------------------------------------------------------------------------------------- */
+/* Virtual detectors from events (Table 1: radial sum, sum of all frames; Sec. III)          */
+
+#define STEM_MAX_ANNULI 16
+
+/* Virtual annular detectors (radial sums).  For each of n_det annuli j (1 <= n_det <=
+ * STEM_MAX_ANNULI) and each frame f in [frame0, frame0 + n_frames):
+ *   d_out[j*F + f] = number of events of f at a pixel with
+ *                    r_in[j]^2 <= (kx - cx)^2 + (ky - cy)^2 < r_out[j]^2
+ * in unbinned detector pixels (det.bin is ignored), an exact integer test (the radii are
+ * squared in double on the host).  F = scan.ny * scan.nx; d_out is int32 [n_det][F], indexed by
+ * the global frame number, written only for the given frames.  h_r_in / h_r_out are host
+ * arrays of n_det radii.  One pass over the events: O(C), against O((r_out^2 - r_in^2) F) for
+ * dense frames.
+ * Errors: STEM_EINVAL (NULL pointers, n_det outside [1, STEM_MAX_ANNULI], a negative or NaN
+ * radius, frame range outside [0, F)); STEM_ERANGE / STEM_EOVERFLOW via d_status. */
+int virtual_annular(const int32_t* d_idx, const int64_t* d_off, int64_t frame0, int64_t n_frames,
+                    const stem_det* det, const stem_scan* scan, int n_det, const double* h_r_in,
+                    const double* h_r_out, int32_t* d_out, int32_t* d_status, void* stream);
+
+/* Sum of the frames [frame0, frame0 + n_frames) (Table 1 "sum all frames"): the
+ * position-averaged diffraction pattern (PACBED), or over frames in vacuum the average probe.
+ *   d_sum[ky*W + kx] += number of events of those frames at pixel (kx, ky)   (uint32 [H][W])
+ * The sum is accumulated (the caller zeroes d_sum once, so chunks can be added). If d_mean is
+ * not NULL it then receives d_mean[k] = (float)((double)d_sum[k] / n_frames) (float [H][W]).
+ * Only the events [off[frame0], off[frame0 + n_frames]) are read (offsets validated by
+ * eer_load_csr).  Asynchronous: the event range is read on the device.
+ * Errors: STEM_EINVAL (NULL pointers, n_frames <= 0, negative frame0); via d_status
+ * STEM_ERANGE for indices outside [0, W*H) (skipped) and STEM_EOFFSETS for a decreasing range. */
+int sum_frames(const int32_t* d_idx, const int64_t* d_off, int64_t frame0, int64_t n_frames,
+               const stem_det* det, uint32_t* d_sum, float* d_mean, int32_t* d_status, void* stream);
+
+/* ---------------------------------------------------------------------------------------- */
 /* a4 - a7. Single-sideband reconstruction (Sec. IV, Eq. 2, the double-overlap set, Eq. 3)  */
 
 enum {

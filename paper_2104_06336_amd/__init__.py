@@ -26,6 +26,7 @@ __all__ = [
     "STEM_G_STORE", "STEM_SSB_ACCUMULATE", "STEM_SSB_FINALIZE", "STEM_SSB_REFOCUS",
     "STEM_SSB_ONESHOT", "SsbState", "SSBPhase", "ssb_state_region", "STEM_REGION_D", "STEM_REGION_G",
     "STEM_REGION_T", "STEM_REGION_KC", "STEM_REGION_STATS", "trace_enable", "trace_records",
+    "virtual_annular", "sum_frames",
 ]
 
 
@@ -88,6 +89,45 @@ def eer_load_csr(h_idx, h_off, frame0: int, n_frames: int, n_events: int, det: D
     rc = lib().eer_load_csr(_p(h_idx), _p(h_off), frame0, n_frames, n_events, ctypes.byref(det),
                             _p(d_idx), _p(d_off), _p(d_status), _stream(stream))
     _check(rc, "eer_load_csr")
+
+
+# ----------------------------------------------------------------------------------------------
+# virtual detectors (Table 1: radial sum, sum of all frames)
+
+
+def virtual_annular(d_idx, d_off, frame0: int, n_frames: int, det: Det, scan: Scan, r_in, r_out, out,
+                    d_status=None, stream=None):
+    """Per-frame event counts in annuli r_in[j] <= |k - c| < r_out[j] (pixels): out int32 [n_det*F]."""
+    _dev(d_idx, torch.int32, "d_idx")
+    _dev(d_off, torch.int64, "d_off")
+    _dev(out, torch.int32, "out")
+    n = len(r_in)
+    if len(r_out) != n:
+        raise ValueError("r_in and r_out must have the same length")
+    F = scan.ny * scan.nx
+    if out.numel() < n * F:
+        raise ValueError(f"out needs {n * F} elements")
+    a = (ctypes.c_double * n)(*[float(v) for v in r_in])
+    b = (ctypes.c_double * n)(*[float(v) for v in r_out])
+    rc = lib().virtual_annular(_p(d_idx), _p(d_off), frame0, n_frames, ctypes.byref(det), ctypes.byref(scan), n,
+                               a, b, _p(out), _p(d_status), _stream(stream))
+    _check(rc, "virtual_annular")
+
+
+def sum_frames(d_idx, d_off, frame0: int, n_frames: int, det: Det, out_sum, out_mean=None, d_status=None,
+               stream=None):
+    """Adds the events of frames [frame0, frame0 + n_frames) into out_sum (int32 storage of
+    uint32 [H*W]); out_mean (float32 [H*W]), if given, receives the sum / n_frames."""
+    _dev(d_idx, torch.int32, "d_idx")
+    _dev(d_off, torch.int64, "d_off")
+    _dev(out_sum, torch.int32, "out_sum")
+    if out_sum.numel() < det.W * det.H:
+        raise ValueError("out_sum needs W*H elements")
+    if out_mean is not None:
+        _dev(out_mean, torch.float32, "out_mean")
+    rc = lib().sum_frames(_p(d_idx), _p(d_off), frame0, n_frames, ctypes.byref(det), _p(out_sum), _p(out_mean),
+                          _p(d_status), _stream(stream))
+    _check(rc, "sum_frames")
 
 
 # ----------------------------------------------------------------------------------------------

@@ -7,6 +7,8 @@
 // Frame blocks: a workgroup owns a run of consecutive frames; their events are one contiguous
 // CSR slice, read with coalesced 16-byte loads: staged in LDS for the per-frame sums of k_com,
 // streamed with an LDS map event -> frame for the counts of k_bin.
+#include <cmath>
+
 #include "common.h"
 #include "geom.h"
 #include "kernels.h"
@@ -200,6 +202,132 @@ int launch_com(const int32_t* idx, const int64_t* off, int64_t frame0, int64_t n
                      com64, com32, counts, status);
   STEM_LAUNCH_CHECK();
   return STEM_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// virtual annular detectors: the same staging as k_com; thread t counts the events of frame t in
+// each annulus [lo_j, hi_j) of squared pixel distance (exact int64 thresholds)
+
+struct Annuli {
+  int64_t lo[STEM_MAX_ANNULI], hi[STEM_MAX_ANNULI];
+};
+
+template <int NA>
+__global__ void __launch_bounds__(kComThreads) k_annular(const int32_t* __restrict__ idx,
+                                                         const int64_t* __restrict__ off, int64_t frame0,
+                                                         int64_t n_frames, Magic divw, int32_t cx, int32_t cy,
+                                                         int32_t npix, Annuli an, int64_t F,
+                                                         int32_t* __restrict__ out, int32_t* status) {
+  __shared__ int32_t s_ev[kComWin + 8];
+  __shared__ int32_t s_rel[kComFrames + 1];
+  __shared__ int64_t s_base;
+  const int t = threadIdx.x;
+  const int64_t fb = frame0 + (int64_t)blockIdx.x * kComFrames;
+  const int64_t left = frame0 + n_frames - fb;
+  const int nf = (int)(left < kComFrames ? left : kComFrames);
+  if (!load_rel_offsets(off, fb, nf, s_rel, &s_base, status)) return;
+  __syncthreads();
+  const int span = s_rel[nf];
+  const int lo_t = t < nf ? s_rel[t] : 0, hi_t = t < nf ? s_rel[t + 1] : 0;
+  int32_t cnt[NA];
+#pragma unroll
+  for (int j = 0; j < NA; ++j) cnt[j] = 0;
+  uint32_t nbad = 0;
+  for (int w0 = 0; w0 < span; w0 += kComWin) {
+    const int wn = span - w0 < kComWin ? span - w0 : kComWin;
+    __syncthreads();
+    const int sh = stage_events(idx, s_base + w0, wn, s_ev);
+    __syncthreads();
+    const int lo = (lo_t > w0 ? lo_t : w0) - w0 + sh;
+    const int hi = (hi_t < w0 + wn ? hi_t : w0 + wn) - w0 + sh;
+    for (int e = lo; e < hi; ++e) {
+      const int32_t k = s_ev[e];
+      const bool in = (uint32_t)k < (uint32_t)npix;
+      nbad += in ? 0u : 1u;
+      const uint32_t kk = in ? (uint32_t)k : 0u;
+      const uint32_t ky = magic_div(kk, divw);
+      const int64_t dx = (int64_t)(kk - ky * divw.d) - cx, dy = (int64_t)ky - cy;
+      const int64_t d2 = dx * dx + dy * dy;
+#pragma unroll
+      for (int j = 0; j < NA; ++j) cnt[j] += (in && d2 >= an.lo[j] && d2 < an.hi[j]) ? 1 : 0;
+    }
+  }
+  if (t < nf) {
+#pragma unroll
+    for (int j = 0; j < NA; ++j) out[(int64_t)j * F + fb + t] = cnt[j];
+  }
+  if (nbad) report(status, STEM_ERANGE);
+}
+
+// ---------------------------------------------------------------------------------------------
+// sum of frames: a workgroup counts at most kSumWin consecutive events (so that a 16-bit LDS
+// counter cannot overflow) into packed 16-bit counters over a box of up to 128 x 128 pixels
+// around the zero-frequency pixel, where the bright-field disk and nearly all events fall; events
+// outside the box go straight to global atomics.  The box is then added to the global sum.
+
+constexpr int kSumWin = 65535;
+constexpr int kSumBox = 128;
+
+__global__ void __launch_bounds__(256) k_sum_events(const int32_t* __restrict__ idx, const int64_t* __restrict__ off,
+                                                    int64_t frame0, int64_t n_frames, Magic divw, int32_t npix,
+                                                    int32_t bx0, int32_t by0, int32_t bw, int32_t bh,
+                                                    uint32_t* __restrict__ sum, int32_t* status) {
+  __shared__ uint32_t s_box[kSumBox * kSumBox / 2];
+  const int64_t e0 = off[frame0], e1 = off[frame0 + n_frames];
+  if (e1 < e0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) report(status, STEM_EOFFSETS);
+    return;
+  }
+  const int nwords = (bw * bh + 1) / 2;
+  uint32_t nbad = 0;
+  // windows of kSumWin events, grid-strided over the workgroups
+  for (int64_t a0 = e0 + (int64_t)blockIdx.x * kSumWin; a0 < e1; a0 += (int64_t)gridDim.x * kSumWin) {
+    const int64_t aend = a0 + kSumWin < e1 ? a0 + kSumWin : e1;
+    __syncthreads();
+    for (int i = threadIdx.x; i < nwords; i += blockDim.x) s_box[i] = 0u;
+    __syncthreads();
+    const int sh = (int)((((uintptr_t)(idx + a0)) & 15) >> 2);
+    const int64_t al = a0 - sh;
+    const int ng = (int)((aend - al + 3) >> 2);
+    for (int g = threadIdx.x; g < ng; g += blockDim.x) {
+      int32_t k[4];
+      bool ok[4];
+      load_group(idx, al + 4 * (int64_t)g, a0, aend, k, ok);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (!ok[q]) continue;
+        if ((uint32_t)k[q] >= (uint32_t)npix) {
+          ++nbad;
+          continue;
+        }
+        const uint32_t ky = magic_div((uint32_t)k[q], divw);
+        const int x = (int)((uint32_t)k[q] - ky * divw.d) - bx0, y = (int)ky - by0;
+        if ((uint32_t)x < (uint32_t)bw && (uint32_t)y < (uint32_t)bh) {
+          const int p = y * bw + x;
+          atomicAdd(&s_box[p >> 1], 1u << (16 * (p & 1)));
+        } else {
+          atomicAdd(&sum[k[q]], 1u);
+        }
+      }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nwords; i += blockDim.x) {
+      const uint32_t w = s_box[i];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const uint32_t c = h ? (w >> 16) : (w & 0xffffu);
+        const int p = 2 * i + h;
+        if (c && p < bw * bh) atomicAdd(&sum[(int64_t)(by0 + p / bw) * divw.d + bx0 + p % bw], c);
+      }
+    }
+  }
+  if (nbad) report(status, STEM_ERANGE);
+}
+
+__global__ void __launch_bounds__(256) k_frame_mean(const uint32_t* __restrict__ sum, int64_t npix, double n,
+                                                    float* __restrict__ mean) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < npix) mean[p] = (float)((double)sum[p] / n);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -503,5 +631,76 @@ extern "C" int eer_load_csr(const int32_t* h_idx, const int64_t* h_off, int64_t 
                        n_frames, n_events, h_off ? 1 : 0, lo, hi, det->W * det->H, d_status);
   }
   STEM_LAUNCH_CHECK();
+  return STEM_OK;
+}
+
+extern "C" int virtual_annular(const int32_t* d_idx, const int64_t* d_off, int64_t frame0, int64_t n_frames,
+                               const stem_det* det, const stem_scan* scan, int n_det, const double* h_r_in,
+                               const double* h_r_out, int32_t* d_out, int32_t* d_status, void* stream_) {
+  if (!d_idx || !d_off || !det || !scan || !d_out || !h_r_in || !h_r_out) return STEM_EINVAL;
+  if (det->W <= 0 || det->H <= 0 || (int64_t)det->W * det->H >= (1ll << 31)) return STEM_EINVAL;
+  if (scan->ny <= 0 || scan->nx <= 0 || n_det < 1 || n_det > STEM_MAX_ANNULI) return STEM_EINVAL;
+  const int64_t F = (int64_t)scan->ny * scan->nx;
+  if (frame0 < 0 || n_frames < 0 || frame0 + n_frames > F) return STEM_EINVAL;
+  Annuli an;
+  const double big = 9.0e18;  // beyond every squared distance of a detector with W*H < 2^31
+  for (int j = 0; j < STEM_MAX_ANNULI; ++j) {
+    an.lo[j] = an.hi[j] = 0;
+    if (j >= n_det) continue;
+    const double a = h_r_in[j], b = h_r_out[j];
+    if (!(a >= 0.0) || !(b >= 0.0)) return STEM_EINVAL;  // also rejects NaN
+    // d2 >= a^2 and d2 < b^2 for an integer d2  <=>  d2 >= ceil(a^2) and d2 < ceil(b^2)
+    const double a2 = std::ceil(a * a), b2 = std::ceil(b * b);
+    an.lo[j] = a2 >= big ? (int64_t)big : (int64_t)a2;
+    an.hi[j] = b2 >= big ? (int64_t)big : (int64_t)b2;
+  }
+  if (n_frames == 0) return STEM_OK;
+  hipStream_t s = (hipStream_t)stream_;
+  const int64_t blocks = (n_frames + kComFrames - 1) / kComFrames;
+  const Magic mw = make_magic((uint32_t)det->W);
+  STEM_TRACE("virtual_annular", s);
+  const dim3 grid((unsigned)blocks), blk(kComThreads);
+  const int npix = det->W * det->H;
+  if (n_det <= 1)
+    hipLaunchKernelGGL(k_annular<1>, grid, blk, 0, s, d_idx, d_off, frame0, n_frames, mw, det->cx, det->cy, npix, an,
+                       F, d_out, d_status);
+  else if (n_det <= 2)
+    hipLaunchKernelGGL(k_annular<2>, grid, blk, 0, s, d_idx, d_off, frame0, n_frames, mw, det->cx, det->cy, npix, an,
+                       F, d_out, d_status);
+  else if (n_det <= 4)
+    hipLaunchKernelGGL(k_annular<4>, grid, blk, 0, s, d_idx, d_off, frame0, n_frames, mw, det->cx, det->cy, npix, an,
+                       F, d_out, d_status);
+  else if (n_det <= 8)
+    hipLaunchKernelGGL(k_annular<8>, grid, blk, 0, s, d_idx, d_off, frame0, n_frames, mw, det->cx, det->cy, npix, an,
+                       F, d_out, d_status);
+  else
+    hipLaunchKernelGGL(k_annular<16>, grid, blk, 0, s, d_idx, d_off, frame0, n_frames, mw, det->cx, det->cy, npix,
+                       an, F, d_out, d_status);
+  STEM_LAUNCH_CHECK();
+  return STEM_OK;
+}
+
+extern "C" int sum_frames(const int32_t* d_idx, const int64_t* d_off, int64_t frame0, int64_t n_frames,
+                          const stem_det* det, uint32_t* d_sum, float* d_mean, int32_t* d_status, void* stream_) {
+  if (!d_idx || !d_off || !det || !d_sum || frame0 < 0 || n_frames <= 0) return STEM_EINVAL;
+  if (det->W <= 0 || det->H <= 0 || (int64_t)det->W * det->H >= (1ll << 31)) return STEM_EINVAL;
+  hipStream_t s = (hipStream_t)stream_;
+  const int W = det->W, H = det->H;
+  const int bw = W < kSumBox ? W : kSumBox, bh = H < kSumBox ? H : kSumBox;
+  int bx0 = det->cx - bw / 2, by0 = det->cy - bh / 2;
+  bx0 = bx0 < 0 ? 0 : (bx0 > W - bw ? W - bw : bx0);
+  by0 = by0 < 0 ? 0 : (by0 > H - bh ? H - bh : by0);
+  {
+    STEM_TRACE("sum_frames", s);
+    hipLaunchKernelGGL(k_sum_events, dim3(1024), dim3(256), 0, s, d_idx, d_off, frame0, n_frames,
+                       make_magic((uint32_t)W), W * H, bx0, by0, bw, bh, d_sum, d_status);
+    STEM_LAUNCH_CHECK();
+  }
+  if (d_mean) {
+    const int64_t npix = (int64_t)W * H;
+    hipLaunchKernelGGL(k_frame_mean, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, s, d_sum, npix,
+                       (double)n_frames, d_mean);
+    STEM_LAUNCH_CHECK();
+  }
   return STEM_OK;
 }
