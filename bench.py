@@ -319,6 +319,38 @@ def main():
                              "kernels_us": {k: round(ms / n * 1e3, 2) for k, (n, ms) in ra.items()}}
         log(f"aberrated512 forward + adjoint: {el_a / args.steps * 1e3:.3f} ms")
 
+    # virtual detectors from the same events: bright-field + annular dark-field images, PACBED
+    if not args.no_extras:
+        vd = torch.empty(2 * F, dtype=torch.int32, device=dev)
+        pac = torch.zeros(W * H, dtype=torch.int32, device=dev)
+        r_in, r_out = [0.0, 1.2 * wl.r_bf], [wl.r_bf, 4.0 * wl.r_bf]
+
+        def detectors():
+            stem.virtual_annular(d_idx, d_off, 0, F, det, scan, r_in, r_out, vd, d_status=status)
+            pac.zero_()
+            stem.sum_frames(d_idx, d_off, 0, F, det, pac, d_status=status)
+
+        for _ in range(args.warmup):
+            detectors()
+        torch.cuda.synchronize()
+        stem.trace_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            detectors()
+        torch.cuda.synchronize()
+        el_v = time.perf_counter() - t0
+        rv = stem.trace_records()
+        stem.trace_enable(False)
+        stem.check_status(status, "virtual detectors")
+        kv = {k: round(ms / n * 1e3, 2) for k, (n, ms) in rv.items()}
+        extras["virtual_detectors"] = {
+            "workload": "scan1024: bright field [0, r_bf) and annular dark field [1.2, 4) r_bf per frame; "
+                        "sum of all frames",
+            "ms": round(el_v / args.steps * 1e3, 4), "kernels_us": kv,
+            "annular_events_per_s": round(C / (kv.get("virtual_annular", float("nan")) * 1e-6), 1)}
+        log(f"virtual detectors: {el_v / args.steps * 1e3:.3f} ms {kv}")
+        del vd, pac
+
     # end to end from pinned host memory: 16 chunks of 64 scan rows; the copy (and validation) of
     # chunk k+1 on a copy stream overlaps COM + binning + row transform of chunk k
     if not args.no_extras:

@@ -260,66 +260,75 @@ __global__ void __launch_bounds__(kComThreads) k_annular(const int32_t* __restri
 }
 
 // ---------------------------------------------------------------------------------------------
-// sum of frames: a workgroup counts at most kSumWin consecutive events (so that a 16-bit LDS
-// counter cannot overflow) into packed 16-bit counters over a box of up to 128 x 128 pixels
-// around the zero-frequency pixel, where the bright-field disk and nearly all events fall; events
-// outside the box go straight to global atomics.  The box is then added to the global sum.
+// sum of frames: the event range is split evenly over the workgroups; each counts its events into
+// 32-bit LDS counters over a box of up to 128 x 128 pixels around the zero-frequency pixel, where
+// the bright-field disk and nearly all events fall (events outside the box go straight to global
+// atomics), then adds the box to the global sum once.
 
-constexpr int kSumWin = 65535;
 constexpr int kSumBox = 128;
+constexpr int kSumBlocks = 512;
 
 __global__ void __launch_bounds__(256) k_sum_events(const int32_t* __restrict__ idx, const int64_t* __restrict__ off,
                                                     int64_t frame0, int64_t n_frames, Magic divw, int32_t npix,
                                                     int32_t bx0, int32_t by0, int32_t bw, int32_t bh,
                                                     uint32_t* __restrict__ sum, int32_t* status) {
-  __shared__ uint32_t s_box[kSumBox * kSumBox / 2];
+  __shared__ uint32_t s_box[kSumBox * kSumBox];
   const int64_t e0 = off[frame0], e1 = off[frame0 + n_frames];
   if (e1 < e0) {
     if (blockIdx.x == 0 && threadIdx.x == 0) report(status, STEM_EOFFSETS);
     return;
   }
-  const int nwords = (bw * bh + 1) / 2;
+  const int nbox = bw * bh;
+  for (int i = threadIdx.x; i < nbox; i += blockDim.x) s_box[i] = 0u;
+  __syncthreads();
+  // this workgroup's share of the events, in whole 16-byte groups where possible
+  const int64_t per = ((e1 - e0 + gridDim.x - 1) / gridDim.x + 3) & ~3ll;
+  const int64_t a0 = e0 + (int64_t)blockIdx.x * per;
+  const int64_t aend = a0 + per < e1 ? a0 + per : e1;
   uint32_t nbad = 0;
-  // windows of kSumWin events, grid-strided over the workgroups
-  for (int64_t a0 = e0 + (int64_t)blockIdx.x * kSumWin; a0 < e1; a0 += (int64_t)gridDim.x * kSumWin) {
-    const int64_t aend = a0 + kSumWin < e1 ? a0 + kSumWin : e1;
-    __syncthreads();
-    for (int i = threadIdx.x; i < nwords; i += blockDim.x) s_box[i] = 0u;
-    __syncthreads();
+  if (a0 < aend) {
     const int sh = (int)((((uintptr_t)(idx + a0)) & 15) >> 2);
     const int64_t al = a0 - sh;
-    const int ng = (int)((aend - al + 3) >> 2);
-    for (int g = threadIdx.x; g < ng; g += blockDim.x) {
-      int32_t k[4];
-      bool ok[4];
-      load_group(idx, al + 4 * (int64_t)g, a0, aend, k, ok);
+    const int64_t ng = (aend - al + 3) >> 2;
+    constexpr int U = 4;  // groups per thread in flight
+    for (int64_t g0 = threadIdx.x; g0 < ng; g0 += (int64_t)U * blockDim.x) {
+      int32_t k[U][4];
+      bool ok[U][4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        if (!ok[q]) continue;
-        if ((uint32_t)k[q] >= (uint32_t)npix) {
-          ++nbad;
-          continue;
-        }
-        const uint32_t ky = magic_div((uint32_t)k[q], divw);
-        const int x = (int)((uint32_t)k[q] - ky * divw.d) - bx0, y = (int)ky - by0;
-        if ((uint32_t)x < (uint32_t)bw && (uint32_t)y < (uint32_t)bh) {
-          const int p = y * bw + x;
-          atomicAdd(&s_box[p >> 1], 1u << (16 * (p & 1)));
+      for (int u = 0; u < U; ++u) {
+        const int64_t g = g0 + (int64_t)u * blockDim.x;
+        if (g < ng) {
+          load_group(idx, al + 4 * g, a0, aend, k[u], ok[u]);
         } else {
-          atomicAdd(&sum[k[q]], 1u);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            ok[u][q] = false;
+            k[u][q] = 0;
+          }
         }
       }
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < nwords; i += blockDim.x) {
-      const uint32_t w = s_box[i];
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const uint32_t c = h ? (w >> 16) : (w & 0xffffu);
-        const int p = 2 * i + h;
-        if (c && p < bw * bh) atomicAdd(&sum[(int64_t)(by0 + p / bw) * divw.d + bx0 + p % bw], c);
-      }
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (!ok[u][q]) continue;
+          if ((uint32_t)k[u][q] >= (uint32_t)npix) {
+            ++nbad;
+            continue;
+          }
+          const uint32_t ky = magic_div((uint32_t)k[u][q], divw);
+          const int x = (int)((uint32_t)k[u][q] - ky * divw.d) - bx0, y = (int)ky - by0;
+          if ((uint32_t)x < (uint32_t)bw && (uint32_t)y < (uint32_t)bh)
+            atomicAdd(&s_box[y * bw + x], 1u);
+          else
+            atomicAdd(&sum[k[u][q]], 1u);
+        }
     }
+  }
+  __syncthreads();
+  for (int p = threadIdx.x; p < nbox; p += blockDim.x) {
+    const uint32_t c = s_box[p];
+    if (c) atomicAdd(&sum[(int64_t)(by0 + p / bw) * divw.d + bx0 + p % bw], c);
   }
   if (nbad) report(status, STEM_ERANGE);
 }
@@ -692,7 +701,7 @@ extern "C" int sum_frames(const int32_t* d_idx, const int64_t* d_off, int64_t fr
   by0 = by0 < 0 ? 0 : (by0 > H - bh ? H - bh : by0);
   {
     STEM_TRACE("sum_frames", s);
-    hipLaunchKernelGGL(k_sum_events, dim3(1024), dim3(256), 0, s, d_idx, d_off, frame0, n_frames,
+    hipLaunchKernelGGL(k_sum_events, dim3(kSumBlocks), dim3(256), 0, s, d_idx, d_off, frame0, n_frames,
                        make_magic((uint32_t)W), W * H, bx0, by0, bw, bh, d_sum, d_status);
     STEM_LAUNCH_CHECK();
   }
