@@ -179,3 +179,25 @@ def sum_frames(idx: np.ndarray, off: np.ndarray, W: int, H: int, frame0: int = 0
     n_frames = F - frame0 if n_frames is None else n_frames
     k = np.asarray(idx[off[frame0]:off[frame0 + n_frames]], dtype=np.int64)
     return np.bincount(k, minlength=W * H).reshape(H, W)
+
+
+def rle_encode(idx: np.ndarray, off: np.ndarray) -> np.ndarray:
+    """Run-length form of the events (Fig. 1c): within each frame the indices in ascending order,
+    stored as their distances d_0 = k_0, d_i = k_i - k_(i-1) (a repeated pixel gives 0)."""
+    k = np.asarray(idx, dtype=np.int64).copy()
+    d = np.empty_like(k)
+    for f in range(len(off) - 1):
+        seg = np.sort(k[off[f]:off[f + 1]])
+        if seg.size:
+            d[off[f]:off[f + 1]] = np.diff(seg, prepend=0)
+    return d
+
+
+def rle_decode(dist: np.ndarray, off: np.ndarray) -> np.ndarray:
+    """Linear indices from the run-length form (Table 1: re-coding costs O(C)): k_i is the sum of
+    the frame's distances up to and including i (a prefix sum restarted at every frame)."""
+    d = np.asarray(dist, dtype=np.int64)
+    k = np.empty_like(d)
+    for f in range(len(off) - 1):
+        k[off[f]:off[f + 1]] = np.cumsum(d[off[f]:off[f + 1]])
+    return k

@@ -218,3 +218,36 @@ def test_frame_sum_brute_force_and_ranges():
     left = eer.sum_frames(idx, off, W, H, 0, 17)
     right = eer.sum_frames(idx, off, W, H, 17, 23)
     assert np.array_equal(left + right, eer.sum_frames(idx, off, W, H))
+
+
+# ----------------------------------------------------------------------------------------------
+# run-length form (Fig. 1c) and its re-coding to linear indices
+
+
+def test_rle_hand_example():
+    g = _read_golden("eer_hand.txt")
+    idx = np.array(g["idx"], dtype=np.int32)
+    off = np.array(g["off"], dtype=np.int64)
+    d = eer.rle_encode(idx, off)
+    assert d.tolist() == [int(v) for v in g["rle"]]
+    assert eer.rle_decode(d, off).tolist() == [int(v) for v in g["idx_sorted"]]
+
+
+def test_rle_round_trip_and_invariants():
+    rng = np.random.default_rng(41)
+    W, H = 30, 20
+    idx, off = random_csr(rng, 400, W, H, 15.0, sort=False)
+    d = eer.rle_encode(idx, off)
+    assert (d >= 0).all()
+    k = eer.rle_decode(d, off)
+    for f in range(len(off) - 1):
+        seg = slice(off[f], off[f + 1])
+        assert np.array_equal(k[seg], np.sort(idx[seg]))
+        if off[f + 1] > off[f]:
+            # the distances of a frame add up to its largest index
+            assert d[seg].sum() == idx[seg].max()
+    # decoding a sorted list and re-encoding it is the identity
+    assert np.array_equal(eer.rle_encode(k, off), d)
+    # the reductions see the same events
+    assert np.array_equal(eer.com(k, off, W, H)[4], eer.com(idx, off, W, H)[4])
+    assert np.array_equal(eer.sum_frames(k, off, W, H), eer.sum_frames(idx, off, W, H))
