@@ -135,6 +135,17 @@ int eer_load_csr(const int32_t* h_idx, const int64_t* h_off, int64_t frame0, int
                  int64_t n_events, const stem_det* det, int32_t* d_idx, int64_t* d_off,
                  int32_t* d_status, void* stream);
 
+/* Re-coding of the run-length form (Fig. 1c; Table 1: O(C)) into linear indices: within each
+ * frame f of [frame0, frame0 + n_frames), events in ascending pixel order are stored as
+ * distances d_0 = k_0, d_i = k_i - k_(i-1) (>= 0; a repeated pixel gives 0), with the same CSR
+ * offsets d_off as the linear-index form.  Writes d_idx[e] = sum of the frame's distances up to
+ * and including e (a prefix sum restarted at every frame) for the events of those frames.
+ * d_dist and d_idx may not overlap.  Indices outside [0, W*H) (from a negative distance or a
+ * sum past the detector) are written as -1 and set STEM_ERANGE in d_status.
+ * Errors: STEM_EINVAL (NULL pointers, negative frame0 or n_frames, W*H >= 2^31). */
+int eer_decode_rle(const int32_t* d_dist, const int64_t* d_off, int64_t frame0, int64_t n_frames,
+                   const stem_det* det, int32_t* d_idx, int32_t* d_status, void* stream);
+
 /* ---------------------------------------------------------------------------------------- */
 /* a2 + a3. Centre of mass (Eq. 4, Table 1) and DPC integration (Sec. V)                     */
 

@@ -26,7 +26,7 @@ __all__ = [
     "STEM_G_STORE", "STEM_SSB_ACCUMULATE", "STEM_SSB_FINALIZE", "STEM_SSB_REFOCUS",
     "STEM_SSB_ONESHOT", "SsbState", "SSBPhase", "ssb_state_region", "STEM_REGION_D", "STEM_REGION_G",
     "STEM_REGION_T", "STEM_REGION_KC", "STEM_REGION_STATS", "trace_enable", "trace_records",
-    "virtual_annular", "sum_frames",
+    "virtual_annular", "sum_frames", "eer_decode_rle",
 ]
 
 
@@ -89,6 +89,16 @@ def eer_load_csr(h_idx, h_off, frame0: int, n_frames: int, n_events: int, det: D
     rc = lib().eer_load_csr(_p(h_idx), _p(h_off), frame0, n_frames, n_events, ctypes.byref(det),
                             _p(d_idx), _p(d_off), _p(d_status), _stream(stream))
     _check(rc, "eer_load_csr")
+
+
+def eer_decode_rle(d_dist, d_off, frame0: int, n_frames: int, det: Det, d_idx, d_status=None, stream=None):
+    """Run-length form (per-frame distances between ascending hits) -> linear indices d_idx."""
+    _dev(d_dist, torch.int32, "d_dist")
+    _dev(d_off, torch.int64, "d_off")
+    _dev(d_idx, torch.int32, "d_idx")
+    rc = lib().eer_decode_rle(_p(d_dist), _p(d_off), frame0, n_frames, ctypes.byref(det), _p(d_idx), _p(d_status),
+                              _stream(stream))
+    _check(rc, "eer_decode_rle")
 
 
 # ----------------------------------------------------------------------------------------------

@@ -80,6 +80,8 @@ _SIGS = {
                                     ctypes.POINTER(Optics), ctypes.POINTER(Ssb), ctypes.c_void_p,
                                     ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p,
                                     ctypes.c_void_p, ctypes.c_void_p]),
+    "eer_decode_rle": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                      ctypes.POINTER(Det), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "virtual_annular": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
                                        ctypes.POINTER(Det), ctypes.POINTER(Scan), ctypes.c_int,
                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),

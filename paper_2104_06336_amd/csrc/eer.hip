@@ -132,7 +132,7 @@ __global__ void __launch_bounds__(kComThreads) k_com(const int32_t* __restrict__
                                                      float* __restrict__ com32,
                                                      int32_t* __restrict__ counts,
                                                      int32_t* status) {
-  __shared__ int32_t s_ev[kComWin + 8];
+  __shared__ __align__(16) int32_t s_ev[kComWin + 8];
   __shared__ int32_t s_rel[kComFrames + 1];
   __shared__ int64_t s_base;
   const int t = threadIdx.x;
@@ -218,7 +218,7 @@ __global__ void __launch_bounds__(kComThreads) k_annular(const int32_t* __restri
                                                          int64_t n_frames, Magic divw, int32_t cx, int32_t cy,
                                                          int32_t npix, Annuli an, int64_t F,
                                                          int32_t* __restrict__ out, int32_t* status) {
-  __shared__ int32_t s_ev[kComWin + 8];
+  __shared__ __align__(16) int32_t s_ev[kComWin + 8];
   __shared__ int32_t s_rel[kComFrames + 1];
   __shared__ int64_t s_base;
   const int t = threadIdx.x;
@@ -337,6 +337,60 @@ __global__ void __launch_bounds__(256) k_frame_mean(const uint32_t* __restrict__
                                                     float* __restrict__ mean) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p < npix) mean[p] = (float)((double)sum[p] / n);
+}
+
+// ---------------------------------------------------------------------------------------------
+// run-length form -> linear indices: the block's distances are staged in LDS like k_com's
+// events, thread t replaces its frame's distances by their running sum in place, and the
+// workgroup writes the window back with 16-byte stores (the store groups that are not wholly
+// inside the window are written element by element).
+
+__global__ void __launch_bounds__(kComThreads) k_decode_rle(const int32_t* __restrict__ dist,
+                                                            const int64_t* __restrict__ off, int64_t frame0,
+                                                            int64_t n_frames, int32_t npix,
+                                                            int32_t* __restrict__ idx, int32_t* status) {
+  __shared__ __align__(16) int32_t s_ev[kComWin + 8];
+  __shared__ int32_t s_rel[kComFrames + 1];
+  __shared__ int64_t s_base;
+  const int t = threadIdx.x;
+  const int64_t fb = frame0 + (int64_t)blockIdx.x * kComFrames;
+  const int64_t left = frame0 + n_frames - fb;
+  const int nf = (int)(left < kComFrames ? left : kComFrames);
+  if (!load_rel_offsets(off, fb, nf, s_rel, &s_base, status)) return;
+  __syncthreads();
+  const int span = s_rel[nf];
+  const int lo_t = t < nf ? s_rel[t] : 0, hi_t = t < nf ? s_rel[t + 1] : 0;
+  int64_t run = 0;  // running sum of frame t, carried across windows
+  uint32_t nbad = 0;
+  for (int w0 = 0; w0 < span; w0 += kComWin) {
+    const int wn = span - w0 < kComWin ? span - w0 : kComWin;
+    __syncthreads();
+    const int sh = stage_events(dist, s_base + w0, wn, s_ev);
+    __syncthreads();
+    const int lo = (lo_t > w0 ? lo_t : w0) - w0 + sh;
+    const int hi = (hi_t < w0 + wn ? hi_t : w0 + wn) - w0 + sh;
+    for (int e = lo; e < hi; ++e) {
+      run += s_ev[e];
+      const bool in = run >= 0 && run < npix;
+      nbad += in ? 0u : 1u;
+      s_ev[e] = in ? (int32_t)run : -1;
+    }
+    __syncthreads();
+    // write back [sh, sh + wn) of the staging buffer to idx[s_base + w0 ...]
+    const int64_t a0 = s_base + w0, aend = a0 + wn, al = a0 - sh;
+    const int nchunk = (wn + sh + 3) >> 2;
+    for (int c = t; c < nchunk; c += blockDim.x) {
+      const int64_t e = al + 4 * (int64_t)c;
+      if (e >= a0 && e + 4 <= aend && ((((uintptr_t)(idx + e)) & 15) == 0)) {
+        *(int4*)(idx + e) = *(const int4*)&s_ev[4 * c];
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (e + j >= a0 && e + j < aend) idx[e + j] = s_ev[4 * c + j];
+      }
+    }
+  }
+  if (nbad) report(status, STEM_ERANGE);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -711,5 +765,19 @@ extern "C" int sum_frames(const int32_t* d_idx, const int64_t* d_off, int64_t fr
                        (double)n_frames, d_mean);
     STEM_LAUNCH_CHECK();
   }
+  return STEM_OK;
+}
+
+extern "C" int eer_decode_rle(const int32_t* d_dist, const int64_t* d_off, int64_t frame0, int64_t n_frames,
+                              const stem_det* det, int32_t* d_idx, int32_t* d_status, void* stream_) {
+  if (!d_dist || !d_off || !det || !d_idx || frame0 < 0 || n_frames < 0) return STEM_EINVAL;
+  if (det->W <= 0 || det->H <= 0 || (int64_t)det->W * det->H >= (1ll << 31)) return STEM_EINVAL;
+  if (n_frames == 0) return STEM_OK;
+  hipStream_t s = (hipStream_t)stream_;
+  const int64_t blocks = (n_frames + kComFrames - 1) / kComFrames;
+  STEM_TRACE("decode_rle", s);
+  hipLaunchKernelGGL(k_decode_rle, dim3((unsigned)blocks), dim3(kComThreads), 0, s, d_dist, d_off, frame0, n_frames,
+                     det->W * det->H, d_idx, d_status);
+  STEM_LAUNCH_CHECK();
   return STEM_OK;
 }
