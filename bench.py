@@ -350,6 +350,26 @@ def main():
             "annular_events_per_s": round(C / (kv.get("virtual_annular", float("nan")) * 1e-6), 1)}
         log(f"virtual detectors: {el_v / args.steps * 1e3:.3f} ms {kv}")
         del vd, pac
+        # run-length form of the same events re-coded to linear indices
+        from gen import run_length_form
+        dist = run_length_form(d_idx, d_off)
+        dec = torch.empty_like(d_idx)
+        for _ in range(args.warmup):
+            stem.eer_decode_rle(dist, d_off, 0, F, det, dec, d_status=status)
+        torch.cuda.synchronize()
+        stem.trace_enable(True)
+        for _ in range(args.steps):
+            stem.eer_decode_rle(dist, d_off, 0, F, det, dec, d_status=status)
+        torch.cuda.synchronize()
+        rr = stem.trace_records()
+        stem.trace_enable(False)
+        stem.check_status(status, "run-length decoding")
+        assert torch.equal(dec, d_idx)
+        n_, ms_ = rr["decode_rle"]
+        extras["decode_rle"] = {"workload": "scan1024 events in run-length form", "us": round(ms_ / n_ * 1e3, 2),
+                                "events_per_s": round(C / (ms_ / n_ * 1e-3), 1)}
+        log(f"run-length decoding: {ms_ / n_ * 1e3:.1f} us")
+        del dist, dec
 
     # end to end from pinned host memory: 16 chunks of 64 scan rows; the copy (and validation) of
     # chunk k+1 on a copy stream overlaps COM + binning + row transform of chunk k

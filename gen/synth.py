@@ -358,3 +358,14 @@ def shuffle_within_frames(rng: np.random.Generator, idx: np.ndarray, off: np.nda
         seg = out[off[f]:off[f + 1]]
         rng.shuffle(seg)
     return out
+
+
+def run_length_form(idx, off):
+    """Run-length form (Fig. 1c) of events sorted within their frames, as synthetic input for the
+    re-coding path: d_0 = k_0 and d_i = k_i - k_(i-1) inside each frame (torch, same device)."""
+    k = idx.to(torch.int64)
+    d = k.clone()
+    d[1:] -= k[:-1]
+    starts = off[:-1][off[1:] > off[:-1]]  # first event of every non-empty frame
+    d[starts] = k[starts]
+    return d.to(torch.int32)

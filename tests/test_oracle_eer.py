@@ -251,3 +251,14 @@ def test_rle_round_trip_and_invariants():
     # the reductions see the same events
     assert np.array_equal(eer.com(k, off, W, H)[4], eer.com(idx, off, W, H)[4])
     assert np.array_equal(eer.sum_frames(k, off, W, H), eer.sum_frames(idx, off, W, H))
+
+
+def test_generator_run_length_form_matches_oracle():
+    """The benchmark's synthetic run-length input equals the oracle's encoding of sorted frames."""
+    import torch
+    from gen import run_length_form
+
+    rng = np.random.default_rng(52)
+    idx, off = random_csr(rng, 300, 25, 17, 12.0, p_empty=0.2, sort=True)
+    got = run_length_form(torch.from_numpy(idx), torch.from_numpy(off)).numpy()
+    assert np.array_equal(got, eer.rle_encode(idx, off))
