@@ -22,7 +22,8 @@ constexpr int kMaxPixels = 4096;
 struct SsbLayout {
   int n_k, nby, nh;
   int64_t F;
-  size_t rows, kc, kchi, cst, lut, stats, D, X, T, A, Tb, pdc, pdth, part, total;
+  size_t rows, kc, kchi, cst, cmask, lut, stats, D, X, T, A, Tb, pdc, pdth, part, total;
+  int nmw;      // 64-bit words per column set of the active-pixel mask
   int groups;  // pixel groups of the fused column transform + sum
   int ncs;     // column sets (B = 1024/Ny half-spectrum columns each)
   int64_t nwy; // waves of the fused kernels
@@ -66,6 +67,8 @@ static size_t make_layout(const stem_det& det, const stem_scan& scan, const stem
   L->kc = o;    o = align256(o + sizeof(double2) * n_k);
   L->kchi = o;  o = align256(o + sizeof(double) * n_k);
   L->cst = o;   o = align256(o + sizeof(int4) * n_k * L->nh);
+  L->nmw = (n_k + 63) / 64;
+  L->cmask = o; o = align256(o + sizeof(uint64_t) * (size_t)L->nmw * ((L->nh + 1024 / scan.ny - 1) / (1024 / scan.ny)));
   L->lut = o;   o = align256(o + sizeof(int16_t) * (size_t)det.W * det.H);
   L->stats = o; o = align256(o + sizeof(unsigned long long) * 4);
   L->D = o;     o = align256(o + (size_t)n_k * L->F * (ssb.d_bits / 8));
@@ -114,23 +117,52 @@ __global__ void __launch_bounds__(256) k_colsets(const double2* __restrict__ kc,
   cst[t] = make_int4(pk(d.a0, d.a1), pk(d.b0, d.b1), pk(m.a0, m.a1), pk(m.b0, m.b1));
 }
 
-// the interval table, then the fused column sum
-static int launch_yreduce(int prec, int ny, float2* X, const double2* kc, const double* kchi, int4* cst, int n_k,
-                          int nx, int ngroups, const Optics& o, int store_g, float2* part,
-                          unsigned long long* stats, hipStream_t s) {
+// active-pixel mask: bit kd of word (cs, kd/64) is set when some column of column set cs (B = 1024/Ny
+// half-spectrum columns) has a non-empty set for pixel kd
+__global__ void __launch_bounds__(256) k_colmask(const int4* __restrict__ cst, int n_k, int nc, int B, int ncs,
+                                                 int nmw, uint64_t* __restrict__ mask) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)ncs * nmw) return;
+  const int cs = (int)(t / nmw), w = (int)(t % nmw);
+  uint64_t bits = 0;
+  for (int j = 0; j < 64 && 64 * w + j < n_k; ++j) {
+    const int kd = 64 * w + j;
+    bool any = false;
+    for (int c = cs * B; c < cs * B + B && c < nc; ++c) {
+      const int4 r = cst[(int64_t)kd * nc + c];
+      const bool de = (int)(short)(r.x & 0xffff) > (r.x >> 16), me = (int)(short)(r.z & 0xffff) > (r.z >> 16);
+      any = any || !de || !me;
+    }
+    if (any) bits |= 1ull << j;
+  }
+  mask[t] = bits;
+}
+
+// the interval table and the active-pixel mask, then the fused column sum
+static int launch_yreduce(int prec, int ny, float2* X, const double2* kc, const double* kchi, int4* cst,
+                          uint64_t* cmask, int nmw, int n_k, int nx, int ngroups, const Optics& o, int store_g,
+                          float2* part, unsigned long long* stats, hipStream_t s) {
   {
     STEM_TRACE("ssb_colsets", s);
-    const int64_t n = (int64_t)n_k * (nx / 2 + 1);
+    const int nc = nx / 2 + 1, B = 1024 / ny, ncs = (nc + B - 1) / B;
+    const int64_t n = (int64_t)n_k * nc;
     hipLaunchKernelGGL(k_colsets, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, kc, n_k, nx, ny, o, cst);
+    STEM_LAUNCH_CHECK();
+    const int64_t nm = (int64_t)ncs * nmw;
+    hipLaunchKernelGGL(k_colmask, dim3((unsigned)((nm + 255) / 256)), dim3(256), 0, s, cst, n_k, nc, B, ncs, nmw,
+                       cmask);
     STEM_LAUNCH_CHECK();
   }
   switch (prec) {
     case STEM_DFT_BF16_SPLIT:
-      return launch_yreduce_p<STEM_DFT_BF16_SPLIT>(ny, X, kc, kchi, cst, n_k, nx, ngroups, o, store_g, part, stats, s);
+      return launch_yreduce_p<STEM_DFT_BF16_SPLIT>(ny, X, kc, kchi, cst, cmask, nmw, n_k, nx, ngroups, o, store_g,
+                                                   part, stats, s);
     case STEM_DFT_FP16_SPLIT:
-      return launch_yreduce_p<STEM_DFT_FP16_SPLIT>(ny, X, kc, kchi, cst, n_k, nx, ngroups, o, store_g, part, stats, s);
+      return launch_yreduce_p<STEM_DFT_FP16_SPLIT>(ny, X, kc, kchi, cst, cmask, nmw, n_k, nx, ngroups, o, store_g,
+                                                   part, stats, s);
     default:
-      return launch_yreduce_p<STEM_FFT_FP32>(ny, X, kc, kchi, cst, n_k, nx, ngroups, o, store_g, part, stats, s);
+      return launch_yreduce_p<STEM_FFT_FP32>(ny, X, kc, kchi, cst, cmask, nmw, n_k, nx, ngroups, o, store_g, part,
+                                             stats, s);
   }
 }
 
@@ -308,6 +340,7 @@ struct Bufs {
   double2* kc;
   double* kchi;
   int4* cst;
+  uint64_t* cmask;
   int16_t* lut;
   unsigned long long* stats;
   void* D;
@@ -323,7 +356,7 @@ struct Bufs {
 static Bufs carve(void* state, const SsbLayout& L) {
   char* p = (char*)state;
   return Bufs{(RowRun*)(p + L.rows), (double2*)(p + L.kc), (double*)(p + L.kchi), (int4*)(p + L.cst),
-              (int16_t*)(p + L.lut),
+              (uint64_t*)(p + L.cmask), (int16_t*)(p + L.lut),
               (unsigned long long*)(p + L.stats), (void*)(p + L.D),
               (float2*)(p + L.X),    (float2*)(p + L.T),  (float2*)(p + L.A),     (float2*)(p + L.Tb),
               (double*)(p + L.pdc),  (float*)(p + L.pdth), (float2*)(p + L.part)};
@@ -483,7 +516,7 @@ extern "C" int ssb_reconstruct(const int32_t* d_idx, const int64_t* d_off, int64
   if (ssb->normalize && ssb->precision != STEM_FFT_FP32) {
     // split precision: the fused kernel transforms X -> G in place (its partial sums are not
     // used); the counters are reset before the per-Q normalised sum
-    if ((st = launch_yreduce(ssb->precision, ny, b.X, b.kc, b.kchi, b.cst, n_k, nx, L.groups, o, 1, b.part, b.stats, s)))
+    if ((st = launch_yreduce(ssb->precision, ny, b.X, b.kc, b.kchi, b.cst, b.cmask, L.nmw, n_k, nx, L.groups, o, 1, b.part, b.stats, s)))
       return st;
     if ((st = run_chi_table(b, d_theta, n_k, o, 1, s))) return st;
     if ((st = run_reduce_stored(L, b, ny, nx, o, 1, s))) return st;
@@ -502,7 +535,7 @@ extern "C" int ssb_reconstruct(const int32_t* d_idx, const int64_t* d_off, int64
     if ((st = run_reduce_stored(L, b, ny, nx, o, 1, s))) return st;
     return run_phase(L, b, *scan, b.T, 1, d_phase, d_T, s);
   }
-  if ((st = launch_yreduce(ssb->precision, ny, b.X, b.kc, b.kchi, b.cst, n_k, nx, L.groups, o, ssb->g_mode == STEM_G_STORE,
+  if ((st = launch_yreduce(ssb->precision, ny, b.X, b.kc, b.kchi, b.cst, b.cmask, L.nmw, n_k, nx, L.groups, o, ssb->g_mode == STEM_G_STORE,
                            b.part, b.stats, s)))
     return st;
   return run_phase(L, b, *scan, b.part, L.groups, d_phase, d_T, s);

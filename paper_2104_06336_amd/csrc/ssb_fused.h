@@ -230,7 +230,8 @@ __device__ __forceinline__ void load_colsets(const int4* __restrict__ cst, int64
 template <typename XF>
 __global__ void __launch_bounds__(kYThreads, 2) k_yreduce(float2* __restrict__ X, const double2* __restrict__ kc,
                                                        const double* __restrict__ kchi,
-                                                       const int4* __restrict__ cst, int n_k, int nx,
+                                                       const int4* __restrict__ cst,
+                                                       const uint64_t* __restrict__ cmask, int nmw, int n_k, int nx,
                                                        int ngroups, Optics o, int store_g,
                                                        float2* __restrict__ part,
                                                        unsigned long long* __restrict__ stats) {
@@ -259,11 +260,42 @@ __global__ void __launch_bounds__(kYThreads, 2) k_yreduce(float2* __restrict__ X
   for (int i = 0; i < 16; ++i) accd[i] = accm[i] = make_float2(0.f, 0.f);
   unsigned cnt = 0;
   const int64_t kstride = (int64_t)nc * NY;
-  for (int kd = kd_a; kd < kd_b; ++kd) {
+  // the pixels of [kd_a, kd_b) with a non-empty set in this column set (every pixel with store_g):
+  // bits of the column set's mask, scanned with scalar operations
+  const uint64_t* mrow = cmask + (int64_t)cs * nmw;
+  auto next_kd = [&](int from) -> int {
+    if (store_g) return from < kd_b ? from : kd_b;
+    for (int kd = from; kd < kd_b;) {
+      const int w = kd >> 6;
+      const uint64_t bits = mrow[w] >> (kd & 63);
+      if (bits) {
+        kd += __builtin_ctzll(bits);
+        return kd < kd_b ? kd : kd_b;
+      }
+      kd = (w + 1) << 6;
+    }
+    return kd_b;
+  };
+  auto load_col = [&](int kd, float2* v) {
+    const float2* xcol = X + kd * kstride + (int64_t)c0 * NY;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      int b, n;
+      XF::in(lane, i, b, n);
+      v[i] = (c0 + b < nc) ? xcol[(int64_t)b * NY + n] : make_float2(0.f, 0.f);
+    }
+  };
+  int kd = next_kd(kd_a);
+  float2 v[16];
+  if (kd < kd_b) load_col(kd, v);
+  while (kd < kd_b) {
+    // the next active pixel's column is loaded while this one is transformed and summed
+    const int kdn = next_kd(kd + 1);
+    float2 vn[16];
+    if (kdn < kd_b) load_col(kdn, vn);
     const double2 k = kc[kd];
     // double-overlap sets of this pixel for the lane's columns (direct and mirrored)
     ColSet sd[SL::kSlots], sm[SL::kSlots];
-    bool any = false;
 #pragma unroll
     for (int sl = 0; sl < SL::kSlots; ++sl) {
       int b0, m0;
@@ -272,17 +304,6 @@ __global__ void __launch_bounds__(kYThreads, 2) k_yreduce(float2* __restrict__ X
       sd[sl] = ColSet{1, 0, 1, 0};
       sm[sl] = ColSet{1, 0, 1, 0};
       if (c < nc) load_colsets(cst, (int64_t)kd * nc + c, sd[sl], sm[sl]);
-      any = any || !sd[sl].empty() || !sm[sl].empty();
-    }
-    // with store_g every pixel is transformed, so that the stored G is complete
-    if (!store_g && !__ballot(any)) continue;
-    float2 v[16];
-    const float2* xcol = X + kd * kstride + (int64_t)c0 * NY;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      int b, n;
-      XF::in(lane, i, b, n);
-      v[i] = (c0 + b < nc) ? xcol[(int64_t)b * NY + n] : make_float2(0.f, 0.f);
     }
     XF::template run<false>(v, buf, s_tw, s_tab, lane);
     if (store_g) {
@@ -328,6 +349,9 @@ __global__ void __launch_bounds__(kYThreads, 2) k_yreduce(float2* __restrict__ X
         }
       }
     }
+    kd = kdn;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = vn[i];
   }
   float2* pg = part + (int64_t)g * nx * NY;
 #pragma unroll
@@ -500,8 +524,8 @@ int launch_xstage_p(int nx, const DT* D, int ny, int ry0, int nr, int64_t nrows,
 }
 
 template <int PREC>
-int launch_yreduce_p(int ny, float2* X, const double2* kc, const double* kchi, const int4* cst, int n_k, int nx,
-                     int ngroups, const Optics& o,
+int launch_yreduce_p(int ny, float2* X, const double2* kc, const double* kchi, const int4* cst,
+                     const uint64_t* cmask, int nmw, int n_k, int nx, int ngroups, const Optics& o,
                      int store_g, float2* part, unsigned long long* stats, hipStream_t s) {
   const int B = 1024 / ny;
   const int ncs = (nx / 2 + 1 + B - 1) / B;
@@ -509,8 +533,8 @@ int launch_yreduce_p(int ny, float2* X, const double2* kc, const double* kchi, c
   STEM_TRACE(PREC == STEM_FFT_FP32 ? "ssb_yreduce" : "ssb_yreduce_mfma", s);
   const int st = with_n(ny, [&](auto nc) {
     using XF = typename XfSel<decltype(nc)::value, PREC>::type;
-    hipLaunchKernelGGL((k_yreduce<XF>), grid, blk, 0, s, X, kc, kchi, cst, n_k, nx, ngroups, o, store_g, part,
-                       stats);
+    hipLaunchKernelGGL((k_yreduce<XF>), grid, blk, 0, s, X, kc, kchi, cst, cmask, nmw, n_k, nx, ngroups, o, store_g,
+                       part, stats);
   });
   if (st) return st;
   STEM_LAUNCH_CHECK();
@@ -537,13 +561,13 @@ int launch_yadjoint_p(int ny, const float2* X, const double2* kc, const double* 
 
 extern template int launch_xstage_p<STEM_DFT_BF16_SPLIT, uint8_t>(int, const uint8_t*, int, int, int, int64_t, float2*, hipStream_t);
 extern template int launch_xstage_p<STEM_DFT_BF16_SPLIT, uint16_t>(int, const uint16_t*, int, int, int, int64_t, float2*, hipStream_t);
-extern template int launch_yreduce_p<STEM_DFT_BF16_SPLIT>(int, float2*, const double2*, const double*, const int4*, int, int, int,
+extern template int launch_yreduce_p<STEM_DFT_BF16_SPLIT>(int, float2*, const double2*, const double*, const int4*, const uint64_t*, int, int, int, int,
                                             const Optics&, int, float2*, unsigned long long*, hipStream_t);
 extern template int launch_yadjoint_p<STEM_DFT_BF16_SPLIT>(int, const float2*, const double2*, const double*, const int4*, int, int, int,
                                              const Optics&, int, const float2*, double*, float*, hipStream_t);
 extern template int launch_xstage_p<STEM_DFT_FP16_SPLIT, uint8_t>(int, const uint8_t*, int, int, int, int64_t, float2*, hipStream_t);
 extern template int launch_xstage_p<STEM_DFT_FP16_SPLIT, uint16_t>(int, const uint16_t*, int, int, int, int64_t, float2*, hipStream_t);
-extern template int launch_yreduce_p<STEM_DFT_FP16_SPLIT>(int, float2*, const double2*, const double*, const int4*, int, int, int,
+extern template int launch_yreduce_p<STEM_DFT_FP16_SPLIT>(int, float2*, const double2*, const double*, const int4*, const uint64_t*, int, int, int, int,
                                             const Optics&, int, float2*, unsigned long long*, hipStream_t);
 extern template int launch_yadjoint_p<STEM_DFT_FP16_SPLIT>(int, const float2*, const double2*, const double*, const int4*, int, int, int,
                                              const Optics&, int, const float2*, double*, float*, hipStream_t);
