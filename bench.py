@@ -75,6 +75,89 @@ def load_traffic(kernel, workload):
     return ent.get("bytes_per_launch")
 
 
+# rocprofv3 kernel names of the kernels bench.py reports, by their trace name
+PROFILED = {
+    "stem::k_com": "com_moments",
+    "stem::k_bin<unsigned char>": "bin_densify",
+    "stem::k_xstage<stem::XfFft<1024>, unsigned char>": "xstage_fft",
+    "stem::k_yreduce<stem::XfFft<1024> >": "ssb_yreduce",
+    "stem::k_dpc_update": "dpc_update",
+}
+
+
+def _pmc_rows(path):
+    """Per-dispatch counter sums of a rocprofv3 --pmc CSV: {(dispatch, kernel, grid): {counter: value}}."""
+    import csv
+    rows = {}
+    with open(path, newline="") as fh:
+        for r in csv.DictReader(fh):
+            key = (int(r["Dispatch_Id"]), r["Kernel_Name"], int(r["Grid_Size"]))
+            rows.setdefault(key, {})[r["Counter_Name"]] = float(r["Counter_Value"])
+    return rows
+
+
+def summarize_profile(d, workload):
+    """Turns the CSVs of the three counter runs and the kernel-trace run (written by the
+    commands in the profile notes) into profiles/traffic.json and markdown tables.
+
+    Reads: raw TCC_EA0_RDREQ_{32B,64B,128B} request counts times their sizes, divided by the factor
+    the same counters give for k_validate (a plain streaming read of 4C + 8(F+1) bytes; C and F
+    from the JSON line of that run).  Writes: WRITE_SIZE (KiB) divided by its factor for the
+    1 GiB device copy (the copy kernel whose grid covers 2^28 floats in 8-float pieces)."""
+    import statistics
+    out_line = [ln for ln in open(os.path.join(d, "RDREQ.out")) if ln.startswith("{")][-1]
+    cfg = json.loads(out_line)["config"]
+    C, F = cfg["events"], cfg["frames"]
+    rd, wr = _pmc_rows(os.path.join(d, "RDREQ.csv")), _pmc_rows(os.path.join(d, "WRITE_SIZE.csv"))
+    fetch = _pmc_rows(os.path.join(d, "FETCH_SIZE.csv")) if os.path.exists(os.path.join(d, "FETCH_SIZE.csv")) else {}
+
+    def rbytes(c):
+        return (32 * c.get("TCC_EA0_RDREQ_32B_sum", 0) + 64 * c.get("TCC_EA0_RDREQ_64B_sum", 0)
+                + 128 * c.get("TCC_EA0_RDREQ_128B_sum", 0))
+
+    def per_kernel(rows, name, f):
+        v = [f(c) for (_, k, _), c in rows.items() if k.startswith(("void " + name + "(", name + "("))]
+        return (statistics.mean(v), len(v)) if v else (None, 0)
+
+    val = per_kernel(rd, "stem::k_validate", rbytes)[0]
+    read_factor = val / (4 * C + 8 * (F + 1))
+    copies = [c["WRITE_SIZE"] * 1024 for (_, k, g), c in wr.items() if "direct_copy" in k and g == 33546240]
+    write_factor = statistics.mean(copies) / (1 << 30)
+    rec = {"_note": summarize_profile.__doc__.split("\n\n")[1].replace("\n    ", " ").strip(),
+           "read_factor": round(read_factor, 5), "write_factor": round(write_factor, 5)}
+    sha = source_sha()
+    lines = ["| Kernel | Trace name | Dispatches | FETCH_SIZE (MB, raw) | Reads (MB, calibrated) "
+             "| Writes (MB, calibrated) |", "|---|---|---:|---:|---:|---:|"]
+    for kname, tname in PROFILED.items():
+        r, n = per_kernel(rd, kname, rbytes)
+        w, _ = per_kernel(wr, kname, lambda c: c["WRITE_SIZE"] * 1024)
+        fs, _ = per_kernel(fetch, kname, lambda c: c["FETCH_SIZE"] * 1024)
+        if r is None or w is None:
+            continue
+        r, w = r / read_factor, w / write_factor
+        rec[f"{tname}@{workload}"] = {"bytes_per_launch": int(r + w), "read_bytes": int(r), "write_bytes": int(w),
+                                      "source_sha": sha}
+        lines.append(f"| `{kname}` | {tname} | {n} | {fs / 1e6 if fs else float('nan'):.1f} | {r / 1e6:.1f} "
+                     f"| {w / 1e6:.1f} |")
+    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
+        json.dump(rec, fh, indent=1)
+        fh.write("\n")
+    print(f"C = {C}, F = {F}; read factor {read_factor:.5f} (k_validate), write factor {write_factor:.5f} "
+          f"(1 GiB copy, {len(copies)} dispatches); sources sha {sha}\n")
+    print("\n".join(lines))
+    stats = os.path.join(d, "kernel_stats.csv")
+    if os.path.exists(stats):
+        import csv
+        print("\n| Kernel | Calls | Average µs | Min µs | Max µs |\n|---|---:|---:|---:|---:|")
+        with open(stats, newline="") as fh:
+            for r in csv.DictReader(fh):
+                name = r["Name"].removeprefix("void ")
+                if name.startswith("stem::"):
+                    name = name[:name.rfind("(")] if name.endswith(")") else name
+                    print(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} "
+                          f"| {float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} |")
+
+
 def cpu_baseline(idx, off, wl):
     """The FP64 oracle on the host over the whole workload (COM + DPC, binning, scan DFT,
     Eq. 3 sum, phase), each stage timed; numpy runs these single-threaded."""
@@ -123,7 +206,12 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the refocus and adjoint timings")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run a device copy of this many MiB first (counter calibration)")
+    ap.add_argument("--summarize-profile", metavar="DIR",
+                    help="no GPU work: turn the rocprofv3 CSVs in DIR into profiles/traffic.json and tables")
     args = ap.parse_args()
+    if args.summarize_profile:
+        summarize_profile(args.summarize_profile, args.workload)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the path has no multi-GPU mode in this build "
               "(see the sharding notes in the design document); run with --gpus 1", file=sys.stderr)

@@ -102,57 +102,50 @@ static int launch_xstage_t(int prec, int nx, const DT* D, int ny, int ry0, int n
   }
 }
 
-// double-overlap intervals of every (pixel, half-spectrum column) and of its mirror
+// Double-overlap intervals of every (pixel, half-spectrum column) and of its mirror, and the
+// active-pixel mask: bit j of word (cs, w) is set when pixel 64 w + j has a non-empty set in some
+// column of column set cs (B = 1024/Ny consecutive half-spectrum columns).  One wave per mask
+// word: lane j takes pixel 64 w + j over the columns of the set, a ballot packs the 64 answers.
 __global__ void __launch_bounds__(256) k_colsets(const double2* __restrict__ kc, int n_k, int nx, int ny, Optics o,
-                                                 int4* __restrict__ cst) {
+                                                 int B, int ncs, int nmw, int4* __restrict__ cst,
+                                                 uint64_t* __restrict__ mask) {
   const int nc = nx / 2 + 1;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)n_k * nc) return;
-  const int kd = (int)(t / nc), c = (int)(t % nc);
-  const double2 k = kc[kd];
-  const ColSet d = col_set(k.x, k.y, signed_index(c, nx), ny, o);
-  ColSet m{1, 0, 1, 0};
-  if (c > 0 && 2 * c < nx) m = col_set(k.x, k.y, signed_index(nx - c, nx), ny, o);
+  const int64_t word = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (word >= (int64_t)ncs * nmw) return;  // uniform across the wave
+  const int cs = (int)(word / nmw), w = (int)(word % nmw);
+  const int kd = 64 * w + (int)(threadIdx.x & 63);
   auto pk = [](int lo, int hi) { return (int)(((uint32_t)lo & 0xffffu) | ((uint32_t)hi << 16)); };
-  cst[t] = make_int4(pk(d.a0, d.a1), pk(d.b0, d.b1), pk(m.a0, m.a1), pk(m.b0, m.b1));
+  bool any = false;
+  if (kd < n_k) {
+    const double2 k = kc[kd];
+    const int c1 = cs * B + B < nc ? cs * B + B : nc;
+    for (int c = cs * B; c < c1; ++c) {
+      const ColSet d = col_set(k.x, k.y, signed_index(c, nx), ny, o);
+      ColSet m{1, 0, 1, 0};
+      if (c > 0 && 2 * c < nx) m = col_set(k.x, k.y, signed_index(nx - c, nx), ny, o);
+      cst[(int64_t)kd * nc + c] = make_int4(pk(d.a0, d.a1), pk(d.b0, d.b1), pk(m.a0, m.a1), pk(m.b0, m.b1));
+      any = any || d.a0 <= d.a1 || m.a0 <= m.a1;
+    }
+  }
+  const uint64_t bits = __ballot(any);
+  if ((threadIdx.x & 63) == 0) mask[word] = bits;
 }
 
-// active-pixel mask: bit kd of word (cs, kd/64) is set when some column of column set cs (B = 1024/Ny
-// half-spectrum columns) has a non-empty set for pixel kd
-__global__ void __launch_bounds__(256) k_colmask(const int4* __restrict__ cst, int n_k, int nc, int B, int ncs,
-                                                 int nmw, uint64_t* __restrict__ mask) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)ncs * nmw) return;
-  const int cs = (int)(t / nmw), w = (int)(t % nmw);
-  uint64_t bits = 0;
-  for (int j = 0; j < 64 && 64 * w + j < n_k; ++j) {
-    const int kd = 64 * w + j;
-    bool any = false;
-    for (int c = cs * B; c < cs * B + B && c < nc; ++c) {
-      const int4 r = cst[(int64_t)kd * nc + c];
-      const bool de = (int)(short)(r.x & 0xffff) > (r.x >> 16), me = (int)(short)(r.z & 0xffff) > (r.z >> 16);
-      any = any || !de || !me;
-    }
-    if (any) bits |= 1ull << j;
-  }
-  mask[t] = bits;
+static void launch_colsets(const double2* kc, int n_k, int nx, int ny, const Optics& o, int4* cst, uint64_t* cmask,
+                           int nmw, hipStream_t s) {
+  STEM_TRACE("ssb_colsets", s);
+  const int B = 1024 / ny, ncs = (nx / 2 + 1 + B - 1) / B;
+  const int64_t words = (int64_t)ncs * nmw;
+  hipLaunchKernelGGL(k_colsets, dim3((unsigned)((words + 3) / 4)), dim3(256), 0, s, kc, n_k, nx, ny, o, B, ncs, nmw,
+                     cst, cmask);
 }
 
 // the interval table and the active-pixel mask, then the fused column sum
 static int launch_yreduce(int prec, int ny, float2* X, const double2* kc, const double* kchi, int4* cst,
                           uint64_t* cmask, int nmw, int n_k, int nx, int ngroups, const Optics& o, int store_g,
                           float2* part, unsigned long long* stats, hipStream_t s) {
-  {
-    STEM_TRACE("ssb_colsets", s);
-    const int nc = nx / 2 + 1, B = 1024 / ny, ncs = (nc + B - 1) / B;
-    const int64_t n = (int64_t)n_k * nc;
-    hipLaunchKernelGGL(k_colsets, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, kc, n_k, nx, ny, o, cst);
-    STEM_LAUNCH_CHECK();
-    const int64_t nm = (int64_t)ncs * nmw;
-    hipLaunchKernelGGL(k_colmask, dim3((unsigned)((nm + 255) / 256)), dim3(256), 0, s, cst, n_k, nc, B, ncs, nmw,
-                       cmask);
-    STEM_LAUNCH_CHECK();
-  }
+  launch_colsets(kc, n_k, nx, ny, o, cst, cmask, nmw, s);
+  STEM_LAUNCH_CHECK();
   switch (prec) {
     case STEM_DFT_BF16_SPLIT:
       return launch_yreduce_p<STEM_DFT_BF16_SPLIT>(ny, X, kc, kchi, cst, cmask, nmw, n_k, nx, ngroups, o, store_g,
@@ -167,14 +160,10 @@ static int launch_yreduce(int prec, int ny, float2* X, const double2* kc, const 
 }
 
 static int launch_yadjoint(int prec, int ny, const float2* X, const double2* kc, const double* kchi, int4* cst,
-                           int n_k, int nx, int ngroups, const Optics& o, int g_stored, const float2* Tbt,
-                           double* pdc, float* pdth, hipStream_t s) {
-  {
-    STEM_TRACE("ssb_colsets", s);
-    const int64_t n = (int64_t)n_k * (nx / 2 + 1);
-    hipLaunchKernelGGL(k_colsets, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, kc, n_k, nx, ny, o, cst);
-    STEM_LAUNCH_CHECK();
-  }
+                           uint64_t* cmask, int nmw, int n_k, int nx, int ngroups, const Optics& o, int g_stored,
+                           const float2* Tbt, double* pdc, float* pdth, hipStream_t s) {
+  launch_colsets(kc, n_k, nx, ny, o, cst, cmask, nmw, s);
+  STEM_LAUNCH_CHECK();
   switch (prec) {
     case STEM_DFT_BF16_SPLIT:
       return launch_yadjoint_p<STEM_DFT_BF16_SPLIT>(ny, X, kc, kchi, cst, n_k, nx, ngroups, o, g_stored, Tbt, pdc,
@@ -575,7 +564,7 @@ extern "C" int ssb_backward(const float* d_dLdphi, const stem_det* det, const st
   a.tag = "adj_fft";
   if ((st = launch_row_fft(ny, false, IN_C64, OUT_ROW_C64, a, s))) return st;
   if ((st = run_chi_table(b, d_theta, n_k, o, L.groups, s))) return st;
-  if ((st = launch_yadjoint(ssb->precision, ny, b.X, b.kc, b.kchi, b.cst, n_k, nx, L.groups, o, ssb->g_mode == STEM_G_STORE,
+  if ((st = launch_yadjoint(ssb->precision, ny, b.X, b.kc, b.kchi, b.cst, b.cmask, L.nmw, n_k, nx, L.groups, o, ssb->g_mode == STEM_G_STORE,
                             b.Tb, b.pdc, b.pdth, s)))
     return st;
   {

@@ -126,3 +126,32 @@ def test_host_argument_errors_return_einval_without_device_work():
     assert L.ssb_backward(fake, ctypes.byref(det), ctypes.byref(scan), ctypes.byref(optics), ctypes.byref(norm),
                           None, fake, big, fake, None, None, None) == 1
     assert null.value is None
+
+
+def test_detector_and_rle_argument_errors_return_einval_without_device_work():
+    """virtual_annular, sum_frames and eer_decode_rle reject bad host arguments before any
+    launch; an empty frame range is a successful no-op."""
+    wl = WORKLOADS["small"]
+    det, scan, _ = _geom(wl)
+    L = stem.lib()
+    fake = ctypes.c_void_p(256)
+    F = scan.ny * scan.nx
+    rin = (ctypes.c_double * 2)(0.0, 4.0)
+    rout = (ctypes.c_double * 2)(4.0, 9.5)
+    ann = lambda f0, nf, n, a=rin, b=rout, d=det: L.virtual_annular(fake, fake, f0, nf, ctypes.byref(d),
+                                                                   ctypes.byref(scan), n, a, b, fake, None, None)
+    assert ann(0, 0, 2) == 0                       # nothing to do
+    assert ann(0, 1, 0) == 1 and ann(0, 1, 17) == 1  # n_det outside [1, 16]
+    assert ann(-1, 1, 2) == 1 and ann(F - 1, 2, 2) == 1 and ann(0, -1, 2) == 1
+    assert ann(0, 1, 2, a=(ctypes.c_double * 2)(0.0, float("nan"))) == 1
+    assert ann(0, 1, 2, b=(ctypes.c_double * 2)(-1.0, 3.0)) == 1
+    assert ann(0, 1, 2, d=stem.Det(1 << 16, 1 << 15, 0, 0, 1)) == 1   # W*H >= 2^31
+    assert L.virtual_annular(None, fake, 0, 1, ctypes.byref(det), ctypes.byref(scan), 2, rin, rout, fake,
+                             None, None) == 1
+    assert L.sum_frames(fake, fake, 0, 0, ctypes.byref(det), fake, None, None, None) == 1
+    assert L.sum_frames(fake, fake, -1, 4, ctypes.byref(det), fake, None, None, None) == 1
+    assert L.sum_frames(fake, fake, 0, 4, ctypes.byref(det), None, None, None, None) == 1
+    assert L.eer_decode_rle(fake, fake, 0, 0, ctypes.byref(det), fake, None, None) == 0
+    assert L.eer_decode_rle(fake, fake, 0, -1, ctypes.byref(det), fake, None, None) == 1
+    assert L.eer_decode_rle(None, fake, 0, 4, ctypes.byref(det), fake, None, None) == 1
+    assert L.eer_decode_rle(fake, fake, 0, 4, ctypes.byref(stem.Det(0, 64, 0, 0, 1)), fake, None, None) == 1
