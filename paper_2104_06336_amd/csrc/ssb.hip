@@ -140,22 +140,29 @@ static void launch_colsets(const double2* kc, int n_k, int nx, int ny, const Opt
                      cst, cmask);
 }
 
+// chi identically zero (every monomial coefficient 0) and no per-pixel theta: the phase factors of
+// Eq. 3 are all exactly 1
+static int chi_is_zero(const Optics& o, const float* theta) {
+  return !theta && o.p20 == 0.0 && o.p02 == 0.0 && o.p11 == 0.0 && o.p30 == 0.0 && o.p21 == 0.0 && o.p12 == 0.0 &&
+         o.p03 == 0.0 && o.p4 == 0.0;
+}
+
 // the interval table and the active-pixel mask, then the fused column sum
 static int launch_yreduce(int prec, int ny, float2* X, const double2* kc, const double* kchi, int4* cst,
                           uint64_t* cmask, int nmw, int n_k, int nx, int ngroups, const Optics& o, int store_g,
-                          float2* part, unsigned long long* stats, hipStream_t s) {
+                          int chi0, float2* part, unsigned long long* stats, hipStream_t s) {
   launch_colsets(kc, n_k, nx, ny, o, cst, cmask, nmw, s);
   STEM_LAUNCH_CHECK();
   switch (prec) {
     case STEM_DFT_BF16_SPLIT:
       return launch_yreduce_p<STEM_DFT_BF16_SPLIT>(ny, X, kc, kchi, cst, cmask, nmw, n_k, nx, ngroups, o, store_g,
-                                                   part, stats, s);
+                                                   chi0, part, stats, s);
     case STEM_DFT_FP16_SPLIT:
       return launch_yreduce_p<STEM_DFT_FP16_SPLIT>(ny, X, kc, kchi, cst, cmask, nmw, n_k, nx, ngroups, o, store_g,
-                                                   part, stats, s);
+                                                   chi0, part, stats, s);
     default:
-      return launch_yreduce_p<STEM_FFT_FP32>(ny, X, kc, kchi, cst, cmask, nmw, n_k, nx, ngroups, o, store_g, part,
-                                             stats, s);
+      return launch_yreduce_p<STEM_FFT_FP32>(ny, X, kc, kchi, cst, cmask, nmw, n_k, nx, ngroups, o, store_g, chi0,
+                                             part, stats, s);
   }
 }
 
@@ -505,7 +512,8 @@ extern "C" int ssb_reconstruct(const int32_t* d_idx, const int64_t* d_off, int64
   if (ssb->normalize && ssb->precision != STEM_FFT_FP32) {
     // split precision: the fused kernel transforms X -> G in place (its partial sums are not
     // used); the counters are reset before the per-Q normalised sum
-    if ((st = launch_yreduce(ssb->precision, ny, b.X, b.kc, b.kchi, b.cst, b.cmask, L.nmw, n_k, nx, L.groups, o, 1, b.part, b.stats, s)))
+    if ((st = launch_yreduce(ssb->precision, ny, b.X, b.kc, b.kchi, b.cst, b.cmask, L.nmw, n_k, nx, L.groups, o, 1,
+                             1, b.part, b.stats, s)))
       return st;
     if ((st = run_chi_table(b, d_theta, n_k, o, 1, s))) return st;
     if ((st = run_reduce_stored(L, b, ny, nx, o, 1, s))) return st;
@@ -524,8 +532,8 @@ extern "C" int ssb_reconstruct(const int32_t* d_idx, const int64_t* d_off, int64
     if ((st = run_reduce_stored(L, b, ny, nx, o, 1, s))) return st;
     return run_phase(L, b, *scan, b.T, 1, d_phase, d_T, s);
   }
-  if ((st = launch_yreduce(ssb->precision, ny, b.X, b.kc, b.kchi, b.cst, b.cmask, L.nmw, n_k, nx, L.groups, o, ssb->g_mode == STEM_G_STORE,
-                           b.part, b.stats, s)))
+  if ((st = launch_yreduce(ssb->precision, ny, b.X, b.kc, b.kchi, b.cst, b.cmask, L.nmw, n_k, nx, L.groups, o,
+                           ssb->g_mode == STEM_G_STORE, chi_is_zero(o, d_theta), b.part, b.stats, s)))
     return st;
   return run_phase(L, b, *scan, b.part, L.groups, d_phase, d_T, s);
 }

@@ -227,7 +227,10 @@ __device__ __forceinline__ void load_colsets(const int4* __restrict__ cst, int64
   m = ColSet{(int)(short)(r.z & 0xffff), r.z >> 16, (int)(short)(r.w & 0xffff), r.w >> 16};
 }
 
-template <typename XF>
+// CHI0: the aberration function and theta are identically zero, so every phase factor of Eq. 3
+// is exactly 1 and the sum adds G itself (conj G for mirrored frequencies): the same values the
+// general path produces for chi = 0, without evaluating them.
+template <typename XF, bool CHI0>
 __global__ void __launch_bounds__(kYThreads, 2) k_yreduce(float2* __restrict__ X, const double2* __restrict__ kc,
                                                        const double* __restrict__ kchi,
                                                        const int4* __restrict__ cst,
@@ -315,37 +318,57 @@ __global__ void __launch_bounds__(kYThreads, 2) k_yreduce(float2* __restrict__ X
         if (c0 + b < nc) gcol[(int64_t)b * NY + m] = v[i];
       }
     }
-    const double kch = kchi[kd];
-#pragma unroll
-    for (int sl = 0; sl < SL::kSlots; ++sl) {
-      int b0, m0;
-      XF::out(lane, sl * kSlotStride, b0, m0);
-      const int c = c0 + b0;
-      const ChiCol chd = chi_column(o.lk * (k.x - (double)signed_index(c, nx) * o.sx), o);
-      const ChiCol chm = chi_column(o.lk * (k.x - (double)signed_index(nx - c, nx) * o.sx), o);
+    if constexpr (CHI0) {
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
-        if (SL::slot_of(i) != sl) continue;
+        const int sl = SL::slot_of(i);
         int b, m;
         XF::out(lane, i, b, m);
-        // keep the per-register frequency arithmetic inside the pixel loop: hoisted out of it, the
-        // 16 registers' frequencies stay live across the loop and cost occupancy
         asm volatile("" : "+v"(m));
-        const int iy = signed_index(m, NY);
-        if (sd[sl].has(iy)) {
-          const double wy = o.lk * (k.y - (double)iy * o.sy);
-          const float2 e = expi_reduced(chi_eval(chd, wy) - kch);
-          accd[i].x += v[i].x * e.x - v[i].y * e.y;
-          accd[i].y += v[i].x * e.y + v[i].y * e.x;
+        if (sd[sl].has(signed_index(m, NY))) {
+          accd[i].x += v[i].x;
+          accd[i].y += v[i].y;
           ++cnt;
         }
-        const int jy = signed_index((NY - m) & (NY - 1), NY);
-        if (sm[sl].has(jy)) {
-          const double wy = o.lk * (k.y - (double)jy * o.sy);
-          const float2 e = expi_reduced(chi_eval(chm, wy) - kch);
-          accm[i].x += v[i].x * e.x + v[i].y * e.y;
-          accm[i].y += v[i].x * e.y - v[i].y * e.x;
+        if (sm[sl].has(signed_index((NY - m) & (NY - 1), NY))) {
+          accm[i].x += v[i].x;
+          accm[i].y -= v[i].y;
           ++cnt;
+        }
+      }
+    } else {
+      const double kch = kchi[kd];
+#pragma unroll
+      for (int sl = 0; sl < SL::kSlots; ++sl) {
+        int b0, m0;
+        XF::out(lane, sl * kSlotStride, b0, m0);
+        const int c = c0 + b0;
+        const ChiCol chd = chi_column(o.lk * (k.x - (double)signed_index(c, nx) * o.sx), o);
+        const ChiCol chm = chi_column(o.lk * (k.x - (double)signed_index(nx - c, nx) * o.sx), o);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          if (SL::slot_of(i) != sl) continue;
+          int b, m;
+          XF::out(lane, i, b, m);
+          // keep the per-register frequency arithmetic inside the pixel loop: hoisted out of it, the
+          // 16 registers' frequencies stay live across the loop and cost occupancy
+          asm volatile("" : "+v"(m));
+          const int iy = signed_index(m, NY);
+          if (sd[sl].has(iy)) {
+            const double wy = o.lk * (k.y - (double)iy * o.sy);
+            const float2 e = expi_reduced(chi_eval(chd, wy) - kch);
+            accd[i].x += v[i].x * e.x - v[i].y * e.y;
+            accd[i].y += v[i].x * e.y + v[i].y * e.x;
+            ++cnt;
+          }
+          const int jy = signed_index((NY - m) & (NY - 1), NY);
+          if (sm[sl].has(jy)) {
+            const double wy = o.lk * (k.y - (double)jy * o.sy);
+            const float2 e = expi_reduced(chi_eval(chm, wy) - kch);
+            accm[i].x += v[i].x * e.x + v[i].y * e.y;
+            accm[i].y += v[i].x * e.y - v[i].y * e.x;
+            ++cnt;
+          }
         }
       }
     }
@@ -526,15 +549,19 @@ int launch_xstage_p(int nx, const DT* D, int ny, int ry0, int nr, int64_t nrows,
 template <int PREC>
 int launch_yreduce_p(int ny, float2* X, const double2* kc, const double* kchi, const int4* cst,
                      const uint64_t* cmask, int nmw, int n_k, int nx, int ngroups, const Optics& o,
-                     int store_g, float2* part, unsigned long long* stats, hipStream_t s) {
+                     int store_g, int chi0, float2* part, unsigned long long* stats, hipStream_t s) {
   const int B = 1024 / ny;
   const int ncs = (nx / 2 + 1 + B - 1) / B;
   const dim3 grid((unsigned)(((ncs + 3) / 4) * ngroups)), blk(kYThreads);
   STEM_TRACE(PREC == STEM_FFT_FP32 ? "ssb_yreduce" : "ssb_yreduce_mfma", s);
   const int st = with_n(ny, [&](auto nc) {
     using XF = typename XfSel<decltype(nc)::value, PREC>::type;
-    hipLaunchKernelGGL((k_yreduce<XF>), grid, blk, 0, s, X, kc, kchi, cst, cmask, nmw, n_k, nx, ngroups, o, store_g,
-                       part, stats);
+    if (chi0)
+      hipLaunchKernelGGL((k_yreduce<XF, true>), grid, blk, 0, s, X, kc, kchi, cst, cmask, nmw, n_k, nx, ngroups, o,
+                         store_g, part, stats);
+    else
+      hipLaunchKernelGGL((k_yreduce<XF, false>), grid, blk, 0, s, X, kc, kchi, cst, cmask, nmw, n_k, nx, ngroups, o,
+                         store_g, part, stats);
   });
   if (st) return st;
   STEM_LAUNCH_CHECK();
@@ -562,13 +589,13 @@ int launch_yadjoint_p(int ny, const float2* X, const double2* kc, const double* 
 extern template int launch_xstage_p<STEM_DFT_BF16_SPLIT, uint8_t>(int, const uint8_t*, int, int, int, int64_t, float2*, hipStream_t);
 extern template int launch_xstage_p<STEM_DFT_BF16_SPLIT, uint16_t>(int, const uint16_t*, int, int, int, int64_t, float2*, hipStream_t);
 extern template int launch_yreduce_p<STEM_DFT_BF16_SPLIT>(int, float2*, const double2*, const double*, const int4*, const uint64_t*, int, int, int, int,
-                                            const Optics&, int, float2*, unsigned long long*, hipStream_t);
+                                            const Optics&, int, int, float2*, unsigned long long*, hipStream_t);
 extern template int launch_yadjoint_p<STEM_DFT_BF16_SPLIT>(int, const float2*, const double2*, const double*, const int4*, int, int, int,
                                              const Optics&, int, const float2*, double*, float*, hipStream_t);
 extern template int launch_xstage_p<STEM_DFT_FP16_SPLIT, uint8_t>(int, const uint8_t*, int, int, int, int64_t, float2*, hipStream_t);
 extern template int launch_xstage_p<STEM_DFT_FP16_SPLIT, uint16_t>(int, const uint16_t*, int, int, int, int64_t, float2*, hipStream_t);
 extern template int launch_yreduce_p<STEM_DFT_FP16_SPLIT>(int, float2*, const double2*, const double*, const int4*, const uint64_t*, int, int, int, int,
-                                            const Optics&, int, float2*, unsigned long long*, hipStream_t);
+                                            const Optics&, int, int, float2*, unsigned long long*, hipStream_t);
 extern template int launch_yadjoint_p<STEM_DFT_FP16_SPLIT>(int, const float2*, const double2*, const double*, const int4*, int, int, int,
                                              const Optics&, int, const float2*, double*, float*, hipStream_t);
 

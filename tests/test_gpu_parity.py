@@ -191,6 +191,23 @@ def test_recompute_mode_matches_oracle(gpu, name):
     assert rel_l2(dth.cpu().numpy(), dtho) <= 1e-4
 
 
+@pytest.mark.parametrize("prec", [stem.STEM_FFT_FP32, stem.STEM_DFT_BF16_SPLIT], ids=["fp32", "bf16"])
+@pytest.mark.parametrize("name", ["small", "rect"])
+def test_zero_aberration_sum_equals_general_sum(gpu, name, prec):
+    """With chi identically zero and no theta the fused sum adds G itself; given theta = 0 it takes
+    the general path, whose phase factors are then exactly 1: the two agree bit for bit."""
+    wl, idx, off = data(name)
+    d_idx, d_off = to_device(idx, off)
+    det, _, optics = structs(wl)
+    zeros = np.zeros(stem.ssb_num_pixels(det, optics), dtype=np.float32)
+    _, fast = gpu_ssb(d_idx, d_off, wl, g_mode=stem.STEM_G_RECOMPUTE, precision=prec)
+    _, gen = gpu_ssb(d_idx, d_off, wl, theta=zeros, g_mode=stem.STEM_G_RECOMPUTE, precision=prec)
+    assert np.array_equal(fast["T"], gen["T"])
+    assert np.array_equal(fast["phi"], gen["phi"])
+    ref = oracle_ssb(idx, off, wl)
+    assert rel_l2(fast["phi"], ref["phi"]) <= (TOL if prec == stem.STEM_FFT_FP32 else 1e-4)
+
+
 def test_chunked_accumulate_equals_oneshot(gpu):
     wl, idx, off = data("mid")
     d_idx, d_off = to_device(idx, off)
