@@ -51,6 +51,7 @@ struct XfMfma {
   static constexpr bool kMfma = true;
   static constexpr int slot_of(int) { return 0; }  // all 16 registers of a lane share its column
   static constexpr int kSlots = 1;
+  static constexpr bool kUniformCol = false;        // (the lanes of a wave do not)
   // x-stage workgroup: 16 waves (one workgroup per CU holds the operand tables once); the
   // staging buffer pads one element per 32, so that a lane's outputs (32 apart) hit distinct
   // banks, and the wave stride (8 mod 32 elements) spreads the waves' rows over the banks
@@ -266,11 +267,17 @@ __global__ void __launch_bounds__(kYThreads, 2) k_yreduce(float2* __restrict__ X
   // the pixels of [kd_a, kd_b) with a non-empty set in this column set (every pixel with store_g):
   // bits of the column set's mask, scanned with scalar operations
   const uint64_t* mrow = cmask + (int64_t)cs * nmw;
+  int mw = -1;  // the mask word last read, kept in scalar registers
+  uint64_t mword = 0;
   auto next_kd = [&](int from) -> int {
     if (store_g) return from < kd_b ? from : kd_b;
     for (int kd = from; kd < kd_b;) {
       const int w = kd >> 6;
-      const uint64_t bits = mrow[w] >> (kd & 63);
+      if (w != mw) {
+        mw = w;
+        mword = mrow[w];
+      }
+      const uint64_t bits = mword >> (kd & 63);
       if (bits) {
         kd += __builtin_ctzll(bits);
         return kd < kd_b ? kd : kd_b;
@@ -318,7 +325,42 @@ __global__ void __launch_bounds__(kYThreads, 2) k_yreduce(float2* __restrict__ X
         if (c0 + b < nc) gcol[(int64_t)b * NY + m] = v[i];
       }
     }
-    if constexpr (CHI0) {
+    if constexpr (CHI0 && !XF::kMfma && XF::kUniformCol) {
+      // Every register of a slot belongs to one column; the lane's frequencies in it are
+      // m = lane + 64 j, j = 0 .. N/64 - 1.  In signed order iy = 64 p - (N/2 - lane) with
+      // p = (j + N/128) mod N/64, so each interval of a double-overlap set is a run of p, formed
+      // once per pixel as a bit mask; a register then adds its value times its bit (1 adds the
+      // value exactly, 0 adds nothing).
+      constexpr int NP = NY / 64;
+      static_assert(NP == (XF::NB / 64) * XF::RL, "register layout of the uniform-column transform");
+      const int base = NY / 2 - lane;
+      auto pbits = [&](int lo, int hi) -> uint32_t {  // p with lo <= iy(p) <= hi
+        int p0 = (lo + base + 63) >> 6, p1 = (hi + base) >> 6;
+        p0 = p0 < 0 ? 0 : p0;
+        p1 = p1 > NP - 1 ? NP - 1 : p1;
+        return p1 >= p0 ? (2u << p1) - (1u << p0) : 0u;
+      };
+      uint32_t md[SL::kSlots], mm[SL::kSlots];
+#pragma unroll
+      for (int sl = 0; sl < SL::kSlots; ++sl) {
+        md[sl] = pbits(sd[sl].a0, sd[sl].a1) & ~pbits(sd[sl].b0, sd[sl].b1);
+        // mirrored frequency jy = -iy, except iy = -N/2 (lane 0, p = 0), which is its own mirror
+        mm[sl] = pbits(-sm[sl].a1, -sm[sl].a0) & ~pbits(-sm[sl].b1, -sm[sl].b0);
+        if (lane == 0) mm[sl] = (mm[sl] & ~1u) | (sm[sl].has(-NY / 2) ? 1u : 0u);
+        cnt += __builtin_popcount(md[sl]) + __builtin_popcount(mm[sl]);
+      }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int sl = SL::slot_of(i);
+        const int j = (i / XF::RL) % (XF::NB / 64) + (XF::NB / 64) * (i % XF::RL);
+        const int pb = (j + NP / 2) % NP;
+        const float wd = (float)((md[sl] >> pb) & 1u), wm = (float)((mm[sl] >> pb) & 1u);
+        accd[i].x = fmaf(v[i].x, wd, accd[i].x);
+        accd[i].y = fmaf(v[i].y, wd, accd[i].y);
+        accm[i].x = fmaf(v[i].x, wm, accm[i].x);
+        accm[i].y = fmaf(-v[i].y, wm, accm[i].y);
+      }
+    } else if constexpr (CHI0) {
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
         const int sl = SL::slot_of(i);

@@ -30,7 +30,10 @@ ABERR = SMALL.replace(name="small aberrated", aberr=C4_TRUE_ABERRATIONS)
 N128 = SMALL.replace(name="scan 128x128", scan=(128, 128), aberr=C4_TRUE_ABERRATIONS)
 N512 = SMALL.replace(name="scan 512x256, binned 2x", scan=(512, 256), bin=2, mean_e=10.0)
 
-CASES = {"small": SMALL, "mid": MID, "rect": RECT, "aberr": ABERR, "n128": N128, "n512": N512}
+# 1024-point column transform (plan 16.16.4) on a tall, narrow scan
+N1024 = SMALL.replace(name="scan 1024x32", scan=(1024, 32), mean_e=15.0)
+
+CASES = {"small": SMALL, "mid": MID, "rect": RECT, "aberr": ABERR, "n128": N128, "n512": N512, "n1024": N1024}
 _DATA = {}
 
 
@@ -120,7 +123,7 @@ def test_binning_and_scan_transform(gpu, name):
     assert np.all(G[:, 0, 0].imag == 0)
 
 
-@pytest.mark.parametrize("name", ["small", "mid", "rect", "aberr", "n128", "n512"])
+@pytest.mark.parametrize("name", ["small", "mid", "rect", "aberr", "n128", "n512", "n1024"])
 def test_ssb_phase_parity(gpu, name):
     wl, idx, off = data(name)
     d_idx, d_off = to_device(idx, off)
@@ -192,7 +195,7 @@ def test_recompute_mode_matches_oracle(gpu, name):
 
 
 @pytest.mark.parametrize("prec", [stem.STEM_FFT_FP32, stem.STEM_DFT_BF16_SPLIT], ids=["fp32", "bf16"])
-@pytest.mark.parametrize("name", ["small", "rect"])
+@pytest.mark.parametrize("name", ["small", "rect", "n512", "n1024"])
 def test_zero_aberration_sum_equals_general_sum(gpu, name, prec):
     """With chi identically zero and no theta the fused sum adds G itself; given theta = 0 it takes
     the general path, whose phase factors are then exactly 1: the two agree bit for bit."""
