@@ -8,6 +8,7 @@
 
 #include "common.h"
 #include "fft_wave.h"
+#include "geom.h"
 #include "mfma_dft.h"
 #include "optics.h"
 #include "trace.h"
@@ -101,7 +102,8 @@ static int with_n(int n, F&& f) {
 
 template <typename XF, typename DT>
 __global__ void __launch_bounds__(64 * XF::kXWaves) k_xstage(const DT* __restrict__ D, int ny, int ry0, int nr,
-                                                      int64_t nrows, int pair_store, float2* __restrict__ X) {
+                                                      Magic mnr, int nrows, int pair_store,
+                                                      float2* __restrict__ X) {
   constexpr int N = XF::N;
   // counts below 256 are exact in the split formats and need no low part
   constexpr bool kExact = std::is_same<DT, uint8_t>::value;
@@ -119,25 +121,41 @@ __global__ void __launch_bounds__(64 * XF::kXWaves) k_xstage(const DT* __restric
   XF::fill(s_tab, s_tw, threadIdx.x, kThreads);
   if (XF::kMfma) __syncthreads();
   float2* buf = s_buf + wave * XF::kXStride;
-  const int64_t ntiles = (nrows + TR - 1) / TR;
-  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const int64_t r0 = tile * TR + wave * 2 * B;  // first real row of this wave
-    // stage the wave's 2B rows of D in its LDS buffer with 16-byte loads
-    {
-      uint4* raw = (uint4*)buf;
-      constexpr int CH = 2 * B * ROWB / 16;  // 16-byte chunks
+  const int ntiles = (nrows + TR - 1) / TR;
+  // real row r (< 2^31) -> pixel kd = r / nr and scan row ry0 + r % nr
+  auto row_of = [&](int r, int& kd, int& ry) {
+    kd = (int)magic_div((uint32_t)r, mnr);
+    ry = ry0 + (r - kd * nr);
+  };
+  // the wave's 2B rows of D as 16-byte chunks, CPL per lane; the next tile's chunks are loaded
+  // while this tile is transformed and written
+  constexpr int CH = 2 * B * ROWB / 16;
+  constexpr int CPL = CH / kWave;
+  static_assert(CH % kWave == 0, "row chunks per lane");
+  auto load_rows = [&](int tile, uint4* pre) {
+    const int r0 = tile * TR + wave * 2 * B;  // first real row of this wave
 #pragma unroll
-      for (int c = lane; c < CH; c += kWave) {
-        const int j = c * 16 / ROWB, col = c * 16 % ROWB;
-        const int64_t r = r0 + j;
-        uint4 v = make_uint4(0u, 0u, 0u, 0u);
-        if (r < nrows) {
-          const int64_t kd = r / nr, ry = ry0 + r % nr;
-          v = *(const uint4*)((const char*)D + (kd * ny + ry) * ROWB + col);
-        }
-        raw[c] = v;
+    for (int k = 0; k < CPL; ++k) {
+      const int c = lane + kWave * k;
+      const int j = c * 16 / ROWB, col = c * 16 % ROWB;
+      const int r = r0 + j;
+      pre[k] = make_uint4(0u, 0u, 0u, 0u);
+      if (r < nrows) {
+        int kd, ry;
+        row_of(r, kd, ry);
+        pre[k] = *(const uint4*)((const char*)D + ((int64_t)kd * ny + ry) * ROWB + col);
       }
     }
+  };
+  uint4 pre[CPL];
+  if ((int)blockIdx.x < ntiles) load_rows(blockIdx.x, pre);
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    {
+      uint4* raw = (uint4*)buf;
+#pragma unroll
+      for (int k = 0; k < CPL; ++k) raw[lane + kWave * k] = pre[k];
+    }
+    if (tile + gridDim.x < ntiles) load_rows(tile + gridDim.x, pre);
     wave_lds_sync();
     float2 v[16];
     {
@@ -168,18 +186,16 @@ __global__ void __launch_bounds__(64 * XF::kXWaves) k_xstage(const DT* __restric
       const float2 zc = cconj(wb[XF::pad(b * N + ((N - m) & (N - 1)))]);
       const float2 va = cscale(cadd(z, zc), 0.5f);
       const float2 vb = cscale(cmul_mi(csub(z, zc)), 0.5f);
-      const int64_t rho = tile * TR + 2 * pr;
+      const int rho = tile * TR + 2 * pr;
+      int kd, ry;
+      row_of(rho, kd, ry);
       if (pair_store && rho + 1 < nrows) {
-        const int64_t kd = rho / nr, ry = ry0 + rho % nr;
-        *(float4*)(X + (kd * NH + m) * ny + ry) = make_float4(va.x, va.y, vb.x, vb.y);
+        *(float4*)(X + ((int64_t)kd * NH + m) * ny + ry) = make_float4(va.x, va.y, vb.x, vb.y);
       } else {
-        if (rho < nrows) {
-          const int64_t kd = rho / nr, ry = ry0 + rho % nr;
-          X[(kd * NH + m) * ny + ry] = va;
-        }
+        if (rho < nrows) X[((int64_t)kd * NH + m) * ny + ry] = va;
         if (rho + 1 < nrows) {
-          const int64_t kd = (rho + 1) / nr, ry = ry0 + (rho + 1) % nr;
-          X[(kd * NH + m) * ny + ry] = vb;
+          row_of(rho + 1, kd, ry);
+          X[((int64_t)kd * NH + m) * ny + ry] = vb;
         }
       }
     }
@@ -575,13 +591,19 @@ int launch_xstage_p(int nx, const DT* D, int ny, int ry0, int nr, int64_t nrows,
   // rows 2p, 2p+1 of a tile share a pixel and sit at adjacent, 16-byte aligned ry when the
   // chunk starts on an even row and holds an even number of rows per pixel
   const int pair_store = (nr % 2 == 0) && (ry0 % 2 == 0);
+  // rows are counted in 32 bits (n_K * Ny is far below 2^31 for any cube that fits in memory)
+  if (nrows <= 0 || nrows > ((int64_t)1 << 31) - 4096 || nr <= 0) return nrows == 0 ? STEM_OK : STEM_EINVAL;
   STEM_TRACE(PREC == STEM_FFT_FP32 ? "xstage_fft" : "xstage_mfma", s);
   const int st = with_n(nx, [&](auto nc) {
     using XF = typename XfSel<decltype(nc)::value, PREC>::type;
     const int64_t tr = 2 * XF::kXWaves * (1024 / nx);
     const int64_t tiles = (nrows + tr - 1) / tr;
-    const dim3 grid((unsigned)(tiles < 4096 ? tiles : 4096)), blk(64 * XF::kXWaves);
-    hipLaunchKernelGGL((k_xstage<XF, DT>), grid, blk, 0, s, D, ny, ry0, nr, nrows, pair_store, X);
+    // every workgroup resident, each streaming its tiles with the next tile's rows in flight
+    const int res = resident_blocks(k_xstage<XF, DT>, 64 * XF::kXWaves);
+    const int64_t cap = res > 0 ? res : 4096;
+    const dim3 grid((unsigned)(tiles < cap ? tiles : cap)), blk(64 * XF::kXWaves);
+    hipLaunchKernelGGL((k_xstage<XF, DT>), grid, blk, 0, s, D, ny, ry0, nr, make_magic((uint32_t)nr), (int)nrows,
+                       pair_store, X);
   });
   if (st) return st;
   STEM_LAUNCH_CHECK();
