@@ -311,14 +311,27 @@ __global__ void __launch_bounds__(kYThreads, 2) k_yreduce(float2* __restrict__ X
       v[i] = (c0 + b < nc) ? xcol[(int64_t)b * NY + n] : make_float2(0.f, 0.f);
     }
   };
+  // the columns of the next active pixel (of the next two on the zero-aberration path, whose sum
+  // leaves the registers for it) are loaded while this one is transformed and summed
+  constexpr int kAhead = (CHI0 && !XF::kMfma && XF::kUniformCol) ? 2 : 1;
   int kd = next_kd(kd_a);
-  float2 v[16];
+  int kd1 = kAhead == 2 && kd < kd_b ? next_kd(kd + 1) : kd_b;
+  float2 v[16], v1[kAhead == 2 ? 16 : 1];
   if (kd < kd_b) load_col(kd, v);
+  if constexpr (kAhead == 2) {
+    if (kd1 < kd_b) load_col(kd1, v1);
+  }
   while (kd < kd_b) {
-    // the next active pixel's column is loaded while this one is transformed and summed
-    const int kdn = next_kd(kd + 1);
+    int kdn;
     float2 vn[16];
-    if (kdn < kd_b) load_col(kdn, vn);
+    if constexpr (kAhead == 2) {
+      kdn = kd1;
+      kd1 = kd1 < kd_b ? next_kd(kd1 + 1) : kd_b;
+      if (kd1 < kd_b) load_col(kd1, vn);
+    } else {
+      kdn = next_kd(kd + 1);
+      if (kdn < kd_b) load_col(kdn, vn);
+    }
     const double2 k = kc[kd];
     // double-overlap sets of this pixel for the lane's columns (direct and mirrored)
     ColSet sd[SL::kSlots], sm[SL::kSlots];
@@ -431,8 +444,16 @@ __global__ void __launch_bounds__(kYThreads, 2) k_yreduce(float2* __restrict__ X
       }
     }
     kd = kdn;
+    if constexpr (kAhead == 2) {
 #pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = vn[i];
+      for (int i = 0; i < 16; ++i) {
+        v[i] = v1[i];
+        v1[i] = vn[i];
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) v[i] = vn[i];
+    }
   }
   float2* pg = part + (int64_t)g * nx * NY;
 #pragma unroll
