@@ -492,12 +492,11 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(const int32_t* __restrict__
                                                      int64_t n_frames, int32_t npix,
                                                      const int16_t* __restrict__ lut, int32_t n_k,
                                                      int64_t F, DT* __restrict__ D, int32_t* status) {
-  __shared__ uint32_t s_hist[kBinWords];
+  __shared__ __align__(16) uint32_t s_hist[kBinWords];
   __shared__ uint32_t s_map[(kBinWin + 16) / 4];
   __shared__ int32_t s_rel[kBinFrames + 1];
   __shared__ int64_t s_base;
   const int t = threadIdx.x;
-  const int lane = t & 63, wave = t >> 6, nw = kBinThreads / 64;
   const int nchunks = (n_k + kBinKd - 1) / kBinKd;
   const int kd0 = (int)(blockIdx.x % nchunks) * kBinKd;
   const int kc = n_k - kd0 < kBinKd ? n_k - kd0 : kBinKd;
@@ -509,6 +508,7 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(const int32_t* __restrict__
   const int wide = __syncthreads_or(t < nf && s_rel[t + 1] - s_rel[t] > 255);
   const int span = s_rel[nf];
   const int lo_t = t < nf ? s_rel[t] : 0, hi_t = t < nf ? s_rel[t + 1] : 0;
+  const int64_t base = s_base;
   uint8_t* map = (uint8_t*)s_map;
   int32_t bad = 0;
   const int npass = wide ? 2 : 1;
@@ -516,13 +516,15 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(const int32_t* __restrict__
   const int wpr = wide ? kBinFrames / 2 : kBinFrames / 4;  // words per pixel row
   const int wps = wpr + 1;                        // row stride in words (padded)
   const uint32_t cap = sizeof(DT) == 1 ? 255u : 65535u;
+  // 8-bit counts go out as 16 frames (four counter words) per 16-byte store when aligned
+  const bool vec = sizeof(DT) == 1 && !wide && (((uintptr_t)D & 15) == 0) && (F & 15) == 0 && (fb & 15) == 0;
   for (int pass = 0; pass < npass; ++pass) {
     const int ka = kd0 + pass * kpp;
     const int kn = (kd0 + kc) - ka < kpp ? (kd0 + kc) - ka : kpp;
-    for (int i = t; i < kn * wps; i += kBinThreads) s_hist[i] = 0u;
+    for (int i = t; i < (kn * wps + 3) >> 2; i += kBinThreads) ((uint4*)s_hist)[i] = make_uint4(0u, 0u, 0u, 0u);
     for (int w0 = 0; w0 < span; w0 += kBinWin) {
       const int wn = span - w0 < kBinWin ? span - w0 : kBinWin;
-      const int64_t a0 = s_base + w0;
+      const int64_t a0 = base + w0;
       const int sh = (int)((((uintptr_t)(idx + a0)) & 15) >> 2);  // map[sh + j] <-> event a0 + j
       __syncthreads();
       {
@@ -536,83 +538,89 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(const int32_t* __restrict__
         for (; j < hi; ++j) map[j] = (uint8_t)t;
       }
       __syncthreads();
-      const int64_t al = a0 - sh, aend = a0 + wn;
-      const int ng = (wn + sh + 3) >> 2;  // groups of four events in this window
-      constexpr int U = 4;                // groups per lane in flight
-      for (int g0 = lane + 64 * wave; g0 < ng; g0 += U * 64 * nw) {
-        int32_t k[U][4];
-        bool ok[U][4];
+      // Positions p = 4 g + q of the 16-byte aligned run from ib: [sh, sh + wn) are this window's
+      // events.  Every group g < ng holds at least one of them, so its whole 16-byte line lies in
+      // the event array's pages; the other positions of the line are masked out.
+      const int32_t* ib = idx + (a0 - sh);
+      const int ng = (wn + sh + 3) >> 2;
+      constexpr int U = 4;  // groups per thread in flight
+      for (int g0 = t; g0 < ng; g0 += U * kBinThreads) {
+        int4 kv[U];
         uint32_t fr4[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          const int g = g0 + u * 64 * nw;
+          const int g = g0 + u * kBinThreads;
+          kv[u] = make_int4(0, 0, 0, 0);
+          fr4[u] = 0u;
           if (g < ng) {
-            load_group(idx, al + 4 * (int64_t)g, a0, aend, k[u], ok[u]);
+            kv[u] = *(const int4*)(ib + 4 * g);
             fr4[u] = s_map[g];
-          } else {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              ok[u][q] = false;
-              k[u][q] = 0;
-            }
-            fr4[u] = 0u;
           }
         }
-        // the table lookups are issued together; out-of-range indices look up pixel 0 and are
-        // dropped (and reported)
+        // the table lookups are issued together; masked or out-of-range positions look up pixel 0
         int kd[U][4];
-        bool in[U][4];
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            in[u][q] = (uint32_t)k[u][q] < (uint32_t)npix;
-            if (ok[u][q] && !in[u][q]) bad |= STEM_ERANGE;
-            kd[u][q] = (int)lut[in[u][q] ? k[u][q] : 0] - ka;
+            const int p = 4 * (g0 + u * kBinThreads) + q;
+            const int k = q == 0 ? kv[u].x : q == 1 ? kv[u].y : q == 2 ? kv[u].z : kv[u].w;
+            const bool ok = (uint32_t)(p - sh) < (uint32_t)wn;
+            const bool in = (uint32_t)k < (uint32_t)npix;
+            if (ok && !in) bad |= STEM_ERANGE;
+            const uint32_t kk = ok && in ? (uint32_t)k : 0u;  // 32-bit offset from the table base
+            const int v = (int)*(const int16_t*)((const char*)lut + 2u * kk) - ka;
+            kd[u][q] = ok && in ? v : -1;
           }
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             // a dropped bin (-1), or a pixel of another chunk or pass, is not counted here
-            if (!(ok[u][q] && in[u][q] && (uint32_t)kd[u][q] < (uint32_t)kn)) continue;
-            const int f = (int)((fr4[u] >> (8 * q)) & 0xffu);
+            if ((uint32_t)kd[u][q] >= (uint32_t)kn) continue;
+            const uint32_t f = (fr4[u] >> (8 * q)) & 0xffu;
             const int shift = wide ? 16 * (f & 1) : 8 * (f & 3);
             const int col = wide ? (f >> 1) : (f >> 2);
-            atomicAdd(&s_hist[kd[u][q] * wps + col], 1u << shift);
+            atomicAdd(&s_hist[__umul24(kd[u][q], wps) + col], 1u << shift);
           }
       }
     }
     __syncthreads();
-    // one counter word per thread and step: fpw consecutive frames of one pixel row
-    const int fpw = wide ? 2 : 4;
-    for (int i = t; i < kn * wpr; i += kBinThreads) {
-      const int kd = i / wpr, q = i % wpr;
-      const int f0 = q * fpw;
-      if (f0 >= nf) continue;
-      const uint32_t w = s_hist[kd * wps + q];
-      uint32_t c[4];
-      if (wide) {
-        c[0] = w & 0xffffu;
-        c[1] = w >> 16;
-        c[2] = c[3] = 0u;
-      } else {
-        c[0] = w & 0xffu;
-        c[1] = (w >> 8) & 0xffu;
-        c[2] = (w >> 16) & 0xffu;
-        c[3] = w >> 24;
-      }
-      DT* dst = D + (int64_t)(ka + kd) * F + (fb + f0);
-      if (f0 + fpw <= nf) {
-        if (sizeof(DT) == 1 && !wide) {
-          *(uint32_t*)dst = w;  // four 8-bit counts are the four bytes
+    if (vec) {
+      // four counter words (16 frames) of one pixel row per thread and step
+      const int qpr = wpr / 4;
+      for (int i = t; i < kn * qpr; i += kBinThreads) {
+        const int kd = i / qpr, q4 = i % qpr;
+        const int f0 = 16 * q4;
+        if (f0 >= nf) continue;
+        const uint32_t* hw = s_hist + kd * wps + 4 * q4;
+        uint8_t* dst = (uint8_t*)D + (int64_t)(ka + kd) * F + (fb + f0);
+        if (f0 + 16 <= nf) {
+          *(uint4*)dst = make_uint4(hw[0], hw[1], hw[2], hw[3]);
         } else {
-          for (int j = 0; j < fpw; ++j) {
-            if (c[j] > cap) bad |= STEM_EOVERFLOW;
-            dst[j] = (DT)c[j];
-          }
+          for (int j = 0; f0 + j < nf; ++j) dst[j] = (uint8_t)(hw[j >> 2] >> (8 * (j & 3)));
         }
-      } else {
+      }
+    } else {
+      // one counter word per thread and step: fpw consecutive frames of one pixel row
+      const int fpw = wide ? 2 : 4;
+      for (int i = t; i < kn * wpr; i += kBinThreads) {
+        const int kd = i / wpr, q = i % wpr;
+        const int f0 = q * fpw;
+        if (f0 >= nf) continue;
+        const uint32_t w = s_hist[kd * wps + q];
+        uint32_t c[4];
+        if (wide) {
+          c[0] = w & 0xffffu;
+          c[1] = w >> 16;
+          c[2] = c[3] = 0u;
+        } else {
+          c[0] = w & 0xffu;
+          c[1] = (w >> 8) & 0xffu;
+          c[2] = (w >> 16) & 0xffu;
+          c[3] = w >> 24;
+        }
+        DT* dst = D + (int64_t)(ka + kd) * F + (fb + f0);
         for (int j = 0; j < fpw && f0 + j < nf; ++j) {
           if (c[j] > cap) bad |= STEM_EOVERFLOW;
           dst[j] = (DT)c[j];
