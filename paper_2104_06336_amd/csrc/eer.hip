@@ -485,13 +485,26 @@ constexpr int kBinWords = 5976;                       // 23 KB of counters
 // frame (same column, different pixels) fall into different LDS banks
 constexpr int kBinKd = kBinWords / (kBinFrames / 4 + 1);  // 181 pixels per workgroup
 constexpr int kBinWin = 4096;                         // events per window of the frame map
+constexpr int kBinBoxMax = 4096;                      // bins of the largest LDS bin table (8 KB)
 
-template <typename DT>
+// The kept bins' bounding box (in bins) and the divisions that take a pixel to its bin: with it
+// (BOX) the pixel -> bin table is a small per-workgroup LDS copy over the box, looked up with a
+// division by W (magic number) and by the binning (multiply-high), instead of a gather from the
+// global per-pixel table.
+struct BinBox {
+  Magic mw;           // division by the detector width W
+  uint32_t mbin;      // ceil(2^32 / bin); 0 for bin = 1
+  int32_t W, bin;
+  int32_t bx0, by0, bw, bh;
+};
+
+template <typename DT, bool BOX>
 __global__ void __launch_bounds__(kBinThreads) k_bin(const int32_t* __restrict__ idx,
                                                      const int64_t* __restrict__ off, int64_t frame0,
                                                      int64_t n_frames, int32_t npix,
-                                                     const int16_t* __restrict__ lut, int32_t n_k,
+                                                     const int16_t* __restrict__ lut, BinBox box, int32_t n_k,
                                                      int64_t F, DT* __restrict__ D, int32_t* status) {
+  extern __shared__ int16_t s_box[];  // [bh][bw] kept-bin index of each bin of the box, or -1
   __shared__ __align__(16) uint32_t s_hist[kBinWords];
   __shared__ uint32_t s_map[(kBinWin + 16) / 4];
   __shared__ int32_t s_rel[kBinFrames + 1];
@@ -504,6 +517,13 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(const int32_t* __restrict__
   const int64_t fend = frame0 + n_frames;
   const int nf = (int)((fend - fb) < kBinFrames ? (fend - fb) : kBinFrames);
   if (!load_rel_offsets(off, fb, nf, s_rel, &s_base, status)) return;
+  if constexpr (BOX) {
+    // the table entry of a bin is the global table's entry of its first pixel
+    for (int i = t; i < box.bw * box.bh; i += kBinThreads) {
+      const int by = box.by0 + i / box.bw, bx = box.bx0 + i % box.bw;
+      s_box[i] = lut[(int64_t)by * box.bin * box.W + (int64_t)bx * box.bin];
+    }
+  }
   __syncthreads();
   const int wide = __syncthreads_or(t < nf && s_rel[t + 1] - s_rel[t] > 255);
   const int span = s_rel[nf];
@@ -569,8 +589,16 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(const int32_t* __restrict__
             const bool in = (uint32_t)k < (uint32_t)npix;
             if (ok && !in) bad |= STEM_ERANGE;
             const uint32_t kk = ok && in ? (uint32_t)k : 0u;  // 32-bit offset from the table base
-            const int v = (int)*(const int16_t*)((const char*)lut + 2u * kk) - ka;
-            kd[u][q] = ok && in ? v : -1;
+            int v;
+            if constexpr (BOX) {
+              const uint32_t ky = magic_div(kk, box.mw), kx = kk - ky * (uint32_t)box.W;
+              const uint32_t rx = (box.mbin ? __umulhi(kx, box.mbin) : kx) - (uint32_t)box.bx0;
+              const uint32_t ry = (box.mbin ? __umulhi(ky, box.mbin) : ky) - (uint32_t)box.by0;
+              v = rx < (uint32_t)box.bw && ry < (uint32_t)box.bh ? (int)s_box[ry * box.bw + rx] : -1;
+            } else {
+              v = (int)*(const int16_t*)((const char*)lut + 2u * kk);
+            }
+            kd[u][q] = ok && in && v >= 0 ? v - ka : -1;
           }
 #pragma unroll
         for (int u = 0; u < U; ++u)
@@ -633,19 +661,53 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(const int32_t* __restrict__
 }
 
 int launch_bin(const int32_t* idx, const int64_t* off, int64_t frame0, int64_t n_frames,
-               const stem_det& det, const int16_t* lut, int n_k, int64_t F, void* D, int d_bits,
+               const stem_det& det, double r2, const int16_t* lut, int n_k, int64_t F, void* D, int d_bits,
                int32_t* status, hipStream_t stream) {
   if (n_frames == 0) return STEM_OK;
   const int nchunks = (n_k + kBinKd - 1) / kBinKd;
   const int64_t fblocks = (n_frames + kBinFrames - 1) / kBinFrames;
   const dim3 grid((unsigned)(fblocks * nchunks));
+  // bounding box of the kept bins
+  const int nbx = det.W / det.bin, nby = det.H / det.bin;
+  BinBox box{};
+  int bxa = nbx, bxb = 0, bya = nby, byb = 0;
+  for (int by = 0; by < nby; ++by) {
+    int lo, hi;
+    kept_run(det.bin, by, nbx, det.cx, det.cy, r2, lo, hi);
+    if (hi <= lo) continue;
+    bxa = lo < bxa ? lo : bxa;
+    bxb = hi > bxb ? hi : bxb;
+    bya = by < bya ? by : bya;
+    byb = by + 1;
+  }
+  box.W = det.W;
+  box.bin = det.bin;
+  box.mw = make_magic((uint32_t)det.W);
+  box.mbin = det.bin == 1 ? 0u : (uint32_t)((((uint64_t)1 << 32) + det.bin - 1) / det.bin);
+  box.bx0 = bxa;
+  box.by0 = bya;
+  box.bw = bxb > bxa ? bxb - bxa : 0;
+  box.bh = byb > bya ? byb - bya : 0;
+  // the LDS table when it is small; the bin divisions by multiply-high are exact for W, H < 2^16
+  const int64_t cells = (int64_t)box.bw * box.bh;
+  const bool use_box = cells > 0 && cells <= kBinBoxMax && det.W < 65536 && det.H < 65536;
+  const size_t lds = use_box ? (size_t)((cells * 2 + 15) & ~15ll) : 0;
   STEM_TRACE("bin_densify", stream);
-  if (d_bits == 8)
-    hipLaunchKernelGGL(k_bin<uint8_t>, grid, dim3(kBinThreads), 0, stream, idx, off, frame0, n_frames,
-                       det.W * det.H, lut, n_k, F, (uint8_t*)D, status);
-  else
-    hipLaunchKernelGGL(k_bin<uint16_t>, grid, dim3(kBinThreads), 0, stream, idx, off, frame0, n_frames,
-                       det.W * det.H, lut, n_k, F, (uint16_t*)D, status);
+  if (d_bits == 8) {
+    if (use_box)
+      hipLaunchKernelGGL((k_bin<uint8_t, true>), grid, dim3(kBinThreads), lds, stream, idx, off, frame0, n_frames,
+                         det.W * det.H, lut, box, n_k, F, (uint8_t*)D, status);
+    else
+      hipLaunchKernelGGL((k_bin<uint8_t, false>), grid, dim3(kBinThreads), 0, stream, idx, off, frame0, n_frames,
+                         det.W * det.H, lut, box, n_k, F, (uint8_t*)D, status);
+  } else {
+    if (use_box)
+      hipLaunchKernelGGL((k_bin<uint16_t, true>), grid, dim3(kBinThreads), lds, stream, idx, off, frame0,
+                         n_frames, det.W * det.H, lut, box, n_k, F, (uint16_t*)D, status);
+    else
+      hipLaunchKernelGGL((k_bin<uint16_t, false>), grid, dim3(kBinThreads), 0, stream, idx, off, frame0,
+                         n_frames, det.W * det.H, lut, box, n_k, F, (uint16_t*)D, status);
+  }
   STEM_LAUNCH_CHECK();
   return STEM_OK;
 }

@@ -13,7 +13,7 @@ int launch_com(const int32_t* idx, const int64_t* off, int64_t frame0, int64_t n
 // kept-set geometry: row runs, bin centres Kc and the pixel -> kept-bin table lut[W*H]
 int launch_geometry(const stem_det& det, double r2, RowRun* rows, double2* kc, int16_t* lut, hipStream_t stream);
 int launch_bin(const int32_t* idx, const int64_t* off, int64_t frame0, int64_t n_frames,
-               const stem_det& det, const int16_t* lut, int n_k, int64_t F, void* D, int d_bits,
+               const stem_det& det, double r2, const int16_t* lut, int n_k, int64_t F, void* D, int d_bits,
                int32_t* status, hipStream_t stream);
 
 // ---- fft2.hip: batched row FFTs of length n (power of two, 32..1024) --------------------------

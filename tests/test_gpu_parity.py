@@ -32,8 +32,13 @@ N512 = SMALL.replace(name="scan 512x256, binned 2x", scan=(512, 256), bin=2, mea
 
 # 1024-point column transform (plan 16.16.4) on a tall, narrow scan
 N1024 = SMALL.replace(name="scan 1024x32", scan=(1024, 32), mean_e=15.0)
+# unbinned wide disk: about 4600 bins in the kept set's bounding box, more than the binning kernel's
+# LDS table holds, so pixels are mapped through the global per-pixel table
+WIDE = SMALL.replace(name="wide disk: detector 192x192 unbinned, r_bf 34 px", det=(192, 192), r_bf=34.0,
+                     sim=192, mean_e=60.0)
 
-CASES = {"small": SMALL, "mid": MID, "rect": RECT, "aberr": ABERR, "n128": N128, "n512": N512, "n1024": N1024}
+CASES = {"small": SMALL, "mid": MID, "rect": RECT, "aberr": ABERR, "n128": N128, "n512": N512, "n1024": N1024,
+         "wide": WIDE}
 _DATA = {}
 
 
@@ -105,7 +110,7 @@ def test_dpc_phase_parity(gpu, name, reg):
 # binning, scan transform, sideband sum, phase
 
 
-@pytest.mark.parametrize("name", ["small", "mid", "rect", "n128", "n512"])
+@pytest.mark.parametrize("name", ["small", "mid", "rect", "n128", "n512", "wide"])
 def test_binning_and_scan_transform(gpu, name):
     wl, idx, off = data(name)
     d_idx, d_off = to_device(idx, off)
