@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libstem4d.so")
-SOURCES = ["eer.hip", "fft2.hip", "ssb.hip", "ssb_bf16.hip", "ssb_fp16.hip", "trace.hip"]
+SOURCES = ["device.hip", "eer.hip", "fft2.hip", "ssb.hip", "ssb_bf16.hip", "ssb_fp16.hip", "trace.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

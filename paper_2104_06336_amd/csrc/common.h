@@ -66,20 +66,10 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
     if (e_ != hipSuccess) return STEM_EHIP;      \
   } while (0)
 
-// Workgroups of `kernel` (launched with `threads` threads, no dynamic LDS) that the current device
-// holds at once, remembered per device (0 if the runtime cannot tell).  A grid-stride kernel
-// launched with this many workgroups keeps every workgroup resident for the whole launch.
-template <typename K>
-inline int resident_blocks(K kernel, int threads) {
-  static int cache[64];
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
-  if (cache[dev] > 0) return cache[dev];
-  int cus = 0, per = 0;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0) != hipSuccess) return 0;
-  cache[dev] = cus * per;
-  return cache[dev];
-}
+// Workgroups of the kernel `fn` (launched with `threads` threads and `lds` bytes of dynamic LDS)
+// that the current device holds at once, remembered per (kernel, device, LDS size); 0 if the
+// runtime cannot tell.  A grid-stride kernel launched with this many workgroups keeps every
+// workgroup resident for the whole launch.
+int resident_blocks(const void* fn, int threads, size_t lds = 0);
 
 }  // namespace stem

@@ -620,7 +620,7 @@ int launch_xstage_p(int nx, const DT* D, int ny, int ry0, int nr, int64_t nrows,
     const int64_t tr = 2 * XF::kXWaves * (1024 / nx);
     const int64_t tiles = (nrows + tr - 1) / tr;
     // every workgroup resident, each streaming its tiles with the next tile's rows in flight
-    const int res = resident_blocks(k_xstage<XF, DT>, 64 * XF::kXWaves);
+    const int res = resident_blocks((const void*)k_xstage<XF, DT>, 64 * XF::kXWaves);
     const int64_t cap = res > 0 ? res : 4096;
     const dim3 grid((unsigned)(tiles < cap ? tiles : cap)), blk(64 * XF::kXWaves);
     hipLaunchKernelGGL((k_xstage<XF, DT>), grid, blk, 0, s, D, ny, ry0, nr, make_magic((uint32_t)nr), (int)nrows,
