@@ -78,9 +78,9 @@ def load_traffic(kernel, workload):
 # rocprofv3 kernel names of the kernels bench.py reports, by their trace name
 PROFILED = {
     "stem::k_com": "com_moments",
-    "stem::k_bin<unsigned char>": "bin_densify",
+    "stem::k_bin<unsigned char, true>": "bin_densify",
     "stem::k_xstage<stem::XfFft<1024>, unsigned char>": "xstage_fft",
-    "stem::k_yreduce<stem::XfFft<1024> >": "ssb_yreduce",
+    "stem::k_yreduce<stem::XfFft<1024>, true>": "ssb_yreduce",
     "stem::k_dpc_update": "dpc_update",
 }
 
