@@ -163,6 +163,21 @@ def ssb_sum_bruteforce(G, Kc, step, dk, lam, r_bf, c=(0.0,) * N_COEF):
     return T
 
 
+def g_panel(G: np.ndarray, lut: np.ndarray, qs) -> np.ndarray:
+    """The scan transform at fixed scan frequencies as binned detector images (the panel of G
+    at selected Q shown in Fig. 2): img[j, by, bx] = G[lut[by, bx], my_j, mx_j] for a kept bin,
+    0 for a dropped one.  G is the full-spectrum cube G[kd, my, mx] of step 1; qs lists
+    (my, mx) frequency indices in numpy fftfreq order, 0 <= my < Ny, 0 <= mx < Nx."""
+    n_k, ny, nx = G.shape
+    out = np.zeros((len(qs),) + lut.shape, dtype=np.complex128)
+    kept = lut >= 0
+    for j, (my, mx) in enumerate(qs):
+        if not (0 <= my < ny and 0 <= mx < nx):
+            raise ValueError("frequency index out of range")
+        out[j][kept] = G[lut[kept], my, mx]
+    return out
+
+
 def phase_from_T(T: np.ndarray) -> np.ndarray:
     """phi = Im IFFT2(T) (step 4)."""
     return np.imag(np.fft.ifft2(T))

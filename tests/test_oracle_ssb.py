@@ -59,6 +59,36 @@ def test_hermitian_and_parseval():
     assert abs((np.abs(G) ** 2).sum() - 128 * (D ** 2).sum()) < 1e-10 * (np.abs(G) ** 2).sum()
 
 
+def test_g_panel_pins():
+    """The panel of G at fixed Q: at Q = 0 it is the summed pattern of the events binned over
+    bin x bin blocks on the kept bins (from the events, not from G); at -Q it is the conjugate
+    of the panel at Q; a scan shifted by one position along x multiplies the panel at (my, mx)
+    by exp(-2 pi i mx / Nx)."""
+    wl = WORKLOADS["small"].replace(scan=(16, 8), bin=2, mean_e=30.0)
+    d = simulate(wl, device="cpu")
+    idx, off = d.numpy()
+    H, W = wl.det
+    ny, nx = wl.scan
+    kc, lut = eer.bin_geometry(W, H, wl.bin, wl.r_bf)
+    D = eer.bin_counts(idx, off, W, wl.bin, lut)
+    G = ssb.scan_dft(ssb.cube(D, ny, nx))
+    qs = [(0, 0), (3, 2), (ny - 3, nx - 2), (ny // 2, nx // 2), (1, nx - 1)]
+    P = ssb.g_panel(G, lut, qs)
+    assert P.shape == (len(qs), H // wl.bin, W // wl.bin)
+    pac = eer.sum_frames(idx, off, W, H).reshape(H // wl.bin, wl.bin, W // wl.bin, wl.bin).sum(axis=(1, 3))
+    assert np.array_equal(P[0].real, np.where(lut >= 0, pac, 0).astype(np.float64))
+    assert np.all(P[0].imag == 0)
+    assert np.all(P[:, lut < 0] == 0)
+    assert np.max(np.abs(P[2] - np.conj(P[1]))) < 1e-9 * np.abs(P[1]).max()
+    D3 = ssb.cube(D, ny, nx)
+    Gs = ssb.scan_dft(np.roll(D3, 1, axis=2))
+    Ps = ssb.g_panel(Gs, lut, qs)
+    for j, (my, mx) in enumerate(qs):
+        assert np.max(np.abs(Ps[j] - P[j] * np.exp(-2j * math.pi * mx / nx))) < 1e-9 * max(1.0, np.abs(P[j]).max())
+    with pytest.raises(ValueError):
+        ssb.g_panel(G, lut, [(ny, 0)])
+
+
 def test_signed_frequency_index_and_scale():
     assert ssb.signed_freq_index(8).tolist() == [0, 1, 2, 3, -4, -3, -2, -1]
     assert ssb.q_scale(1024, 0.2, 0.5) == 1.0 / ((1024.0 * 0.2) * 0.5)
