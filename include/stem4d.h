@@ -266,6 +266,24 @@ enum { STEM_REGION_D = 0, STEM_REGION_G = 1, STEM_REGION_T = 2, STEM_REGION_KC =
 int ssb_state_region(const stem_det* det, const stem_scan* scan, const stem_optics* optics,
                      const stem_ssb* ssb, int region, size_t* offset, size_t* bytes);
 
+#define STEM_MAX_PANEL 64
+
+/* The scan transform at selected scan frequencies as binned detector images (Fig. 2 shows
+ * such a panel of G at fixed Q, the regions where the sidebands overlap the bright-field
+ * disk).  For j < n_q (1 <= n_q <= STEM_MAX_PANEL), Q_j = (h_my[j], h_mx[j]) frequency indices
+ * in numpy fftfreq order (0 <= my < Ny, 0 <= mx < Nx), and every bin (bx, by) of the binned
+ * detector (nbx = W/bin, nby = H/bin):
+ *   d_img[(j*nby + by)*nbx + bx] = G(kd, Q_j) for the kept bin kd at (bx, by), 0 for a dropped bin
+ * as complex64 (interleaved re, im).  The state must hold a finished reconstruction with these
+ * arguments (FINALIZE, ONESHOT or REFOCUS last): G is read from it (g_mode STORE) or computed as
+ * the DFT along ry of the row-transformed cube with FP64 accumulation (g_mode RECOMPUTE).  For
+ * mx > Nx/2 the value is conj G(kd, -Q) from the stored half spectrum (D is real).
+ * Errors: STEM_EINVAL (NULL pointers, n_q outside [1, STEM_MAX_PANEL], an index outside its
+ * range), STEM_EWORKSPACE. */
+int ssb_g_panel(const stem_det* det, const stem_scan* scan, const stem_optics* optics, const stem_ssb* ssb,
+                const void* state, size_t state_bytes, int n_q, const int32_t* h_my, const int32_t* h_mx,
+                float* d_img, void* stream);
+
 /* ---------------------------------------------------------------------------------------- */
 /* a8. Adjoint of the sideband phase (not in the paper)                                     */
 

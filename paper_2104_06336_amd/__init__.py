@@ -26,7 +26,7 @@ __all__ = [
     "STEM_G_STORE", "STEM_SSB_ACCUMULATE", "STEM_SSB_FINALIZE", "STEM_SSB_REFOCUS",
     "STEM_SSB_ONESHOT", "SsbState", "SSBPhase", "ssb_state_region", "STEM_REGION_D", "STEM_REGION_G",
     "STEM_REGION_T", "STEM_REGION_KC", "STEM_REGION_STATS", "trace_enable", "trace_records",
-    "virtual_annular", "sum_frames", "eer_decode_rle",
+    "virtual_annular", "sum_frames", "eer_decode_rle", "ssb_g_panel",
 ]
 
 
@@ -228,6 +228,20 @@ def ssb_backward(dLdphi, det: Det, scan: Scan, optics: Optics, ssb: Ssb, state, 
     _check(rc, "ssb_backward")
 
 
+def ssb_g_panel(det: Det, scan: Scan, optics: Optics, ssb: Ssb, state, qs, out, stream=None):
+    """G(K, Q) of the kept bins at the scan frequencies qs = [(my, mx), ...] as binned detector
+    images: out complex64 [len(qs), H/bin, W/bin], 0 on dropped bins."""
+    _dev(state, torch.uint8, "state")
+    n = len(qs)
+    nby, nbx = det.H // det.bin, det.W // det.bin
+    _dev(out, torch.complex64, "out", n * nby * nbx)
+    my = (ctypes.c_int32 * max(n, 1))(*[int(q[0]) for q in qs])
+    mx = (ctypes.c_int32 * max(n, 1))(*[int(q[1]) for q in qs])
+    rc = lib().ssb_g_panel(ctypes.byref(det), ctypes.byref(scan), ctypes.byref(optics), ctypes.byref(ssb),
+                           _p(state), state.numel(), n, my, mx, _p(out), _stream(stream))
+    _check(rc, "ssb_g_panel")
+
+
 # ----------------------------------------------------------------------------------------------
 # stateful convenience + autograd
 
@@ -281,6 +295,14 @@ class SsbState:
         o = self.optics if c is None else self.optics_with(c)
         ssb_reconstruct(d_idx, d_off, 0, self.F, self.det, self.scan, o, self.ssb, STEM_SSB_ONESHOT,
                         self.state, theta=theta, phase=phase, T=T, d_status=self.status, stream=stream)
+
+    def g_panel(self, qs, stream=None) -> torch.Tensor:
+        """G at the scan frequencies qs = [(my, mx), ...] as binned detector images
+        (complex64 [len(qs), H/bin, W/bin]); call after finalize, oneshot or refocus."""
+        out = torch.empty(len(qs), self.det.H // self.det.bin, self.det.W // self.det.bin, dtype=torch.complex64,
+                          device=self.state.device)
+        ssb_g_panel(self.det, self.scan, self.optics, self.ssb, self.state, qs, out, stream=stream)
+        return out
 
     def backward(self, dLdphi, c=None, theta=None, with_theta=True, stream=None):
         o = self.optics if c is None else self.optics_with(c)

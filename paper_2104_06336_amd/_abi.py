@@ -76,6 +76,10 @@ _SIGS = {
     "ssb_state_region": (ctypes.c_int, [ctypes.POINTER(Det), ctypes.POINTER(Scan), ctypes.POINTER(Optics),
                                         ctypes.POINTER(Ssb), ctypes.c_int, ctypes.POINTER(ctypes.c_size_t),
                                         ctypes.POINTER(ctypes.c_size_t)]),
+    "ssb_g_panel": (ctypes.c_int, [ctypes.POINTER(Det), ctypes.POINTER(Scan), ctypes.POINTER(Optics),
+                                   ctypes.POINTER(Ssb), ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int,
+                                   ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                   ctypes.c_void_p, ctypes.c_void_p]),
     "ssb_backward": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Det), ctypes.POINTER(Scan),
                                     ctypes.POINTER(Optics), ctypes.POINTER(Ssb), ctypes.c_void_p,
                                     ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p,

@@ -539,6 +539,87 @@ extern "C" int ssb_reconstruct(const int32_t* d_idx, const int64_t* d_off, int64
   return run_phase(L, b, *scan, b.part, L.groups, d_phase, d_T, s);
 }
 
+// ---------------------------------------------------------------------------------------------
+// G(K, Q) at selected Q as binned detector images: one wave per (bin, Q)
+
+struct PanelQ {
+  int32_t my[STEM_MAX_PANEL], mx[STEM_MAX_PANEL];
+};
+
+__global__ void __launch_bounds__(64) k_g_panel(const float2* __restrict__ X, const RowRun* __restrict__ rows,
+                                               int nbx, int n_k, int ny, int nx, PanelQ q, int g_stored,
+                                               float2* __restrict__ img) {
+  const int bin = blockIdx.x, j = blockIdx.y;  // bin = by * nbx + bx
+  const int by = bin / nbx, bx = bin % nbx;
+  const int lane = threadIdx.x;
+  float2* out = img + (int64_t)j * gridDim.x + bin;
+  const RowRun rr = rows[by];
+  if (bx < rr.lo || bx >= rr.hi) {
+    if (lane == 0) *out = make_float2(0.f, 0.f);
+    return;
+  }
+  const int kd = rr.start + bx - rr.lo;
+  if (kd < 0 || kd >= n_k) {  // a state whose geometry was never computed: nothing is read
+    if (lane == 0) *out = make_float2(0.f, 0.f);
+    return;
+  }
+  int my = q.my[j], mx = q.mx[j];
+  const bool cj = 2 * mx > nx;  // G(K, Q) = conj G(K, -Q): read the half spectrum at -Q
+  if (cj) {
+    mx = nx - mx;
+    my = (ny - my) & (ny - 1);
+  }
+  const float2* col = X + ((int64_t)kd * (nx / 2 + 1) + mx) * ny;
+  float2 v;
+  if (g_stored) {
+    v = col[my];
+  } else {
+    // sum over ry of X exp(-2 pi i my ry / Ny), angles reduced exactly as integers mod Ny
+    double re = 0.0, im = 0.0;
+    for (int ry = lane; ry < ny; ry += 64) {
+      const int k = (my * ry) & (ny - 1);
+      double sn, cs;
+      sincospi(2.0 * (double)k / (double)ny, &sn, &cs);
+      const float2 x = col[ry];
+      re += (double)x.x * cs + (double)x.y * sn;
+      im += (double)x.y * cs - (double)x.x * sn;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      re += __shfl_xor(re, o);
+      im += __shfl_xor(im, o);
+    }
+    v = make_float2((float)re, (float)im);
+  }
+  if (cj) v.y = -v.y;
+  if (lane == 0) *out = v;
+}
+
+extern "C" int ssb_g_panel(const stem_det* det, const stem_scan* scan, const stem_optics* optics,
+                           const stem_ssb* ssb, const void* state, size_t state_bytes, int n_q,
+                           const int32_t* h_my, const int32_t* h_mx, float* d_img, void* stream_) {
+  int n_k;
+  int st = check_common(det, scan, optics, ssb, &n_k);
+  if (st) return st;
+  if (!h_my || !h_mx || !d_img || n_q < 1 || n_q > STEM_MAX_PANEL) return STEM_EINVAL;
+  PanelQ q{};
+  for (int j = 0; j < n_q; ++j) {
+    if (h_my[j] < 0 || h_my[j] >= scan->ny || h_mx[j] < 0 || h_mx[j] >= scan->nx) return STEM_EINVAL;
+    q.my[j] = h_my[j];
+    q.mx[j] = h_mx[j];
+  }
+  SsbLayout L;
+  make_layout(*det, *scan, *ssb, n_k, &L);
+  if (!state || ((uintptr_t)state & 255) || state_bytes < L.total) return STEM_EWORKSPACE;
+  const Bufs b = carve(const_cast<void*>(state), L);
+  const int nbx = det->W / det->bin, nby = det->H / det->bin;
+  hipStream_t s = (hipStream_t)stream_;
+  STEM_TRACE("g_panel", s);
+  hipLaunchKernelGGL(k_g_panel, dim3((unsigned)(nbx * nby), (unsigned)n_q), dim3(64), 0, s, b.X, b.rows, nbx, n_k,
+                     scan->ny, scan->nx, q, ssb->g_mode == STEM_G_STORE ? 1 : 0, (float2*)d_img);
+  STEM_LAUNCH_CHECK();
+  return STEM_OK;
+}
+
 extern "C" int ssb_backward(const float* d_dLdphi, const stem_det* det, const stem_scan* scan,
                             const stem_optics* optics, const stem_ssb* ssb, const float* d_theta, void* state,
                             size_t state_bytes, double* d_dLdc, float* d_dLdtheta, int32_t* d_status,

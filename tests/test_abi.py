@@ -155,3 +155,24 @@ def test_detector_and_rle_argument_errors_return_einval_without_device_work():
     assert L.eer_decode_rle(fake, fake, 0, -1, ctypes.byref(det), fake, None, None) == 1
     assert L.eer_decode_rle(None, fake, 0, 4, ctypes.byref(det), fake, None, None) == 1
     assert L.eer_decode_rle(fake, fake, 0, 4, ctypes.byref(stem.Det(0, 64, 0, 0, 1)), fake, None, None) == 1
+
+
+def test_g_panel_argument_errors_return_without_device_work():
+    wl = WORKLOADS["small"]
+    det, scan, optics = _geom(wl)
+    L = stem.lib()
+    ssb = stem.Ssb(stem.STEM_FFT_FP32, 0, stem.STEM_G_STORE, 8)
+    fake = ctypes.c_void_p(256)
+    big = stem.ssb_state_bytes(det, scan, optics, ssb)
+    my = (ctypes.c_int32 * 2)(0, 3)
+    mx = (ctypes.c_int32 * 2)(0, 5)
+    call = lambda n, a=my, b=mx, st=fake, nb=big: L.ssb_g_panel(ctypes.byref(det), ctypes.byref(scan),
+                                                                ctypes.byref(optics), ctypes.byref(ssb), st, nb, n,
+                                                                a, b, fake, None)
+    assert call(0) == 1 and call(65) == 1
+    assert call(2, a=(ctypes.c_int32 * 2)(0, scan.ny)) == 1
+    assert call(2, b=(ctypes.c_int32 * 2)(-1, 0)) == 1
+    assert call(2, st=None) == 16
+    assert call(2, nb=256) == 16
+    assert L.ssb_g_panel(ctypes.byref(det), ctypes.byref(scan), ctypes.byref(optics), ctypes.byref(ssb), fake, big,
+                         2, None, mx, fake, None) == 1
