@@ -166,6 +166,30 @@ static int launch_yreduce(int prec, int ny, float2* X, const double2* kc, const 
   }
 }
 
+// Eq. 3 from the stored G without normalisation (REFOCUS): the fused sum over the stored columns
+static int launch_ysum_stored(int ny, float2* G, const double2* kc, const double* kchi, int4* cst, uint64_t* cmask,
+                              int nmw, int n_k, int nx, int ngroups, const Optics& o, int chi0, float2* part,
+                              unsigned long long* stats, hipStream_t s) {
+  launch_colsets(kc, n_k, nx, ny, o, cst, cmask, nmw, s);
+  STEM_LAUNCH_CHECK();
+  const int B = 1024 / ny;
+  const int ncs = (nx / 2 + 1 + B - 1) / B;
+  const dim3 grid((unsigned)(((ncs + 3) / 4) * ngroups)), blk(kYThreads);
+  STEM_TRACE("ssb_reduce", s);
+  const int st = with_n(ny, [&](auto nc) {
+    using XF = XfNone<decltype(nc)::value>;
+    if (chi0)
+      hipLaunchKernelGGL((k_yreduce<XF, true>), grid, blk, 0, s, G, kc, kchi, cst, cmask, nmw, n_k, nx, ngroups, o,
+                         0, part, stats);
+    else
+      hipLaunchKernelGGL((k_yreduce<XF, false>), grid, blk, 0, s, G, kc, kchi, cst, cmask, nmw, n_k, nx, ngroups, o,
+                         0, part, stats);
+  });
+  if (st) return st;
+  STEM_LAUNCH_CHECK();
+  return STEM_OK;
+}
+
 static int launch_yadjoint(int prec, int ny, const float2* X, const double2* kc, const double* kchi, int4* cst,
                            uint64_t* cmask, int nmw, int n_k, int nx, int ngroups, const Optics& o, int g_stored,
                            const float2* Tbt, double* pdc, float* pdth, hipStream_t s) {
@@ -503,12 +527,17 @@ extern "C" int ssb_reconstruct(const int32_t* d_idx, const int64_t* d_off, int64
     if (st) return st;
     if (mode == STEM_SSB_ACCUMULATE) return STEM_OK;
   }
-  if ((st = run_chi_table(b, d_theta, n_k, o, (mode == STEM_SSB_REFOCUS || ssb->normalize) ? 1 : L.groups, s)))
-    return st;
+  if ((st = run_chi_table(b, d_theta, n_k, o, ssb->normalize ? 1 : L.groups, s))) return st;
   if (mode == STEM_SSB_REFOCUS) {
-    // Eq. 3 again from the stored G
-    if ((st = run_reduce_stored(L, b, ny, nx, o, ssb->normalize, s))) return st;
-    return run_phase(L, b, *scan, b.T, 1, d_phase, d_T, s);
+    // Eq. 3 again from the stored G: per-Q normalised sum, or the fused sum over stored columns
+    if (ssb->normalize) {
+      if ((st = run_reduce_stored(L, b, ny, nx, o, 1, s))) return st;
+      return run_phase(L, b, *scan, b.T, 1, d_phase, d_T, s);
+    }
+    if ((st = launch_ysum_stored(ny, b.X, b.kc, b.kchi, b.cst, b.cmask, L.nmw, n_k, nx, L.groups, o,
+                                 chi_is_zero(o, d_theta), b.part, b.stats, s)))
+      return st;
+    return run_phase(L, b, *scan, b.part, L.groups, d_phase, d_T, s);
   }
   if (ssb->normalize && ssb->precision != STEM_FFT_FP32) {
     // split precision: the fused kernel transforms X -> G in place (its partial sums are not

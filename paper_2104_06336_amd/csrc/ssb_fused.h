@@ -70,6 +70,15 @@ struct XfMfma {
   }
 };
 
+// No transform: the registers hold a stored G column in the FFT's output layout, so the fused
+// sum's slots and membership masks apply unchanged (Eq. 3 again from a stored G).
+template <int N_>
+struct XfNone : XfFft<N_> {
+  static __device__ __forceinline__ void in(int lane, int i, int& b, int& n) { fft_out_index<N_>(lane, i, b, n); }
+  template <bool EXACT>
+  static __device__ __forceinline__ void run(float2*, float2*, const float2*, const uint4*, int) {}
+};
+
 template <int N, int PREC>
 struct XfSel {
   using type = XfMfma<N, PREC>;
