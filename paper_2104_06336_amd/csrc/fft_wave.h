@@ -23,10 +23,38 @@ constexpr int kFftLds = 1024 + 64;  // float2 per wave
 
 // tw[t] = exp(-2 pi i t / 1024), FP32 rounded from an FP64 evaluation with exact angle t/512.
 __device__ __forceinline__ void fill_twiddles(float2* tw, int tid, int nthreads) {
-  for (int t = tid; t < 1024; t += nthreads) {
+  // Only the first octant is evaluated: (cos, sin)(pi u / 512) for u = 0 .. 128 from FP64
+  // sincospi, rounded to FP32.  With t = 256 q + r, the angle pi t / 512 is q quarter turns plus
+  // phi = pi r / 512, and phi is pi u / 512 (r <= 128) or pi/2 - pi u / 512 (u = 256 - r), so every
+  // entry is a sign change or swap of an octant value: exact, and equal to the rounded value
+  // itself.  Every thread of the workgroup takes part (the function synchronises it); nthreads >= 64.
+  for (int u = tid; u <= 128; u += nthreads) {
     double s, c;
-    sincospi(-(double)t / 512.0, &s, &c);
-    tw[t] = make_float2((float)c, (float)s);
+    sincospi((double)u / 512.0, &s, &c);
+    tw[u] = make_float2((float)c, (float)s);
+  }
+  __syncthreads();
+  float2 val[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int t = tid + k * nthreads;
+    if (t < 1024) {
+      const int q = t >> 8, r = t & 255;
+      const float2 o = tw[r <= 128 ? r : 256 - r];
+      const float cp = r <= 128 ? o.x : o.y, sp = r <= 128 ? o.y : o.x;  // cos, sin of phi
+      float c, sn;
+      if (q == 0) { c = cp; sn = sp; }
+      else if (q == 1) { c = -sp; sn = cp; }
+      else if (q == 2) { c = -cp; sn = -sp; }
+      else { c = sp; sn = -cp; }
+      val[k] = make_float2(c, -sn);  // exp(-i pi t / 512)
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int t = tid + k * nthreads;
+    if (t < 1024) tw[t] = val[k];
   }
 }
 
