@@ -262,17 +262,22 @@ def main():
     def run(precision, steps, warmup, overlap=True, opt=optics):
         """Times `steps` whole steps with the given scan-DFT precision; returns
         (elapsed s, kernel trace, SSB phase, SsbState).  With overlap, COM + DPC run on a second
-        stream concurrently with the SSB reconstruction (the two share only the read-only events)."""
+        stream concurrently with the second half of the SSB reconstruction (FINALIZE after
+        ACCUMULATE over all frames, the same work as ONESHOT; the two share only the read-only
+        events)."""
         st = stem.SsbState(det, scan, opt, stem.Ssb(precision, 0, stem.STEM_G_RECOMPUTE, 8), device=dev)
         main = torch.cuda.current_stream(dev)
 
         def step():
             if overlap:
+                # binning + row transform first; COM + DPC (HBM- and latency-bound) then run beside the
+                # VALU-bound column transform + Eq. 3 and the phase passes
+                st.accumulate(d_idx, d_off, 0, F)
                 side.wait_stream(main)
                 with torch.cuda.stream(side):
                     stem.com_dpc(d_idx, d_off, 0, F, det, scan, optics, dpc, com64=com64, phase=phase_dpc, ws=ws,
                                  d_status=status)
-                st.oneshot(d_idx, d_off, phase=phase_ssb)
+                st.finalize(phase=phase_ssb)
                 main.wait_stream(side)
             else:
                 stem.com_dpc(d_idx, d_off, 0, F, det, scan, optics, dpc, com64=com64, phase=phase_dpc, ws=ws,
