@@ -15,7 +15,9 @@ namespace stem {
 
 constexpr int kWaveStride = kFftLds + 4;  // float2 per wave buffer; the +4 staggers LDS banks
 
-template <int N, bool INV, int W>
+// SUM: the input is the sum of a.nparts partial planes (in_mode IN_C64_SUM), read four at a time;
+// a separate instantiation, so that the other input modes keep their lower register count.
+template <int N, bool INV, int W, bool SUM>
 __global__ void __launch_bounds__(64 * W) k_row_fft(RowFftArgs a, int in_mode, int out_mode) {
   constexpr int kRowThreads = 64 * W;
   __shared__ float2 s_tw[1024];
@@ -31,13 +33,12 @@ __global__ void __launch_bounds__(64 * W) k_row_fft(RowFftArgs a, int in_mode, i
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int64_t r0 = tile * TR + wave * B;
     float2 v[16];
-    if (in_mode == IN_C64_SUM) {
-      // partial sums in a fixed order; the 16 loads of one partial are issued together
+    if constexpr (SUM) {
+      // partial sums added in a fixed order; the 64 loads of four partials are issued together
 #pragma unroll
       for (int i = 0; i < 16; ++i) v[i] = make_float2(0.f, 0.f);
-      for (int p = 0; p < a.nparts; ++p) {
+      auto load_part = [&](int p, float2* t) {
         const float2* src = a.in_c + (int64_t)p * a.part_stride;
-        float2 t[16];
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
           int b, n;
@@ -45,6 +46,20 @@ __global__ void __launch_bounds__(64 * W) k_row_fft(RowFftArgs a, int in_mode, i
           const int64_t r = r0 + b;
           t[i] = r < a.nrows ? src[r * N + n] : make_float2(0.f, 0.f);
         }
+      };
+      int p = 0;
+      for (; p + 4 <= a.nparts; p += 4) {
+        float2 t[4][16];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) load_part(p + k, t[k]);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+          for (int i = 0; i < 16; ++i) v[i] = cadd(v[i], t[k][i]);
+      }
+      for (; p < a.nparts; ++p) {
+        float2 t[16];
+        load_part(p, t);
 #pragma unroll
         for (int i = 0; i < 16; ++i) v[i] = cadd(v[i], t[i]);
       }
@@ -124,10 +139,16 @@ static void launch_nw(bool inv, const RowFftArgs& a, int in, int out, hipStream_
   const int64_t tr = W * (1024 / N);
   const int64_t tiles = (a.nrows + tr - 1) / tr;
   const dim3 grid((unsigned)(tiles < 2048 ? tiles : 2048));
-  if (inv)
-    hipLaunchKernelGGL((k_row_fft<N, true, W>), grid, dim3(64 * W), 0, s, a, in, out);
-  else
-    hipLaunchKernelGGL((k_row_fft<N, false, W>), grid, dim3(64 * W), 0, s, a, in, out);
+  if (in == IN_C64_SUM) {
+    if (inv)
+      hipLaunchKernelGGL((k_row_fft<N, true, W, true>), grid, dim3(64 * W), 0, s, a, in, out);
+    else
+      hipLaunchKernelGGL((k_row_fft<N, false, W, true>), grid, dim3(64 * W), 0, s, a, in, out);
+  } else if (inv) {
+    hipLaunchKernelGGL((k_row_fft<N, true, W, false>), grid, dim3(64 * W), 0, s, a, in, out);
+  } else {
+    hipLaunchKernelGGL((k_row_fft<N, false, W, false>), grid, dim3(64 * W), 0, s, a, in, out);
+  }
 }
 
 template <int N>
