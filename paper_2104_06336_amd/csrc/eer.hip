@@ -452,15 +452,11 @@ __global__ void __launch_bounds__(256) k_pixel_lut(const RowRun* __restrict__ ro
   lut[p] = (int16_t)(bx >= rr.lo && bx < rr.hi ? rr.start + bx - rr.lo : -1);
 }
 
-int launch_geometry(const stem_det& det, double r2, RowRun* rows, double2* kc, int16_t* lut, hipStream_t stream) {
+int launch_geometry(const stem_det& det, double r2, RowRun* rows, double2* kc, hipStream_t stream) {
   const int nbx = det.W / det.bin, nby = det.H / det.bin;
   STEM_TRACE("ssb_geometry", stream);
   hipLaunchKernelGGL(k_geometry, dim3(1), dim3(256), 0, stream, det.bin, nbx, nby, det.cx, det.cy, r2,
                      rows, kc);
-  STEM_LAUNCH_CHECK();
-  const int64_t npix = (int64_t)det.W * det.H;
-  hipLaunchKernelGGL(k_pixel_lut, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, stream, rows, det.W, det.H,
-                     det.bin, lut);
   STEM_LAUNCH_CHECK();
   return STEM_OK;
 }
@@ -502,7 +498,8 @@ template <typename DT, bool BOX>
 __global__ void __launch_bounds__(kBinThreads) k_bin(const int32_t* __restrict__ idx,
                                                      const int64_t* __restrict__ off, int64_t frame0,
                                                      int64_t n_frames, int32_t npix,
-                                                     const int16_t* __restrict__ lut, BinBox box, int32_t n_k,
+                                                     const int16_t* __restrict__ lut,
+                                                     const RowRun* __restrict__ rows, BinBox box, int32_t n_k,
                                                      int64_t F, DT* __restrict__ D, int32_t* status) {
   extern __shared__ int16_t s_box[];  // [bh][bw] kept-bin index of each bin of the box, or -1
   __shared__ __align__(16) uint32_t s_hist[kBinWords];
@@ -518,10 +515,11 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(const int32_t* __restrict__
   const int nf = (int)((fend - fb) < kBinFrames ? (fend - fb) : kBinFrames);
   if (!load_rel_offsets(off, fb, nf, s_rel, &s_base, status)) return;
   if constexpr (BOX) {
-    // the table entry of a bin is the global table's entry of its first pixel
+    // kept index of each bin of the box from the row runs (the rule of the per-pixel table)
     for (int i = t; i < box.bw * box.bh; i += kBinThreads) {
       const int by = box.by0 + i / box.bw, bx = box.bx0 + i % box.bw;
-      s_box[i] = lut[(int64_t)by * box.bin * box.W + (int64_t)bx * box.bin];
+      const RowRun rr = rows[by];
+      s_box[i] = (int16_t)(bx >= rr.lo && bx < rr.hi ? rr.start + bx - rr.lo : -1);
     }
   }
   __syncthreads();
@@ -661,8 +659,8 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(const int32_t* __restrict__
 }
 
 int launch_bin(const int32_t* idx, const int64_t* off, int64_t frame0, int64_t n_frames,
-               const stem_det& det, double r2, const int16_t* lut, int n_k, int64_t F, void* D, int d_bits,
-               int32_t* status, hipStream_t stream) {
+               const stem_det& det, double r2, const RowRun* rows, int16_t* lut, int n_k, int64_t F, void* D,
+               int d_bits, int32_t* status, hipStream_t stream) {
   if (n_frames == 0) return STEM_OK;
   const int nchunks = (n_k + kBinKd - 1) / kBinKd;
   const int64_t fblocks = (n_frames + kBinFrames - 1) / kBinFrames;
@@ -692,21 +690,29 @@ int launch_bin(const int32_t* idx, const int64_t* off, int64_t frame0, int64_t n
   const int64_t cells = (int64_t)box.bw * box.bh;
   const bool use_box = cells > 0 && cells <= kBinBoxMax && det.W < 65536 && det.H < 65536;
   const size_t lds = use_box ? (size_t)((cells * 2 + 15) & ~15ll) : 0;
+  if (!use_box) {
+    // the per-pixel table, read by the binning kernel
+    STEM_TRACE("pixel_lut", stream);
+    const int64_t npix = (int64_t)det.W * det.H;
+    hipLaunchKernelGGL(k_pixel_lut, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, stream, rows, det.W, det.H,
+                       det.bin, lut);
+    STEM_LAUNCH_CHECK();
+  }
   STEM_TRACE("bin_densify", stream);
   if (d_bits == 8) {
     if (use_box)
       hipLaunchKernelGGL((k_bin<uint8_t, true>), grid, dim3(kBinThreads), lds, stream, idx, off, frame0, n_frames,
-                         det.W * det.H, lut, box, n_k, F, (uint8_t*)D, status);
+                         det.W * det.H, lut, rows, box, n_k, F, (uint8_t*)D, status);
     else
       hipLaunchKernelGGL((k_bin<uint8_t, false>), grid, dim3(kBinThreads), 0, stream, idx, off, frame0, n_frames,
-                         det.W * det.H, lut, box, n_k, F, (uint8_t*)D, status);
+                         det.W * det.H, lut, rows, box, n_k, F, (uint8_t*)D, status);
   } else {
     if (use_box)
       hipLaunchKernelGGL((k_bin<uint16_t, true>), grid, dim3(kBinThreads), lds, stream, idx, off, frame0,
-                         n_frames, det.W * det.H, lut, box, n_k, F, (uint16_t*)D, status);
+                         n_frames, det.W * det.H, lut, rows, box, n_k, F, (uint16_t*)D, status);
     else
       hipLaunchKernelGGL((k_bin<uint16_t, false>), grid, dim3(kBinThreads), 0, stream, idx, off, frame0,
-                         n_frames, det.W * det.H, lut, box, n_k, F, (uint16_t*)D, status);
+                         n_frames, det.W * det.H, lut, rows, box, n_k, F, (uint16_t*)D, status);
   }
   STEM_LAUNCH_CHECK();
   return STEM_OK;
