@@ -480,7 +480,8 @@ constexpr int kBinWords = 5976;                       // 23 KB of counters
 // pixel rows of counters are kBinFrames/4 (+1 padding) words apart, so that the events of one
 // frame (same column, different pixels) fall into different LDS banks
 constexpr int kBinKd = kBinWords / (kBinFrames / 4 + 1);  // 181 pixels per workgroup
-constexpr int kBinWin = 4096;                         // events per window of the frame map
+constexpr int kBinWin = 6144;                         // events per window of the frame map (a block of
+                                                      // 128 frames at 40 events per frame fits one)
 constexpr int kBinBoxMax = 4096;                      // bins of the largest LDS bin table (8 KB)
 
 // The kept bins' bounding box (in bins) and the divisions that take a pixel to its bin: with it
@@ -561,7 +562,7 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(const int32_t* __restrict__
       // the event array's pages; the other positions of the line are masked out.
       const int32_t* ib = idx + (a0 - sh);
       const int ng = (wn + sh + 3) >> 2;
-      constexpr int U = 4;  // groups per thread in flight
+      constexpr int U = kBinWin / (4 * kBinThreads);  // groups per thread in flight: one pass per window
       for (int g0 = t; g0 < ng; g0 += U * kBinThreads) {
         int4 kv[U];
         uint32_t fr4[U];
