@@ -88,29 +88,29 @@ __device__ __forceinline__ void load_group(const int32_t* __restrict__ idx, int6
   }
 }
 
-// Staging of a workgroup's events in LDS: the events [a0, a0 + n) (absolute indices) are copied
-// from the 16-byte aligned position at or below a0; s[sh + j] then holds event a0 + j (sh < 4 is
-// returned).  Each thread issues kStageUnroll loads before its LDS stores, so that many loads are
-// in flight; nothing outside the window is read.
-constexpr int kStageUnroll = 8;
+// Staging of a workgroup's events in LDS: the events [a0, a0 + n) (absolute indices, n <= kComWin)
+// are copied as whole 16-byte lines from the aligned position at or below a0; s[sh + j] then holds
+// event a0 + j (sh < 4 is returned).  Every line holds at least one of the events, so it lies in
+// the event array's pages; its other entries land outside [sh, sh + n) and are never read.  Each
+// thread issues kStageGroups loads before its LDS stores: a window takes one round.
+constexpr int kComWin = 12288;
+constexpr int kStageGroups = kComWin / (4 * kComThreads);
 
 __device__ __forceinline__ int stage_events(const int32_t* __restrict__ idx, int64_t a0, int n, int32_t* s) {
   const int sh = (int)((((uintptr_t)(idx + a0)) & 15) >> 2);
-  const int64_t al = a0 - sh, aend = a0 + n;
-  const int nchunk = (n + sh + 3) >> 2;
-  const int step = blockDim.x * kStageUnroll;
-  for (int c0 = threadIdx.x; c0 < nchunk; c0 += step) {
-    int32_t k[kStageUnroll][4];
-    bool ok[kStageUnroll][4];
+  const int32_t* ib = idx + (a0 - sh);
+  const int ng = (n + sh + 3) >> 2;
+  for (int c0 = threadIdx.x; c0 < ng; c0 += kComThreads * kStageGroups) {
+    int4 v[kStageGroups];
 #pragma unroll
-    for (int u = 0; u < kStageUnroll; ++u) {
-      const int c = c0 + u * blockDim.x;
-      if (c < nchunk) load_group(idx, al + 4 * (int64_t)c, a0, aend, k[u], ok[u]);
+    for (int u = 0; u < kStageGroups; ++u) {
+      const int c = c0 + u * kComThreads;
+      v[u] = c < ng ? *(const int4*)(ib + 4 * c) : make_int4(0, 0, 0, 0);
     }
 #pragma unroll
-    for (int u = 0; u < kStageUnroll; ++u) {
-      const int c = c0 + u * blockDim.x;
-      if (c < nchunk) *(int4*)&s[4 * c] = make_int4(k[u][0], k[u][1], k[u][2], k[u][3]);
+    for (int u = 0; u < kStageGroups; ++u) {
+      const int c = c0 + u * kComThreads;
+      if (c < ng) *(int4*)&s[4 * c] = v[u];
     }
   }
   return sh;
@@ -122,7 +122,6 @@ __device__ __forceinline__ int stage_events(const int32_t* __restrict__ idx, int
 // from LDS with four independent accumulators (int32 within a window, int64 across windows).
 
 constexpr int kComFrames = 256;
-constexpr int kComWin = 12288;
 
 __global__ void __launch_bounds__(kComThreads) k_com(const int32_t* __restrict__ idx,
                                                      const int64_t* __restrict__ off,
