@@ -278,7 +278,12 @@ __global__ void __launch_bounds__(256) k_reduce(const float2* __restrict__ G, co
 static int yreduce_groups(int ny, int nx, int n_k) {
   const int B = 1024 / ny;
   const int ncs = (nx / 2 + 1 + B - 1) / B;
-  int g = (4096 + ncs - 1) / ncs;
+  // about 2560 waves: 1.25 times the waves the GPU holds at once (256 CUs x 8 at this kernel's
+  // register use), so that waves of cheap columns (few pixels with a non-empty set) free their
+  // slots for the rest; measured at scan1024 (513 column sets): 5 groups 139 us, 4 groups 145 us,
+  // 8 groups 156 us
+  const int blocks_per_group = (ncs + 3) / 4;
+  int g = (2560 + 2 * blocks_per_group) / (4 * blocks_per_group);
   const int64_t F = (int64_t)ny * nx;
   const int gmax = (int)((64ll << 20) / (F * 8));
   if (g > gmax) g = gmax;
