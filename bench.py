@@ -46,8 +46,11 @@ def algorithmic_bytes(name, g):
         "ssb_yreduce": X + 8 * F * g["groups"],                # X in, partial T per pixel group out
         "ssb_reduce": 8 * P + 8 * F,                            # G on the double-overlap pairs, T out
         "phase_fft": 8 * F * (1 + g["groups"]) // 2 + 8 * F,  # the two passes averaged: partial sums in, T out
-        "dpc_fft": 2 * 8 * F,
-        "dpc_update": 16 * F,
+        # DPC: COM planes (FP64) in, half spectra Gx, Gy out; both in, half-spectrum result out;
+        # that in, the phase image (FP32) out
+        "dpc_rows": 16 * F + 2 * 8 * nh * ny,
+        "dpc_cols": 2 * 8 * nh * ny + 8 * nh * ny,
+        "dpc_fft": 8 * nh * ny + 4 * F,
     }
     return table.get(name)
 
@@ -81,7 +84,7 @@ PROFILED = {
     "stem::k_bin<unsigned char, true>": "bin_densify",
     "stem::k_xstage<stem::XfFft<1024>, unsigned char>": "xstage_fft",
     "stem::k_yreduce<stem::XfFft<1024>, true>": "ssb_yreduce",
-    "stem::k_dpc_update": "dpc_update",
+    "stem::k_dpc_cols<1024, 4>": "dpc_cols",
 }
 
 

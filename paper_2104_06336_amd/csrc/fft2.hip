@@ -82,6 +82,10 @@ __global__ void __launch_bounds__(64 * W) k_row_fft(RowFftArgs a, int in_mode, i
           const int64_t e = r * N + n;
           if (in_mode == IN_C64) {
             x = a.in_c[e];
+          } else if (in_mode == IN_HALF_C64) {
+            // Hermitian row from its first N/2 + 1 entries: x(N - m) = conj x(m)
+            const float2* hr = a.in_c + r * (N / 2 + 1);
+            x = 2 * n <= N ? hr[n] : cconj(hr[N - n]);
           } else if (in_mode == IN_F32_PAIR) {
             x.x = a.in_f0[e] * a.s0;
             x.y = a.in_f1 ? a.in_f1[e] * a.s1 : 0.f;
@@ -182,51 +186,207 @@ int launch_row_fft(int n, bool inverse, RowIn in, RowOut out, const RowFftArgs& 
 // d = lam1 + |2 pi q|^2 + lam2 |2 pi q|^4:  Phi <- Phi + mu conj(D).(G - D Phi)/d, L times, in
 // double; q = 0 and the Nyquist row/column are held at zero.
 
-__global__ void __launch_bounds__(256) k_dpc_update(const float2* __restrict__ C, float2* __restrict__ Phi,
-                                                    int ny, int nx, double step, double mu, double lam1,
-                                                    double lam2, int n_iter) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (int64_t)ny * nx) return;
-  const int my = (int)(e / nx), mx = (int)(e % nx);
-  const int myn = (ny - my) % ny, mxn = (nx - mx) % nx;
-  const float2 c = C[e], cm = C[(int64_t)myn * nx + mxn];
-  // Gx = (c + conj cm)/2, Gy = (c - conj cm)/(2i)
-  const double gxr = 0.5 * ((double)c.x + cm.x), gxi = 0.5 * ((double)c.y - cm.y);
-  const double dyr = 0.5 * ((double)c.x - cm.x), dyi = 0.5 * ((double)c.y + cm.y);
-  const double gyr = dyi, gyi = -dyr;  // (a + ib)/i = b - ia
-  const int sy = my < (ny + 1) / 2 ? my : my - ny;
-  const int sx = mx < (nx + 1) / 2 ? mx : mx - nx;
-  const double two_pi = 6.283185307179586476925286766559;
-  const double qy = two_pi * ((double)sy / ((double)ny * step));
-  const double qx = two_pi * ((double)sx / ((double)nx * step));
-  const double q2 = qx * qx + qy * qy;
-  const double d = lam1 + q2 + lam2 * q2 * q2;
-  const bool live = d != 0.0 && !(my == 0 && mx == 0) && !((ny % 2 == 0) && my == ny / 2) &&
-                    !((nx % 2 == 0) && mx == nx / 2);
-  double pr = 0.0, pi = 0.0;
-  if (live) {
-    const double md = mu / d;  // the step size over the regularised denominator, fixed per frequency
-    for (int l = 0; l < n_iter; ++l) {
-      // residuals G - D Phi with D = i q:  i q (pr + i pi) = -q pi + i q pr
-      const double rxr = gxr + qx * pi, rxi = gxi - qx * pr;
-      const double ryr = gyr + qy * pi, ryi = gyi - qy * pr;
-      // conj(D) r = -i q r = q ri - i q rr
-      const double ur = qx * rxi + qy * ryi, ui = -(qx * rxr + qy * ryr);
-      pr += md * ur;
-      pi += md * ui;
+// ---------------------------------------------------------------------------------------------
+// DPC integration in three passes over the packed gradient z = gx + i gy (Sec. V):
+//  k_dpc_rows  rows ry: FFT along rx, split into the half spectra Gx, Gy along x (z(m) and
+//              conj z(-m)), written transposed [mx][ry] for mx in [0, Nx/2];
+//  k_dpc_cols  rows mx: FFT of both along ry, the per-frequency gradient descent (no mirror
+//              element needed: Gx and Gy are separate), inverse FFT along my, written
+//              transposed [ry][mx] (half spectrum along x);
+//  then k_row_fft (IN_HALF_C64) rows ry: inverse along mx of the Hermitian row, real part / F.
+
+template <int N, int W>
+__global__ void __launch_bounds__(64 * W) k_dpc_rows(const double* __restrict__ c64, const float* __restrict__ c32,
+                                                   int64_t plane, int ny, float g, float2* __restrict__ Ax,
+                                                   float2* __restrict__ Ay) {
+  constexpr int kThreads = 64 * W;
+  constexpr int B = 1024 / N, TR = W * B, NH = N / 2 + 1;
+  __shared__ float2 s_tw[1024];
+  __shared__ float2 s_buf[W * kWaveStride];
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  fill_twiddles(s_tw, threadIdx.x, kThreads);
+  __syncthreads();
+  float2* buf = s_buf + wave * kWaveStride;
+  const int ntiles = (ny + TR - 1) / TR;
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int r0 = tile * TR + wave * B;
+    float2 v[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      int b, n;
+      fft_in_index<N>(lane, i, b, n);
+      const int r = r0 + b;
+      float2 x = make_float2(0.f, 0.f);
+      if (r < ny) {
+        const int64_t e = (int64_t)r * N + n;
+        x = c64 ? make_float2((float)(c64[e] * (double)g), (float)(c64[plane + e] * (double)g))
+                : make_float2(c32[e] * g, c32[plane + e] * g);
+      }
+      v[i] = x;
     }
+    wave_fft<N>(v, buf, s_tw, lane);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      int b, m;
+      fft_out_index<N>(lane, i, b, m);
+      buf[fft_pad(b * N + m)] = v[i];
+    }
+    __syncthreads();
+    for (int u = threadIdx.x; u < TR * NH; u += kThreads) {
+      const int m = u / TR, rl = u % TR;
+      const int w = rl / B, b = rl % B;
+      const int r = tile * TR + rl;
+      if (r < ny) {
+        const float2* wb = s_buf + w * kWaveStride;
+        const float2 z = wb[fft_pad(b * N + m)];
+        const float2 zc = cconj(wb[fft_pad(b * N + ((N - m) & (N - 1)))]);
+        Ax[(int64_t)m * ny + r] = cscale(cadd(z, zc), 0.5f);
+        Ay[(int64_t)m * ny + r] = cscale(cmul_mi(csub(z, zc)), 0.5f);
+      }
+    }
+    __syncthreads();
   }
-  Phi[e] = make_float2((float)pr, (float)pi);
 }
 
-int launch_dpc_update(const float2* C, float2* Phi, int ny, int nx, double step, const stem_dpc& p,
-                      hipStream_t stream) {
-  const int64_t n = (int64_t)ny * nx;
-  STEM_TRACE("dpc_update", stream);
-  hipLaunchKernelGGL(k_dpc_update, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, C, Phi, ny, nx,
-                     step, p.mu, p.lam1, p.lam2, p.n_iter);
-  STEM_LAUNCH_CHECK();
-  return STEM_OK;
+template <int N, int W>
+__global__ void __launch_bounds__(64 * W) k_dpc_cols(const float2* __restrict__ Ax, const float2* __restrict__ Ay,
+                                                   int nx, double step, double mu, double lam1, double lam2,
+                                                   int n_iter, float2* __restrict__ Q) {
+  constexpr int kThreads = 64 * W;
+  constexpr int B = 1024 / N, TR = W * B;
+  __shared__ float2 s_tw[1024];
+  __shared__ float2 s_buf[W * kWaveStride];
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  fill_twiddles(s_tw, threadIdx.x, kThreads);
+  __syncthreads();
+  float2* buf = s_buf + wave * kWaveStride;
+  const int nh = nx / 2 + 1;
+  const int ntiles = (nh + TR - 1) / TR;
+  const double two_pi = 6.283185307179586476925286766559;
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int r0 = tile * TR + wave * B;  // rows are frequencies mx
+    float2 vx[16], vy[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      int b, n;
+      fft_in_index<N>(lane, i, b, n);
+      const int r = r0 + b;
+      vx[i] = r < nh ? Ax[(int64_t)r * N + n] : make_float2(0.f, 0.f);
+      vy[i] = r < nh ? Ay[(int64_t)r * N + n] : make_float2(0.f, 0.f);
+    }
+    wave_fft<N>(vx, buf, s_tw, lane);
+    wave_fft<N>(vy, buf, s_tw, lane);
+    // gradient descent per frequency (my, mx); the result goes to LDS in natural order
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      int b, my;
+      fft_out_index<N>(lane, i, b, my);
+      const int mx = r0 + b;
+      const int sy = my < (N + 1) / 2 ? my : my - N;
+      const int sx = mx < (nx + 1) / 2 ? mx : mx - nx;
+      const double qy = two_pi * ((double)sy / ((double)N * step));
+      const double qx = two_pi * ((double)sx / ((double)nx * step));
+      const double q2 = qx * qx + qy * qy;
+      const double d = lam1 + q2 + lam2 * q2 * q2;
+      const bool live = d != 0.0 && !(my == 0 && mx == 0) && my != N / 2 && mx != nx / 2 && mx < nh;
+      double pr = 0.0, pi = 0.0;
+      if (live) {
+        const double gxr = vx[i].x, gxi = vx[i].y, gyr = vy[i].x, gyi = vy[i].y;
+        const double md = mu / d;
+        for (int l = 0; l < n_iter; ++l) {
+          // residuals G - D Phi with D = i q, then conj(D) r = -i q r
+          const double rxr = gxr + qx * pi, rxi = gxi - qx * pr;
+          const double ryr = gyr + qy * pi, ryi = gyi - qy * pr;
+          const double ur = qx * rxi + qy * ryi, ui = -(qx * rxr + qy * ryr);
+          pr += md * ur;
+          pi += md * ui;
+        }
+      }
+      buf[fft_pad(b * N + my)] = make_float2((float)pr, (float)pi);
+    }
+    wave_lds_sync();
+    // inverse along my: conj, forward transform, conj
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      int b, n;
+      fft_in_index<N>(lane, i, b, n);
+      vx[i] = cconj(buf[fft_pad(b * N + n)]);
+    }
+    wave_lds_sync();
+    wave_fft<N>(vx, buf, s_tw, lane);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      int b, m;
+      fft_out_index<N>(lane, i, b, m);
+      buf[fft_pad(b * N + m)] = cconj(vx[i]);
+    }
+    __syncthreads();
+    // transposed write: Q[ry][mx], runs of TR frequencies mx
+    for (int u = threadIdx.x; u < TR * N; u += kThreads) {
+      const int m = u / TR, rl = u % TR;
+      const int w = rl / B, b = rl % B;
+      const int r = tile * TR + rl;
+      if (r < nh) Q[(int64_t)m * nh + r] = s_buf[w * kWaveStride + fft_pad(b * N + m)];
+    }
+    __syncthreads();
+  }
+}
+
+template <int N>
+static void launch_dpc_rows(const double* c64, const float* c32, int64_t plane, int ny, float g, float2* Ax,
+                            float2* Ay, hipStream_t s) {
+  constexpr int W = 4;
+  const int tiles = (ny + W * (1024 / N) - 1) / (W * (1024 / N));
+  hipLaunchKernelGGL((k_dpc_rows<N, W>), dim3((unsigned)tiles), dim3(64 * W), 0, s, c64, c32, plane, ny, g, Ax, Ay);
+}
+
+template <int N>
+static void launch_dpc_cols(const float2* Ax, const float2* Ay, int nx, double step, const stem_dpc& p, float2* Q,
+                            hipStream_t s) {
+  constexpr int W = 4;
+  const int nh = nx / 2 + 1;
+  const int tiles = (nh + W * (1024 / N) - 1) / (W * (1024 / N));
+  hipLaunchKernelGGL((k_dpc_cols<N, W>), dim3((unsigned)tiles), dim3(64 * W), 0, s, Ax, Ay, nx, step, p.mu, p.lam1,
+                     p.lam2, p.n_iter, Q);
+}
+
+// the three DPC passes for power-of-two lengths in [32, 1024]
+static int launch_dpc(const double* c64, const float* c32, int64_t F, int ny, int nx, float g, double step,
+                      const stem_dpc& p, float2* Ax, float2* Ay, float2* Q, float* phase, hipStream_t s) {
+  {
+    STEM_TRACE("dpc_rows", s);
+    switch (nx) {
+      case 32: launch_dpc_rows<32>(c64, c32, F, ny, g, Ax, Ay, s); break;
+      case 64: launch_dpc_rows<64>(c64, c32, F, ny, g, Ax, Ay, s); break;
+      case 128: launch_dpc_rows<128>(c64, c32, F, ny, g, Ax, Ay, s); break;
+      case 256: launch_dpc_rows<256>(c64, c32, F, ny, g, Ax, Ay, s); break;
+      case 512: launch_dpc_rows<512>(c64, c32, F, ny, g, Ax, Ay, s); break;
+      case 1024: launch_dpc_rows<1024>(c64, c32, F, ny, g, Ax, Ay, s); break;
+      default: return STEM_EINVAL;
+    }
+    STEM_LAUNCH_CHECK();
+  }
+  {
+    STEM_TRACE("dpc_cols", s);
+    switch (ny) {
+      case 32: launch_dpc_cols<32>(Ax, Ay, nx, step, p, Q, s); break;
+      case 64: launch_dpc_cols<64>(Ax, Ay, nx, step, p, Q, s); break;
+      case 128: launch_dpc_cols<128>(Ax, Ay, nx, step, p, Q, s); break;
+      case 256: launch_dpc_cols<256>(Ax, Ay, nx, step, p, Q, s); break;
+      case 512: launch_dpc_cols<512>(Ax, Ay, nx, step, p, Q, s); break;
+      case 1024: launch_dpc_cols<1024>(Ax, Ay, nx, step, p, Q, s); break;
+      default: return STEM_EINVAL;
+    }
+    STEM_LAUNCH_CHECK();
+  }
+  // inverse along mx of the Hermitian rows, real part / F -> phase[ry][rx]
+  RowFftArgs a{};
+  a.nrows = ny;
+  a.in_c = Q;
+  a.out_f = phase;
+  a.osc = make_float2((float)(1.0 / (double)F), 0.f);
+  a.tag = "dpc_fft";
+  return launch_row_fft(nx, true, IN_HALF_C64, OUT_ROW_RE, a, s);
 }
 
 }  // namespace stem
@@ -238,7 +398,8 @@ using namespace stem;
 
 extern "C" size_t com_dpc_workspace_bytes(const stem_scan* scan) {
   if (!scan || scan->ny <= 0 || scan->nx <= 0) return 0;
-  return 2 * align256((size_t)scan->ny * scan->nx * sizeof(float2));
+  // the half spectra Gx, Gy along x and the half-spectrum result, (Nx/2+1) Ny complex64 each
+  return 3 * align256((size_t)scan->ny * (scan->nx / 2 + 1) * sizeof(float2));
 }
 
 extern "C" int com_dpc(const int32_t* d_idx, const int64_t* d_off, int64_t frame0, int64_t n_frames,
@@ -261,50 +422,10 @@ extern "C" int com_dpc(const int32_t* d_idx, const int64_t* d_off, int64_t frame
   if (st != STEM_OK || !d_phase) return st;
 
   const int ny = scan->ny, nx = scan->nx;
-  float2* A = (float2*)ws;
-  float2* Bb = (float2*)((char*)ws + align256((size_t)F * sizeof(float2)));
+  const size_t half = align256((size_t)ny * (nx / 2 + 1) * sizeof(float2));
+  float2* Ax = (float2*)ws;
+  float2* Ay = (float2*)((char*)ws + half);
+  float2* Q = (float2*)((char*)ws + 2 * half);
   const float g = (float)(2.0 * 3.14159265358979323846 * optics->dk);
-  RowFftArgs a{};
-  // pass 1: rows (ry) of gx + i gy along rx -> A[mx][ry]
-  a.nrows = ny;
-  if (d_com64) {
-    a.in_d0 = d_com64;
-    a.in_d1 = d_com64 + F;
-  } else {
-    a.in_f0 = d_com32;
-    a.in_f1 = d_com32 + F;
-  }
-  a.s0 = a.s1 = g;
-  a.out_c = A;
-  a.out_stride = ny;
-  a.osc = make_float2(1.f, 0.f);
-  a.tag = "dpc_fft";
-  st = launch_row_fft(nx, false, d_com64 ? IN_F64_PAIR : IN_F32_PAIR, OUT_T_C64, a, stream);
-  if (st) return st;
-  // pass 2: rows (mx) of A along ry -> Bb[my][mx]
-  a = RowFftArgs{};
-  a.nrows = nx;
-  a.in_c = A;
-  a.out_c = Bb;
-  a.out_stride = nx;
-  a.osc = make_float2(1.f, 0.f);
-  a.tag = "dpc_fft";
-  if ((st = launch_row_fft(ny, false, IN_C64, OUT_T_C64, a, stream))) return st;
-  // gradient descent per frequency: Bb -> A (Phi, [my][mx])
-  if ((st = launch_dpc_update(Bb, A, ny, nx, scan->step, *dpc, stream))) return st;
-  // pass 3: inverse along mx -> Bb[rx][my]
-  a.nrows = ny;
-  a.in_c = A;
-  a.out_c = Bb;
-  a.out_stride = ny;
-  if ((st = launch_row_fft(nx, true, IN_C64, OUT_T_C64, a, stream))) return st;
-  // pass 4: inverse along my -> phase[ry][rx] = Re / N_R
-  a = RowFftArgs{};
-  a.nrows = nx;
-  a.in_c = Bb;
-  a.out_f = d_phase;
-  a.out_stride = nx;
-  a.osc = make_float2((float)(1.0 / (double)F), 0.f);
-  a.tag = "dpc_fft";
-  return launch_row_fft(ny, true, IN_C64, OUT_T_RE, a, stream);
+  return launch_dpc(d_com64, d_com64 ? nullptr : d_com32, F, ny, nx, g, scan->step, *dpc, Ax, Ay, Q, d_phase, stream);
 }

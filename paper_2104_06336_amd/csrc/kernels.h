@@ -18,13 +18,14 @@ int launch_bin(const int32_t* idx, const int64_t* off, int64_t frame0, int64_t n
                int d_bits, int32_t* status, hipStream_t stream);
 
 // ---- fft2.hip: batched row FFTs of length n (power of two, 32..1024) --------------------------
-enum RowIn { IN_C64 = 0, IN_C64_SUM = 1, IN_F32_PAIR = 2, IN_F64_PAIR = 3 };
+enum RowIn { IN_C64 = 0, IN_C64_SUM = 1, IN_F32_PAIR = 2, IN_F64_PAIR = 3, IN_HALF_C64 = 4 };
 enum RowOut { OUT_T_C64 = 0, OUT_ROW_C64 = 1, OUT_ROW_RE = 2, OUT_ROW_IM = 3, OUT_T_RE = 4, OUT_T_IM = 5 };
 
 struct RowFftArgs {
   int64_t nrows;
   // inputs
-  const float2* in_c;      // IN_C64 / IN_C64_SUM: row r at in_c + r*n (+ p*part_stride)
+  const float2* in_c;      // IN_C64 / IN_C64_SUM: row r at in_c + r*n (+ p*part_stride);
+                           // IN_HALF_C64: entries 0..n/2 of a Hermitian row at in_c + r*(n/2+1)
   int64_t part_stride;
   int32_t nparts;
   float2* sum_out;         // IN_C64_SUM: if set, the summed input is also stored here (row-major)
@@ -42,11 +43,6 @@ struct RowFftArgs {
 };
 
 int launch_row_fft(int n, bool inverse, RowIn in, RowOut out, const RowFftArgs& a, hipStream_t stream);
-
-// DPC per-frequency gradient descent on the packed spectrum C = FFT2(gx + i gy), row-major
-// [my][mx]; writes Phi (row-major).
-int launch_dpc_update(const float2* C, float2* Phi, int ny, int nx, double step, const stem_dpc& p,
-                      hipStream_t stream);
 
 // ---- ssb.hip ---------------------------------------------------------------------------------
 size_t ssb_layout(const stem_det& det, const stem_scan& scan, const stem_optics& optics,
