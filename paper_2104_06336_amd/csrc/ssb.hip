@@ -106,9 +106,22 @@ static int launch_xstage_t(int prec, int nx, const DT* D, int ny, int ry0, int n
 // active-pixel mask: bit j of word (cs, w) is set when pixel 64 w + j has a non-empty set in some
 // column of column set cs (B = 1024/Ny consecutive half-spectrum columns).  One wave per mask
 // word: lane j takes pixel 64 w + j over the columns of the set, a ballot packs the 64 answers.
+// Workgroups past the mask's also tabulate chi(Kc) + theta per pixel and reset the counters of
+// the sum that follows (the work of k_chi_table), when kchi is given.
 __global__ void __launch_bounds__(256) k_colsets(const double2* __restrict__ kc, int n_k, int nx, int ny, Optics o,
                                                  int B, int ncs, int nmw, int4* __restrict__ cst,
-                                                 uint64_t* __restrict__ mask) {
+                                                 uint64_t* __restrict__ mask, int mask_blocks,
+                                                 const float* __restrict__ theta, double* __restrict__ kchi,
+                                                 unsigned long long* __restrict__ stats, int groups) {
+  if ((int)blockIdx.x >= mask_blocks) {
+    const int kd = (blockIdx.x - mask_blocks) * blockDim.x + threadIdx.x;
+    if (kd < 4) stats[kd] = kd == 1 ? (unsigned long long)groups : 0ull;
+    if (kd < n_k) {
+      const double2 k = kc[kd];
+      kchi[kd] = chi_poly(k.x, k.y, o) + (theta ? (double)theta[kd] : 0.0);
+    }
+    return;
+  }
   const int nc = nx / 2 + 1;
   const int64_t word = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (word >= (int64_t)ncs * nmw) return;  // uniform across the wave
@@ -131,13 +144,23 @@ __global__ void __launch_bounds__(256) k_colsets(const double2* __restrict__ kc,
   if ((threadIdx.x & 63) == 0) mask[word] = bits;
 }
 
+// chi(Kc) + theta and the counter reset, done by the interval-table kernel when kchi is given
+struct ChiArgs {
+  const float* theta;
+  double* kchi;
+  unsigned long long* stats;
+  int groups;
+};
+
 static void launch_colsets(const double2* kc, int n_k, int nx, int ny, const Optics& o, int4* cst, uint64_t* cmask,
-                           int nmw, hipStream_t s) {
+                           int nmw, hipStream_t s, const ChiArgs& chi = ChiArgs{}) {
   STEM_TRACE("ssb_colsets", s);
   const int B = 1024 / ny, ncs = (nx / 2 + 1 + B - 1) / B;
   const int64_t words = (int64_t)ncs * nmw;
-  hipLaunchKernelGGL(k_colsets, dim3((unsigned)((words + 3) / 4)), dim3(256), 0, s, kc, n_k, nx, ny, o, B, ncs, nmw,
-                     cst, cmask);
+  const int mask_blocks = (int)((words + 3) / 4);
+  const int chi_blocks = chi.kchi ? (n_k + 255) / 256 : 0;
+  hipLaunchKernelGGL(k_colsets, dim3((unsigned)(mask_blocks + chi_blocks)), dim3(256), 0, s, kc, n_k, nx, ny, o, B, ncs,
+                     nmw, cst, cmask, mask_blocks, chi.theta, chi.kchi, chi.stats, chi.groups);
 }
 
 // chi identically zero (every monomial coefficient 0) and no per-pixel theta: the phase factors of
@@ -150,8 +173,9 @@ static int chi_is_zero(const Optics& o, const float* theta) {
 // the interval table and the active-pixel mask, then the fused column sum
 static int launch_yreduce(int prec, int ny, float2* X, const double2* kc, const double* kchi, int4* cst,
                           uint64_t* cmask, int nmw, int n_k, int nx, int ngroups, const Optics& o, int store_g,
-                          int chi0, float2* part, unsigned long long* stats, hipStream_t s) {
-  launch_colsets(kc, n_k, nx, ny, o, cst, cmask, nmw, s);
+                          int chi0, float2* part, unsigned long long* stats, hipStream_t s,
+                          const ChiArgs& chi = ChiArgs{}) {
+  launch_colsets(kc, n_k, nx, ny, o, cst, cmask, nmw, s, chi);
   STEM_LAUNCH_CHECK();
   switch (prec) {
     case STEM_DFT_BF16_SPLIT:
@@ -169,8 +193,8 @@ static int launch_yreduce(int prec, int ny, float2* X, const double2* kc, const 
 // Eq. 3 from the stored G without normalisation (REFOCUS): the fused sum over the stored columns
 static int launch_ysum_stored(int ny, float2* G, const double2* kc, const double* kchi, int4* cst, uint64_t* cmask,
                               int nmw, int n_k, int nx, int ngroups, const Optics& o, int chi0, float2* part,
-                              unsigned long long* stats, hipStream_t s) {
-  launch_colsets(kc, n_k, nx, ny, o, cst, cmask, nmw, s);
+                              unsigned long long* stats, hipStream_t s, const ChiArgs& chi) {
+  launch_colsets(kc, n_k, nx, ny, o, cst, cmask, nmw, s, chi);
   STEM_LAUNCH_CHECK();
   const int B = 1024 / ny;
   const int ncs = (nx / 2 + 1 + B - 1) / B;
@@ -192,8 +216,8 @@ static int launch_ysum_stored(int ny, float2* G, const double2* kc, const double
 
 static int launch_yadjoint(int prec, int ny, const float2* X, const double2* kc, const double* kchi, int4* cst,
                            uint64_t* cmask, int nmw, int n_k, int nx, int ngroups, const Optics& o, int g_stored,
-                           const float2* Tbt, double* pdc, float* pdth, hipStream_t s) {
-  launch_colsets(kc, n_k, nx, ny, o, cst, cmask, nmw, s);
+                           const float2* Tbt, double* pdc, float* pdth, hipStream_t s, const ChiArgs& chi) {
+  launch_colsets(kc, n_k, nx, ny, o, cst, cmask, nmw, s, chi);
   STEM_LAUNCH_CHECK();
   switch (prec) {
     case STEM_DFT_BF16_SPLIT:
@@ -532,7 +556,9 @@ extern "C" int ssb_reconstruct(const int32_t* d_idx, const int64_t* d_off, int64
     if (st) return st;
     if (mode == STEM_SSB_ACCUMULATE) return STEM_OK;
   }
-  if ((st = run_chi_table(b, d_theta, n_k, o, ssb->normalize ? 1 : L.groups, s))) return st;
+  // without normalisation chi(Kc) + theta comes with the interval table of the fused sum
+  const ChiArgs chi{d_theta, b.kchi, b.stats, L.groups};
+  if (ssb->normalize && (st = run_chi_table(b, d_theta, n_k, o, 1, s))) return st;
   if (mode == STEM_SSB_REFOCUS) {
     // Eq. 3 again from the stored G: per-Q normalised sum, or the fused sum over stored columns
     if (ssb->normalize) {
@@ -540,7 +566,7 @@ extern "C" int ssb_reconstruct(const int32_t* d_idx, const int64_t* d_off, int64
       return run_phase(L, b, *scan, b.T, 1, d_phase, d_T, s);
     }
     if ((st = launch_ysum_stored(ny, b.X, b.kc, b.kchi, b.cst, b.cmask, L.nmw, n_k, nx, L.groups, o,
-                                 chi_is_zero(o, d_theta), b.part, b.stats, s)))
+                                 chi_is_zero(o, d_theta), b.part, b.stats, s, chi)))
       return st;
     return run_phase(L, b, *scan, b.part, L.groups, d_phase, d_T, s);
   }
@@ -568,7 +594,7 @@ extern "C" int ssb_reconstruct(const int32_t* d_idx, const int64_t* d_off, int64
     return run_phase(L, b, *scan, b.T, 1, d_phase, d_T, s);
   }
   if ((st = launch_yreduce(ssb->precision, ny, b.X, b.kc, b.kchi, b.cst, b.cmask, L.nmw, n_k, nx, L.groups, o,
-                           ssb->g_mode == STEM_G_STORE, chi_is_zero(o, d_theta), b.part, b.stats, s)))
+                           ssb->g_mode == STEM_G_STORE, chi_is_zero(o, d_theta), b.part, b.stats, s, chi)))
     return st;
   return run_phase(L, b, *scan, b.part, L.groups, d_phase, d_T, s);
 }
@@ -687,9 +713,9 @@ extern "C" int ssb_backward(const float* d_dLdphi, const stem_det* det, const st
   a.osc = make_float2(0.f, (float)(1.0 / (double)L.F));
   a.tag = "adj_fft";
   if ((st = launch_row_fft(ny, false, IN_C64, OUT_ROW_C64, a, s))) return st;
-  if ((st = run_chi_table(b, d_theta, n_k, o, L.groups, s))) return st;
-  if ((st = launch_yadjoint(ssb->precision, ny, b.X, b.kc, b.kchi, b.cst, b.cmask, L.nmw, n_k, nx, L.groups, o, ssb->g_mode == STEM_G_STORE,
-                            b.Tb, b.pdc, b.pdth, s)))
+  if ((st = launch_yadjoint(ssb->precision, ny, b.X, b.kc, b.kchi, b.cst, b.cmask, L.nmw, n_k, nx, L.groups, o,
+                            ssb->g_mode == STEM_G_STORE, b.Tb, b.pdc, b.pdth, s,
+                            ChiArgs{d_theta, b.kchi, b.stats, L.groups})))
     return st;
   {
     STEM_TRACE("ssb_adjoint_final", s);
