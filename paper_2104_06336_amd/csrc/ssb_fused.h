@@ -33,8 +33,9 @@ struct XfFft {
   static constexpr bool kUniformCol = NB >= kWave;
   static constexpr int slot_of(int i) { return kUniformCol ? (kWave * (i / RL)) / NB : i / RL; }
   static constexpr int kSlots = slot_of(15) + 1;
-  // x-stage workgroup: 8 waves, each with an LDS buffer for the FFT exchanges
-  static constexpr int kXWaves = 8;
+  // x-stage workgroup: 16 waves (one per CU), each with an LDS buffer for the FFT exchanges; the
+  // tile of 32 rows is written in 256-byte runs (measured 2-4 us faster than 8 waves, 128 bytes)
+  static constexpr int kXWaves = 16;
   static constexpr int kXStride = kXWaveStride;
   static __device__ __forceinline__ int pad(int i) { return fft_pad(i); }
   static __device__ __forceinline__ void in(int lane, int i, int& b, int& n) { fft_in_index<N>(lane, i, b, n); }
