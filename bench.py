@@ -201,8 +201,8 @@ def cpu_baseline(idx, off, wl):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="scan1024")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-split", action="store_true", help="skip the split-precision scan-DFT variants")
@@ -262,12 +262,13 @@ def main():
 
     side = torch.cuda.Stream(device=dev)  # default priority
 
-    def run(precision, steps, warmup, overlap=True, opt=optics):
+    def run(precision, steps, warmup, overlap=True, opt=optics, trace=False):
         """Times `steps` whole steps with the given scan-DFT precision; returns
         (elapsed s, kernel trace, SSB phase, SsbState).  With overlap, COM + DPC run on a second
         stream concurrently with the second half of the SSB reconstruction (FINALIZE after
         ACCUMULATE over all frames, the same work as ONESHOT; the two share only the read-only
-        events)."""
+        events).  With trace, a HIP event pair brackets every kernel (per-kernel times); the event
+        records add queue packets between kernels, so step times are taken without them."""
         st = stem.SsbState(det, scan, opt, stem.Ssb(precision, 0, stem.STEM_G_RECOMPUTE, 8), device=dev)
         main = torch.cuda.current_stream(dev)
 
@@ -292,19 +293,22 @@ def main():
         torch.cuda.synchronize()
         stem.check_status(status, "com_dpc")
         stem.check_status(st.status, "ssb_reconstruct")
-        stem.trace_enable(True)
+        stem.trace_enable(trace)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
             step()
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
-        recs = stem.trace_records()
+        recs = stem.trace_records() if trace else {}
         stem.trace_enable(False)
         return elapsed, recs, phase_ssb.clone(), st
 
-    # kernel times from a serial run (no overlap: each kernel's HIP-event time is its own)
-    el_serial, recs, phi32, st = run(stem.STEM_FFT_FP32, args.steps, args.warmup, overlap=False)
+    # kernel times from a traced serial run (no overlap: each kernel's HIP-event time is its own),
+    # step times from untraced runs
+    _, recs, phi32, st = run(stem.STEM_FFT_FP32, args.steps, args.warmup, overlap=False, trace=True)
+    del st
+    el_serial, _, _, st = run(stem.STEM_FFT_FP32, args.steps, args.warmup, overlap=False)
     del st
     elapsed, _, _, st = run(stem.STEM_FFT_FP32, args.steps, args.warmup)
     ms_per_step = elapsed / args.steps * 1e3
@@ -340,7 +344,7 @@ def main():
     variants = {}
     if not args.no_split:
         for label, prec in (("bf16_split", stem.STEM_DFT_BF16_SPLIT), ("fp16_split", stem.STEM_DFT_FP16_SPLIT)):
-            _, rv, phi, st = run(prec, args.steps, args.warmup, overlap=False)  # kernel times
+            _, rv, phi, st = run(prec, args.steps, args.warmup, overlap=False, trace=True)  # kernel times
             del st
             el, _, _, st = run(prec, args.steps, args.warmup)                # overlapped step
             del st
@@ -358,11 +362,27 @@ def main():
             log(f"{label}: {el / args.steps * 1e3:.3f} ms/step (SSB {sm:.3f} ms vs FP32 {ssb32:.3f} ms), "
                 f"phi vs FP32 path rel L2 {d:.2e}")
 
+    def timed(fn):
+        """(seconds for args.steps untraced calls of fn, kernel records of as many traced calls)"""
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        stem.trace_enable(True)
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        recs = stem.trace_records()
+        stem.trace_enable(False)
+        return el, recs
+
     # the same step with aberration correction (the general phase factors of Eq. 3 evaluated)
     extras = {}
     if not args.no_extras:
         opt_c = stem.Optics.from_values(wl.lam, wl.r_bf, wl.dk, C4_TRUE_ABERRATIONS)
-        _, ra, _, st = run(stem.STEM_FFT_FP32, args.steps, args.warmup, overlap=False, opt=opt_c)
+        _, ra, _, st = run(stem.STEM_FFT_FP32, args.steps, args.warmup, overlap=False, opt=opt_c, trace=True)
         del st
         el_c, _, _, st = run(stem.STEM_FFT_FP32, args.steps, args.warmup, opt=opt_c)
         del st
@@ -380,15 +400,7 @@ def main():
         c_new = tuple(0.5 * v for v in C4_TRUE_ABERRATIONS)
         for _ in range(args.warmup):
             st.refocus(c=c_new, phase=phase_ssb)
-        torch.cuda.synchronize()
-        stem.trace_enable(True)
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            st.refocus(c=c_new, phase=phase_ssb)
-        torch.cuda.synchronize()
-        el_r = time.perf_counter() - t0
-        rr = stem.trace_records()
-        stem.trace_enable(False)
+        el_r, rr = timed(lambda: st.refocus(c=c_new, phase=phase_ssb))
         # the panel of G at nine scan frequencies (Fig. 2), read from the stored G
         qs9 = [(my, mx) for my in (1, 2, 3) for mx in (1, 2, 3)]
         st.g_panel(qs9)
@@ -428,14 +440,7 @@ def main():
         for _ in range(args.warmup):
             fb()
         torch.cuda.synchronize()
-        stem.trace_enable(True)
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            fb()
-        torch.cuda.synchronize()
-        el_a = time.perf_counter() - t0
-        ra = stem.trace_records()
-        stem.trace_enable(False)
+        el_a, ra = timed(fb)
         del st, d4
         extras["adjoint"] = {"workload": f"aberrated512: {wl4.name}", "n_k": int(stem.ssb_num_pixels(det4, opt4)),
                              "forward_plus_backward_ms": round(el_a / args.steps * 1e3, 4),
@@ -456,14 +461,7 @@ def main():
         for _ in range(args.warmup):
             detectors()
         torch.cuda.synchronize()
-        stem.trace_enable(True)
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            detectors()
-        torch.cuda.synchronize()
-        el_v = time.perf_counter() - t0
-        rv = stem.trace_records()
-        stem.trace_enable(False)
+        el_v, rv = timed(detectors)
         stem.check_status(status, "virtual detectors")
         kv = {k: round(ms / n * 1e3, 2) for k, (n, ms) in rv.items()}
         extras["virtual_detectors"] = {
@@ -563,6 +561,25 @@ def main():
             f"({host_bytes / (res['copy_only'] * 1e-3) / 1e9:.1f} GB/s)")
         del st, h_idx, h_off, s_idx, s_off
 
+    # what plain streaming kernels reach on this HBM (torch's copy and fill of 1 GiB), for context
+    # beside the roofline fraction: the x-stage's traffic is 80% writes
+    hbm_ref = {}
+    a = torch.empty((1 << 30) // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    for label, fn, nbytes in (("copy", lambda: b.copy_(a), 2 << 30), ("fill", lambda: b.fill_(2.0), 1 << 30)):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        hbm_ref[f"{label}_gbs"] = round(nbytes * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+    del a, b
+    hbm_ref["dominant_frac_of_copy"] = (round(roofline["achieved"] / hbm_ref["copy_gbs"], 3)
+                                        if roofline["achieved"] else None)
+    log(f"HBM reference: copy {hbm_ref['copy_gbs']} GB/s, fill {hbm_ref['fill_gbs']} GB/s")
+
     cpu = None
     if not args.no_cpu_baseline:
         idx_np = d_idx.cpu().numpy()
@@ -598,6 +615,7 @@ def main():
         "precision_variants": variants,
         **extras,
         "roofline": roofline,
+        "hbm_reference": hbm_ref,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
