@@ -41,6 +41,7 @@ def algorithmic_bytes(name, g):
     table = {
         "com_moments": 4 * C + 8 * (F + 1) + 16 * F,           # events, offsets, COM (FP64, 2 planes)
         "bin_densify": 4 * C + 8 * (F + 1) + nk * F * g["d_bytes"],
+        "bin_com": 4 * C + 8 * (F + 1) + nk * F * g["d_bytes"] + 16 * F,  # binning + COM (FP64) out
         "xstage_fft": nk * F * g["d_bytes"] + X,               # D in, X out
         "ystage_fft": 2 * X,                                    # X in, G out (in place)
         "ssb_yreduce": X + 8 * F * g["groups"],                # X in, partial T per pixel group out
@@ -81,7 +82,8 @@ def load_traffic(kernel, workload):
 # rocprofv3 kernel names of the kernels bench.py reports, by their trace name
 PROFILED = {
     "stem::k_com": "com_moments",
-    "stem::k_bin<unsigned char, true>": "bin_densify",
+    "stem::k_bin<unsigned char, true, false>": "bin_densify",
+    "stem::k_bin<unsigned char, true, true>": "bin_com",
     "stem::k_xstage<stem::XfFft<1024>, unsigned char>": "xstage_fft",
     "stem::k_yreduce<stem::XfFft<1024>, true>": "ssb_yreduce",
     "stem::k_dpc_cols<1024, 4>": "dpc_cols",
@@ -207,6 +209,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-split", action="store_true", help="skip the split-precision scan-DFT variants")
     ap.add_argument("--no-extras", action="store_true", help="skip the refocus and adjoint timings")
+    ap.add_argument("--fused-com", action="store_true",
+                    help="centre of mass formed by the binning pass (ssb_reconstruct_com) instead of its own "
+                         "pass over the events on the second stream")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run a device copy of this many MiB first (counter calibration)")
     ap.add_argument("--summarize-profile", metavar="DIR",
@@ -272,17 +277,28 @@ def main():
         st = stem.SsbState(det, scan, opt, stem.Ssb(precision, 0, stem.STEM_G_RECOMPUTE, 8), device=dev)
         main = torch.cuda.current_stream(dev)
 
+        # com_dpc reads the events itself on the second stream (beside FINALIZE); with --fused-com
+        # the binning pass forms the centre of mass (one read of the events, on the critical path)
+        # and com_dpc only integrates (n_frames = 0)
+        fused = args.fused_com
+        com_kw = {"com64": com64} if fused else {}
+        n_com = 0 if fused else F
+
         def step():
             if overlap:
-                # binning + row transform first; COM + DPC (HBM- and latency-bound) then run beside the
-                # VALU-bound column transform + Eq. 3 and the phase passes
-                st.accumulate(d_idx, d_off, 0, F)
+                # binning (+ COM) and the row transform first; DPC (latency-bound) then runs beside
+                # the VALU-bound column transform + Eq. 3 and the phase passes
+                st.accumulate(d_idx, d_off, 0, F, **com_kw)
                 side.wait_stream(main)
                 with torch.cuda.stream(side):
-                    stem.com_dpc(d_idx, d_off, 0, F, det, scan, optics, dpc, com64=com64, phase=phase_dpc, ws=ws,
-                                 d_status=status)
+                    stem.com_dpc(d_idx, d_off, 0, n_com, det, scan, optics, dpc, com64=com64, phase=phase_dpc,
+                                 ws=ws, d_status=status)
                 st.finalize(phase=phase_ssb)
                 main.wait_stream(side)
+            elif fused:
+                st.oneshot(d_idx, d_off, phase=phase_ssb, **com_kw)
+                stem.com_dpc(d_idx, d_off, 0, 0, det, scan, optics, dpc, com64=com64, phase=phase_dpc, ws=ws,
+                             d_status=status)
             else:
                 stem.com_dpc(d_idx, d_off, 0, F, det, scan, optics, dpc, com64=com64, phase=phase_dpc, ws=ws,
                              d_status=status)
@@ -609,6 +625,8 @@ def main():
                    "double_overlap_pairs": P, "ssb_path": "FP32 FFT, fused column transform + sum (G recomputed); no aberrations, so the "
                                    "phase factors of Eq. 3 are exactly 1 (the aberration-corrected step is "
                                    "reported beside it)",
+                   "com": ("formed by the binning pass (ssb_reconstruct_com); com_dpc integrates only"
+                           if args.fused_com else "own pass over the events (com_dpc) on the second stream"),
                    "parallelism": "single GPU"},
         "kernels": kernels,
         "ssb_ms_fp32": round(ssb32, 4),

@@ -250,6 +250,20 @@ int ssb_reconstruct(const int32_t* d_idx, const int64_t* d_off, int64_t frame0, 
                     size_t state_bytes, float* d_phase, float* d_T, int32_t* d_status,
                     void* stream);
 
+/* a1 + a2 + a4 in one pass over the events (Eq. 4 beside the binning of Sec. IV):
+ * ssb_reconstruct in mode ACCUMULATE or ONESHOT that also writes the centre of mass of frames
+ * [frame0, frame0 + n_frames) (all F frames for ONESHOT) exactly as com_dpc does: d_com64 /
+ * d_com32 [2][F] planes (x then y, global frame number) and d_counts[F], each may be NULL but
+ * not all three; the values are bit-identical to com_dpc's.  The DPC integration can then run
+ * from d_com64 (or d_com32) by com_dpc with n_frames = 0.  Same ownership, stream order and
+ * error rules as ssb_reconstruct; also STEM_EINVAL for another mode, no COM output, or a
+ * detector of 65536 or more pixels in either dimension. */
+int ssb_reconstruct_com(const int32_t* d_idx, const int64_t* d_off, int64_t frame0, int64_t n_frames,
+                        const stem_det* det, const stem_scan* scan, const stem_optics* optics,
+                        const stem_ssb* ssb, int mode, const float* d_theta, void* state,
+                        size_t state_bytes, float* d_phase, float* d_T, double* d_com64,
+                        float* d_com32, int32_t* d_counts, int32_t* d_status, void* stream);
+
 /* Regions of the state buffer a caller may read after the calls that fill them.
  *  STEM_REGION_D  binned counts D[kd][ry][rx], uint8 or uint16 (d_bits), after ACCUMULATE.
  *  STEM_REGION_G  complex64 [kd][mx][my], mx in [0, Nx/2], my in [0, Ny): after ACCUMULATE

@@ -26,7 +26,7 @@ __all__ = [
     "STEM_G_STORE", "STEM_SSB_ACCUMULATE", "STEM_SSB_FINALIZE", "STEM_SSB_REFOCUS",
     "STEM_SSB_ONESHOT", "SsbState", "SSBPhase", "ssb_state_region", "STEM_REGION_D", "STEM_REGION_G",
     "STEM_REGION_T", "STEM_REGION_KC", "STEM_REGION_STATS", "trace_enable", "trace_records",
-    "virtual_annular", "sum_frames", "eer_decode_rle", "ssb_g_panel",
+    "virtual_annular", "sum_frames", "eer_decode_rle", "ssb_g_panel", "ssb_reconstruct_com",
 ]
 
 
@@ -213,6 +213,28 @@ def ssb_reconstruct(d_idx, d_off, frame0: int, n_frames: int, det: Det, scan: Sc
     _check(rc, "ssb_reconstruct")
 
 
+def ssb_reconstruct_com(d_idx, d_off, frame0: int, n_frames: int, det: Det, scan: Scan, optics: Optics,
+                        ssb: Ssb, mode: int, state, com64=None, com32=None, counts=None, theta=None, phase=None,
+                        T=None, d_status=None, stream=None):
+    """ACCUMULATE or ONESHOT that also writes the frames' centre of mass (as com_dpc) from the
+    same pass over the events."""
+    F = scan.ny * scan.nx
+    _dev(d_idx, torch.int32, "d_idx")
+    _dev(d_off, torch.int64, "d_off")
+    _dev(state, torch.uint8, "state")
+    _dev(theta, torch.float32, "theta")
+    _dev(phase, torch.float32, "phase", F)
+    _dev(T, torch.complex64, "T", F)
+    _dev(com64, torch.float64, "com64", 2 * F)
+    _dev(com32, torch.float32, "com32", 2 * F)
+    _dev(counts, torch.int32, "counts", F)
+    rc = lib().ssb_reconstruct_com(_p(d_idx), _p(d_off), frame0, n_frames, ctypes.byref(det), ctypes.byref(scan),
+                                   ctypes.byref(optics), ctypes.byref(ssb), mode, _p(theta), _p(state),
+                                   state.numel(), _p(phase), _p(T), _p(com64), _p(com32), _p(counts),
+                                   _p(d_status), _stream(stream))
+    _check(rc, "ssb_reconstruct_com")
+
+
 def ssb_backward(dLdphi, det: Det, scan: Scan, optics: Optics, ssb: Ssb, state, dLdc, theta=None,
                  dLdtheta=None, d_status=None, stream=None):
     """Adjoint of the sideband phase: fills dLdc (float64 [8]) and dLdtheta (float32 [n_K])."""
@@ -277,9 +299,17 @@ class SsbState:
         o = Optics.from_values(self.optics.lam, self.optics.r_bf, self.optics.dk, c)
         return o
 
-    def accumulate(self, d_idx, d_off, frame0: int, n_frames: int, stream=None):
-        ssb_reconstruct(d_idx, d_off, frame0, n_frames, self.det, self.scan, self.optics, self.ssb,
-                        STEM_SSB_ACCUMULATE, self.state, d_status=self.status, stream=stream)
+    def accumulate(self, d_idx, d_off, frame0: int, n_frames: int, com64=None, com32=None, counts=None,
+                   stream=None):
+        """Bin and row-transform whole scan rows; with a centre-of-mass output, the same pass over
+        the events also writes the frames' centre of mass (as com_dpc)."""
+        if com64 is None and com32 is None and counts is None:
+            ssb_reconstruct(d_idx, d_off, frame0, n_frames, self.det, self.scan, self.optics, self.ssb,
+                            STEM_SSB_ACCUMULATE, self.state, d_status=self.status, stream=stream)
+        else:
+            ssb_reconstruct_com(d_idx, d_off, frame0, n_frames, self.det, self.scan, self.optics, self.ssb,
+                                STEM_SSB_ACCUMULATE, self.state, com64=com64, com32=com32, counts=counts,
+                                d_status=self.status, stream=stream)
 
     def finalize(self, c=None, theta=None, phase=None, T=None, stream=None):
         o = self.optics if c is None else self.optics_with(c)
@@ -291,10 +321,16 @@ class SsbState:
         ssb_reconstruct(None, None, 0, 0, self.det, self.scan, o, self.ssb, STEM_SSB_REFOCUS, self.state,
                         theta=theta, phase=phase, T=T, d_status=self.status, stream=stream)
 
-    def oneshot(self, d_idx, d_off, c=None, theta=None, phase=None, T=None, stream=None):
+    def oneshot(self, d_idx, d_off, c=None, theta=None, phase=None, T=None, com64=None, com32=None, counts=None,
+                stream=None):
         o = self.optics if c is None else self.optics_with(c)
-        ssb_reconstruct(d_idx, d_off, 0, self.F, self.det, self.scan, o, self.ssb, STEM_SSB_ONESHOT,
-                        self.state, theta=theta, phase=phase, T=T, d_status=self.status, stream=stream)
+        if com64 is None and com32 is None and counts is None:
+            ssb_reconstruct(d_idx, d_off, 0, self.F, self.det, self.scan, o, self.ssb, STEM_SSB_ONESHOT,
+                            self.state, theta=theta, phase=phase, T=T, d_status=self.status, stream=stream)
+        else:
+            ssb_reconstruct_com(d_idx, d_off, 0, self.F, self.det, self.scan, o, self.ssb, STEM_SSB_ONESHOT,
+                                self.state, com64=com64, com32=com32, counts=counts, theta=theta, phase=phase,
+                                T=T, d_status=self.status, stream=stream)
 
     def g_panel(self, qs, stream=None) -> torch.Tensor:
         """G at the scan frequencies qs = [(my, mx), ...] as binned detector images

@@ -73,6 +73,11 @@ _SIGS = {
                                        ctypes.POINTER(Ssb), ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_void_p]),
+    "ssb_reconstruct_com": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                           ctypes.POINTER(Det), ctypes.POINTER(Scan), ctypes.POINTER(Optics),
+                                           ctypes.POINTER(Ssb), ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "ssb_state_region": (ctypes.c_int, [ctypes.POINTER(Det), ctypes.POINTER(Scan), ctypes.POINTER(Optics),
                                         ctypes.POINTER(Ssb), ctypes.c_int, ctypes.POINTER(ctypes.c_size_t),
                                         ctypes.POINTER(ctypes.c_size_t)]),

@@ -8,6 +8,7 @@
 // CSR slice, read with coalesced 16-byte loads: staged in LDS for the per-frame sums of k_com,
 // streamed with an LDS map event -> frame for the counts of k_bin.
 #include <cmath>
+#include <type_traits>
 
 #include "common.h"
 #include "geom.h"
@@ -494,19 +495,42 @@ struct BinBox {
   int32_t bx0, by0, bw, bh;
 };
 
-template <typename DT, bool BOX>
+// One step of a segmented inclusive scan within rows of 16 lanes: lane i adds the sums of lane
+// i - d of its row when both hold the same key (sorted keys: equal keys are contiguous).  Lanes
+// whose source lies before the row start get the sentinel key -1 and add nothing.
+template <int CTRL>
+__device__ __forceinline__ void seg_step(int key, int32_t& ax, int32_t& ay) {
+  const int k2 = __builtin_amdgcn_update_dpp(-1, key, CTRL, 0xf, 0xf, false);
+  const int x2 = __builtin_amdgcn_update_dpp(0, ax, CTRL, 0xf, 0xf, false);
+  const int y2 = __builtin_amdgcn_update_dpp(0, ay, CTRL, 0xf, 0xf, false);
+  if (k2 == key) {
+    ax += x2;
+    ay += y2;
+  }
+}
+
+// With COM, the workgroups of the first pixel chunk also form each frame's exact integer first
+// moments from the same event loads (Eq. 4): a lane folds its four events into runs of equal
+// frame, a segmented scan over each row of 16 lanes (events are in frame order) merges the runs
+// that cross lanes, and one LDS atomic per run end adds them to the frame's window sums (int32: a window
+// holds at most kBinWin events, each |kx - cx| < 2^16), which thread f folds into its frame's
+// int64 sums at the next window barrier.  The centre of mass is then S / N_f by one double
+// division, as the centre-of-mass kernel computes it.
+template <typename DT, bool BOX, bool COM>
 __global__ void __launch_bounds__(kBinThreads) k_bin(const int32_t* __restrict__ idx,
                                                      const int64_t* __restrict__ off, int64_t frame0,
                                                      int64_t n_frames, int32_t npix,
                                                      const int16_t* __restrict__ lut,
                                                      const RowRun* __restrict__ rows, BinBox box, int32_t n_k,
-                                                     int64_t F, DT* __restrict__ D, int32_t* status) {
+                                                     int64_t F, DT* __restrict__ D, ComOut com, int32_t* status) {
   extern __shared__ int16_t s_box[];  // [bh][bw] kept-bin index of each bin of the box, or -1
   __shared__ __align__(16) uint32_t s_hist[kBinWords];
   __shared__ uint32_t s_map[(kBinWin + 16) / 4];
   __shared__ int32_t s_rel[kBinFrames + 1];
   __shared__ int64_t s_base;
+  __shared__ int32_t s_mom[COM ? 2 * kBinFrames : 1];  // [x | y][frame] moment sums of a window
   const int t = threadIdx.x;
+  const int lane = t & 63;
   const int nchunks = (n_k + kBinKd - 1) / kBinKd;
   const int kd0 = (int)(blockIdx.x % nchunks) * kBinKd;
   const int kc = n_k - kd0 < kBinKd ? n_k - kd0 : kBinKd;
@@ -514,6 +538,21 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(const int32_t* __restrict__
   const int64_t fend = frame0 + n_frames;
   const int nf = (int)((fend - fb) < kBinFrames ? (fend - fb) : kBinFrames);
   if (!load_rel_offsets(off, fb, nf, s_rel, &s_base, status)) return;
+  const bool com_blk = COM && kd0 == 0;  // workgroup-uniform
+  if constexpr (COM) {
+    if (com_blk)
+      for (int i = t; i < 2 * kBinFrames; i += kBinThreads) s_mom[i] = 0;
+  }
+  int64_t msx = 0, msy = 0;  // thread t: the moments of frame t so far
+  // after a barrier that follows a window's atomics and precedes the next window's
+  auto fold_moments = [&]() {
+    if (COM && com_blk && t < kBinFrames) {
+      msx += s_mom[t];
+      msy += s_mom[kBinFrames + t];
+      s_mom[t] = 0;
+      s_mom[kBinFrames + t] = 0;
+    }
+  };
   if constexpr (BOX) {
     // kept index of each bin of the box from the row runs (the rule of the per-pixel table)
     for (int i = t; i < box.bw * box.bh; i += kBinThreads) {
@@ -545,6 +584,7 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(const int32_t* __restrict__
       const int64_t a0 = base + w0;
       const int sh = (int)((((uintptr_t)(idx + a0)) & 15) >> 2);  // map[sh + j] <-> event a0 + j
       __syncthreads();
+      fold_moments();
       {
         // frame t's events of this window: map entries [lo, hi)
         const int lo = (lo_t > w0 ? lo_t : w0) - w0 + sh;
@@ -598,6 +638,54 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(const int32_t* __restrict__
             }
             kd[u][q] = ok && in && v >= 0 ? v - ka : -1;
           }
+        if constexpr (COM) {
+          if (com_blk && pass == 0) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+              // runs of equal frame among the lane's events in this window; all but the last go
+              // to LDS at once (a lane crosses a frame boundary only at frames of few events)
+              int fc = -1;
+              int32_t ax = 0, ay = 0;
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                const int p = 4 * (g0 + u * kBinThreads) + q;
+                if ((uint32_t)(p - sh) >= (uint32_t)wn) continue;
+                const int k = q == 0 ? kv[u].x : q == 1 ? kv[u].y : q == 2 ? kv[u].z : kv[u].w;
+                const int f = (int)((fr4[u] >> (8 * q)) & 0xffu);
+                if (f != fc) {
+                  if (fc >= 0) {
+                    atomicAdd(&s_mom[fc], ax);
+                    atomicAdd(&s_mom[kBinFrames + fc], ay);
+                  }
+                  fc = f;
+                  ax = ay = 0;
+                }
+                // an index outside the detector adds nothing (it is reported by the binning)
+                if ((uint32_t)k < (uint32_t)npix) {
+                  const uint32_t ky = magic_div((uint32_t)k, box.mw), kx = (uint32_t)k - ky * (uint32_t)box.W;
+                  ax += (int32_t)kx - com.cx;
+                  ay += (int32_t)ky - com.cy;
+                }
+              }
+              // the lanes' last runs: inclusive scan within each row of 16 lanes, segmented by
+              // frame, by DPP row shifts (register moves, no LDS traffic); lower lanes hold
+              // earlier events, and the lanes of this loop trip are a prefix of the wave
+              const int key = fc >= 0 ? fc : 256 + lane;  // a lane without events merges with none
+              seg_step<0x111>(key, ax, ay);               // row_shr:1
+              seg_step<0x112>(key, ax, ay);               // row_shr:2
+              seg_step<0x114>(key, ax, ay);               // row_shr:4
+              seg_step<0x118>(key, ax, ay);               // row_shr:8
+              // a run ends where the next lane's frame differs, at a row's last lane (row_shl:1
+              // leaves the sentinel there) and before a lane outside this loop trip
+              const int nkey = __builtin_amdgcn_update_dpp(-2, key, 0x101, 0xf, 0xf, false);
+              const bool last = g0 + 1 >= ng || nkey != key;
+              if (fc >= 0 && last) {
+                atomicAdd(&s_mom[fc], ax);
+                atomicAdd(&s_mom[kBinFrames + fc], ay);
+              }
+            }
+          }
+        }
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -655,12 +743,31 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(const int32_t* __restrict__
     }
     __syncthreads();
   }
+  if constexpr (COM) {
+    fold_moments();  // the pass loop ends with a barrier: the last window's sums
+    if (com_blk && t < nf) {
+      const int64_t fr = fb + t;
+      const int64_t n = hi_t - lo_t;
+      const int64_t sx = msx, sy = msy;
+      const double x = n > 0 ? (double)sx / (double)n : 0.0;
+      const double y = n > 0 ? (double)sy / (double)n : 0.0;
+      if (com.com64) {
+        com.com64[fr] = x;
+        com.com64[com.nplane + fr] = y;
+      }
+      if (com.com32) {
+        com.com32[fr] = (float)x;
+        com.com32[com.nplane + fr] = (float)y;
+      }
+      if (com.counts) com.counts[fr] = (int32_t)n;
+    }
+  }
   if (bad) report(status, bad);
 }
 
 int launch_bin(const int32_t* idx, const int64_t* off, int64_t frame0, int64_t n_frames,
                const stem_det& det, double r2, const RowRun* rows, int16_t* lut, int n_k, int64_t F, void* D,
-               int d_bits, int32_t* status, hipStream_t stream) {
+               int d_bits, int32_t* status, hipStream_t stream, const ComOut* com) {
   if (n_frames == 0) return STEM_OK;
   const int nchunks = (n_k + kBinKd - 1) / kBinKd;
   const int64_t fblocks = (n_frames + kBinFrames - 1) / kBinFrames;
@@ -698,21 +805,23 @@ int launch_bin(const int32_t* idx, const int64_t* off, int64_t frame0, int64_t n
                        det.bin, lut);
     STEM_LAUNCH_CHECK();
   }
-  STEM_TRACE("bin_densify", stream);
+  STEM_TRACE(com ? "bin_com" : "bin_densify", stream);
+  const ComOut co = com ? *com : ComOut{};
+  const int npix = det.W * det.H;
+  auto go = [&](auto dt, auto bx, auto cm) {
+    using DT = decltype(dt);
+    constexpr bool BX = decltype(bx)::value, CM = decltype(cm)::value;
+    hipLaunchKernelGGL((k_bin<DT, BX, CM>), grid, dim3(kBinThreads), BX ? lds : 0, stream, idx, off, frame0,
+                       n_frames, npix, lut, rows, box, n_k, F, (DT*)D, co, status);
+  };
+  using T_ = std::true_type;
+  using F_ = std::false_type;
   if (d_bits == 8) {
-    if (use_box)
-      hipLaunchKernelGGL((k_bin<uint8_t, true>), grid, dim3(kBinThreads), lds, stream, idx, off, frame0, n_frames,
-                         det.W * det.H, lut, rows, box, n_k, F, (uint8_t*)D, status);
-    else
-      hipLaunchKernelGGL((k_bin<uint8_t, false>), grid, dim3(kBinThreads), 0, stream, idx, off, frame0, n_frames,
-                         det.W * det.H, lut, rows, box, n_k, F, (uint8_t*)D, status);
+    if (use_box) com ? go(uint8_t{}, T_{}, T_{}) : go(uint8_t{}, T_{}, F_{});
+    else com ? go(uint8_t{}, F_{}, T_{}) : go(uint8_t{}, F_{}, F_{});
   } else {
-    if (use_box)
-      hipLaunchKernelGGL((k_bin<uint16_t, true>), grid, dim3(kBinThreads), lds, stream, idx, off, frame0,
-                         n_frames, det.W * det.H, lut, rows, box, n_k, F, (uint16_t*)D, status);
-    else
-      hipLaunchKernelGGL((k_bin<uint16_t, false>), grid, dim3(kBinThreads), 0, stream, idx, off, frame0,
-                         n_frames, det.W * det.H, lut, rows, box, n_k, F, (uint16_t*)D, status);
+    if (use_box) com ? go(uint16_t{}, T_{}, T_{}) : go(uint16_t{}, T_{}, F_{});
+    else com ? go(uint16_t{}, F_{}, T_{}) : go(uint16_t{}, F_{}, F_{});
   }
   STEM_LAUNCH_CHECK();
   return STEM_OK;

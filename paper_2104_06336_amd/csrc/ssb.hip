@@ -517,11 +517,10 @@ extern "C" int ssb_state_region(const stem_det* det, const stem_scan* scan, cons
   return STEM_OK;
 }
 
-extern "C" int ssb_reconstruct(const int32_t* d_idx, const int64_t* d_off, int64_t frame0, int64_t n_frames,
-                               const stem_det* det, const stem_scan* scan, const stem_optics* optics,
-                               const stem_ssb* ssb, int mode, const float* d_theta, void* state,
-                               size_t state_bytes, float* d_phase, float* d_T, int32_t* d_status,
-                               void* stream_) {
+static int reconstruct(const int32_t* d_idx, const int64_t* d_off, int64_t frame0, int64_t n_frames,
+                       const stem_det* det, const stem_scan* scan, const stem_optics* optics, const stem_ssb* ssb,
+                       int mode, const float* d_theta, void* state, size_t state_bytes, float* d_phase, float* d_T,
+                       const ComOut* com, int32_t* d_status, void* stream_) {
   int n_k;
   int st = check_common(det, scan, optics, ssb, &n_k);
   if (st) return st;
@@ -545,7 +544,7 @@ extern "C" int ssb_reconstruct(const int32_t* d_idx, const int64_t* d_off, int64
       return STEM_EINVAL;
     if ((st = launch_geometry(*det, o.r2, b.rows, b.kc, s))) return st;
     if ((st = launch_bin(d_idx, d_off, frame0, n_frames, *det, o.r2, b.rows, b.lut, n_k, L.F, b.D, ssb->d_bits,
-                          d_status, s)))
+                          d_status, s, com)))
       return st;
     const int ry0 = (int)(frame0 / nx), nr = (int)(n_frames / nx);
     const int64_t nrows = (int64_t)n_k * nr;
@@ -597,6 +596,29 @@ extern "C" int ssb_reconstruct(const int32_t* d_idx, const int64_t* d_off, int64
                            ssb->g_mode == STEM_G_STORE, chi_is_zero(o, d_theta), b.part, b.stats, s, chi)))
     return st;
   return run_phase(L, b, *scan, b.part, L.groups, d_phase, d_T, s);
+}
+
+extern "C" int ssb_reconstruct(const int32_t* d_idx, const int64_t* d_off, int64_t frame0, int64_t n_frames,
+                               const stem_det* det, const stem_scan* scan, const stem_optics* optics,
+                               const stem_ssb* ssb, int mode, const float* d_theta, void* state,
+                               size_t state_bytes, float* d_phase, float* d_T, int32_t* d_status,
+                               void* stream_) {
+  return reconstruct(d_idx, d_off, frame0, n_frames, det, scan, optics, ssb, mode, d_theta, state, state_bytes,
+                     d_phase, d_T, nullptr, d_status, stream_);
+}
+
+extern "C" int ssb_reconstruct_com(const int32_t* d_idx, const int64_t* d_off, int64_t frame0, int64_t n_frames,
+                                   const stem_det* det, const stem_scan* scan, const stem_optics* optics,
+                                   const stem_ssb* ssb, int mode, const float* d_theta, void* state,
+                                   size_t state_bytes, float* d_phase, float* d_T, double* d_com64,
+                                   float* d_com32, int32_t* d_counts, int32_t* d_status, void* stream_) {
+  if (mode != STEM_SSB_ACCUMULATE && mode != STEM_SSB_ONESHOT) return STEM_EINVAL;
+  if (!d_com64 && !d_com32 && !d_counts) return STEM_EINVAL;
+  if (!det || det->W >= 65536 || det->H >= 65536) return STEM_EINVAL;
+  if (!scan) return STEM_EINVAL;
+  const ComOut com{d_com64, d_com32, d_counts, (int64_t)scan->ny * scan->nx, det->cx, det->cy};
+  return reconstruct(d_idx, d_off, frame0, n_frames, det, scan, optics, ssb, mode, d_theta, state, state_bytes,
+                     d_phase, d_T, &com, d_status, stream_);
 }
 
 // ---------------------------------------------------------------------------------------------

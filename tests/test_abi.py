@@ -121,6 +121,15 @@ def test_host_argument_errors_return_einval_without_device_work():
     big_r = stem.ssb_state_bytes(det, scan, optics, rec)
     assert L.ssb_reconstruct(None, None, 0, 0, ctypes.byref(det), ctypes.byref(scan), ctypes.byref(optics),
                              ctypes.byref(rec), 2, None, fake, big_r, None, None, None, None) == 64
+    # the fused centre of mass: only ACCUMULATE / ONESHOT, at least one output, detectors < 65536
+    com = lambda mode, c64=fake, d=det: L.ssb_reconstruct_com(fake, fake, 0, 1024, ctypes.byref(d),
+                                                              ctypes.byref(scan), ctypes.byref(optics),
+                                                              ctypes.byref(ssb), mode, None, fake, big, None, None,
+                                                              c64, None, None, None, None)
+    assert com(1) == 1 and com(2) == 1 and com(7) == 1
+    assert com(0, c64=None) == 1
+    assert com(0, d=stem.Det(65536, 16, 32768, 8, 1)) == 1
+    assert com(0, d=bad_det) == 1
     # the adjoint rejects the normalised sum
     norm = stem.Ssb(stem.STEM_FFT_FP32, 1, stem.STEM_G_STORE, 8)
     assert L.ssb_backward(fake, ctypes.byref(det), ctypes.byref(scan), ctypes.byref(optics), ctypes.byref(norm),
