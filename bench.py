@@ -209,6 +209,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-split", action="store_true", help="skip the split-precision scan-DFT variants")
     ap.add_argument("--no-extras", action="store_true", help="skip the refocus and adjoint timings")
+    ap.add_argument("--com-beside", choices=("finalize", "binning"), default="finalize",
+                    help="where COM runs on the second stream: beside FINALIZE (with DPC), or from the start "
+                         "of the step beside the binning (DPC still beside FINALIZE)")
     ap.add_argument("--fused-com", action="store_true",
                     help="centre of mass formed by the binning pass (ssb_reconstruct_com) instead of its own "
                          "pass over the events on the second stream")
@@ -284,8 +287,23 @@ def main():
         com_kw = {"com64": com64} if fused else {}
         n_com = 0 if fused else F
 
+        early_com = args.com_beside == "binning" and not fused
+
         def step():
-            if overlap:
+            if overlap and early_com:
+                # COM reads the events beside the binning (which reads them too); DPC waits for it and
+                # for the row transform, then runs beside FINALIZE
+                side.wait_stream(main)
+                with torch.cuda.stream(side):
+                    stem.com_dpc(d_idx, d_off, 0, F, det, scan, com64=com64, d_status=status)
+                st.accumulate(d_idx, d_off, 0, F)
+                side.wait_stream(main)
+                with torch.cuda.stream(side):
+                    stem.com_dpc(d_idx, d_off, 0, 0, det, scan, optics, dpc, com64=com64, phase=phase_dpc,
+                                 ws=ws, d_status=status)
+                st.finalize(phase=phase_ssb)
+                main.wait_stream(side)
+            elif overlap:
                 # binning (+ COM) and the row transform first; DPC (latency-bound) then runs beside
                 # the VALU-bound column transform + Eq. 3 and the phase passes
                 st.accumulate(d_idx, d_off, 0, F, **com_kw)
