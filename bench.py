@@ -224,7 +224,7 @@ def main():
         summarize_profile(args.summarize_profile, args.workload)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: the path has no multi-GPU mode in this build "
+        print("bench.py measures one GPU: the library has no multi-GPU mode "
               "(see the sharding notes in the design document); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
