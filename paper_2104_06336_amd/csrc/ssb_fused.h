@@ -399,6 +399,41 @@ __global__ void __launch_bounds__(kYThreads, 2) k_yreduce(float2* __restrict__ X
         accm[i].x = fmaf(v[i].x, wm, accm[i].x);
         accm[i].y = fmaf(-v[i].y, wm, accm[i].y);
       }
+    } else if constexpr (CHI0 && XF::kMfma && NY >= 64) {
+      // Matrix-core layout: the lane's 16 frequencies are m = 32 (c mod N/32) + q, c = lane mod 32,
+      // with q = 8 (i/4) + 4 h + i mod 4, h = lane / 32: one aligned block of 32 that never
+      // straddles N/2, so in signed order iy = base + q and each interval of a double-overlap set
+      // is a run of q, formed once per pixel as a bit mask (as in the uniform-column sum above).
+      static_assert(SL::kSlots == 1, "one column per lane in the matrix-core layout");
+      const int h = lane >> 5;
+      const int mb = 32 * ((lane & 31) % (NY / 32));
+      const int base = mb < NY / 2 ? mb : mb - NY;
+      auto qbits = [&](int lo, int hi) -> uint32_t {  // q in [0, 32) with lo <= base + q <= hi
+        int q0 = lo - base, q1 = hi - base;
+        q0 = q0 < 0 ? 0 : q0;
+        q1 = q1 > 31 ? 31 : q1;
+        return q1 >= q0 ? (2u << q1) - (1u << q0) : 0u;  // 2u << 31 wraps to 0: bits q0..31
+      };
+      uint32_t md = qbits(sd[0].a0, sd[0].a1) & ~qbits(sd[0].b0, sd[0].b1);
+      uint32_t mm = qbits(-sm[0].a1, -sm[0].a0) & ~qbits(-sm[0].b1, -sm[0].b0);
+      // iy = -N/2 (the block's q = 0 when base = -N/2) is its own mirror
+      if (base == -NY / 2) mm = (mm & ~1u) | (sm[0].has(-NY / 2) ? 1u : 0u);
+      const uint32_t own = 0x0f0f0f0fu << (4 * h);  // the q of this lane's registers
+      cnt += __builtin_popcount(md & own) + __builtin_popcount(mm & own);
+      md >>= 4 * h;
+      mm >>= 4 * h;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int q = 8 * (i >> 2) + (i & 3);
+        uint32_t bd = (md >> q) & 1u, bm = (mm >> q) & 1u;
+        // one register's weights at a time: formed all at once, the 32 weights cost registers
+        asm volatile("" : "+v"(bd), "+v"(bm));
+        const float wd = (float)bd, wm = (float)bm;
+        accd[i].x = fmaf(v[i].x, wd, accd[i].x);
+        accd[i].y = fmaf(v[i].y, wd, accd[i].y);
+        accm[i].x = fmaf(v[i].x, wm, accm[i].x);
+        accm[i].y = fmaf(-v[i].y, wm, accm[i].y);
+      }
     } else if constexpr (CHI0) {
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
