@@ -323,7 +323,7 @@ __global__ void __launch_bounds__(kYThreads, 2) k_yreduce(float2* __restrict__ X
   };
   // the columns of the next active pixel (of the next two on the zero-aberration path, whose sum
   // leaves the registers for it) are loaded while this one is transformed and summed
-  constexpr int kAhead = (CHI0 && !XF::kMfma && XF::kUniformCol) ? 2 : 1;
+  constexpr int kAhead = (CHI0 && ((!XF::kMfma && XF::kUniformCol) || (XF::kMfma && NY == 1024))) ? 2 : 1;
   int kd = next_kd(kd_a);
   int kd1 = kAhead == 2 && kd < kd_b ? next_kd(kd + 1) : kd_b;
   float2 v[16], v1[kAhead == 2 ? 16 : 1];

@@ -199,7 +199,8 @@ def test_recompute_mode_matches_oracle(gpu, name):
     assert rel_l2(dth.cpu().numpy(), dtho) <= 1e-4
 
 
-@pytest.mark.parametrize("prec", [stem.STEM_FFT_FP32, stem.STEM_DFT_BF16_SPLIT], ids=["fp32", "bf16"])
+@pytest.mark.parametrize("prec", [stem.STEM_FFT_FP32, stem.STEM_DFT_BF16_SPLIT, stem.STEM_DFT_FP16_SPLIT],
+                         ids=["fp32", "bf16", "fp16"])
 @pytest.mark.parametrize("name", ["small", "rect", "n512", "n1024"])
 def test_zero_aberration_sum_equals_general_sum(gpu, name, prec):
     """With chi identically zero and no theta the fused sum adds G itself; given theta = 0 it takes
