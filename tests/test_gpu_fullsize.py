@@ -118,6 +118,35 @@ def test_full_com_dpc(gpu, name):
 
 
 @pytest.mark.parametrize("name", ["scan256", "scan1024", "aberrated512"])
+def test_full_com_from_binning_pass(gpu, name):
+    """ssb_reconstruct_com: the COM planes and counts formed by the binning pass equal the
+    oracle's bit for bit, and the phase equals that of the call without COM outputs."""
+    wl, d_idx, d_off, idx, off, _ = case(name)
+    det, scan, optics = structs(wl, wl.aberr)
+    F = wl.n_frames
+    com64 = torch.full((2 * F,), -7.0, dtype=torch.float64, device="cuda")
+    com32 = torch.full((2 * F,), -7.0, dtype=torch.float32, device="cuda")
+    counts = torch.full((F,), -7, dtype=torch.int32, device="cuda")
+    phases = []
+    for with_com in (True, False):
+        st = stem.SsbState(det, scan, optics, stem.Ssb(stem.STEM_FFT_FP32, 0, stem.STEM_G_RECOMPUTE, 8),
+                           device="cuda")
+        ph = torch.zeros(F, dtype=torch.float32, device="cuda")
+        kw = dict(com64=com64, com32=com32, counts=counts) if with_com else {}
+        st.oneshot(d_idx, d_off, phase=ph, **kw)
+        torch.cuda.synchronize()
+        assert int(st.status.item()) == 0
+        phases.append(ph.cpu().numpy())
+        del st
+    cx, cy, sx, sy, n = oracle(name, "com")
+    c64 = com64.cpu().numpy().reshape(2, F)
+    assert np.array_equal(counts.cpu().numpy(), n)
+    assert np.array_equal(c64[0], cx) and np.array_equal(c64[1], cy)
+    assert np.array_equal(com32.cpu().numpy().reshape(2, F), c64.astype(np.float32))
+    assert np.array_equal(phases[0], phases[1])
+
+
+@pytest.mark.parametrize("name", ["scan256", "scan1024", "aberrated512"])
 def test_full_binning_transform_and_sum(gpu, name):
     """Stored-G mode: binned cube bit-exact, G, T and phi against the oracle."""
     wl, d_idx, d_off, idx, off, _ = case(name)
