@@ -396,13 +396,14 @@ __global__ void __launch_bounds__(kComThreads) k_decode_rle(const int32_t* __res
 // ---------------------------------------------------------------------------------------------
 // geometry of the kept set (one workgroup)
 
-__global__ void __launch_bounds__(256) k_geometry(int32_t b, int32_t nbx, int32_t nby, int32_t cx,
-                                                  int32_t cy, double r2, RowRun* __restrict__ rows,
-                                                  double2* __restrict__ kc) {
-  __shared__ int32_t s_lo[1024];
-  __shared__ int32_t s_hi[1024];
-  __shared__ int32_t s_start[1024];
-  __shared__ int32_t s_base;
+// The kept set's row runs and bin centres, by one workgroup of blockDim.x threads; s holds
+// 3 * 1024 + 1 ints of LDS scratch.
+__device__ void build_geometry(int32_t b, int32_t nbx, int32_t nby, int32_t cx, int32_t cy, double r2,
+                               RowRun* __restrict__ rows, double2* __restrict__ kc, int32_t* s) {
+  int32_t* s_lo = s;
+  int32_t* s_hi = s + 1024;
+  int32_t* s_start = s + 2048;
+  int32_t& s_base = s[3072];
   if (threadIdx.x == 0) s_base = 0;
   // nby <= 4096 is checked on the host; rows are handled in slices of 1024
   for (int r0 = 0; r0 < nby; r0 += 1024) {
@@ -436,6 +437,13 @@ __global__ void __launch_bounds__(256) k_geometry(int32_t b, int32_t nbx, int32_
     }
     __syncthreads();
   }
+}
+
+__global__ void __launch_bounds__(256) k_geometry(int32_t b, int32_t nbx, int32_t nby, int32_t cx,
+                                                  int32_t cy, double r2, RowRun* __restrict__ rows,
+                                                  double2* __restrict__ kc) {
+  __shared__ int32_t s[3 * 1024 + 1];
+  build_geometry(b, nbx, nby, cx, cy, r2, rows, kc, s);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -488,11 +496,22 @@ constexpr int kBinBoxMax = 4096;                      // bins of the largest LDS
 // (BOX) the pixel -> bin table is a small per-workgroup LDS copy over the box, looked up with a
 // division by W (magic number) and by the binning (multiply-high), instead of a gather from the
 // global per-pixel table.
+constexpr int kBoxRows = 64;  // bin rows of the largest box whose row runs travel as arguments
 struct BinBox {
   Magic mw;           // division by the detector width W
   uint32_t mbin;      // ceil(2^32 / bin); 0 for bin = 1
   int32_t W, bin;
   int32_t bx0, by0, bw, bh;
+  int32_t start[kBoxRows], lo[kBoxRows], hi[kBoxRows];  // row runs of the box's rows (BOX)
+};
+
+// The kept set's geometry, written by the first workgroup of the binning kernel (BOX: the
+// binning itself takes the box's row runs from its arguments)
+struct GeomOut {
+  RowRun* rows;       // nullptr: nothing to write
+  double2* kc;
+  int32_t nbx, nby, cx, cy;
+  double r2;
 };
 
 // One step of a segmented inclusive scan within rows of 16 lanes: lane i adds the sums of lane
@@ -522,7 +541,8 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(const int32_t* __restrict__
                                                      int64_t n_frames, int32_t npix,
                                                      const int16_t* __restrict__ lut,
                                                      const RowRun* __restrict__ rows, BinBox box, int32_t n_k,
-                                                     int64_t F, DT* __restrict__ D, ComOut com, int32_t* status) {
+                                                     int64_t F, DT* __restrict__ D, ComOut com, GeomOut geo,
+                                                     int32_t* status) {
   extern __shared__ int16_t s_box[];  // [bh][bw] kept-bin index of each bin of the box, or -1
   __shared__ __align__(16) uint32_t s_hist[kBinWords];
   __shared__ uint32_t s_map[(kBinWin + 16) / 4];
@@ -531,6 +551,11 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(const int32_t* __restrict__
   __shared__ int32_t s_mom[COM ? 2 * kBinFrames : 1];  // [x | y][frame] moment sums of a window
   const int t = threadIdx.x;
   const int lane = t & 63;
+  if (geo.rows && blockIdx.x == 0) {
+    // the counters' LDS is free until the first pass clears it
+    build_geometry(box.bin, geo.nbx, geo.nby, geo.cx, geo.cy, geo.r2, geo.rows, geo.kc, (int32_t*)s_hist);
+    __syncthreads();
+  }
   const int nchunks = (n_k + kBinKd - 1) / kBinKd;
   const int kd0 = (int)(blockIdx.x % nchunks) * kBinKd;
   const int kc = n_k - kd0 < kBinKd ? n_k - kd0 : kBinKd;
@@ -556,9 +581,8 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(const int32_t* __restrict__
   if constexpr (BOX) {
     // kept index of each bin of the box from the row runs (the rule of the per-pixel table)
     for (int i = t; i < box.bw * box.bh; i += kBinThreads) {
-      const int by = box.by0 + i / box.bw, bx = box.bx0 + i % box.bw;
-      const RowRun rr = rows[by];
-      s_box[i] = (int16_t)(bx >= rr.lo && bx < rr.hi ? rr.start + bx - rr.lo : -1);
+      const int ry = i / box.bw, bx = box.bx0 + i % box.bw;
+      s_box[i] = (int16_t)(bx >= box.lo[ry] && bx < box.hi[ry] ? box.start[ry] + bx - box.lo[ry] : -1);
     }
   }
   __syncthreads();
@@ -766,8 +790,8 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(const int32_t* __restrict__
 }
 
 int launch_bin(const int32_t* idx, const int64_t* off, int64_t frame0, int64_t n_frames,
-               const stem_det& det, double r2, const RowRun* rows, int16_t* lut, int n_k, int64_t F, void* D,
-               int d_bits, int32_t* status, hipStream_t stream, const ComOut* com) {
+               const stem_det& det, double r2, RowRun* rows, double2* kc, int16_t* lut, int n_k, int64_t F,
+               void* D, int d_bits, int32_t* status, hipStream_t stream, const ComOut* com) {
   if (n_frames == 0) return STEM_OK;
   const int nchunks = (n_k + kBinKd - 1) / kBinKd;
   const int64_t fblocks = (n_frames + kBinFrames - 1) / kBinFrames;
@@ -776,14 +800,22 @@ int launch_bin(const int32_t* idx, const int64_t* off, int64_t frame0, int64_t n
   const int nbx = det.W / det.bin, nby = det.H / det.bin;
   BinBox box{};
   int bxa = nbx, bxb = 0, bya = nby, byb = 0;
+  int run_start = 0;
   for (int by = 0; by < nby; ++by) {
     int lo, hi;
     kept_run(det.bin, by, nbx, det.cx, det.cy, r2, lo, hi);
     if (hi <= lo) continue;
     bxa = lo < bxa ? lo : bxa;
     bxb = hi > bxb ? hi : bxb;
-    bya = by < bya ? by : bya;
+    if (bya == nby) bya = by;
     byb = by + 1;
+    // row runs of the box's rows, in box-row order (kept rows of the box are contiguous)
+    if (by - bya < kBoxRows) {
+      box.start[by - bya] = run_start;
+      box.lo[by - bya] = lo;
+      box.hi[by - bya] = hi;
+    }
+    run_start += hi - lo;
   }
   box.W = det.W;
   box.bin = det.bin;
@@ -795,9 +827,15 @@ int launch_bin(const int32_t* idx, const int64_t* off, int64_t frame0, int64_t n
   box.bh = byb > bya ? byb - bya : 0;
   // the LDS table when it is small; the bin divisions by multiply-high are exact for W, H < 2^16
   const int64_t cells = (int64_t)box.bw * box.bh;
-  const bool use_box = cells > 0 && cells <= kBinBoxMax && det.W < 65536 && det.H < 65536;
+  const bool use_box = cells > 0 && cells <= kBinBoxMax && box.bh <= kBoxRows && det.W < 65536 && det.H < 65536;
   const size_t lds = use_box ? (size_t)((cells * 2 + 15) & ~15ll) : 0;
-  if (!use_box) {
+  // BOX: the binning kernel's first workgroup writes the row runs and bin centres; otherwise the
+  // per-pixel table needs them first
+  GeomOut geo{};
+  if (use_box) {
+    geo = GeomOut{rows, kc, nbx, nby, det.cx, det.cy, r2};
+  } else {
+    if (int st = launch_geometry(det, r2, rows, kc, stream)) return st;
     // the per-pixel table, read by the binning kernel
     STEM_TRACE("pixel_lut", stream);
     const int64_t npix = (int64_t)det.W * det.H;
@@ -812,7 +850,7 @@ int launch_bin(const int32_t* idx, const int64_t* off, int64_t frame0, int64_t n
     using DT = decltype(dt);
     constexpr bool BX = decltype(bx)::value, CM = decltype(cm)::value;
     hipLaunchKernelGGL((k_bin<DT, BX, CM>), grid, dim3(kBinThreads), BX ? lds : 0, stream, idx, off, frame0,
-                       n_frames, npix, lut, rows, box, n_k, F, (DT*)D, co, status);
+                       n_frames, npix, lut, rows, box, n_k, F, (DT*)D, co, geo, status);
   };
   using T_ = std::true_type;
   using F_ = std::false_type;

@@ -20,11 +20,12 @@ struct ComOut {
   int64_t nplane;
   int32_t cx, cy;
 };
-// binning; builds the per-pixel table lut[W*H] first when the kept bins' box is too large for LDS.
-// With com, the same pass also writes the frames' centre of mass (as launch_com does).
+// binning; also writes the kept-set geometry (row runs, bin centres Kc), and builds the per-pixel
+// table lut[W*H] first when the kept bins' box is too large for LDS.  With com, the same pass also
+// writes the frames' centre of mass (as launch_com does).
 int launch_bin(const int32_t* idx, const int64_t* off, int64_t frame0, int64_t n_frames,
-               const stem_det& det, double r2, const RowRun* rows, int16_t* lut, int n_k, int64_t F, void* D,
-               int d_bits, int32_t* status, hipStream_t stream, const ComOut* com = nullptr);
+               const stem_det& det, double r2, RowRun* rows, double2* kc, int16_t* lut, int n_k, int64_t F,
+               void* D, int d_bits, int32_t* status, hipStream_t stream, const ComOut* com = nullptr);
 
 // ---- fft2.hip: batched row FFTs of length n (power of two, 32..1024) --------------------------
 enum RowIn { IN_C64 = 0, IN_C64_SUM = 1, IN_F32_PAIR = 2, IN_F64_PAIR = 3, IN_HALF_C64 = 4 };

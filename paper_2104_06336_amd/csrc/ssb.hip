@@ -542,9 +542,8 @@ static int reconstruct(const int32_t* d_idx, const int64_t* d_off, int64_t frame
     if (!d_idx || !d_off) return STEM_EINVAL;
     if (frame0 < 0 || n_frames <= 0 || frame0 % nx || n_frames % nx || frame0 + n_frames > L.F)
       return STEM_EINVAL;
-    if ((st = launch_geometry(*det, o.r2, b.rows, b.kc, s))) return st;
-    if ((st = launch_bin(d_idx, d_off, frame0, n_frames, *det, o.r2, b.rows, b.lut, n_k, L.F, b.D, ssb->d_bits,
-                          d_status, s, com)))
+    if ((st = launch_bin(d_idx, d_off, frame0, n_frames, *det, o.r2, b.rows, b.kc, b.lut, n_k, L.F, b.D,
+                          ssb->d_bits, d_status, s, com)))
       return st;
     const int ry0 = (int)(frame0 / nx), nr = (int)(n_frames / nx);
     const int64_t nrows = (int64_t)n_k * nr;
