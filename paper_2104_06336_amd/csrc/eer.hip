@@ -13,6 +13,7 @@
 #include "common.h"
 #include "geom.h"
 #include "kernels.h"
+#include "optics.h"
 #include "trace.h"
 
 namespace stem {
@@ -542,7 +543,7 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(const int32_t* __restrict__
                                                      const int16_t* __restrict__ lut,
                                                      const RowRun* __restrict__ rows, BinBox box, int32_t n_k,
                                                      int64_t F, DT* __restrict__ D, ComOut com, GeomOut geo,
-                                                     int32_t* status) {
+                                                     SetsJob sj, int32_t* status) {
   extern __shared__ int16_t s_box[];  // [bh][bw] kept-bin index of each bin of the box, or -1
   __shared__ __align__(16) uint32_t s_hist[kBinWords];
   __shared__ uint32_t s_map[(kBinWin + 16) / 4];
@@ -556,6 +557,24 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(const int32_t* __restrict__
     build_geometry(box.bin, geo.nbx, geo.nby, geo.cx, geo.cy, geo.r2, geo.rows, geo.kc, (int32_t*)s_hist);
     __syncthreads();
   }
+  if constexpr (BOX) {
+    // workgroups 1, 2, ... build the interval table and the mask, one word per wave, with Kc of
+    // the lane's pixel from the box's row runs (as the geometry computes it)
+    const int64_t word = (int64_t)(blockIdx.x - 1) * (kBinThreads / 64) + (t >> 6);
+    if (sj.cst && blockIdx.x >= 1 && word < (int64_t)sj.ncs * sj.nmw) {
+      const int kd = 64 * (int)(word % sj.nmw) + lane;
+      double2 k = make_double2(0.0, 0.0);
+      if (kd < sj.n_k) {
+        int r = 0;
+        while (r < box.bh - 1 && kd >= box.start[r] + box.hi[r] - box.lo[r]) ++r;
+        k = make_double2(bin_centre(box.bin, box.lo[r] + kd - box.start[r], geo.cx),
+                         bin_centre(box.bin, box.by0 + r, geo.cy));
+      }
+      sets_word(sj, word, lane, k);
+    }
+  }
+  // workgroups added for the table only (tiny scans) bin nothing
+  if ((int64_t)(blockIdx.x / ((n_k + kBinKd - 1) / kBinKd)) * kBinFrames >= n_frames) return;
   const int nchunks = (n_k + kBinKd - 1) / kBinKd;
   const int kd0 = (int)(blockIdx.x % nchunks) * kBinKd;
   const int kc = n_k - kd0 < kBinKd ? n_k - kd0 : kBinKd;
@@ -789,16 +808,11 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(const int32_t* __restrict__
   if (bad) report(status, bad);
 }
 
-int launch_bin(const int32_t* idx, const int64_t* off, int64_t frame0, int64_t n_frames,
-               const stem_det& det, double r2, RowRun* rows, double2* kc, int16_t* lut, int n_k, int64_t F,
-               void* D, int d_bits, int32_t* status, hipStream_t stream, const ComOut* com) {
-  if (n_frames == 0) return STEM_OK;
-  const int nchunks = (n_k + kBinKd - 1) / kBinKd;
-  const int64_t fblocks = (n_frames + kBinFrames - 1) / kBinFrames;
-  const dim3 grid((unsigned)(fblocks * nchunks));
-  // bounding box of the kept bins
+// The kept bins' bounding box and its rows' runs; true when the binning uses the LDS bin table
+// over it (and then also takes the geometry's and the interval table's work).
+static bool make_box(const stem_det& det, double r2, BinBox& box) {
   const int nbx = det.W / det.bin, nby = det.H / det.bin;
-  BinBox box{};
+  box = BinBox{};
   int bxa = nbx, bxb = 0, bya = nby, byb = 0;
   int run_start = 0;
   for (int by = 0; by < nby; ++by) {
@@ -827,8 +841,33 @@ int launch_bin(const int32_t* idx, const int64_t* off, int64_t frame0, int64_t n
   box.bh = byb > bya ? byb - bya : 0;
   // the LDS table when it is small; the bin divisions by multiply-high are exact for W, H < 2^16
   const int64_t cells = (int64_t)box.bw * box.bh;
-  const bool use_box = cells > 0 && cells <= kBinBoxMax && box.bh <= kBoxRows && det.W < 65536 && det.H < 65536;
+  return cells > 0 && cells <= kBinBoxMax && box.bh <= kBoxRows && det.W < 65536 && det.H < 65536;
+}
+
+bool bin_builds_sets(const stem_det& det, double r2) {
+  BinBox box;
+  return make_box(det, r2, box);
+}
+
+int launch_bin(const int32_t* idx, const int64_t* off, int64_t frame0, int64_t n_frames,
+               const stem_det& det, double r2, RowRun* rows, double2* kc, int16_t* lut, int n_k, int64_t F,
+               void* D, int d_bits, int32_t* status, hipStream_t stream, const ComOut* com, const SetsJob* sets) {
+  if (n_frames == 0) return STEM_OK;
+  const int nchunks = (n_k + kBinKd - 1) / kBinKd;
+  const int64_t fblocks = (n_frames + kBinFrames - 1) / kBinFrames;
+  const int nbx = det.W / det.bin, nby = det.H / det.bin;
+  BinBox box;
+  const bool use_box = make_box(det, r2, box);
+  const int64_t cells = (int64_t)box.bw * box.bh;
   const size_t lds = use_box ? (size_t)((cells * 2 + 15) & ~15ll) : 0;
+  // BOX with the interval table: enough workgroups for one wave per mask word besides the first
+  const SetsJob sj = use_box && sets ? *sets : SetsJob{};
+  int64_t blocks = fblocks * nchunks;
+  if (sj.cst) {
+    const int64_t need = 1 + ((int64_t)sj.ncs * sj.nmw + kBinThreads / 64 - 1) / (kBinThreads / 64);
+    if (need > blocks) blocks = need;
+  }
+  const dim3 grid((unsigned)blocks);
   // BOX: the binning kernel's first workgroup writes the row runs and bin centres; otherwise the
   // per-pixel table needs them first
   GeomOut geo{};
@@ -850,7 +889,7 @@ int launch_bin(const int32_t* idx, const int64_t* off, int64_t frame0, int64_t n
     using DT = decltype(dt);
     constexpr bool BX = decltype(bx)::value, CM = decltype(cm)::value;
     hipLaunchKernelGGL((k_bin<DT, BX, CM>), grid, dim3(kBinThreads), BX ? lds : 0, stream, idx, off, frame0,
-                       n_frames, npix, lut, rows, box, n_k, F, (DT*)D, co, geo, status);
+                       n_frames, npix, lut, rows, box, n_k, F, (DT*)D, co, geo, sj, status);
   };
   using T_ = std::true_type;
   using F_ = std::false_type;

@@ -25,6 +25,28 @@ __global__ void __launch_bounds__(64 * W) k_row_fft(RowFftArgs a, int in_mode, i
   constexpr int B = 1024 / N;
   constexpr int TR = W * B;  // rows per tile
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if constexpr (SUM) {
+    if (a.stats && blockIdx.x == 0) {
+      // every thread of the first workgroup sums a strided share, four loads in flight
+      __shared__ unsigned long long s_red[W];
+      unsigned long long c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+      for (int64_t i = threadIdx.x; i < a.nwcnt; i += 4 * kRowThreads) {
+        c0 += a.wcnt[i];
+        if (i + kRowThreads < a.nwcnt) c1 += a.wcnt[i + kRowThreads];
+        if (i + 2 * kRowThreads < a.nwcnt) c2 += a.wcnt[i + 2 * kRowThreads];
+        if (i + 3 * kRowThreads < a.nwcnt) c3 += a.wcnt[i + 3 * kRowThreads];
+      }
+      unsigned long long c = (c0 + c1) + (c2 + c3);
+      for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+      if (lane == 0) s_red[wave] = c;
+      __syncthreads();
+      if (threadIdx.x < 4) {
+        unsigned long long t = 0;
+        for (int w = 0; w < W; ++w) t += s_red[w];
+        a.stats[threadIdx.x] = threadIdx.x == 0 ? t : threadIdx.x == 1 ? (unsigned long long)a.stats_groups : 0ull;
+      }
+    }
+  }
   fill_twiddles(s_tw, threadIdx.x, kRowThreads);
   __syncthreads();
   float2* buf = s_buf + wave * kWaveStride;

@@ -3,6 +3,7 @@
 
 #include "common.h"
 #include "geom.h"
+#include "optics.h"
 
 namespace stem {
 
@@ -23,9 +24,13 @@ struct ComOut {
 // binning; also writes the kept-set geometry (row runs, bin centres Kc), and builds the per-pixel
 // table lut[W*H] first when the kept bins' box is too large for LDS.  With com, the same pass also
 // writes the frames' centre of mass (as launch_com does).
+// With sets (and the LDS bin table: bin_builds_sets), the binning also builds the interval table
+// and the active-pixel mask of the fused column sum.
 int launch_bin(const int32_t* idx, const int64_t* off, int64_t frame0, int64_t n_frames,
                const stem_det& det, double r2, RowRun* rows, double2* kc, int16_t* lut, int n_k, int64_t F,
-               void* D, int d_bits, int32_t* status, hipStream_t stream, const ComOut* com = nullptr);
+               void* D, int d_bits, int32_t* status, hipStream_t stream, const ComOut* com = nullptr,
+               const SetsJob* sets = nullptr);
+bool bin_builds_sets(const stem_det& det, double r2);
 
 // ---- fft2.hip: batched row FFTs of length n (power of two, 32..1024) --------------------------
 enum RowIn { IN_C64 = 0, IN_C64_SUM = 1, IN_F32_PAIR = 2, IN_F64_PAIR = 3, IN_HALF_C64 = 4 };
@@ -50,6 +55,12 @@ struct RowFftArgs {
   int64_t out_stride;
   float2 osc;              // complex factor applied to every output value
   const char* tag;         // name under which the launch is traced
+  // IN_C64_SUM: if stats is set, workgroup 0 also writes stats[0] = the sum of wcnt[0, nwcnt),
+  // stats[1] = stats_groups, stats[2..3] = 0
+  const unsigned long long* wcnt;
+  int64_t nwcnt;
+  unsigned long long* stats;
+  int32_t stats_groups;
 };
 
 int launch_row_fft(int n, bool inverse, RowIn in, RowOut out, const RowFftArgs& a, hipStream_t stream);

@@ -215,4 +215,56 @@ __device__ __forceinline__ float2 expi_reduced(double psi) {
   }
 }
 
+// Double-overlap sets of pixel K along column ix: iy in [a0, a1] but not in [b0, b1].
+struct ColSet {
+  int a0, a1, b0, b1;
+  __device__ __forceinline__ bool has(int iy) const { return iy >= a0 && iy <= a1 && !(iy >= b0 && iy <= b1); }
+  __device__ __forceinline__ bool empty() const { return a0 > a1; }
+};
+
+__device__ __forceinline__ ColSet col_set(double kx, double ky, int ix, int ny, const Optics& o) {
+  const double qx = (double)ix * o.sx;
+  ColSet cs;
+  disk_interval(kx, ky, qx, o.sy, o.r, o.r2, -1, ny, cs.a0, cs.a1);
+  if (cs.a0 > cs.a1) {
+    cs.b0 = 1;
+    cs.b1 = 0;
+    return cs;
+  }
+  disk_interval(kx, ky, qx, o.sy, o.r, o.r2, +1, ny, cs.b0, cs.b1);
+  return cs;
+}
+
+// The double-overlap interval table of the fused column sum and its active-pixel mask: for
+// column set cs (B = 1024/ny consecutive half-spectrum columns) and mask word w, lane j takes
+// pixel kd = 64 w + j; cst[kd * nc + c] packs its direct and mirrored sets of every column c of
+// the set, and bit j of mask[cs * nmw + w] says whether any of them is non-empty.
+struct SetsJob {
+  Optics o;
+  int n_k, nx, ny, ncs, nmw;
+  int4* cst;          // nullptr: nothing to do
+  uint64_t* mask;
+};
+
+// One mask word (one wave, every lane active); k = Kc of the lane's pixel when kd < n_k.
+__device__ __forceinline__ void sets_word(const SetsJob& j, int64_t word, int lane, double2 k) {
+  const int nc = j.nx / 2 + 1, B = 1024 / j.ny;
+  const int cs = (int)(word / j.nmw), w = (int)(word % j.nmw);
+  const int kd = 64 * w + lane;
+  auto pk = [](int lo, int hi) { return (int)(((uint32_t)lo & 0xffffu) | ((uint32_t)hi << 16)); };
+  bool any = false;
+  if (kd < j.n_k) {
+    const int c1 = cs * B + B < nc ? cs * B + B : nc;
+    for (int c = cs * B; c < c1; ++c) {
+      const ColSet d = col_set(k.x, k.y, signed_index(c, j.nx), j.ny, j.o);
+      ColSet m{1, 0, 1, 0};
+      if (c > 0 && 2 * c < j.nx) m = col_set(k.x, k.y, signed_index(j.nx - c, j.nx), j.ny, j.o);
+      j.cst[(int64_t)kd * nc + c] = make_int4(pk(d.a0, d.a1), pk(d.b0, d.b1), pk(m.a0, m.a1), pk(m.b0, m.b1));
+      any = any || d.a0 <= d.a1 || m.a0 <= m.a1;
+    }
+  }
+  const uint64_t bits = __ballot(any);
+  if (lane == 0) j.mask[word] = bits;
+}
+
 }  // namespace stem

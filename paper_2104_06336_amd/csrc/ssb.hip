@@ -22,7 +22,7 @@ constexpr int kMaxPixels = 4096;
 struct SsbLayout {
   int n_k, nby, nh;
   int64_t F;
-  size_t rows, kc, kchi, cst, cmask, lut, stats, D, X, T, A, Tb, pdc, pdth, part, total;
+  size_t rows, kc, kchi, cst, cmask, lut, stats, D, X, T, A, Tb, pdc, pdth, part, wcnt, total;
   int nmw;      // 64-bit words per column set of the active-pixel mask
   int groups;  // pixel groups of the fused column transform + sum
   int ncs;     // column sets (B = 1024/Ny half-spectrum columns each)
@@ -85,6 +85,7 @@ static size_t make_layout(const stem_det& det, const stem_scan& scan, const stem
   L->pdc = o;   o = align256(o + (size_t)L->nwy * 8 * sizeof(double));
   L->pdth = o;  o = align256(o + (size_t)L->ncs * n_k * sizeof(float));
   L->part = o;  o = align256(o + (size_t)L->groups * L->F * sizeof(float2));
+  L->wcnt = o;  o = align256(o + (size_t)L->nwy * sizeof(unsigned long long));
   L->total = o;
   return o;
 }
@@ -122,26 +123,11 @@ __global__ void __launch_bounds__(256) k_colsets(const double2* __restrict__ kc,
     }
     return;
   }
-  const int nc = nx / 2 + 1;
   const int64_t word = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (word >= (int64_t)ncs * nmw) return;  // uniform across the wave
-  const int cs = (int)(word / nmw), w = (int)(word % nmw);
-  const int kd = 64 * w + (int)(threadIdx.x & 63);
-  auto pk = [](int lo, int hi) { return (int)(((uint32_t)lo & 0xffffu) | ((uint32_t)hi << 16)); };
-  bool any = false;
-  if (kd < n_k) {
-    const double2 k = kc[kd];
-    const int c1 = cs * B + B < nc ? cs * B + B : nc;
-    for (int c = cs * B; c < c1; ++c) {
-      const ColSet d = col_set(k.x, k.y, signed_index(c, nx), ny, o);
-      ColSet m{1, 0, 1, 0};
-      if (c > 0 && 2 * c < nx) m = col_set(k.x, k.y, signed_index(nx - c, nx), ny, o);
-      cst[(int64_t)kd * nc + c] = make_int4(pk(d.a0, d.a1), pk(d.b0, d.b1), pk(m.a0, m.a1), pk(m.b0, m.b1));
-      any = any || d.a0 <= d.a1 || m.a0 <= m.a1;
-    }
-  }
-  const uint64_t bits = __ballot(any);
-  if ((threadIdx.x & 63) == 0) mask[word] = bits;
+  const int lane = (int)(threadIdx.x & 63), kd = 64 * (int)(word % nmw) + lane;
+  const SetsJob j{o, n_k, nx, ny, ncs, nmw, cst, mask};
+  sets_word(j, word, lane, kd < n_k ? kc[kd] : make_double2(0.0, 0.0));
 }
 
 // chi(Kc) + theta and the counter reset, done by the interval-table kernel when kchi is given
@@ -171,29 +157,33 @@ static int chi_is_zero(const Optics& o, const float* theta) {
 }
 
 // the interval table and the active-pixel mask, then the fused column sum
+// the interval table and the active-pixel mask (unless the x-stage built them: sets_ready), then
+// the fused column sum; wcnt receives its pair count per wave
 static int launch_yreduce(int prec, int ny, float2* X, const double2* kc, const double* kchi, int4* cst,
                           uint64_t* cmask, int nmw, int n_k, int nx, int ngroups, const Optics& o, int store_g,
-                          int chi0, float2* part, unsigned long long* stats, hipStream_t s,
-                          const ChiArgs& chi = ChiArgs{}) {
-  launch_colsets(kc, n_k, nx, ny, o, cst, cmask, nmw, s, chi);
-  STEM_LAUNCH_CHECK();
+                          int chi0, float2* part, unsigned long long* wcnt, hipStream_t s,
+                          const ChiArgs& chi = ChiArgs{}, int sets_ready = 0) {
+  if (!sets_ready) {
+    launch_colsets(kc, n_k, nx, ny, o, cst, cmask, nmw, s, chi);
+    STEM_LAUNCH_CHECK();
+  }
   switch (prec) {
     case STEM_DFT_BF16_SPLIT:
       return launch_yreduce_p<STEM_DFT_BF16_SPLIT>(ny, X, kc, kchi, cst, cmask, nmw, n_k, nx, ngroups, o, store_g,
-                                                   chi0, part, stats, s);
+                                                   chi0, part, wcnt, s);
     case STEM_DFT_FP16_SPLIT:
       return launch_yreduce_p<STEM_DFT_FP16_SPLIT>(ny, X, kc, kchi, cst, cmask, nmw, n_k, nx, ngroups, o, store_g,
-                                                   chi0, part, stats, s);
+                                                   chi0, part, wcnt, s);
     default:
       return launch_yreduce_p<STEM_FFT_FP32>(ny, X, kc, kchi, cst, cmask, nmw, n_k, nx, ngroups, o, store_g, chi0,
-                                             part, stats, s);
+                                             part, wcnt, s);
   }
 }
 
 // Eq. 3 from the stored G without normalisation (REFOCUS): the fused sum over the stored columns
 static int launch_ysum_stored(int ny, float2* G, const double2* kc, const double* kchi, int4* cst, uint64_t* cmask,
                               int nmw, int n_k, int nx, int ngroups, const Optics& o, int chi0, float2* part,
-                              unsigned long long* stats, hipStream_t s, const ChiArgs& chi) {
+                              unsigned long long* wcnt, hipStream_t s, const ChiArgs& chi) {
   launch_colsets(kc, n_k, nx, ny, o, cst, cmask, nmw, s, chi);
   STEM_LAUNCH_CHECK();
   const int B = 1024 / ny;
@@ -204,10 +194,10 @@ static int launch_ysum_stored(int ny, float2* G, const double2* kc, const double
     using XF = XfNone<decltype(nc)::value>;
     if (chi0)
       hipLaunchKernelGGL((k_yreduce<XF, true>), grid, blk, 0, s, G, kc, kchi, cst, cmask, nmw, n_k, nx, ngroups, o,
-                         0, part, stats);
+                         0, part, wcnt);
     else
       hipLaunchKernelGGL((k_yreduce<XF, false>), grid, blk, 0, s, G, kc, kchi, cst, cmask, nmw, n_k, nx, ngroups, o,
-                         0, part, stats);
+                         0, part, wcnt);
   });
   if (st) return st;
   STEM_LAUNCH_CHECK();
@@ -400,6 +390,7 @@ struct Bufs {
   double* pdc;
   float* pdth;
   float2* part;
+  unsigned long long* wcnt;  // pair counts per wave of the fused sum
 };
 
 static Bufs carve(void* state, const SsbLayout& L) {
@@ -408,7 +399,8 @@ static Bufs carve(void* state, const SsbLayout& L) {
               (uint64_t*)(p + L.cmask), (int16_t*)(p + L.lut),
               (unsigned long long*)(p + L.stats), (void*)(p + L.D),
               (float2*)(p + L.X),    (float2*)(p + L.T),  (float2*)(p + L.A),     (float2*)(p + L.Tb),
-              (double*)(p + L.pdc),  (float*)(p + L.pdth), (float2*)(p + L.part)};
+              (double*)(p + L.pdc),  (float*)(p + L.pdth), (float2*)(p + L.part),
+              (unsigned long long*)(p + L.wcnt)};
 }
 
 static int check_common(const stem_det* det, const stem_scan* scan, const stem_optics* optics,
@@ -442,6 +434,13 @@ static int run_phase(const SsbLayout& L, const Bufs& b, const stem_scan& sc, con
   a.out_stride = nx;
   a.osc = make_float2(1.f, 0.f);
   a.tag = "phase_fft";
+  if (parts == b.part) {
+    // the fused sum's pair counts per wave become the state's counters
+    a.wcnt = b.wcnt;
+    a.nwcnt = L.nwy;
+    a.stats = b.stats;
+    a.stats_groups = nparts;
+  }
   int st = launch_row_fft(ny, true, IN_C64_SUM, OUT_T_C64, a, s);
   if (st) return st;
   if (d_phase) {
@@ -542,8 +541,10 @@ static int reconstruct(const int32_t* d_idx, const int64_t* d_off, int64_t frame
     if (!d_idx || !d_off) return STEM_EINVAL;
     if (frame0 < 0 || n_frames <= 0 || frame0 % nx || n_frames % nx || frame0 + n_frames > L.F)
       return STEM_EINVAL;
+    // the binning also builds the interval table and the active-pixel mask when it can (geometry only)
+    const SetsJob job{o, n_k, nx, ny, L.ncs, L.nmw, b.cst, b.cmask};
     if ((st = launch_bin(d_idx, d_off, frame0, n_frames, *det, o.r2, b.rows, b.kc, b.lut, n_k, L.F, b.D,
-                          ssb->d_bits, d_status, s, com)))
+                          ssb->d_bits, d_status, s, com, &job)))
       return st;
     const int ry0 = (int)(frame0 / nx), nr = (int)(n_frames / nx);
     const int64_t nrows = (int64_t)n_k * nr;
@@ -564,7 +565,7 @@ static int reconstruct(const int32_t* d_idx, const int64_t* d_off, int64_t frame
       return run_phase(L, b, *scan, b.T, 1, d_phase, d_T, s);
     }
     if ((st = launch_ysum_stored(ny, b.X, b.kc, b.kchi, b.cst, b.cmask, L.nmw, n_k, nx, L.groups, o,
-                                 chi_is_zero(o, d_theta), b.part, b.stats, s, chi)))
+                                 chi_is_zero(o, d_theta), b.part, b.wcnt, s, chi)))
       return st;
     return run_phase(L, b, *scan, b.part, L.groups, d_phase, d_T, s);
   }
@@ -572,7 +573,7 @@ static int reconstruct(const int32_t* d_idx, const int64_t* d_off, int64_t frame
     // split precision: the fused kernel transforms X -> G in place (its partial sums are not
     // used); the counters are reset before the per-Q normalised sum
     if ((st = launch_yreduce(ssb->precision, ny, b.X, b.kc, b.kchi, b.cst, b.cmask, L.nmw, n_k, nx, L.groups, o, 1,
-                             1, b.part, b.stats, s)))
+                             1, b.part, b.wcnt, s)))
       return st;
     if ((st = run_chi_table(b, d_theta, n_k, o, 1, s))) return st;
     if ((st = run_reduce_stored(L, b, ny, nx, o, 1, s))) return st;
@@ -591,8 +592,13 @@ static int reconstruct(const int32_t* d_idx, const int64_t* d_off, int64_t frame
     if ((st = run_reduce_stored(L, b, ny, nx, o, 1, s))) return st;
     return run_phase(L, b, *scan, b.T, 1, d_phase, d_T, s);
   }
+  // without aberrations the sum needs only the interval table and the mask, which ACCUMULATE's
+  // binning built (when it bins through its LDS table); otherwise the table kernel also tabulates
+  // chi(Kc) + theta
+  const int chi0 = chi_is_zero(o, d_theta);
+  const int sets_ready = chi0 && bin_builds_sets(*det, o.r2);
   if ((st = launch_yreduce(ssb->precision, ny, b.X, b.kc, b.kchi, b.cst, b.cmask, L.nmw, n_k, nx, L.groups, o,
-                           ssb->g_mode == STEM_G_STORE, chi_is_zero(o, d_theta), b.part, b.stats, s, chi)))
+                           ssb->g_mode == STEM_G_STORE, chi0, b.part, b.wcnt, s, chi, sets_ready)))
     return st;
   return run_phase(L, b, *scan, b.part, L.groups, d_phase, d_T, s);
 }

@@ -225,25 +225,6 @@ __global__ void __launch_bounds__(64 * XF::kXWaves) k_xstage(const DT* __restric
 // pass sums the groups in a fixed order.  With store_g the transformed columns are also written
 // back in place (X becomes G) for later refocusing.
 
-// Double-overlap sets of pixel K along column ix: iy in [a0, a1] but not in [b0, b1].
-struct ColSet {
-  int a0, a1, b0, b1;
-  __device__ __forceinline__ bool has(int iy) const { return iy >= a0 && iy <= a1 && !(iy >= b0 && iy <= b1); }
-  __device__ __forceinline__ bool empty() const { return a0 > a1; }
-};
-
-__device__ __forceinline__ ColSet col_set(double kx, double ky, int ix, int ny, const Optics& o) {
-  const double qx = (double)ix * o.sx;
-  ColSet cs;
-  disk_interval(kx, ky, qx, o.sy, o.r, o.r2, -1, ny, cs.a0, cs.a1);
-  if (cs.a0 > cs.a1) {
-    cs.b0 = 1;
-    cs.b1 = 0;
-    return cs;
-  }
-  disk_interval(kx, ky, qx, o.sy, o.r, o.r2, +1, ny, cs.b0, cs.b1);
-  return cs;
-}
 
 // The sets of one pixel for a half-spectrum column c (direct) and for -c (mirror) depend only on
 // the geometry; they are tabulated once per reconstruction (k_colsets), 16 bytes per (pixel,
@@ -257,6 +238,7 @@ __device__ __forceinline__ void load_colsets(const int4* __restrict__ cst, int64
 // CHI0: the aberration function and theta are identically zero, so every phase factor of Eq. 3
 // is exactly 1 and the sum adds G itself (conj G for mirrored frequencies): the same values the
 // general path produces for chi = 0, without evaluating them.
+
 template <typename XF, bool CHI0>
 __global__ void __launch_bounds__(kYThreads, 2) k_yreduce(float2* __restrict__ X, const double2* __restrict__ kc,
                                                        const double* __restrict__ kchi,
@@ -264,7 +246,7 @@ __global__ void __launch_bounds__(kYThreads, 2) k_yreduce(float2* __restrict__ X
                                                        const uint64_t* __restrict__ cmask, int nmw, int n_k, int nx,
                                                        int ngroups, Optics o, int store_g,
                                                        float2* __restrict__ part,
-                                                       unsigned long long* __restrict__ stats) {
+                                                       unsigned long long* __restrict__ wcnt) {
   constexpr int NY = XF::N;
   __shared__ float2 s_tw[1024];
   __shared__ float2 s_buf[XF::kMfma ? 1 : 4 * kXWaveStride];
@@ -281,7 +263,10 @@ __global__ void __launch_bounds__(kYThreads, 2) k_yreduce(float2* __restrict__ X
   __syncthreads();
   XF::fill(s_tab, s_tw, threadIdx.x, kYThreads);
   if (XF::kMfma) __syncthreads();
-  if (cs >= ncs) return;
+  if (cs >= ncs) {
+    if (lane == 0) wcnt[blockIdx.x * 4 + wave] = 0ull;
+    return;
+  }
   float2* buf = s_buf + wave * kXWaveStride;
   const int c0 = cs * B;
   const int kd_a = (int)((int64_t)n_k * g / ngroups), kd_b = (int)((int64_t)n_k * (g + 1) / ngroups);
@@ -512,7 +497,7 @@ __global__ void __launch_bounds__(kYThreads, 2) k_yreduce(float2* __restrict__ X
   }
   unsigned long long cc = cnt;
   for (int off = 32; off > 0; off >>= 1) cc += __shfl_xor(cc, off);
-  if (lane == 0) atomicAdd(stats, cc);
+  if (lane == 0) wcnt[blockIdx.x * 4 + wave] = cc;
 }
 
 // Fused column transform + adjoint of Eq. 3 (G recomputed, never stored).  Same work split as
@@ -679,7 +664,7 @@ int launch_xstage_p(int nx, const DT* D, int ny, int ry0, int nr, int64_t nrows,
 template <int PREC>
 int launch_yreduce_p(int ny, float2* X, const double2* kc, const double* kchi, const int4* cst,
                      const uint64_t* cmask, int nmw, int n_k, int nx, int ngroups, const Optics& o,
-                     int store_g, int chi0, float2* part, unsigned long long* stats, hipStream_t s) {
+                     int store_g, int chi0, float2* part, unsigned long long* wcnt, hipStream_t s) {
   const int B = 1024 / ny;
   const int ncs = (nx / 2 + 1 + B - 1) / B;
   const dim3 grid((unsigned)(((ncs + 3) / 4) * ngroups)), blk(kYThreads);
@@ -688,10 +673,10 @@ int launch_yreduce_p(int ny, float2* X, const double2* kc, const double* kchi, c
     using XF = typename XfSel<decltype(nc)::value, PREC>::type;
     if (chi0)
       hipLaunchKernelGGL((k_yreduce<XF, true>), grid, blk, 0, s, X, kc, kchi, cst, cmask, nmw, n_k, nx, ngroups, o,
-                         store_g, part, stats);
+                         store_g, part, wcnt);
     else
       hipLaunchKernelGGL((k_yreduce<XF, false>), grid, blk, 0, s, X, kc, kchi, cst, cmask, nmw, n_k, nx, ngroups, o,
-                         store_g, part, stats);
+                         store_g, part, wcnt);
   });
   if (st) return st;
   STEM_LAUNCH_CHECK();
