@@ -154,6 +154,30 @@ def test_ssb_normalized_parity(gpu):
     assert rel_l2(out["phi"], ref["phi"]) <= TOL
 
 
+@pytest.mark.parametrize("name", ["small", "mid", "rect", "aberr", "n512", "n1024", "wide"])
+def test_pair_count_matches_oracle(gpu, name):
+    """The state's first counter is the number of (pixel, Q) pairs in the double-overlap sets (the
+    oracle's per-Q pair counts summed), however the sum ran: fused (interval table from the binning,
+    or from the table kernel with aberrations or the global bin table), from a stored G (REFOCUS),
+    or normalised per Q."""
+    wl, idx, off = data(name)
+    d_idx, d_off = to_device(idx, off)
+    H, W = wl.det
+    ny, nx = wl.scan
+    kc, _ = oeer.bin_geometry(W, H, wl.bin, wl.r_bf)
+    _, npair = ossb.ssb_sum(np.zeros((len(kc), ny, nx)), kc, wl.step, wl.dk, wl.lam, wl.r_bf)
+    P = int(npair.sum())
+    st, out = gpu_ssb(d_idx, d_off, wl, c=wl.aberr, g_mode=stem.STEM_G_STORE)
+    s = st.stats()
+    assert out["status"] == 0
+    assert s[0] == P and s[1] >= 1 and s[2] == 0 and s[3] == 0
+    st.refocus(c=wl.aberr)
+    torch.cuda.synchronize()
+    assert st.stats()[0] == P
+    stn, outn = gpu_ssb(d_idx, d_off, wl, c=wl.aberr, normalize=1)
+    assert outn["status"] == 0 and stn.stats()[:2] == [P, 1]
+
+
 def test_refocus_matches_fresh_reconstruction(gpu):
     """Interactive refocus (Sec. IV): only Eq. 3 and the phase are recomputed from stored G."""
     wl, idx, off = data("aberr")
