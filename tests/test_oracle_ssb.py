@@ -120,6 +120,37 @@ def test_vectorised_sum_equals_nested_loops():
     assert np.max(np.abs(T - Tb)) < 1e-10 * np.abs(Tb).max()
 
 
+def test_normalised_sum_is_plain_sum_over_pair_count():
+    """The normalised form of Eq. 3 (T divided by the size of the double-overlap set) against the
+    nested-loop plain sum and a pair count by distances written out here: T_norm * n = T_plain
+    where n > 0, and T_norm = 0 where the set is empty (Q = 0 among them)."""
+    W, H, r_bf, kc, lut = _tiny_geometry()
+    rng = np.random.default_rng(5)
+    ny, nx, step, lam = 8, 12, 0.2, 0.0196875
+    dk = (0.025 / lam) / r_bf
+    D = rng.integers(0, 4, size=(len(kc), ny * nx))
+    G = ssb.scan_dft(ssb.cube(D, ny, nx))
+    c = (40.0, 10.0, -15.0, 200.0, -100.0, 150.0, 80.0, 5e3)
+    Tn, _ = ssb.ssb_sum(G, kc, step, dk, lam, r_bf, c, normalize=True)
+    Tb = ssb.ssb_sum_bruteforce(G, kc, step, dk, lam, r_bf, c)
+    fy = np.rint(np.fft.fftfreq(ny) * ny)
+    fx = np.rint(np.fft.fftfreq(nx) * nx)
+    sy, sx = 1.0 / (ny * step * dk), 1.0 / (nx * step * dk)
+    n = np.zeros((ny, nx), dtype=np.int64)
+    for my in range(ny):
+        for mx in range(nx):
+            qx, qy = fx[mx] * sx, fy[my] * sy
+            for kx, ky in kc:
+                d_minus = math.hypot(kx - qx, ky - qy)
+                d_plus = math.hypot(kx + qx, ky + qy)
+                assert abs(d_minus - r_bf) > 1e-9 and abs(d_plus - r_bf) > 1e-9  # no ties here
+                n[my, mx] += (math.hypot(kx, ky) < r_bf) and d_minus < r_bf and d_plus >= r_bf
+    assert n[0, 0] == 0 and (n > 0).sum() > ny * nx // 2 and (n == 0).sum() > 1
+    live = n > 0
+    assert np.max(np.abs(Tn[live] * n[live] - Tb[live])) < 1e-10 * np.abs(Tb).max()
+    assert np.all(Tn[~live] == 0)
+
+
 def test_double_overlap_set_properties():
     W, H, r_bf, kc, lut = _tiny_geometry()
     ny, nx, step, lam = 8, 8, 0.2, 0.0196875
