@@ -171,6 +171,25 @@ int com_dpc(const int32_t* d_idx, const int64_t* d_off, int64_t frame0, int64_t 
             const stem_dpc* dpc, double* d_com64, float* d_com32, int32_t* d_counts,
             float* d_phase, void* ws, size_t ws_bytes, int32_t* d_status, void* stream);
 
+/* Allocation-free variant of com_dpc, for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  Same arguments,
+ * computation and outputs as com_dpc without (ws, ws_bytes): the DPC integration's workspace is a
+ * library-owned device array of com_dpc_noalloc_max_workspace() bytes (16 MiB, enough for scans
+ * with com_dpc_workspace_bytes(scan) up to that size, e.g. 1024 x 1024).  Each GPU the library
+ * runs on holds its own copy of the array from the first call there until the process ends.
+ * Every call on one GPU shares that copy, so calls that overlap on one GPU (several streams or
+ * threads) race: the caller orders them.  Nothing is allocated; nothing needs clearing (every
+ * call writes the workspace before reading it).
+ * Errors: as com_dpc; STEM_EWORKSPACE when the scan needs more workspace than the maximum;
+ * STEM_EHIP if the array's address on the current device cannot be found. */
+int com_dpc_noalloc(const int32_t* d_idx, const int64_t* d_off, int64_t frame0, int64_t n_frames,
+                    const stem_det* det, const stem_scan* scan, const stem_optics* optics,
+                    const stem_dpc* dpc, double* d_com64, float* d_com32, int32_t* d_counts,
+                    float* d_phase, int32_t* d_status, void* stream);
+
+/* Bytes of the device array com_dpc_noalloc uses as its workspace. */
+size_t com_dpc_noalloc_max_workspace(void);
+
 /* ---------------------------------------------------------------------------------------- */
 /* Virtual detectors from events (Table 1: radial sum, sum of all frames; Sec. III)          */
 

@@ -65,6 +65,11 @@ _SIGS = {
                                ctypes.POINTER(Dpc), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                                ctypes.c_void_p]),
+    "com_dpc_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                       ctypes.POINTER(Det), ctypes.POINTER(Scan), ctypes.POINTER(Optics),
+                                       ctypes.POINTER(Dpc), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "com_dpc_noalloc_max_workspace": (ctypes.c_size_t, []),
     "ssb_num_pixels": (ctypes.c_int, [ctypes.POINTER(Det), ctypes.POINTER(Optics)]),
     "ssb_state_bytes": (ctypes.c_size_t, [ctypes.POINTER(Det), ctypes.POINTER(Scan), ctypes.POINTER(Optics),
                                           ctypes.POINTER(Ssb)]),

@@ -6,6 +6,8 @@
 // fft_wave.h.  Row-major outputs are stored straight from registers; transposed outputs
 // (element (r, m) -> out[m*stride + r]) are first staged in the waves' LDS buffers so that the
 // workgroup writes runs of W B consecutive rows per frequency.
+#include <mutex>
+
 #include "common.h"
 #include "fft_wave.h"
 #include "kernels.h"
@@ -424,10 +426,10 @@ extern "C" size_t com_dpc_workspace_bytes(const stem_scan* scan) {
   return 3 * align256((size_t)scan->ny * (scan->nx / 2 + 1) * sizeof(float2));
 }
 
-extern "C" int com_dpc(const int32_t* d_idx, const int64_t* d_off, int64_t frame0, int64_t n_frames,
-                       const stem_det* det, const stem_scan* scan, const stem_optics* optics,
-                       const stem_dpc* dpc, double* d_com64, float* d_com32, int32_t* d_counts,
-                       float* d_phase, void* ws, size_t ws_bytes, int32_t* d_status, void* stream_) {
+static int run_com_dpc(const int32_t* d_idx, const int64_t* d_off, int64_t frame0, int64_t n_frames,
+                       const stem_det* det, const stem_scan* scan, const stem_optics* optics, const stem_dpc* dpc,
+                       double* d_com64, float* d_com32, int32_t* d_counts, float* d_phase, void* ws,
+                       size_t ws_bytes, int32_t* d_status, void* stream_) {
   if (!d_idx || !d_off || !det || !scan) return STEM_EINVAL;
   if (det->W <= 0 || det->H <= 0 || (int64_t)det->W * det->H >= (1ll << 31)) return STEM_EINVAL;
   if (scan->ny <= 0 || scan->nx <= 0) return STEM_EINVAL;
@@ -450,4 +452,59 @@ extern "C" int com_dpc(const int32_t* d_idx, const int64_t* d_off, int64_t frame
   float2* Q = (float2*)((char*)ws + 2 * half);
   const float g = (float)(2.0 * 3.14159265358979323846 * optics->dk);
   return launch_dpc(d_com64, d_com64 ? nullptr : d_com32, F, ny, nx, g, scan->step, *dpc, Ax, Ay, Q, d_phase, stream);
+}
+
+extern "C" int com_dpc(const int32_t* d_idx, const int64_t* d_off, int64_t frame0, int64_t n_frames,
+                       const stem_det* det, const stem_scan* scan, const stem_optics* optics,
+                       const stem_dpc* dpc, double* d_com64, float* d_com32, int32_t* d_counts,
+                       float* d_phase, void* ws, size_t ws_bytes, int32_t* d_status, void* stream_) {
+  return run_com_dpc(d_idx, d_off, frame0, n_frames, det, scan, optics, dpc, d_com64, d_com32, d_counts, d_phase, ws,
+                     ws_bytes, d_status, stream_);
+}
+
+// ---------------------------------------------------------------------------------------------
+// com_dpc without a caller workspace: the DPC integration's half-spectrum planes live in a
+// file-scope device array (one copy per GPU, held until the process ends).  In host code the
+// array's name is not a device address: its address on each device is looked up once, with that
+// device current, and only that pointer is passed to kernels.
+
+namespace {
+
+constexpr size_t kNoAllocScratchBytes = (size_t)16 << 20;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// this device's copy of `scratch`, looked up on its first use (nullptr if the lookup fails)
+void* scratch_on_current_device() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+extern "C" size_t com_dpc_noalloc_max_workspace(void) { return kNoAllocScratchBytes; }
+
+extern "C" int com_dpc_noalloc(const int32_t* d_idx, const int64_t* d_off, int64_t frame0, int64_t n_frames,
+                               const stem_det* det, const stem_scan* scan, const stem_optics* optics,
+                               const stem_dpc* dpc, double* d_com64, float* d_com32, int32_t* d_counts,
+                               float* d_phase, int32_t* d_status, void* stream_) {
+  void* ws = nullptr;
+  if (d_phase) {
+    if (!scan) return STEM_EINVAL;
+    if (com_dpc_workspace_bytes(scan) > kNoAllocScratchBytes) return STEM_EWORKSPACE;
+    ws = scratch_on_current_device();
+    if (!ws) return STEM_EHIP;
+  }
+  return run_com_dpc(d_idx, d_off, frame0, n_frames, det, scan, optics, dpc, d_com64, d_com32, d_counts, d_phase, ws,
+                     d_phase ? kNoAllocScratchBytes : 0, d_status, stream_);
 }
