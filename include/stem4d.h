@@ -100,17 +100,23 @@ enum { STEM_FFT_FP32 = 0, STEM_DFT_BF16_SPLIT = 1, STEM_DFT_FP16_SPLIT = 2 };
 enum { STEM_G_RECOMPUTE = 0, STEM_G_STORE = 1 };
 
 /* Sideband path options.
- *  precision: STEM_FFT_FP32 (FP32 FFT) or one of the split-precision MFMA scan DFTs.
- *  normalize: 0 = plain Eq. 3 sum; 1 = divide T(Q) by the number of pixels in the set.
- *  g_mode:    STEM_G_STORE keeps G(K,Q) in the state buffer (needed for REFOCUS);
- *             STEM_G_RECOMPUTE keeps only the row-transformed cube and recomputes G.
- *  d_bits:    8 or 16, element width of the binned count cube (a larger count sets
- *             STEM_EOVERFLOW; it is never clamped silently). */
+ *  precision:   STEM_FFT_FP32 (FP32 FFT) or one of the split-precision MFMA scan DFTs.
+ *  normalize:   0 = plain Eq. 3 sum; 1 = divide T(Q) by the number of pixels in the set.
+ *  g_mode:      STEM_G_STORE keeps the row-transformed cube of every pixel (written during
+ *               ACCUMULATE) and, from FINALIZE on, G(K,Q) on the double-overlap pairs only (the
+ *               values Eq. 3 uses): REFOCUS and the adjoint read those.  STEM_G_RECOMPUTE keeps
+ *               only the binned counts: every sum and the adjoint transform a chunk of pixels at a
+ *               time in a bounded scratch, so the state is a fraction of the STORE one.
+ *  d_bits:      8 or 16, element width of the binned count cube (a larger count sets
+ *               STEM_EOVERFLOW; it is never clamped silently).
+ *  scratch_mib: STEM_G_RECOMPUTE: at most this many MiB of row-transformed columns are held at
+ *               once (0: 64 MiB; at least one pixel's); ignored by STEM_G_STORE. */
 typedef struct {
   int32_t precision;
   int32_t normalize;
   int32_t g_mode;
   int32_t d_bits;
+  int32_t scratch_mib;
 } stem_ssb;
 
 /* ---------------------------------------------------------------------------------------- */
@@ -256,8 +262,9 @@ size_t ssb_state_bytes(const stem_det* det, const stem_scan* scan, const stem_op
  *   and transforms them along x into the state.  d_phase, d_T unused.
  * mode FINALIZE: needs every row accumulated; writes d_phase[F] (row-major, may be NULL)
  *   and d_T[2F] (interleaved complex64 row-major [my][mx], may be NULL).
- * mode REFOCUS: needs a FINALIZE with g_mode = STEM_G_STORE on this state; recomputes only
- *   the sum and the phase for the given optics.c and theta.
+ * mode REFOCUS: needs a FINALIZE on this state; the sum and the phase again for the given
+ *   optics.c and theta: from the stored double-overlap values of G (STEM_G_STORE, the paper's
+ *   interactive mode), or with G recomputed from the binned counts (STEM_G_RECOMPUTE).
  * mode ONESHOT: ACCUMULATE of all F frames then FINALIZE.
  * d_theta[n_K] (FP32, may be NULL = 0) is the per-pixel probe phase.  det, scan, optics
  * r_bf/dk/lam and ssb must stay the same across the calls sharing a state.
@@ -284,18 +291,35 @@ int ssb_reconstruct_com(const int32_t* d_idx, const int64_t* d_off, int64_t fram
                         float* d_com32, int32_t* d_counts, int32_t* d_status, void* stream);
 
 /* Regions of the state buffer a caller may read after the calls that fill them.
- *  STEM_REGION_D  binned counts D[kd][ry][rx], uint8 or uint16 (d_bits), after ACCUMULATE.
- *  STEM_REGION_G  complex64 [kd][mx][my], mx in [0, Nx/2], my in [0, Ny): after ACCUMULATE
- *                 the row-transformed cube; after FINALIZE with g_mode STORE the scan
- *                 transform G(kd, Q) (the other half of Q is its conjugate mirror).
- *  STEM_REGION_T  complex64 T(Q) of the last sum, column-major [mx][my].
- *  STEM_REGION_KC double2 Kc[kd] (x, y) bin centres in unbinned pixels, after ACCUMULATE.
- *  STEM_REGION_STATS uint64 [4]: [0] = number of (pixel, Q) pairs in the double-overlap
- *                 sets of the last sum (FINALIZE / REFOCUS); [1] = number of partial sums of T
- *                 it combined (pixel groups of the fused column transform, 1 otherwise);
- *                 [2..3] reserved (0).
+ *  STEM_REGION_D     binned counts D[kd][ry][rx], uint8 or uint16 (d_bits), after ACCUMULATE.
+ *  STEM_REGION_X     complex64 [kd][mx][ry], mx in [0, Nx/2]: STEM_G_STORE, after ACCUMULATE, the
+ *                    row transform of every pixel (the DFT along rx of D); STEM_G_RECOMPUTE, the
+ *                    scratch of the last chunk of pixels (contents unspecified).
+ *  STEM_REGION_T     complex64 T(Q) of the last sum, column-major [mx][my].
+ *  STEM_REGION_KC    double2 Kc[kd] (x, y) bin centres in unbinned pixels, after ACCUMULATE.
+ *  STEM_REGION_STATS uint64 [4] about the last sum (FINALIZE / REFOCUS): [0] number of (pixel, Q)
+ *                    pairs in the double-overlap sets; [1] number of partial sums of T combined
+ *                    (pixel groups of the fused column kernels); [2] bytes of row-transformed
+ *                    columns or stored G values the sum kernels read; [3] pixel chunks.
+ *  STEM_REGION_PG    STEM_G_STORE, after FINALIZE: G on the double-overlap pairs, complex64.  For
+ *                    pixel kd and scan-frequency column mx in [0, Nx) the values G(kd, (my, mx)),
+ *                    my over the set in ascending signed frequency, start at entry
+ *                    POFF[kd*Nx + mx]; the region holds an upper bound of entries.
+ *  STEM_REGION_POFF  STEM_G_STORE, after FINALIZE: int64 [n_K*Nx + 1] those offsets, the last
+ *                    entry the number of pairs.
+ *  STEM_REGION_NPAIR int32 [F] number of pixels in the double-overlap set of each Q, column-major
+ *                    [mx][my], after a FINALIZE with normalize = 1.
  * Writes the byte offset and size of the region; STEM_EINVAL for bad arguments. */
-enum { STEM_REGION_D = 0, STEM_REGION_G = 1, STEM_REGION_T = 2, STEM_REGION_KC = 3, STEM_REGION_STATS = 4 };
+enum {
+  STEM_REGION_D = 0,
+  STEM_REGION_X = 1,
+  STEM_REGION_T = 2,
+  STEM_REGION_KC = 3,
+  STEM_REGION_STATS = 4,
+  STEM_REGION_PG = 5,
+  STEM_REGION_POFF = 6,
+  STEM_REGION_NPAIR = 7
+};
 int ssb_state_region(const stem_det* det, const stem_scan* scan, const stem_optics* optics,
                      const stem_ssb* ssb, int region, size_t* offset, size_t* bytes);
 
@@ -308,9 +332,9 @@ int ssb_state_region(const stem_det* det, const stem_scan* scan, const stem_opti
  * detector (nbx = W/bin, nby = H/bin):
  *   d_img[(j*nby + by)*nbx + bx] = G(kd, Q_j) for the kept bin kd at (bx, by), 0 for a dropped bin
  * as complex64 (interleaved re, im).  The state must hold a finished reconstruction with these
- * arguments (FINALIZE, ONESHOT or REFOCUS last): G is read from it (g_mode STORE) or computed as
- * the DFT along ry of the row-transformed cube with FP64 accumulation (g_mode RECOMPUTE).  For
- * mx > Nx/2 the value is conj G(kd, -Q) from the stored half spectrum (D is real).
+ * arguments (ACCUMULATE of every row at least): G is computed with FP64 accumulation as the DFT
+ * along ry of the row-transformed cube (g_mode STORE; for mx > Nx/2 as conj G(kd, -Q), D being
+ * real) or as the 2D DFT of the binned counts (g_mode RECOMPUTE, scans up to 1024 x 1024).
  * Errors: STEM_EINVAL (NULL pointers, n_q outside [1, STEM_MAX_PANEL], an index outside its
  * range), STEM_EWORKSPACE. */
 int ssb_g_panel(const stem_det* det, const stem_scan* scan, const stem_optics* optics, const stem_ssb* ssb,
@@ -325,8 +349,9 @@ int ssb_g_panel(const stem_det* det, const stem_scan* scan, const stem_optics* o
  *   Tbar = (i/N_R) FFT2(gbar),  w = Re(conj(Tbar(Q)) i G(kd,Q) exp(i psi)) per pair,
  *   d_dLdc[j] = sum over pairs w (B_j(Kc-Q) - B_j(Kc)),  B_j = d chi / d c_j  (FP64, [8]),
  *   d_dLdtheta[kd] = -sum over Q of w                                  (FP32, [n_K], may be NULL).
- * G is read from the state (g_mode STORE) or recomputed column by column from the
- * row-transformed cube (g_mode RECOMPUTE).  normalize must be 0.
+ * G is read from the stored double-overlap values (g_mode STORE) or recomputed chunk by chunk
+ * from the binned counts (g_mode RECOMPUTE).  normalize must be 0.  The state's counters
+ * (STEM_REGION_STATS) keep describing the last sum.
  * Errors: STEM_EINVAL, STEM_EWORKSPACE, STEM_ESTATE. */
 int ssb_backward(const float* d_dLdphi, const stem_det* det, const stem_scan* scan,
                  const stem_optics* optics, const stem_ssb* ssb, const float* d_theta,

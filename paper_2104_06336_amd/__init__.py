@@ -15,7 +15,8 @@ import torch
 from ._abi import (Det, Dpc, Optics, Scan, Ssb, StemError, lib, LIB_PATH, STEM_FFT_FP32,
                    STEM_DFT_BF16_SPLIT, STEM_DFT_FP16_SPLIT, STEM_G_RECOMPUTE, STEM_G_STORE,
                    STEM_SSB_ACCUMULATE, STEM_SSB_FINALIZE, STEM_SSB_REFOCUS, STEM_SSB_ONESHOT,
-                   STEM_REGION_D, STEM_REGION_G, STEM_REGION_T, STEM_REGION_KC, STEM_REGION_STATS, STATUS_BITS, strerror, trace_enable,
+                   STEM_REGION_D, STEM_REGION_X, STEM_REGION_T, STEM_REGION_KC, STEM_REGION_STATS, STEM_REGION_PG,
+                   STEM_REGION_POFF, STEM_REGION_NPAIR, STATUS_BITS, strerror, trace_enable,
                    trace_records)
 
 __all__ = [
@@ -24,8 +25,9 @@ __all__ = [
     "ssb_num_pixels", "ssb_state_bytes", "status_tensor", "check_status", "strerror",
     "STEM_FFT_FP32", "STEM_DFT_BF16_SPLIT", "STEM_DFT_FP16_SPLIT", "STEM_G_RECOMPUTE",
     "STEM_G_STORE", "STEM_SSB_ACCUMULATE", "STEM_SSB_FINALIZE", "STEM_SSB_REFOCUS",
-    "STEM_SSB_ONESHOT", "SsbState", "SSBPhase", "ssb_state_region", "STEM_REGION_D", "STEM_REGION_G",
-    "STEM_REGION_T", "STEM_REGION_KC", "STEM_REGION_STATS", "trace_enable", "trace_records",
+    "STEM_SSB_ONESHOT", "SsbState", "SSBPhase", "ssb_state_region", "STEM_REGION_D", "STEM_REGION_X",
+    "STEM_REGION_T", "STEM_REGION_KC", "STEM_REGION_STATS", "STEM_REGION_PG", "STEM_REGION_POFF", "STEM_REGION_NPAIR",
+    "com_dpc_noalloc", "trace_enable", "trace_records",
     "virtual_annular", "sum_frames", "eer_decode_rle", "ssb_g_panel", "ssb_reconstruct_com",
 ]
 
@@ -168,6 +170,25 @@ def com_dpc(d_idx, d_off, frame0: int, n_frames: int, det: Det, scan: Scan, opti
                        ctypes.byref(dpc) if dpc is not None else None, _p(com64), _p(com32), _p(counts),
                        _p(phase), _p(ws), ws_bytes, _p(d_status), _stream(stream))
     _check(rc, "com_dpc")
+
+
+def com_dpc_noalloc(d_idx, d_off, frame0: int, n_frames: int, det: Det, scan: Scan, optics: Optics | None = None,
+                    dpc: Dpc | None = None, com64=None, com32=None, counts=None, phase=None, d_status=None,
+                    stream=None):
+    """com_dpc without a caller workspace (the library's per-device array; calls on one GPU must
+    not overlap)."""
+    F = scan.ny * scan.nx
+    _dev(d_idx, torch.int32, "d_idx")
+    _dev(d_off, torch.int64, "d_off")
+    _dev(com64, torch.float64, "com64", 2 * F)
+    _dev(com32, torch.float32, "com32", 2 * F)
+    _dev(counts, torch.int32, "counts", F)
+    _dev(phase, torch.float32, "phase", F)
+    rc = lib().com_dpc_noalloc(_p(d_idx), _p(d_off), frame0, n_frames, ctypes.byref(det), ctypes.byref(scan),
+                               ctypes.byref(optics) if optics is not None else None,
+                               ctypes.byref(dpc) if dpc is not None else None, _p(com64), _p(com32), _p(counts),
+                               _p(phase), _p(d_status), _stream(stream))
+    _check(rc, "com_dpc_noalloc")
 
 
 # ----------------------------------------------------------------------------------------------

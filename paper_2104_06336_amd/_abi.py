@@ -10,7 +10,8 @@ STEM_FFT_FP32, STEM_DFT_BF16_SPLIT, STEM_DFT_FP16_SPLIT = 0, 1, 2
 STEM_G_RECOMPUTE, STEM_G_STORE = 0, 1
 STEM_SSB_ACCUMULATE, STEM_SSB_FINALIZE, STEM_SSB_REFOCUS, STEM_SSB_ONESHOT = 0, 1, 2, 3
 
-STEM_REGION_D, STEM_REGION_G, STEM_REGION_T, STEM_REGION_KC, STEM_REGION_STATS = 0, 1, 2, 3, 4
+STEM_REGION_D, STEM_REGION_X, STEM_REGION_T, STEM_REGION_KC, STEM_REGION_STATS = 0, 1, 2, 3, 4
+STEM_REGION_PG, STEM_REGION_POFF, STEM_REGION_NPAIR = 5, 6, 7
 
 STATUS_BITS = {1: "EINVAL", 2: "ERANGE", 4: "EOFFSETS", 8: "EOVERFLOW", 16: "EWORKSPACE", 32: "EHIP",
                64: "ESTATE"}
@@ -48,7 +49,7 @@ class Dpc(ctypes.Structure):
 
 class Ssb(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("normalize", ctypes.c_int32), ("g_mode", ctypes.c_int32),
-                ("d_bits", ctypes.c_int32)]
+                ("d_bits", ctypes.c_int32), ("scratch_mib", ctypes.c_int32)]
 
 
 _LIB = None

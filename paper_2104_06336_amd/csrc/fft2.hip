@@ -30,22 +30,40 @@ __global__ void __launch_bounds__(64 * W) k_row_fft(RowFftArgs a, int in_mode, i
   if constexpr (SUM) {
     if (a.stats && blockIdx.x == 0) {
       // every thread of the first workgroup sums a strided share, four loads in flight
-      __shared__ unsigned long long s_red[W];
-      unsigned long long c0 = 0, c1 = 0, c2 = 0, c3 = 0;
-      for (int64_t i = threadIdx.x; i < a.nwcnt; i += 4 * kRowThreads) {
-        c0 += a.wcnt[i];
-        if (i + kRowThreads < a.nwcnt) c1 += a.wcnt[i + kRowThreads];
-        if (i + 2 * kRowThreads < a.nwcnt) c2 += a.wcnt[i + 2 * kRowThreads];
-        if (i + 3 * kRowThreads < a.nwcnt) c3 += a.wcnt[i + 3 * kRowThreads];
+      // per wave: pair count below bit 40, 8-byte loads above
+      __shared__ unsigned long long s_red[2][W];
+      constexpr unsigned long long kLow = (1ull << 40) - 1;
+      unsigned long long c0 = 0, c1 = 0, l0 = 0, l1 = 0;
+      for (int64_t i = threadIdx.x; i < a.nwcnt; i += 2 * kRowThreads) {
+        const unsigned long long u = a.wcnt[i];
+        c0 += u & kLow;
+        l0 += u >> 40;
+        if (i + kRowThreads < a.nwcnt) {
+          const unsigned long long v = a.wcnt[i + kRowThreads];
+          c1 += v & kLow;
+          l1 += v >> 40;
+        }
       }
-      unsigned long long c = (c0 + c1) + (c2 + c3);
-      for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
-      if (lane == 0) s_red[wave] = c;
+      unsigned long long c = c0 + c1, l = l0 + l1;
+      for (int off = 32; off > 0; off >>= 1) {
+        c += __shfl_xor(c, off);
+        l += __shfl_xor(l, off);
+      }
+      if (lane == 0) {
+        s_red[0][wave] = c;
+        s_red[1][wave] = l;
+      }
       __syncthreads();
       if (threadIdx.x < 4) {
-        unsigned long long t = 0;
-        for (int w = 0; w < W; ++w) t += s_red[w];
-        a.stats[threadIdx.x] = threadIdx.x == 0 ? t : threadIdx.x == 1 ? (unsigned long long)a.stats_groups : 0ull;
+        unsigned long long t = 0, u = 0;
+        for (int w = 0; w < W; ++w) {
+          t += s_red[0][w];
+          u += s_red[1][w];
+        }
+        a.stats[threadIdx.x] = threadIdx.x == 0   ? t
+                               : threadIdx.x == 1 ? (unsigned long long)a.stats_groups
+                               : threadIdx.x == 2 ? 8ull * u
+                                                  : (unsigned long long)a.stats_chunks;
       }
     }
   }
@@ -92,6 +110,10 @@ __global__ void __launch_bounds__(64 * W) k_row_fft(RowFftArgs a, int in_mode, i
         int b, n;
         fft_in_index<N>(lane, i, b, n);
         const int64_t r = r0 + b;
+        if (a.norm_cnt && r < a.nrows) {
+          const int32_t c = a.norm_cnt[r * N + n];
+          v[i] = c > 0 ? make_float2(v[i].x / (float)c, v[i].y / (float)c) : make_float2(0.f, 0.f);
+        }
         if (a.sum_out && r < a.nrows) a.sum_out[r * N + n] = v[i];
         if (INV) v[i] = cconj(v[i]);
       }

@@ -55,12 +55,17 @@ struct RowFftArgs {
   int64_t out_stride;
   float2 osc;              // complex factor applied to every output value
   const char* tag;         // name under which the launch is traced
-  // IN_C64_SUM: if stats is set, workgroup 0 also writes stats[0] = the sum of wcnt[0, nwcnt),
-  // stats[1] = stats_groups, stats[2..3] = 0
+  // IN_C64_SUM: if norm_cnt is set, every summed element (r, n) is divided by norm_cnt[r*n + n]
+  // (0 where that count is 0)
+  const int32_t* norm_cnt;
+  // IN_C64_SUM: if stats is set, workgroup 0 also writes stats[0] = the sum of the pair counts
+  // (low 40 bits of wcnt[0, nwcnt)), stats[1] = stats_groups, stats[2] = 8 x the sum of the loads
+  // (wcnt >> 40), stats[3] = stats_chunks
   const unsigned long long* wcnt;
   int64_t nwcnt;
   unsigned long long* stats;
   int32_t stats_groups;
+  int32_t stats_chunks;
 };
 
 int launch_row_fft(int n, bool inverse, RowIn in, RowOut out, const RowFftArgs& a, hipStream_t stream);

@@ -1,13 +1,18 @@
 // Single-sideband (SSB) ptychography from linear-index events (Sec. IV) and its adjoint.
 //
 // Pipeline (state buffer owned by the caller):
-//   k_geometry     kept binned pixels (rows of the bright-field disk) and their centres Kc
-//   k_bin          events -> D[kd][ry][rx] (uint8/uint16 counts)                    (Table 1)
+//   k_bin          events -> D[kd][ry][rx] (uint8/uint16 counts), kept-set geometry     (Table 1)
 //   k_xstage       real row FFT along rx, output transposed X[kd][mx][ry], mx in [0, Nx/2]
-//   y-stage        FFT along ry of every (kd, mx) column, in place: G[kd][mx][my]   (Eq. 2)
-//   k_reduce       Eq. 3 over the double-overlap set for every Q -> T[mx][my]
+//   k_yreduce      FFT along ry of every (kd, mx) column in registers (G, Eq. 2) fused with
+//                  Eq. 3 over the double-overlap set -> partial sums of T per pixel group
 //   phase          two inverse row FFT passes -> phi = Im IFFT2(T)
 // The other half of the Q plane (mx > Nx/2) uses G(K, Q) = conj G(K, -Q) of the real input.
+//
+// G modes.  STEM_G_STORE keeps X for every pixel (written during ACCUMULATE) and, at FINALIZE,
+// the double-overlap values of G (the pruned array, 8 bytes per pair): REFOCUS and the adjoint
+// read only those.  STEM_G_RECOMPUTE keeps D only; every sum (and the adjoint) re-runs the row
+// transform for a chunk of pixels at a time into a bounded scratch and fuses the column
+// transform and the sum on it.
 #include "common.h"
 #include "fft_wave.h"
 #include "ssb_fused.h"
@@ -18,16 +23,20 @@
 namespace stem {
 
 constexpr int kMaxPixels = 4096;
+constexpr int kDefaultScratchMib = 64;  // row-transformed columns held at once in STEM_G_RECOMPUTE
 
 struct SsbLayout {
   int n_k, nby, nh;
   int64_t F;
-  size_t rows, kc, kchi, cst, cmask, lut, stats, D, X, T, A, Tb, pdc, pdth, part, wcnt, total;
+  bool store;     // STEM_G_STORE
+  int xpix;       // pixels whose row-transformed columns the X region holds (n_k, or one chunk)
+  int nchunks;    // pixel chunks of a sum
+  int64_t pcap;   // entries of the pruned G array (0 without STEM_G_STORE)
+  size_t rows, kc, kchi, cst, cmask, lut, stats, npq, D, X, poff, pg, T, A, Tb, pdc, pdth, part, wcnt, total;
   int nmw;      // 64-bit words per column set of the active-pixel mask
-  int groups;  // pixel groups of the fused column transform + sum
-  int ncs;     // column sets (B = 1024/Ny half-spectrum columns each)
-  int64_t nwy; // waves of the fused kernels
-  int64_t nblk;  // workgroups of the per-Q kernels
+  int groups;   // pixel groups of the fused column kernels (the same for every chunk)
+  int ncs;      // column sets (B = 1024/Ny half-spectrum columns each)
+  int64_t nwy;  // waves of the fused kernels
 };
 
 static int yreduce_groups(int ny, int nx, int n_k);
@@ -55,33 +64,68 @@ static bool optics_ok(const stem_optics* o) {
   return true;
 }
 
-static size_t make_layout(const stem_det& det, const stem_scan& scan, const stem_ssb& ssb, int n_k,
-                          SsbLayout* L) {
+// Upper bound of the double-overlap values of one pixel: the scan frequencies Q = (ix sx, iy sy)
+// with |K - Q| < r.  The lattice cells around those points are disjoint and lie inside the disk of
+// radius r + d (d the cell's half diagonal), so they number at most pi (r + d)^2 / (sx sy).
+static int64_t pruned_bound(const stem_scan& scan, const stem_optics& op, int n_k) {
+  const double sx = 1.0 / (((double)scan.nx * scan.step) * op.dk);
+  const double sy = 1.0 / (((double)scan.ny * scan.step) * op.dk);
+  const double d = 0.5 * __builtin_sqrt(sx * sx + sy * sy);
+  const double r = op.r_bf * (1.0 + 1e-9) + d;
+  const double F = (double)scan.ny * scan.nx;
+  double per = __builtin_floor(3.14159265358979323846 * r * r / (sx * sy)) + 1.0;
+  if (per > F) per = F;
+  return (int64_t)per * n_k;
+}
+
+static size_t make_layout(const stem_det& det, const stem_scan& scan, const stem_optics& op, const stem_ssb& ssb,
+                          int n_k, SsbLayout* L) {
   L->n_k = n_k;
   L->nby = det.H / det.bin;
   L->nh = scan.nx / 2 + 1;
   L->F = (int64_t)scan.ny * scan.nx;
-  L->nblk = (L->F + 255) / 256;
+  L->store = ssb.g_mode == STEM_G_STORE;
+  const size_t per_pixel = (size_t)L->nh * scan.ny * sizeof(float2);
+  if (L->store) {
+    L->xpix = n_k;
+    L->nchunks = 1;
+    L->pcap = pruned_bound(scan, op, n_k);
+  } else {
+    const size_t cap = (size_t)(ssb.scratch_mib > 0 ? ssb.scratch_mib : kDefaultScratchMib) << 20;
+    int nc = (int)(cap / per_pixel);
+    nc = nc < 1 ? 1 : nc > n_k ? n_k : nc;
+    L->nchunks = (n_k + nc - 1) / nc;
+    L->xpix = (n_k + L->nchunks - 1) / L->nchunks;  // balanced chunks of xpix or xpix - 1 pixels
+    L->pcap = 0;
+  }
   size_t o = 0;
   L->rows = o;  o = align256(o + sizeof(RowRun) * L->nby);
   L->kc = o;    o = align256(o + sizeof(double2) * n_k);
   L->kchi = o;  o = align256(o + sizeof(double) * n_k);
   L->cst = o;   o = align256(o + sizeof(int4) * n_k * L->nh);
   L->nmw = (n_k + 63) / 64;
-  L->cmask = o; o = align256(o + sizeof(uint64_t) * (size_t)L->nmw * ((L->nh + 1024 / scan.ny - 1) / (1024 / scan.ny)));
+  {
+    const int B = 1024 / scan.ny;
+    L->ncs = (L->nh + B - 1) / B;
+  }
+  L->cmask = o; o = align256(o + sizeof(uint64_t) * (size_t)L->nmw * L->ncs);
   L->lut = o;   o = align256(o + sizeof(int16_t) * (size_t)det.W * det.H);
   L->stats = o; o = align256(o + sizeof(unsigned long long) * 4);
+  L->npq = o;   o = align256(o + sizeof(int32_t) * (size_t)L->F);
   L->D = o;     o = align256(o + (size_t)n_k * L->F * (ssb.d_bits / 8));
-  L->X = o;     o = align256(o + (size_t)n_k * L->nh * scan.ny * sizeof(float2));
+  L->X = o;     o = align256(o + (size_t)L->xpix * per_pixel);
+  L->poff = o;  o = align256(o + (L->store ? sizeof(int64_t) * ((size_t)n_k * scan.nx + 1) : 0));
+  L->pg = o;    o = align256(o + sizeof(float2) * (size_t)L->pcap);
   L->T = o;     o = align256(o + (size_t)L->F * sizeof(float2));
   L->A = o;     o = align256(o + (size_t)L->F * sizeof(float2));
   L->Tb = o;    o = align256(o + (size_t)L->F * sizeof(float2));
-  L->groups = yreduce_groups(scan.ny, scan.nx, n_k);
-  {
-    const int B = 1024 / scan.ny;
-    L->ncs = (L->nh + B - 1) / B;                          // column sets of the fused kernels
-    L->nwy = (int64_t)((L->ncs + 3) / 4) * 4 * L->groups;  // their waves
-  }
+  // pixel groups: the same for every chunk (the partial sums of a later chunk add to the same
+  // waves' partials), so at most the smallest chunk's pixel count
+  int g = yreduce_groups(scan.ny, scan.nx, n_k);
+  const int smallest = n_k / L->nchunks;
+  if (g > smallest) g = smallest;
+  L->groups = g < 1 ? 1 : g;
+  L->nwy = (int64_t)((L->ncs + 3) / 4) * 4 * L->groups;
   L->pdc = o;   o = align256(o + (size_t)L->nwy * 8 * sizeof(double));
   L->pdth = o;  o = align256(o + (size_t)L->ncs * n_k * sizeof(float));
   L->part = o;  o = align256(o + (size_t)L->groups * L->F * sizeof(float2));
@@ -107,16 +151,13 @@ static int launch_xstage_t(int prec, int nx, const DT* D, int ny, int ry0, int n
 // active-pixel mask: bit j of word (cs, w) is set when pixel 64 w + j has a non-empty set in some
 // column of column set cs (B = 1024/Ny consecutive half-spectrum columns).  One wave per mask
 // word: lane j takes pixel 64 w + j over the columns of the set, a ballot packs the 64 answers.
-// Workgroups past the mask's also tabulate chi(Kc) + theta per pixel and reset the counters of
-// the sum that follows (the work of k_chi_table), when kchi is given.
+// Workgroups past the mask's also tabulate chi(Kc) + theta per pixel when kchi is given.
 __global__ void __launch_bounds__(256) k_colsets(const double2* __restrict__ kc, int n_k, int nx, int ny, Optics o,
                                                  int B, int ncs, int nmw, int4* __restrict__ cst,
                                                  uint64_t* __restrict__ mask, int mask_blocks,
-                                                 const float* __restrict__ theta, double* __restrict__ kchi,
-                                                 unsigned long long* __restrict__ stats, int groups) {
+                                                 const float* __restrict__ theta, double* __restrict__ kchi) {
   if ((int)blockIdx.x >= mask_blocks) {
     const int kd = (blockIdx.x - mask_blocks) * blockDim.x + threadIdx.x;
-    if (kd < 4) stats[kd] = kd == 1 ? (unsigned long long)groups : 0ull;
     if (kd < n_k) {
       const double2 k = kc[kd];
       kchi[kd] = chi_poly(k.x, k.y, o) + (theta ? (double)theta[kd] : 0.0);
@@ -130,23 +171,18 @@ __global__ void __launch_bounds__(256) k_colsets(const double2* __restrict__ kc,
   sets_word(j, word, lane, kd < n_k ? kc[kd] : make_double2(0.0, 0.0));
 }
 
-// chi(Kc) + theta and the counter reset, done by the interval-table kernel when kchi is given
-struct ChiArgs {
-  const float* theta;
-  double* kchi;
-  unsigned long long* stats;
-  int groups;
-};
-
-static void launch_colsets(const double2* kc, int n_k, int nx, int ny, const Optics& o, int4* cst, uint64_t* cmask,
-                           int nmw, hipStream_t s, const ChiArgs& chi = ChiArgs{}) {
+// the interval table and mask, and chi(Kc) + theta when kchi is given
+static int launch_colsets(const double2* kc, int n_k, int nx, int ny, const Optics& o, int4* cst, uint64_t* cmask,
+                          int nmw, hipStream_t s, const float* theta, double* kchi) {
   STEM_TRACE("ssb_colsets", s);
   const int B = 1024 / ny, ncs = (nx / 2 + 1 + B - 1) / B;
   const int64_t words = (int64_t)ncs * nmw;
   const int mask_blocks = (int)((words + 3) / 4);
-  const int chi_blocks = chi.kchi ? (n_k + 255) / 256 : 0;
-  hipLaunchKernelGGL(k_colsets, dim3((unsigned)(mask_blocks + chi_blocks)), dim3(256), 0, s, kc, n_k, nx, ny, o, B, ncs,
-                     nmw, cst, cmask, mask_blocks, chi.theta, chi.kchi, chi.stats, chi.groups);
+  const int chi_blocks = kchi ? (n_k + 255) / 256 : 0;
+  hipLaunchKernelGGL(k_colsets, dim3((unsigned)(mask_blocks + chi_blocks)), dim3(256), 0, s, kc, n_k, nx, ny, o, B,
+                     ncs, nmw, cst, cmask, mask_blocks, theta, kchi);
+  STEM_LAUNCH_CHECK();
+  return STEM_OK;
 }
 
 // chi identically zero (every monomial coefficient 0) and no per-pixel theta: the phase factors of
@@ -156,69 +192,22 @@ static int chi_is_zero(const Optics& o, const float* theta) {
          o.p03 == 0.0 && o.p4 == 0.0;
 }
 
-// the interval table and the active-pixel mask, then the fused column sum
-// the interval table and the active-pixel mask (unless the x-stage built them: sets_ready), then
-// the fused column sum; wcnt receives its pair count per wave
-static int launch_yreduce(int prec, int ny, float2* X, const double2* kc, const double* kchi, int4* cst,
-                          uint64_t* cmask, int nmw, int n_k, int nx, int ngroups, const Optics& o, int store_g,
-                          int chi0, float2* part, unsigned long long* wcnt, hipStream_t s,
-                          const ChiArgs& chi = ChiArgs{}, int sets_ready = 0) {
-  if (!sets_ready) {
-    launch_colsets(kc, n_k, nx, ny, o, cst, cmask, nmw, s, chi);
-    STEM_LAUNCH_CHECK();
-  }
+// the fused sum with the transform of precision prec (prec < 0: from the pruned G)
+static int launch_yreduce(int prec, int ny, const YArgs& a, const Optics& o, int chi0, int pwrite, hipStream_t s) {
   switch (prec) {
-    case STEM_DFT_BF16_SPLIT:
-      return launch_yreduce_p<STEM_DFT_BF16_SPLIT>(ny, X, kc, kchi, cst, cmask, nmw, n_k, nx, ngroups, o, store_g,
-                                                   chi0, part, wcnt, s);
-    case STEM_DFT_FP16_SPLIT:
-      return launch_yreduce_p<STEM_DFT_FP16_SPLIT>(ny, X, kc, kchi, cst, cmask, nmw, n_k, nx, ngroups, o, store_g,
-                                                   chi0, part, wcnt, s);
-    default:
-      return launch_yreduce_p<STEM_FFT_FP32>(ny, X, kc, kchi, cst, cmask, nmw, n_k, nx, ngroups, o, store_g, chi0,
-                                             part, wcnt, s);
+    case -1: return launch_yreduce_p<-1>(ny, a, o, chi0, 0, s);
+    case STEM_DFT_BF16_SPLIT: return launch_yreduce_p<STEM_DFT_BF16_SPLIT>(ny, a, o, chi0, pwrite, s);
+    case STEM_DFT_FP16_SPLIT: return launch_yreduce_p<STEM_DFT_FP16_SPLIT>(ny, a, o, chi0, pwrite, s);
+    default: return launch_yreduce_p<STEM_FFT_FP32>(ny, a, o, chi0, pwrite, s);
   }
 }
 
-// Eq. 3 from the stored G without normalisation (REFOCUS): the fused sum over the stored columns
-static int launch_ysum_stored(int ny, float2* G, const double2* kc, const double* kchi, int4* cst, uint64_t* cmask,
-                              int nmw, int n_k, int nx, int ngroups, const Optics& o, int chi0, float2* part,
-                              unsigned long long* wcnt, hipStream_t s, const ChiArgs& chi) {
-  launch_colsets(kc, n_k, nx, ny, o, cst, cmask, nmw, s, chi);
-  STEM_LAUNCH_CHECK();
-  const int B = 1024 / ny;
-  const int ncs = (nx / 2 + 1 + B - 1) / B;
-  const dim3 grid((unsigned)(((ncs + 3) / 4) * ngroups)), blk(kYThreads);
-  STEM_TRACE("ssb_reduce", s);
-  const int st = with_n(ny, [&](auto nc) {
-    using XF = XfNone<decltype(nc)::value>;
-    if (chi0)
-      hipLaunchKernelGGL((k_yreduce<XF, true>), grid, blk, 0, s, G, kc, kchi, cst, cmask, nmw, n_k, nx, ngroups, o,
-                         0, part, wcnt);
-    else
-      hipLaunchKernelGGL((k_yreduce<XF, false>), grid, blk, 0, s, G, kc, kchi, cst, cmask, nmw, n_k, nx, ngroups, o,
-                         0, part, wcnt);
-  });
-  if (st) return st;
-  STEM_LAUNCH_CHECK();
-  return STEM_OK;
-}
-
-static int launch_yadjoint(int prec, int ny, const float2* X, const double2* kc, const double* kchi, int4* cst,
-                           uint64_t* cmask, int nmw, int n_k, int nx, int ngroups, const Optics& o, int g_stored,
-                           const float2* Tbt, double* pdc, float* pdth, hipStream_t s, const ChiArgs& chi) {
-  launch_colsets(kc, n_k, nx, ny, o, cst, cmask, nmw, s, chi);
-  STEM_LAUNCH_CHECK();
+static int launch_yadjoint(int prec, int ny, const YArgs& a, const Optics& o, hipStream_t s) {
   switch (prec) {
-    case STEM_DFT_BF16_SPLIT:
-      return launch_yadjoint_p<STEM_DFT_BF16_SPLIT>(ny, X, kc, kchi, cst, n_k, nx, ngroups, o, g_stored, Tbt, pdc,
-                                                    pdth, s);
-    case STEM_DFT_FP16_SPLIT:
-      return launch_yadjoint_p<STEM_DFT_FP16_SPLIT>(ny, X, kc, kchi, cst, n_k, nx, ngroups, o, g_stored, Tbt, pdc,
-                                                    pdth, s);
-    default:
-      return launch_yadjoint_p<STEM_FFT_FP32>(ny, X, kc, kchi, cst, n_k, nx, ngroups, o, g_stored, Tbt, pdc, pdth,
-                                              s);
+    case -1: return launch_yadjoint_p<-1>(ny, a, o, s);
+    case STEM_DFT_BF16_SPLIT: return launch_yadjoint_p<STEM_DFT_BF16_SPLIT>(ny, a, o, s);
+    case STEM_DFT_FP16_SPLIT: return launch_yadjoint_p<STEM_DFT_FP16_SPLIT>(ny, a, o, s);
+    default: return launch_yadjoint_p<STEM_FFT_FP32>(ny, a, o, s);
   }
 }
 
@@ -226,66 +215,84 @@ static int launch_yadjoint(int prec, int ny, const float2* X, const double2* kc,
 // chi(Kc) + theta per kept pixel
 
 __global__ void k_chi_table(const double2* __restrict__ kc, const float* __restrict__ theta, int n_k,
-                            Optics o, double* __restrict__ kchi, unsigned long long* __restrict__ stats,
-                            int groups) {
+                            Optics o, double* __restrict__ kchi) {
   const int kd = blockIdx.x * blockDim.x + threadIdx.x;
-  if (kd < 4) stats[kd] = kd == 1 ? (unsigned long long)groups : 0ull;  // counters of the sum that follows
   if (kd >= n_k) return;
   const double2 k = kc[kd];
   kchi[kd] = chi_poly(k.x, k.y, o) + (theta ? (double)theta[kd] : 0.0);
 }
 
 // ---------------------------------------------------------------------------------------------
-// Eq. 3 from a stored G: one thread per Q, Q in column-major order q = mx*Ny + my (a wave
-// shares one column, so Qx is uniform).  Pixels are visited row by row of the kept set; a
-// row with |Ky - Qy| >= r, or the rest of a row once Kx - Qx >= r, cannot satisfy |K - Q| < r
-// under the same rounded arithmetic (|d| >= r implies fl(d*d) >= fl(r*r)), so skipping them
-// leaves the set unchanged.
+// Number of double-overlap pixels of every scan frequency (the divisor of the normalised sum),
+// column-major [mx][my] like T: one thread per Q, membership from the interval table (the set of
+// column mx > Nx/2 is the mirror set of column Nx - mx).
 
-__global__ void __launch_bounds__(256) k_reduce(const float2* __restrict__ G, const RowRun* __restrict__ rows,
-                                                int nby, const double2* __restrict__ kc,
-                                                const double* __restrict__ kchi, int ny, int nx,
-                                                Optics o, int normalize, float2* __restrict__ Tt,
-                                                unsigned long long* __restrict__ stats) {
-  const int64_t q0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool valid = q0 < (int64_t)ny * nx;
-  const int64_t q = valid ? q0 : 0;
+__global__ void __launch_bounds__(256) k_pair_count(const int4* __restrict__ cst, int n_k, int ny, int nx,
+                                                    int32_t* __restrict__ npq) {
+  const int64_t F = (int64_t)ny * nx;
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= F) return;
   const int mx = (int)(q / ny), my = (int)(q % ny);
-  const int ix = signed_index(mx, nx), iy = signed_index(my, ny);
-  const double qx = (double)ix * o.sx;
-  const double qy = (double)iy * o.sy;
-  const bool mir = mx > nx / 2;
-  const int gmx = mir ? nx - mx : mx, gmy = mir ? (ny - my) % ny : my;
-  const int nh = nx / 2 + 1;
-  const float2* gcol = G + (int64_t)gmx * ny + gmy;
-  const int64_t kstride = (int64_t)nh * ny;
-  float2 acc = make_float2(0.f, 0.f);
+  const int nc = nx / 2 + 1;
+  const bool mir = 2 * mx > nx;
+  const int c = mir ? nx - mx : mx;
+  const int iy = signed_index(my, ny);
   int cnt = 0;
-  for (int by = 0; by < nby; ++by) {
-    const RowRun rr = rows[by];
-    if (rr.hi <= rr.lo) continue;
-    const double ky = kc[rr.start].y;
-    if (!(valid && fabs(ky - qy) < o.r)) continue;
-    for (int kd = rr.start; kd < rr.start + (rr.hi - rr.lo); ++kd) {
-      const double kx = kc[kd].x;
-      if (kx - qx >= o.r) break;
-      if (qx - kx >= o.r) continue;
-      if (!overlap_screened(kx, ky, (float)kx, (float)ky, ix, iy, o)) continue;
-      const double psi = chi_poly(kx - qx, ky - qy, o) - kchi[kd];
-      float2 g = gcol[kd * kstride];
-      if (mir) g = cconj(g);
-      const float2 e = expi_reduced(psi);
-      acc.x += g.x * e.x - g.y * e.y;
-      acc.y += g.x * e.y + g.y * e.x;
-      ++cnt;
-    }
+  int kd = 0;
+  for (; kd + 4 <= n_k; kd += 4) {
+    ColSet d[4], m[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) load_colsets(cst, (int64_t)(kd + u) * nc + c, d[u], m[u]);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) cnt += (mir ? m[u] : d[u]).has(iy) ? 1 : 0;
   }
-  if (normalize && cnt > 0) acc = cscale(acc, 1.f / (float)cnt);
-  if (valid) Tt[q] = acc;
-  // number of double-overlap pairs of this sum, one atomic per wave
-  unsigned long long c = valid ? (unsigned long long)cnt : 0ull;
-  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
-  if ((threadIdx.x & 63) == 0) atomicAdd(stats, c);
+  for (; kd < n_k; ++kd) {
+    ColSet d, m;
+    load_colsets(cst, (int64_t)kd * nc + c, d, m);
+    cnt += (mir ? m : d).has(iy) ? 1 : 0;
+  }
+  npq[q] = cnt;
+}
+
+// Offsets of the pruned double-overlap array: poff[kd * Nx + mx] = number of values of the (pixel,
+// column) pairs before it in pixel-major, column-minor order; poff[n_k * Nx] = the total.  One
+// workgroup: every thread sums a contiguous segment, a scan of the segment sums gives its base.
+__global__ void __launch_bounds__(1024) k_prune_offsets(const int4* __restrict__ cst, int n_k, int nx,
+                                                        int64_t* __restrict__ poff, int64_t pcap,
+                                                        int32_t* __restrict__ status) {
+  __shared__ int64_t s_sum[1024];
+  const int64_t n = (int64_t)n_k * nx;
+  const int t = threadIdx.x;
+  const int64_t seg = (n + 1023) / 1024;
+  const int64_t e0 = (int64_t)t * seg < n ? (int64_t)t * seg : n;
+  const int64_t e1 = e0 + seg < n ? e0 + seg : n;
+  const int nc = nx / 2 + 1;
+  auto size_of = [&](int64_t e) -> int64_t {
+    const int kd = (int)(e / nx), mx = (int)(e % nx);
+    const bool mir = 2 * mx > nx;
+    ColSet d, m;
+    load_colsets(cst, (int64_t)kd * nc + (mir ? nx - mx : mx), d, m);
+    return set_size(mir ? m : d);
+  };
+  int64_t sum = 0;
+  for (int64_t e = e0; e < e1; ++e) sum += size_of(e);
+  s_sum[t] = sum;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {  // inclusive scan of the segment sums
+    const int64_t v = t >= o ? s_sum[t - o] : 0;
+    __syncthreads();
+    s_sum[t] += v;
+    __syncthreads();
+  }
+  int64_t base = t ? s_sum[t - 1] : 0;
+  for (int64_t e = e0; e < e1; ++e) {
+    poff[e] = base;
+    base += size_of(e);
+  }
+  if (t == 1023) {
+    poff[n] = s_sum[1023];
+    if (s_sum[1023] > pcap) report(status, STEM_EWORKSPACE);  // never with the layout's bound
+  }
 }
 
 // number of pixel groups of the fused sum: about 4096 waves, at most n_k, partial sums <= 64 MB
@@ -382,24 +389,27 @@ struct Bufs {
   uint64_t* cmask;
   int16_t* lut;
   unsigned long long* stats;
+  int32_t* npq;
   void* D;
   float2* X;
+  int64_t* poff;
+  float2* pg;
   float2* T;
   float2* A;
   float2* Tb;
   double* pdc;
   float* pdth;
   float2* part;
-  unsigned long long* wcnt;  // pair counts per wave of the fused sum
+  unsigned long long* wcnt;  // pair counts and loads per wave of the fused kernels
 };
 
 static Bufs carve(void* state, const SsbLayout& L) {
   char* p = (char*)state;
   return Bufs{(RowRun*)(p + L.rows), (double2*)(p + L.kc), (double*)(p + L.kchi), (int4*)(p + L.cst),
-              (uint64_t*)(p + L.cmask), (int16_t*)(p + L.lut),
-              (unsigned long long*)(p + L.stats), (void*)(p + L.D),
-              (float2*)(p + L.X),    (float2*)(p + L.T),  (float2*)(p + L.A),     (float2*)(p + L.Tb),
-              (double*)(p + L.pdc),  (float*)(p + L.pdth), (float2*)(p + L.part),
+              (uint64_t*)(p + L.cmask), (int16_t*)(p + L.lut), (unsigned long long*)(p + L.stats),
+              (int32_t*)(p + L.npq), (void*)(p + L.D), (float2*)(p + L.X), (int64_t*)(p + L.poff),
+              (float2*)(p + L.pg), (float2*)(p + L.T), (float2*)(p + L.A), (float2*)(p + L.Tb),
+              (double*)(p + L.pdc), (float*)(p + L.pdth), (float2*)(p + L.part),
               (unsigned long long*)(p + L.wcnt)};
 }
 
@@ -413,34 +423,81 @@ static int check_common(const stem_det* det, const stem_scan* scan, const stem_o
       ssb->precision != STEM_DFT_FP16_SPLIT)
     return STEM_EINVAL;
   if (ssb->g_mode != STEM_G_STORE && ssb->g_mode != STEM_G_RECOMPUTE) return STEM_EINVAL;
+  if (ssb->normalize != 0 && ssb->normalize != 1) return STEM_EINVAL;
+  if (ssb->scratch_mib < 0 || ssb->scratch_mib > (1 << 20)) return STEM_EINVAL;
   const int n = count_pixels(*det, optics->r_bf * optics->r_bf);
   if (n <= 0 || n > kMaxPixels) return STEM_EINVAL;
   *n_k = n;
   return STEM_OK;
 }
 
-// T = sum of the partial sums (column-major [mx][my]); phi = Im IFFT2(T); d_T row-major.
-static int run_phase(const SsbLayout& L, const Bufs& b, const stem_scan& sc, const float2* parts, int nparts,
-                     float* d_phase, float* d_T, hipStream_t s) {
+static YArgs yargs(const SsbLayout& L, const Bufs& b, int nx) {
+  YArgs a{};
+  a.X = b.X;
+  a.xk0 = 0;
+  a.kc = b.kc;
+  a.kchi = b.kchi;
+  a.cst = b.cst;
+  a.cmask = b.cmask;
+  a.nmw = L.nmw;
+  a.n_k = L.n_k;
+  a.nx = nx;
+  a.k0 = 0;
+  a.k1 = L.n_k;
+  a.ngroups = L.groups;
+  a.accumulate = 0;
+  a.pg = b.pg;
+  a.pgw = b.pg;
+  a.poff = b.poff;
+  a.pcap = L.pcap;
+  a.part = b.part;
+  a.wcnt = b.wcnt;
+  a.Tbt = b.Tb;
+  a.pdc = b.pdc;
+  a.pdth = b.pdth;
+  return a;
+}
+
+// pixels [k0, k1) of chunk ch
+static void chunk_range(const SsbLayout& L, int ch, int& k0, int& k1) {
+  k0 = (int)((int64_t)L.n_k * ch / L.nchunks);
+  k1 = (int)((int64_t)L.n_k * (ch + 1) / L.nchunks);
+}
+
+// row transform of the pixels [k0, k1) (all scan rows) into the X region
+static int xstage_pixels(const SsbLayout& L, const Bufs& b, const stem_ssb& ssb, int ny, int nx, int k0, int k1,
+                         hipStream_t s) {
+  const int64_t nrows = (int64_t)(k1 - k0) * ny;
+  if (ssb.d_bits == 8)
+    return launch_xstage_t<uint8_t>(ssb.precision, nx, (const uint8_t*)b.D + (size_t)k0 * L.F, ny, 0, ny, nrows, b.X,
+                                    s);
+  return launch_xstage_t<uint16_t>(ssb.precision, nx, (const uint16_t*)b.D + (size_t)k0 * L.F, ny, 0, ny, nrows, b.X,
+                                   s);
+}
+
+// T = sum of the partial sums (column-major [mx][my]), divided by the pair count of each Q when
+// npq is given; phi = Im IFFT2(T); d_T row-major.  The fused kernels' per-wave counters become the
+// state's counters.
+static int run_phase(const SsbLayout& L, const Bufs& b, const stem_scan& sc, const int32_t* npq, float* d_phase,
+                     float* d_T, hipStream_t s) {
   const int ny = sc.ny, nx = sc.nx;
   RowFftArgs a{};
   // inverse along my of each mx row of T -> A[ry][mx]; the summed T is kept in the state
   a.nrows = nx;
-  a.in_c = parts;
-  a.nparts = nparts;
+  a.in_c = b.part;
+  a.nparts = L.groups;
   a.part_stride = L.F;
-  a.sum_out = parts == b.T ? nullptr : b.T;
+  a.sum_out = b.T;
+  a.norm_cnt = npq;
   a.out_c = b.A;
   a.out_stride = nx;
   a.osc = make_float2(1.f, 0.f);
   a.tag = "phase_fft";
-  if (parts == b.part) {
-    // the fused sum's pair counts per wave become the state's counters
-    a.wcnt = b.wcnt;
-    a.nwcnt = L.nwy;
-    a.stats = b.stats;
-    a.stats_groups = nparts;
-  }
+  a.wcnt = b.wcnt;
+  a.nwcnt = L.nwy;
+  a.stats = b.stats;
+  a.stats_groups = L.groups;
+  a.stats_chunks = L.store ? 1 : L.nchunks;
   int st = launch_row_fft(ny, true, IN_C64_SUM, OUT_T_C64, a, s);
   if (st) return st;
   if (d_phase) {
@@ -461,20 +518,24 @@ static int run_phase(const SsbLayout& L, const Bufs& b, const stem_scan& sc, con
   return STEM_OK;
 }
 
-static int run_chi_table(const Bufs& b, const float* d_theta, int n_k, const Optics& o, int groups,
-                         hipStream_t s) {
+static int run_chi_table(const Bufs& b, const float* d_theta, int n_k, const Optics& o, hipStream_t s) {
   STEM_TRACE("chi_table", s);
-  hipLaunchKernelGGL(k_chi_table, dim3((n_k + 255) / 256), dim3(256), 0, s, b.kc, d_theta, n_k, o, b.kchi,
-                     b.stats, groups);
+  hipLaunchKernelGGL(k_chi_table, dim3((n_k + 255) / 256), dim3(256), 0, s, b.kc, d_theta, n_k, o, b.kchi);
   STEM_LAUNCH_CHECK();
   return STEM_OK;
 }
 
-static int run_reduce_stored(const SsbLayout& L, const Bufs& b, int ny, int nx, const Optics& o, int normalize,
-                             hipStream_t s) {
-  STEM_TRACE("ssb_reduce", s);
-  hipLaunchKernelGGL(k_reduce, dim3((unsigned)L.nblk), dim3(256), 0, s, b.X, b.rows, L.nby, b.kc, b.kchi, ny, nx,
-                     o, normalize, b.T, b.stats);
+static int run_pair_count(const SsbLayout& L, const Bufs& b, int ny, int nx, hipStream_t s) {
+  STEM_TRACE("pair_count", s);
+  hipLaunchKernelGGL(k_pair_count, dim3((unsigned)((L.F + 255) / 256)), dim3(256), 0, s, b.cst, L.n_k, ny, nx,
+                     b.npq);
+  STEM_LAUNCH_CHECK();
+  return STEM_OK;
+}
+
+static int run_prune_offsets(const SsbLayout& L, const Bufs& b, int nx, int32_t* d_status, hipStream_t s) {
+  STEM_TRACE("prune_offsets", s);
+  hipLaunchKernelGGL(k_prune_offsets, dim3(1), dim3(1024), 0, s, b.cst, L.n_k, nx, b.poff, L.pcap, d_status);
   STEM_LAUNCH_CHECK();
   return STEM_OK;
 }
@@ -496,7 +557,7 @@ extern "C" size_t ssb_state_bytes(const stem_det* det, const stem_scan* scan, co
   int n_k;
   if (check_common(det, scan, optics, ssb, &n_k)) return 0;
   SsbLayout L;
-  return make_layout(*det, *scan, *ssb, n_k, &L);
+  return make_layout(*det, *scan, *optics, *ssb, n_k, &L);
 }
 
 extern "C" int ssb_state_region(const stem_det* det, const stem_scan* scan, const stem_optics* optics,
@@ -504,13 +565,19 @@ extern "C" int ssb_state_region(const stem_det* det, const stem_scan* scan, cons
   int n_k;
   if (check_common(det, scan, optics, ssb, &n_k) || !offset || !bytes) return STEM_EINVAL;
   SsbLayout L;
-  make_layout(*det, *scan, *ssb, n_k, &L);
+  make_layout(*det, *scan, *optics, *ssb, n_k, &L);
   switch (region) {
     case STEM_REGION_D: *offset = L.D; *bytes = (size_t)n_k * L.F * (ssb->d_bits / 8); break;
-    case STEM_REGION_G: *offset = L.X; *bytes = (size_t)n_k * L.nh * scan->ny * sizeof(float2); break;
+    case STEM_REGION_X: *offset = L.X; *bytes = (size_t)L.xpix * L.nh * scan->ny * sizeof(float2); break;
     case STEM_REGION_T: *offset = L.T; *bytes = (size_t)L.F * sizeof(float2); break;
     case STEM_REGION_KC: *offset = L.kc; *bytes = (size_t)n_k * sizeof(double2); break;
     case STEM_REGION_STATS: *offset = L.stats; *bytes = 4 * sizeof(unsigned long long); break;
+    case STEM_REGION_PG: *offset = L.pg; *bytes = (size_t)L.pcap * sizeof(float2); break;
+    case STEM_REGION_POFF:
+      *offset = L.poff;
+      *bytes = L.store ? sizeof(int64_t) * ((size_t)n_k * scan->nx + 1) : 0;
+      break;
+    case STEM_REGION_NPAIR: *offset = L.npq; *bytes = (size_t)L.F * sizeof(int32_t); break;
     default: return STEM_EINVAL;
   }
   return STEM_OK;
@@ -525,9 +592,8 @@ static int reconstruct(const int32_t* d_idx, const int64_t* d_off, int64_t frame
   if (st) return st;
   if (mode < STEM_SSB_ACCUMULATE || mode > STEM_SSB_ONESHOT) return STEM_EINVAL;
   SsbLayout L;
-  make_layout(*det, *scan, *ssb, n_k, &L);
+  make_layout(*det, *scan, *optics, *ssb, n_k, &L);
   if (!state || ((uintptr_t)state & 255) || state_bytes < L.total) return STEM_EWORKSPACE;
-  if (mode == STEM_SSB_REFOCUS && ssb->g_mode != STEM_G_STORE) return STEM_ESTATE;
   hipStream_t s = (hipStream_t)stream_;
   const Bufs b = carve(state, L);
   const int ny = scan->ny, nx = scan->nx;
@@ -546,61 +612,51 @@ static int reconstruct(const int32_t* d_idx, const int64_t* d_off, int64_t frame
     if ((st = launch_bin(d_idx, d_off, frame0, n_frames, *det, o.r2, b.rows, b.kc, b.lut, n_k, L.F, b.D,
                           ssb->d_bits, d_status, s, com, &job)))
       return st;
-    const int ry0 = (int)(frame0 / nx), nr = (int)(n_frames / nx);
-    const int64_t nrows = (int64_t)n_k * nr;
-    if (ssb->d_bits == 8)
-      st = launch_xstage_t<uint8_t>(ssb->precision, nx, (const uint8_t*)b.D, ny, ry0, nr, nrows, b.X, s);
-    else
-      st = launch_xstage_t<uint16_t>(ssb->precision, nx, (const uint16_t*)b.D, ny, ry0, nr, nrows, b.X, s);
-    if (st) return st;
+    if (L.store) {
+      // STEM_G_STORE keeps the row transform of every pixel: transform this chunk's rows now
+      const int ry0 = (int)(frame0 / nx), nr = (int)(n_frames / nx);
+      const int64_t nrows = (int64_t)n_k * nr;
+      if (ssb->d_bits == 8)
+        st = launch_xstage_t<uint8_t>(ssb->precision, nx, (const uint8_t*)b.D, ny, ry0, nr, nrows, b.X, s);
+      else
+        st = launch_xstage_t<uint16_t>(ssb->precision, nx, (const uint16_t*)b.D, ny, ry0, nr, nrows, b.X, s);
+      if (st) return st;
+    }
     if (mode == STEM_SSB_ACCUMULATE) return STEM_OK;
   }
-  // without normalisation chi(Kc) + theta comes with the interval table of the fused sum
-  const ChiArgs chi{d_theta, b.kchi, b.stats, L.groups};
-  if (ssb->normalize && (st = run_chi_table(b, d_theta, n_k, o, 1, s))) return st;
-  if (mode == STEM_SSB_REFOCUS) {
-    // Eq. 3 again from the stored G: per-Q normalised sum, or the fused sum over stored columns
-    if (ssb->normalize) {
-      if ((st = run_reduce_stored(L, b, ny, nx, o, 1, s))) return st;
-      return run_phase(L, b, *scan, b.T, 1, d_phase, d_T, s);
-    }
-    if ((st = launch_ysum_stored(ny, b.X, b.kc, b.kchi, b.cst, b.cmask, L.nmw, n_k, nx, L.groups, o,
-                                 chi_is_zero(o, d_theta), b.part, b.wcnt, s, chi)))
-      return st;
-    return run_phase(L, b, *scan, b.part, L.groups, d_phase, d_T, s);
-  }
-  if (ssb->normalize && ssb->precision != STEM_FFT_FP32) {
-    // split precision: the fused kernel transforms X -> G in place (its partial sums are not
-    // used); the counters are reset before the per-Q normalised sum
-    if ((st = launch_yreduce(ssb->precision, ny, b.X, b.kc, b.kchi, b.cst, b.cmask, L.nmw, n_k, nx, L.groups, o, 1,
-                             1, b.part, b.wcnt, s)))
-      return st;
-    if ((st = run_chi_table(b, d_theta, n_k, o, 1, s))) return st;
-    if ((st = run_reduce_stored(L, b, ny, nx, o, 1, s))) return st;
-    return run_phase(L, b, *scan, b.T, 1, d_phase, d_T, s);
-  }
-  if (ssb->normalize) {
-    // the normalised sum needs each Q's pair count over all pixels: column transform in place
-    // (X -> G), then the per-Q sum
-    RowFftArgs a{};
-    a.nrows = (int64_t)n_k * L.nh;
-    a.in_c = b.X;
-    a.out_c = b.X;
-    a.osc = make_float2(1.f, 0.f);
-    a.tag = "ystage_fft";
-    if ((st = launch_row_fft(ny, false, IN_C64, OUT_ROW_C64, a, s))) return st;
-    if ((st = run_reduce_stored(L, b, ny, nx, o, 1, s))) return st;
-    return run_phase(L, b, *scan, b.T, 1, d_phase, d_T, s);
-  }
-  // without aberrations the sum needs only the interval table and the mask, which ACCUMULATE's
-  // binning built (when it bins through its LDS table); otherwise the table kernel also tabulates
-  // chi(Kc) + theta
   const int chi0 = chi_is_zero(o, d_theta);
-  const int sets_ready = chi0 && bin_builds_sets(*det, o.r2);
-  if ((st = launch_yreduce(ssb->precision, ny, b.X, b.kc, b.kchi, b.cst, b.cmask, L.nmw, n_k, nx, L.groups, o,
-                           ssb->g_mode == STEM_G_STORE, chi0, b.part, b.wcnt, s, chi, sets_ready)))
-    return st;
-  return run_phase(L, b, *scan, b.part, L.groups, d_phase, d_T, s);
+  const bool refocus = mode == STEM_SSB_REFOCUS;
+  // The interval table and mask depend only on the geometry: ACCUMULATE's binning built them when
+  // it bins through its LDS table; otherwise the first sum builds them (a refocus finds them from
+  // the FINALIZE before it).  chi(Kc) + theta comes with them, or from its own small kernel.
+  if (!refocus && !bin_builds_sets(*det, o.r2)) {
+    if ((st = launch_colsets(b.kc, n_k, nx, ny, o, b.cst, b.cmask, L.nmw, s, d_theta, chi0 ? nullptr : b.kchi)))
+      return st;
+  } else if (!chi0) {
+    if ((st = run_chi_table(b, d_theta, n_k, o, s))) return st;
+  }
+  if (ssb->normalize && !refocus && (st = run_pair_count(L, b, ny, nx, s))) return st;
+  YArgs a = yargs(L, b, nx);
+  if (L.store && refocus) {
+    // Eq. 3 again from the stored double-overlap values
+    if ((st = launch_yreduce(-1, ny, a, o, chi0, 0, s))) return st;
+  } else if (L.store) {
+    if ((st = run_prune_offsets(L, b, nx, d_status, s))) return st;
+    if ((st = launch_yreduce(ssb->precision, ny, a, o, chi0, 1, s))) return st;
+  } else {
+    // G recomputed chunk by chunk: row transform of the chunk's pixels, then the fused sum on it
+    for (int ch = 0; ch < L.nchunks; ++ch) {
+      int k0, k1;
+      chunk_range(L, ch, k0, k1);
+      if ((st = xstage_pixels(L, b, *ssb, ny, nx, k0, k1, s))) return st;
+      a.xk0 = k0;
+      a.k0 = k0;
+      a.k1 = k1;
+      a.accumulate = ch > 0;
+      if ((st = launch_yreduce(ssb->precision, ny, a, o, chi0, 0, s))) return st;
+    }
+  }
+  return run_phase(L, b, *scan, ssb->normalize ? b.npq : nullptr, d_phase, d_T, s);
 }
 
 extern "C" int ssb_reconstruct(const int32_t* d_idx, const int64_t* d_off, int64_t frame0, int64_t n_frames,
@@ -627,15 +683,16 @@ extern "C" int ssb_reconstruct_com(const int32_t* d_idx, const int64_t* d_off, i
 }
 
 // ---------------------------------------------------------------------------------------------
-// G(K, Q) at selected Q as binned detector images: one wave per (bin, Q)
+// G(K, Q) at selected Q as binned detector images
 
 struct PanelQ {
   int32_t my[STEM_MAX_PANEL], mx[STEM_MAX_PANEL];
 };
 
+// From the row-transformed cube (STEM_G_STORE): one wave per (bin, Q), the DFT along ry of the
+// stored column with FP64 accumulation.
 __global__ void __launch_bounds__(64) k_g_panel(const float2* __restrict__ X, const RowRun* __restrict__ rows,
-                                               int nbx, int n_k, int ny, int nx, PanelQ q, int g_stored,
-                                               float2* __restrict__ img) {
+                                               int nbx, int n_k, int ny, int nx, PanelQ q, float2* __restrict__ img) {
   const int bin = blockIdx.x, j = blockIdx.y;  // bin = by * nbx + bx
   const int by = bin / nbx, bx = bin % nbx;
   const int lane = threadIdx.x;
@@ -654,31 +711,95 @@ __global__ void __launch_bounds__(64) k_g_panel(const float2* __restrict__ X, co
   const bool cj = 2 * mx > nx;  // G(K, Q) = conj G(K, -Q): read the half spectrum at -Q
   if (cj) {
     mx = nx - mx;
-    my = (ny - my) & (ny - 1);
+    my = (ny - my) % ny;
   }
   const float2* col = X + ((int64_t)kd * (nx / 2 + 1) + mx) * ny;
-  float2 v;
-  if (g_stored) {
-    v = col[my];
-  } else {
-    // sum over ry of X exp(-2 pi i my ry / Ny), angles reduced exactly as integers mod Ny
+  // sum over ry of X exp(-2 pi i my ry / Ny), angles reduced exactly as integers mod Ny
+  double re = 0.0, im = 0.0;
+  for (int ry = lane; ry < ny; ry += 64) {
+    const int k = (int)(((int64_t)my * ry) % ny);
+    double sn, cs;
+    sincospi(2.0 * (double)k / (double)ny, &sn, &cs);
+    const float2 x = col[ry];
+    re += (double)x.x * cs + (double)x.y * sn;
+    im += (double)x.y * cs - (double)x.x * sn;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    re += __shfl_xor(re, o);
+    im += __shfl_xor(im, o);
+  }
+  float2 v = make_float2((float)re, (float)im);
+  if (cj) v.y = -v.y;
+  if (lane == 0) *out = v;
+}
+
+// From the binned cube (STEM_G_RECOMPUTE keeps no row-transformed cube): one workgroup per bin, the
+// 2D DFT over (ry, rx) at every Q_j, FP64 accumulation; twiddles W_N^t for exact integer t (FP64
+// sincospi rounded to FP32) in LDS.
+constexpr int kPanelTw = 1024;
+
+template <typename DT>
+__global__ void __launch_bounds__(256) k_g_panel_d(const DT* __restrict__ D, const RowRun* __restrict__ rows,
+                                                  int nbx, int n_k, int ny, int nx, PanelQ q, int n_q,
+                                                  float2* __restrict__ img) {
+  __shared__ float2 s_wx[kPanelTw], s_wy[kPanelTw];
+  __shared__ double s_red[2][4];
+  const int bin = blockIdx.x;
+  const int by = bin / nbx, bx = bin % nbx;
+  const int nbins = gridDim.x;
+  const RowRun rr = rows[by];
+  const int kd = rr.start + bx - rr.lo;
+  if (bx < rr.lo || bx >= rr.hi || kd < 0 || kd >= n_k) {
+    for (int j = threadIdx.x; j < n_q; j += blockDim.x) img[(int64_t)j * nbins + bin] = make_float2(0.f, 0.f);
+    return;
+  }
+  for (int t = threadIdx.x; t < nx; t += blockDim.x) {
+    double sn, cs;
+    sincospi(2.0 * (double)t / (double)nx, &sn, &cs);
+    s_wx[t] = make_float2((float)cs, (float)-sn);
+  }
+  for (int t = threadIdx.x; t < ny; t += blockDim.x) {
+    double sn, cs;
+    sincospi(2.0 * (double)t / (double)ny, &sn, &cs);
+    s_wy[t] = make_float2((float)cs, (float)-sn);
+  }
+  __syncthreads();
+  const DT* d = D + (int64_t)kd * ny * nx;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int j = 0; j < n_q; ++j) {
+    const int my = q.my[j], mx = q.mx[j];
     double re = 0.0, im = 0.0;
-    for (int ry = lane; ry < ny; ry += 64) {
-      const int k = (my * ry) & (ny - 1);
-      double sn, cs;
-      sincospi(2.0 * (double)k / (double)ny, &sn, &cs);
-      const float2 x = col[ry];
-      re += (double)x.x * cs + (double)x.y * sn;
-      im += (double)x.y * cs - (double)x.x * sn;
+    for (int ry = 0; ry < ny; ++ry) {
+      // row sum along rx, then the factor of ry
+      double rr_ = 0.0, ri = 0.0;
+      for (int rx = threadIdx.x; rx < nx; rx += blockDim.x) {
+        const int c = (int)d[(int64_t)ry * nx + rx];
+        if (c) {
+          const float2 w = s_wx[(int)(((int64_t)mx * rx) % nx)];
+          rr_ += (double)c * (double)w.x;
+          ri += (double)c * (double)w.y;
+        }
+      }
+      const float2 w = s_wy[(int)(((int64_t)my * ry) % ny)];
+      re += rr_ * (double)w.x - ri * (double)w.y;
+      im += rr_ * (double)w.y + ri * (double)w.x;
     }
     for (int o = 32; o > 0; o >>= 1) {
       re += __shfl_xor(re, o);
       im += __shfl_xor(im, o);
     }
-    v = make_float2((float)re, (float)im);
+    if (lane == 0) {
+      s_red[0][wave] = re;
+      s_red[1][wave] = im;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const double tr = (s_red[0][0] + s_red[0][1]) + (s_red[0][2] + s_red[0][3]);
+      const double ti = (s_red[1][0] + s_red[1][1]) + (s_red[1][2] + s_red[1][3]);
+      img[(int64_t)j * nbins + bin] = make_float2((float)tr, (float)ti);
+    }
+    __syncthreads();
   }
-  if (cj) v.y = -v.y;
-  if (lane == 0) *out = v;
 }
 
 extern "C" int ssb_g_panel(const stem_det* det, const stem_scan* scan, const stem_optics* optics,
@@ -695,14 +816,24 @@ extern "C" int ssb_g_panel(const stem_det* det, const stem_scan* scan, const ste
     q.mx[j] = h_mx[j];
   }
   SsbLayout L;
-  make_layout(*det, *scan, *ssb, n_k, &L);
+  make_layout(*det, *scan, *optics, *ssb, n_k, &L);
   if (!state || ((uintptr_t)state & 255) || state_bytes < L.total) return STEM_EWORKSPACE;
   const Bufs b = carve(const_cast<void*>(state), L);
   const int nbx = det->W / det->bin, nby = det->H / det->bin;
   hipStream_t s = (hipStream_t)stream_;
   STEM_TRACE("g_panel", s);
-  hipLaunchKernelGGL(k_g_panel, dim3((unsigned)(nbx * nby), (unsigned)n_q), dim3(64), 0, s, b.X, b.rows, nbx, n_k,
-                     scan->ny, scan->nx, q, ssb->g_mode == STEM_G_STORE ? 1 : 0, (float2*)d_img);
+  if (L.store) {
+    hipLaunchKernelGGL(k_g_panel, dim3((unsigned)(nbx * nby), (unsigned)n_q), dim3(64), 0, s, b.X, b.rows, nbx, n_k,
+                       scan->ny, scan->nx, q, (float2*)d_img);
+  } else if (scan->nx > kPanelTw || scan->ny > kPanelTw) {
+    return STEM_EINVAL;
+  } else if (ssb->d_bits == 8) {
+    hipLaunchKernelGGL(k_g_panel_d<uint8_t>, dim3((unsigned)(nbx * nby)), dim3(256), 0, s, (const uint8_t*)b.D,
+                       b.rows, nbx, n_k, scan->ny, scan->nx, q, n_q, (float2*)d_img);
+  } else {
+    hipLaunchKernelGGL(k_g_panel_d<uint16_t>, dim3((unsigned)(nbx * nby)), dim3(256), 0, s, (const uint16_t*)b.D,
+                       b.rows, nbx, n_k, scan->ny, scan->nx, q, n_q, (float2*)d_img);
+  }
   STEM_LAUNCH_CHECK();
   return STEM_OK;
 }
@@ -717,7 +848,7 @@ extern "C" int ssb_backward(const float* d_dLdphi, const stem_det* det, const st
   if (st) return st;
   if (!d_dLdphi || !d_dLdc || ssb->normalize) return STEM_EINVAL;
   SsbLayout L;
-  make_layout(*det, *scan, *ssb, n_k, &L);
+  make_layout(*det, *scan, *optics, *ssb, n_k, &L);
   if (!state || ((uintptr_t)state & 255) || state_bytes < L.total) return STEM_EWORKSPACE;
   hipStream_t s = (hipStream_t)stream_;
   const Bufs b = carve(state, L);
@@ -740,10 +871,23 @@ extern "C" int ssb_backward(const float* d_dLdphi, const stem_det* det, const st
   a.osc = make_float2(0.f, (float)(1.0 / (double)L.F));
   a.tag = "adj_fft";
   if ((st = launch_row_fft(ny, false, IN_C64, OUT_ROW_C64, a, s))) return st;
-  if ((st = launch_yadjoint(ssb->precision, ny, b.X, b.kc, b.kchi, b.cst, b.cmask, L.nmw, n_k, nx, L.groups, o,
-                            ssb->g_mode == STEM_G_STORE, b.Tb, b.pdc, b.pdth, s,
-                            ChiArgs{d_theta, b.kchi, b.stats, L.groups})))
-    return st;
+  // chi(Kc) + theta for these coefficients; the interval table and mask are the last sum's
+  if ((st = run_chi_table(b, d_theta, n_k, o, s))) return st;
+  YArgs y = yargs(L, b, nx);
+  if (L.store) {
+    if ((st = launch_yadjoint(-1, ny, y, o, s))) return st;
+  } else {
+    for (int ch = 0; ch < L.nchunks; ++ch) {
+      int k0, k1;
+      chunk_range(L, ch, k0, k1);
+      if ((st = xstage_pixels(L, b, *ssb, ny, nx, k0, k1, s))) return st;
+      y.xk0 = k0;
+      y.k0 = k0;
+      y.k1 = k1;
+      y.accumulate = ch > 0;
+      if ((st = launch_yadjoint(ssb->precision, ny, y, o, s))) return st;
+    }
+  }
   {
     STEM_TRACE("ssb_adjoint_final", s);
     hipLaunchKernelGGL(k_adjoint_final, dim3(1 + (n_k + 255) / 256), dim3(256), 0, s, b.pdc, L.nwy, b.pdth,

@@ -5,9 +5,7 @@ namespace stem {
 
 template int launch_xstage_p<STEM_DFT_BF16_SPLIT, uint8_t>(int, const uint8_t*, int, int, int, int64_t, float2*, hipStream_t);
 template int launch_xstage_p<STEM_DFT_BF16_SPLIT, uint16_t>(int, const uint16_t*, int, int, int, int64_t, float2*, hipStream_t);
-template int launch_yreduce_p<STEM_DFT_BF16_SPLIT>(int, float2*, const double2*, const double*, const int4*, const uint64_t*, int, int, int, int,
-                                            const Optics&, int, int, float2*, unsigned long long*, hipStream_t);
-template int launch_yadjoint_p<STEM_DFT_BF16_SPLIT>(int, const float2*, const double2*, const double*, const int4*, int, int, int,
-                                             const Optics&, int, const float2*, double*, float*, hipStream_t);
+template int launch_yreduce_p<STEM_DFT_BF16_SPLIT>(int, const YArgs&, const Optics&, int, int, hipStream_t);
+template int launch_yadjoint_p<STEM_DFT_BF16_SPLIT>(int, const YArgs&, const Optics&, hipStream_t);
 
 }  // namespace stem

@@ -28,6 +28,7 @@ template <int N_>
 struct XfFft {
   static constexpr int N = N_;
   static constexpr bool kMfma = false;
+  static constexpr bool kPruned = false;
   static constexpr int RL = fft_last_radix<N>();
   static constexpr int NB = N / RL;
   static constexpr bool kUniformCol = NB >= kWave;
@@ -51,6 +52,7 @@ template <int N_, int PREC>
 struct XfMfma {
   static constexpr int N = N_;
   static constexpr bool kMfma = true;
+  static constexpr bool kPruned = false;
   static constexpr int slot_of(int) { return 0; }  // all 16 registers of a lane share its column
   static constexpr int kSlots = 1;
   static constexpr bool kUniformCol = false;        // (the lanes of a wave do not)
@@ -71,10 +73,12 @@ struct XfMfma {
   }
 };
 
-// No transform: the registers hold a stored G column in the FFT's output layout, so the fused
-// sum's slots and membership masks apply unchanged (Eq. 3 again from a stored G).
+// No transform: the registers hold G read from the pruned double-overlap array in the FFT's output
+// layout, so the fused sum's slots and membership masks apply unchanged (Eq. 3 again from the
+// stored values, and the adjoint from them).
 template <int N_>
-struct XfNone : XfFft<N_> {
+struct XfPruned : XfFft<N_> {
+  static constexpr bool kPruned = true;
   static __device__ __forceinline__ void in(int lane, int i, int& b, int& n) { fft_out_index<N_>(lane, i, b, n); }
   template <bool EXACT>
   static __device__ __forceinline__ void run(float2*, float2*, const float2*, const uint4*, int) {}
@@ -214,74 +218,137 @@ __global__ void __launch_bounds__(64 * XF::kXWaves) k_xstage(const DT* __restric
 }
 
 // ---------------------------------------------------------------------------------------------
-// Fused column transform + Eq. 3 (the path that never stores G).  A wave owns B = 1024/NY
-// consecutive half-spectrum columns c (Qx = c*sx) and a group of kept pixels.  For each pixel it
-// loads the row-transformed columns X[kd][c][0..NY), FFTs them along ry in registers (giving
-// G(kd, (my, c)) for every my), and adds every double-overlap term to its accumulators: the
-// direct frequency Q = (my, c) with G, and for 0 < c < Nx/2 the mirrored frequency
-// (-my, -c) with conj G.  A pixel is skipped without loading when neither Qx nor -Qx of any of
-// its columns lies within r of Kx (then |Kx - Qx| >= r rules out |K - Q| < r for every my).
-// The wave writes its partial T for its columns into part[g] (column-major [mx][my]); the phase
-// pass sums the groups in a fixed order.  With store_g the transformed columns are also written
-// back in place (X becomes G) for later refocusing.
-
+// Fused column transform + Eq. 3.  A wave owns B = 1024/NY consecutive half-spectrum columns c
+// (Qx = c*sx) and a group of kept pixels.  For each pixel it loads the row-transformed columns
+// X[kd][c][0..NY), transforms them along ry in registers (giving G(kd, (my, c)) for every my),
+// and adds every double-overlap term to its accumulators: the direct frequency Q = (my, c) with
+// G, and for 0 < c < Nx/2 the mirrored frequency (-my, -c) with conj G.  Only pixels whose set is
+// non-empty somewhere in the wave's columns are visited (the active-pixel mask).  The wave writes
+// its partial T for its columns into part[g] (column-major [mx][my]); the phase pass sums the
+// groups in a fixed order.
+//
+// Pixels may come in chunks (pixels [k0, k1) of one launch, their columns at X + (kd - xk0) *
+// kstride): with `accumulate` a launch adds to the partial sums and counters of the previous
+// chunk's launch (same grid, same wave -> partial mapping) instead of overwriting them.
+//
+// Pruned G: the double-overlap values only, for later sums (refocus) and the adjoint.  For pixel
+// kd and scan-frequency column mx in [0, Nx), the values G(kd, (iy, mx)) for iy in the set of
+// that column, ascending iy with the hole [b0, b1] skipped, start at poff[kd * Nx + mx].  Column
+// mx <= Nx/2 is half-spectrum column c = mx (direct set); mx > Nx/2 is the mirror of c = Nx - mx,
+// whose values are conj G(kd, (-iy, c)).  PWRITE: the fused sum writes them (FINALIZE that keeps
+// G); XfPruned: the sum reads them instead of transforming X (refocus).
 
 // The sets of one pixel for a half-spectrum column c (direct) and for -c (mirror) depend only on
 // the geometry; they are tabulated once per reconstruction (k_colsets), 16 bytes per (pixel,
-// column): (a0, a1, b0, b1) direct and mirrored as int16 (|iy| <= 512).
+// column): (a0, a1, b0, b1) direct and mirrored as int16 (|iy| <= 2048).
 __device__ __forceinline__ void load_colsets(const int4* __restrict__ cst, int64_t i, ColSet& d, ColSet& m) {
   const int4 r = cst[i];
   d = ColSet{(int)(short)(r.x & 0xffff), r.x >> 16, (int)(short)(r.y & 0xffff), r.y >> 16};
   m = ColSet{(int)(short)(r.z & 0xffff), r.z >> 16, (int)(short)(r.w & 0xffff), r.w >> 16};
 }
 
-// CHI0: the aberration function and theta are identically zero, so every phase factor of Eq. 3
-// is exactly 1 and the sum adds G itself (conj G for mirrored frequencies): the same values the
-// general path produces for chi = 0, without evaluating them.
+// Arguments shared by the fused column kernels.
+struct YArgs {
+  const float2* X;          // row-transformed columns, pixel kd at X + (kd - xk0) * kstride
+  int xk0;
+  const double2* kc;
+  const double* kchi;       // chi(Kc) + theta per pixel (general path and adjoint)
+  const int4* cst;          // double-overlap interval table [n_k][Nx/2 + 1]
+  const uint64_t* cmask;    // active-pixel mask [column set][nmw]
+  int nmw, n_k, nx;
+  int k0, k1;               // pixels of this launch
+  int ngroups;              // pixel groups of [k0, k1)
+  int accumulate;           // add to part / wcnt / pdc (a later chunk of pixels)
+  const float2* pg;         // XfPruned: pruned G read
+  float2* pgw;              // PWRITE: pruned G written
+  const int64_t* poff;      // pruned offsets [n_k][Nx]
+  int64_t pcap;             // capacity of the pruned array (entries)
+  float2* part;             // partial sums of T [groups][F]
+  unsigned long long* wcnt; // per wave: pairs | (8-byte loads << 40)
+  const float2* Tbt;        // adjoint: Tbar column-major [mx][my]
+  double* pdc;              // adjoint: dL/dc partials [wave][8]
+  float* pdth;              // adjoint: dL/dtheta partials [column set][n_k]
+};
 
-template <typename XF, bool CHI0>
-__global__ void __launch_bounds__(kYThreads, 2) k_yreduce(float2* __restrict__ X, const double2* __restrict__ kc,
-                                                       const double* __restrict__ kchi,
-                                                       const int4* __restrict__ cst,
-                                                       const uint64_t* __restrict__ cmask, int nmw, int n_k, int nx,
-                                                       int ngroups, Optics o, int store_g,
-                                                       float2* __restrict__ part,
-                                                       unsigned long long* __restrict__ wcnt) {
+constexpr int kLoadShift = 40;  // wcnt packs the pair count below bit 40, the 8-byte loads above
+
+// Position of iy in the compact run of set s ([a0, a1] without the hole [b0, b1]); iy in s.
+__device__ __forceinline__ int set_rank(const ColSet& s, int iy) {
+  const int h0 = max(s.a0, s.b0), h1 = min(s.a1, s.b1);
+  return iy - s.a0 - ((h0 <= h1 && iy > h1) ? h1 - h0 + 1 : 0);
+}
+
+__device__ __forceinline__ int set_size(const ColSet& s) {
+  if (s.a0 > s.a1) return 0;
+  const int h0 = max(s.a0, s.b0), h1 = min(s.a1, s.b1);
+  return (s.a1 - s.a0 + 1) - (h0 <= h1 ? h1 - h0 + 1 : 0);
+}
+
+// Registers of pixel kd for the wave's columns: the row-transformed input (transform policies) or
+// G itself from the pruned array (XfPruned).  Returns the number of 8-byte loads of this lane.
+template <typename XF>
+__device__ __forceinline__ unsigned load_pixel(const YArgs& a, int kd, int c0, int lane, float2* v) {
   constexpr int NY = XF::N;
-  __shared__ float2 s_tw[1024];
-  __shared__ float2 s_buf[XF::kMfma ? 1 : 4 * kXWaveStride];
-  __shared__ uint4 s_tab[XF::kMfma ? kMfmaTab : 1];
-  constexpr int B = 1024 / NY;
-  using SL = XF;
-  constexpr int kSlotStride = 16 / SL::kSlots;
-  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int nc = nx / 2 + 1;
-  const int ncs = (nc + B - 1) / B;                       // column sets
-  const int g = blockIdx.x % ngroups;
-  const int cs = (blockIdx.x / ngroups) * 4 + wave;       // this wave's column set
-  fill_twiddles(s_tw, threadIdx.x, kYThreads);
-  __syncthreads();
-  XF::fill(s_tab, s_tw, threadIdx.x, kYThreads);
-  if (XF::kMfma) __syncthreads();
-  if (cs >= ncs) {
-    if (lane == 0) wcnt[blockIdx.x * 4 + wave] = 0ull;
-    return;
-  }
-  float2* buf = s_buf + wave * kXWaveStride;
-  const int c0 = cs * B;
-  const int kd_a = (int)((int64_t)n_k * g / ngroups), kd_b = (int)((int64_t)n_k * (g + 1) / ngroups);
-  float2 accd[16], accm[16];
+  const int nc = a.nx / 2 + 1;
+  unsigned n = 0;
+  if constexpr (XF::kPruned) {
+    constexpr int kSlotStride = 16 / XF::kSlots;
 #pragma unroll
-  for (int i = 0; i < 16; ++i) accd[i] = accm[i] = make_float2(0.f, 0.f);
-  unsigned cnt = 0;
-  const int64_t kstride = (int64_t)nc * NY;
-  // the pixels of [kd_a, kd_b) with a non-empty set in this column set (every pixel with store_g):
-  // bits of the column set's mask, scanned with scalar operations
-  const uint64_t* mrow = cmask + (int64_t)cs * nmw;
-  int mw = -1;  // the mask word last read, kept in scalar registers
+    for (int sl = 0; sl < XF::kSlots; ++sl) {
+      int b0, m0;
+      XF::out(lane, sl * kSlotStride, b0, m0);
+      const int c = c0 + b0;
+      ColSet sd{1, 0, 1, 0}, sm{1, 0, 1, 0};
+      int64_t pd = 0, pm = 0;
+      if (c < nc) {
+        load_colsets(a.cst, (int64_t)kd * nc + c, sd, sm);
+        pd = a.poff[(int64_t)kd * a.nx + c];
+        if (c > 0 && 2 * c < a.nx) pm = a.poff[(int64_t)kd * a.nx + (a.nx - c)];
+      }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        if (XF::slot_of(i) != sl) continue;
+        int b, m;
+        XF::out(lane, i, b, m);
+        const int iy = signed_index(m, NY), jy = signed_index((NY - m) & (NY - 1), NY);
+        // entries are read only inside the array (a state whose FINALIZE never ran reads nothing
+        // out of bounds)
+        float2 x = make_float2(0.f, 0.f);
+        if (c < nc && sd.has(iy)) {
+          const int64_t e = pd + set_rank(sd, iy);
+          if (e >= 0 && e < a.pcap) x = a.pg[e];
+          ++n;
+        } else if (c < nc && sm.has(jy)) {
+          const int64_t e = pm + set_rank(sm, jy);
+          if (e >= 0 && e < a.pcap) x = cconj(a.pg[e]);
+          ++n;
+        }
+        v[i] = x;
+      }
+    }
+  } else {
+    const int64_t kstride = (int64_t)nc * NY;
+    const float2* xcol = a.X + (int64_t)(kd - a.xk0) * kstride + (int64_t)c0 * NY;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      int b, n_;
+      XF::in(lane, i, b, n_);
+      const bool in = c0 + b < nc;
+      v[i] = in ? xcol[(int64_t)b * NY + n_] : make_float2(0.f, 0.f);
+      n += in ? 1u : 0u;
+    }
+  }
+  return n;
+}
+
+// the pixels of [kd_a, kd_b) with a non-empty set in column set cs: bits of the active-pixel mask,
+// scanned with scalar operations
+struct MaskScan {
+  const uint64_t* mrow;
+  int kd_b;
+  int mw = -1;
   uint64_t mword = 0;
-  auto next_kd = [&](int from) -> int {
-    if (store_g) return from < kd_b ? from : kd_b;
+  __device__ __forceinline__ int next(int from) {
     for (int kd = from; kd < kd_b;) {
       const int w = kd >> 6;
       if (w != mw) {
@@ -296,38 +363,70 @@ __global__ void __launch_bounds__(kYThreads, 2) k_yreduce(float2* __restrict__ X
       kd = (w + 1) << 6;
     }
     return kd_b;
-  };
-  auto load_col = [&](int kd, float2* v) {
-    const float2* xcol = X + kd * kstride + (int64_t)c0 * NY;
+  }
+};
+
+// CHI0: the aberration function and theta are identically zero, so every phase factor of Eq. 3
+// is exactly 1 and the sum adds G itself (conj G for mirrored frequencies): the same values the
+// general path produces for chi = 0, without evaluating them.
+
+template <typename XF, bool CHI0, bool PWRITE>
+__global__ void __launch_bounds__(kYThreads, 2) k_yreduce(YArgs a, Optics o) {
+  constexpr int NY = XF::N;
+  __shared__ float2 s_tw[XF::kPruned ? 1 : 1024];
+  __shared__ float2 s_buf[(XF::kMfma || XF::kPruned) ? 1 : 4 * kXWaveStride];
+  __shared__ uint4 s_tab[XF::kMfma ? kMfmaTab : 1];
+  constexpr int B = 1024 / NY;
+  using SL = XF;
+  constexpr int kSlotStride = 16 / SL::kSlots;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nx = a.nx;
+  const int nc = nx / 2 + 1;
+  const int ncs = (nc + B - 1) / B;                       // column sets
+  const int g = blockIdx.x % a.ngroups;
+  const int cs = (blockIdx.x / a.ngroups) * 4 + wave;     // this wave's column set
+  const int64_t wid = (int64_t)blockIdx.x * 4 + wave;
+  if constexpr (!XF::kPruned) {
+    fill_twiddles(s_tw, threadIdx.x, kYThreads);
+    __syncthreads();
+    XF::fill(s_tab, s_tw, threadIdx.x, kYThreads);
+    if (XF::kMfma) __syncthreads();
+  }
+  if (cs >= ncs) {
+    if (lane == 0 && !a.accumulate) a.wcnt[wid] = 0ull;
+    return;
+  }
+  float2* buf = s_buf + wave * kXWaveStride;
+  const int c0 = cs * B;
+  const int kd_a = a.k0 + (int)((int64_t)(a.k1 - a.k0) * g / a.ngroups);
+  const int kd_b = a.k0 + (int)((int64_t)(a.k1 - a.k0) * (g + 1) / a.ngroups);
+  float2 accd[16], accm[16];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      int b, n;
-      XF::in(lane, i, b, n);
-      v[i] = (c0 + b < nc) ? xcol[(int64_t)b * NY + n] : make_float2(0.f, 0.f);
-    }
-  };
+  for (int i = 0; i < 16; ++i) accd[i] = accm[i] = make_float2(0.f, 0.f);
+  unsigned cnt = 0, nld = 0;
+  MaskScan ms{a.cmask + (int64_t)cs * a.nmw, kd_b};
   // the columns of the next active pixel (of the next two on the zero-aberration path, whose sum
   // leaves the registers for it) are loaded while this one is transformed and summed
-  constexpr int kAhead = (CHI0 && ((!XF::kMfma && XF::kUniformCol) || (XF::kMfma && NY == 1024))) ? 2 : 1;
-  int kd = next_kd(kd_a);
-  int kd1 = kAhead == 2 && kd < kd_b ? next_kd(kd + 1) : kd_b;
+  constexpr int kAhead = (CHI0 && !PWRITE && ((!XF::kMfma && XF::kUniformCol) || (XF::kMfma && NY == 1024))) ? 2 : 1;
+  int kd = ms.next(kd_a);
+  int kd1 = kAhead == 2 && kd < kd_b ? ms.next(kd + 1) : kd_b;
   float2 v[16], v1[kAhead == 2 ? 16 : 1];
-  if (kd < kd_b) load_col(kd, v);
+  if (kd < kd_b) nld += load_pixel<XF>(a, kd, c0, lane, v);
   if constexpr (kAhead == 2) {
-    if (kd1 < kd_b) load_col(kd1, v1);
+    if (kd1 < kd_b) nld += load_pixel<XF>(a, kd1, c0, lane, v1);
   }
   while (kd < kd_b) {
     int kdn;
     float2 vn[16];
     if constexpr (kAhead == 2) {
       kdn = kd1;
-      kd1 = kd1 < kd_b ? next_kd(kd1 + 1) : kd_b;
-      if (kd1 < kd_b) load_col(kd1, vn);
+      kd1 = kd1 < kd_b ? ms.next(kd1 + 1) : kd_b;
+      if (kd1 < kd_b) nld += load_pixel<XF>(a, kd1, c0, lane, vn);
     } else {
-      kdn = next_kd(kd + 1);
-      if (kdn < kd_b) load_col(kdn, vn);
+      kdn = ms.next(kd + 1);
+      if (kdn < kd_b) nld += load_pixel<XF>(a, kdn, c0, lane, vn);
     }
-    const double2 k = kc[kd];
+    const double2 k = a.kc[kd];
     // double-overlap sets of this pixel for the lane's columns (direct and mirrored)
     ColSet sd[SL::kSlots], sm[SL::kSlots];
 #pragma unroll
@@ -337,16 +436,36 @@ __global__ void __launch_bounds__(kYThreads, 2) k_yreduce(float2* __restrict__ X
       const int c = c0 + b0;
       sd[sl] = ColSet{1, 0, 1, 0};
       sm[sl] = ColSet{1, 0, 1, 0};
-      if (c < nc) load_colsets(cst, (int64_t)kd * nc + c, sd[sl], sm[sl]);
+      if (c < nc) load_colsets(a.cst, (int64_t)kd * nc + c, sd[sl], sm[sl]);
     }
     XF::template run<false>(v, buf, s_tw, s_tab, lane);
-    if (store_g) {
-      float2* gcol = X + kd * kstride + (int64_t)c0 * NY;
+    if constexpr (PWRITE) {
+      // the double-overlap values of this pixel into the pruned array
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        int b, m;
-        XF::out(lane, i, b, m);
-        if (c0 + b < nc) gcol[(int64_t)b * NY + m] = v[i];
+      for (int sl = 0; sl < SL::kSlots; ++sl) {
+        int b0, m0;
+        XF::out(lane, sl * kSlotStride, b0, m0);
+        const int c = c0 + b0;
+        int64_t pd = 0, pm = 0;
+        if (c < nc) {
+          pd = a.poff[(int64_t)kd * nx + c];
+          if (c > 0 && 2 * c < nx) pm = a.poff[(int64_t)kd * nx + (nx - c)];
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          if (SL::slot_of(i) != sl) continue;
+          int b, m;
+          XF::out(lane, i, b, m);
+          const int iy = signed_index(m, NY), jy = signed_index((NY - m) & (NY - 1), NY);
+          if (c < nc && sd[sl].has(iy)) {
+            const int64_t e = pd + set_rank(sd[sl], iy);
+            if (e >= 0 && e < a.pcap) a.pgw[e] = v[i];
+          }
+          if (c < nc && sm[sl].has(jy)) {
+            const int64_t e = pm + set_rank(sm[sl], jy);
+            if (e >= 0 && e < a.pcap) a.pgw[e] = cconj(v[i]);
+          }
+        }
       }
     }
     if constexpr (CHI0 && !XF::kMfma && XF::kUniformCol) {
@@ -438,7 +557,7 @@ __global__ void __launch_bounds__(kYThreads, 2) k_yreduce(float2* __restrict__ X
         }
       }
     } else {
-      const double kch = kchi[kd];
+      const double kch = a.kchi[kd];
 #pragma unroll
       for (int sl = 0; sl < SL::kSlots; ++sl) {
         int b0, m0;
@@ -485,73 +604,84 @@ __global__ void __launch_bounds__(kYThreads, 2) k_yreduce(float2* __restrict__ X
       for (int i = 0; i < 16; ++i) v[i] = vn[i];
     }
   }
-  float2* pg = part + (int64_t)g * nx * NY;
+  float2* pgp = a.part + (int64_t)g * nx * NY;
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
     int b, m;
     XF::out(lane, i, b, m);
     const int c = c0 + b;
     if (c >= nc) continue;
-    pg[(int64_t)c * NY + m] = accd[i];
-    if (c > 0 && 2 * c < nx) pg[(int64_t)(nx - c) * NY + ((NY - m) & (NY - 1))] = accm[i];
+    float2* pd = pgp + (int64_t)c * NY + m;
+    float2* pm = pgp + (int64_t)(nx - c) * NY + ((NY - m) & (NY - 1));
+    const bool mir = c > 0 && 2 * c < nx;
+    if (a.accumulate) {
+      *pd = cadd(*pd, accd[i]);
+      if (mir) *pm = cadd(*pm, accm[i]);
+    } else {
+      *pd = accd[i];
+      if (mir) *pm = accm[i];
+    }
   }
-  unsigned long long cc = cnt;
+  unsigned long long cc = (unsigned long long)cnt + ((unsigned long long)nld << kLoadShift);
   for (int off = 32; off > 0; off >>= 1) cc += __shfl_xor(cc, off);
-  if (lane == 0) wcnt[blockIdx.x * 4 + wave] = cc;
+  if (lane == 0) a.wcnt[wid] = a.accumulate ? a.wcnt[wid] + cc : cc;
 }
 
-// Fused column transform + adjoint of Eq. 3 (G recomputed, never stored).  Same work split as
-// k_yreduce.  For every double-overlap pair, z = G e^{i psi} (conj G for mirrored frequencies),
-// w = Re(conj(Tbar(Q)) i z); dL/dc_j gains w (B_j(K - Q) - B_j(K)) and dL/dtheta[kd] loses w.
-// Partials: pdc[wave][8] (FP64), pdth[column set][kd] (FP32; one writer per entry).
+// Fused column transform + adjoint of Eq. 3.  Same work split as k_yreduce (also over chunks of
+// pixels, with `accumulate`).  For every double-overlap pair, z = G e^{i psi} (conj G for mirrored
+// frequencies), w = Re(conj(Tbar(Q)) i z); dL/dc_j gains w (B_j(K - Q) - B_j(K)) and
+// dL/dtheta[kd] loses w.  Along one column (fixed wx = lam dk (Kx - Qx)) every B_j(K - Q) is a
+// polynomial of degree <= 4 in wy = lam dk (Ky - Qy) whose coefficients are polynomials in wx, so
+// the pairs of a (pixel, column) are reduced to the moments M_n = sum w wy^n, n = 0..4, and the
+// eight gradient terms follow from them once per (pixel, column); sum w B_j(K) is B_j(K) times the
+// pixel's sum of w.  Partials: pdc[wave][8] (FP64), pdth[column set][kd] (FP32; one writer).
 template <typename XF>
-__global__ void __launch_bounds__(kYThreads, 2) k_yadjoint(const float2* __restrict__ X, const double2* __restrict__ kc,
-                                                        const double* __restrict__ kchi,
-                                                        const int4* __restrict__ cst, int n_k, int nx,
-                                                        int ngroups, Optics o, int g_stored,
-                                                        const float2* __restrict__ Tbt, double* __restrict__ pdc,
-                                                        float* __restrict__ pdth) {
+__global__ void __launch_bounds__(kYThreads, 2) k_yadjoint(YArgs a, Optics o) {
   constexpr int NY = XF::N;
-  __shared__ float2 s_tw[1024];
-  __shared__ float2 s_buf[XF::kMfma ? 1 : 4 * kXWaveStride];
+  __shared__ float2 s_tw[XF::kPruned ? 1 : 1024];
+  __shared__ float2 s_buf[(XF::kMfma || XF::kPruned) ? 1 : 4 * kXWaveStride];
   __shared__ uint4 s_tab[XF::kMfma ? kMfmaTab : 1];
   constexpr int B = 1024 / NY;
+  constexpr int kSlotStride = 16 / XF::kSlots;
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nx = a.nx;
   const int nc = nx / 2 + 1;
   const int ncs = (nc + B - 1) / B;
-  const int g = blockIdx.x % ngroups;
-  const int cs = (blockIdx.x / ngroups) * 4 + wave;
+  const int g = blockIdx.x % a.ngroups;
+  const int cs = (blockIdx.x / a.ngroups) * 4 + wave;
   const int64_t wid = (int64_t)blockIdx.x * 4 + wave;
-  fill_twiddles(s_tw, threadIdx.x, kYThreads);
-  __syncthreads();
-  XF::fill(s_tab, s_tw, threadIdx.x, kYThreads);
-  if (XF::kMfma) __syncthreads();
+  if constexpr (!XF::kPruned) {
+    fill_twiddles(s_tw, threadIdx.x, kYThreads);
+    __syncthreads();
+    XF::fill(s_tab, s_tw, threadIdx.x, kYThreads);
+    if (XF::kMfma) __syncthreads();
+  }
   if (cs >= ncs) {
-    if (lane < 8) pdc[wid * 8 + lane] = 0.0;
+    if (lane < 8 && !a.accumulate) a.pdc[wid * 8 + lane] = 0.0;
     return;
   }
   float2* buf = s_buf + wave * kXWaveStride;
   const int c0 = cs * B;
-  const int kd_a = (int)((int64_t)n_k * g / ngroups), kd_b = (int)((int64_t)n_k * (g + 1) / ngroups);
-  constexpr int kSlotStride = 16 / XF::kSlots;
-  float2 tbd[16], tbm[16];
-#pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    int b, m;
-    XF::out(lane, i, b, m);
-    const int c = c0 + b;
-    tbd[i] = c < nc ? Tbt[(int64_t)c * NY + m] : make_float2(0.f, 0.f);
-    tbm[i] = (c < nc && c > 0 && 2 * c < nx) ? Tbt[(int64_t)(nx - c) * NY + ((NY - m) & (NY - 1))]
-                                              : make_float2(0.f, 0.f);
-  }
+  const int kd_a = a.k0 + (int)((int64_t)(a.k1 - a.k0) * g / a.ngroups);
+  const int kd_b = a.k0 + (int)((int64_t)(a.k1 - a.k0) * (g + 1) / a.ngroups);
   double dc[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) dc[j] = 0.0;
-  const int64_t kstride = (int64_t)nc * NY;
-  for (int kd = kd_a; kd < kd_b; ++kd) {
-    const double2 k = kc[kd];
+  const double s2pi = 6.283185307179586476925286766559 / o.lam;
+  float* pth = a.pdth + (int64_t)cs * a.n_k;
+  MaskScan ms{a.cmask + (int64_t)cs * a.nmw, kd_b};
+  int done = kd_a;  // pixels below `done` have their dL/dtheta partial written
+  int kd = ms.next(kd_a);
+  float2 v[16];
+  if (kd < kd_b) load_pixel<XF>(a, kd, c0, lane, v);
+  while (kd < kd_b) {
+    const int kdn = ms.next(kd + 1);
+    float2 vn[16];
+    if (kdn < kd_b) load_pixel<XF>(a, kdn, c0, lane, vn);
+    if (lane == 0)
+      for (int z = done; z < kd; ++z) pth[z] = 0.f;  // pixels without pairs in these columns
+    const double2 k = a.kc[kd];
     ColSet sd[XF::kSlots], sm[XF::kSlots];
-    bool any = false;
 #pragma unroll
     for (int sl = 0; sl < XF::kSlots; ++sl) {
       int b0, m0;
@@ -559,78 +689,86 @@ __global__ void __launch_bounds__(kYThreads, 2) k_yadjoint(const float2* __restr
       const int c = c0 + b0;
       sd[sl] = ColSet{1, 0, 1, 0};
       sm[sl] = ColSet{1, 0, 1, 0};
-      if (c < nc) load_colsets(cst, (int64_t)kd * nc + c, sd[sl], sm[sl]);
-      any = any || !sd[sl].empty() || !sm[sl].empty();
+      if (c < nc) load_colsets(a.cst, (int64_t)kd * nc + c, sd[sl], sm[sl]);
     }
-    if (!__ballot(any)) {
-      if (lane == 0) pdth[(int64_t)cs * n_k + kd] = 0.f;
-      continue;
-    }
-    float2 v[16];
-    const float2* xcol = X + kd * kstride + (int64_t)c0 * NY;
-    if (g_stored) {
+    XF::template run<false>(v, buf, s_tw, s_tab, lane);
+    const double kch = a.kchi[kd];
+    double wl = 0.0;  // this lane's sum of w over the pixel's pairs
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        int b, m;
-        XF::out(lane, i, b, m);
-        v[i] = (c0 + b < nc) ? xcol[(int64_t)b * NY + m] : make_float2(0.f, 0.f);
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        int b, n;
-        XF::in(lane, i, b, n);
-        v[i] = (c0 + b < nc) ? xcol[(int64_t)b * NY + n] : make_float2(0.f, 0.f);
-      }
-      XF::template run<false>(v, buf, s_tw, s_tab, lane);
-    }
-    const double kch = kchi[kd];
-    double bk[8];
-    chi_basis(k.x, k.y, o, bk);
-    float wsum = 0.f;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      int b, m;
-      XF::out(lane, i, b, m);
-      int c = c0 + b;
-      asm volatile("" : "+v"(c), "+v"(m));  // see k_yreduce
-      if (c >= nc) continue;
-      const int sl = XF::slot_of(i);
+    for (int sl = 0; sl < XF::kSlots; ++sl) {
+      int b0, m0;
+      XF::out(lane, sl * kSlotStride, b0, m0);
+      const int c = c0 + b0;
       for (int side = 0; side < 2; ++side) {
-        int ix, iy;
-        if (side == 0) {
-          ix = signed_index(c, nx);
-          iy = signed_index(m, NY);
-          if (!sd[sl].has(iy)) continue;
-        } else {
-          ix = signed_index(nx - c, nx);
-          iy = signed_index((NY - m) & (NY - 1), NY);
-          if (!sm[sl].has(iy)) continue;  // empty unless 0 < c < Nx/2
+        const int ix = signed_index(side ? nx - c : c, nx);
+        const double wx = o.lk * (k.x - (double)ix * o.sx);
+        const ChiCol ch = chi_column(wx, o);
+        double M0 = 0.0, M1 = 0.0, M2 = 0.0, M3 = 0.0, M4 = 0.0;
+        bool any = false;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          if (XF::slot_of(i) != sl) continue;
+          int b, m;
+          XF::out(lane, i, b, m);
+          asm volatile("" : "+v"(m));  // see k_yreduce
+          const int iy = side ? signed_index((NY - m) & (NY - 1), NY) : signed_index(m, NY);
+          if (c >= nc || !(side ? sm[sl].has(iy) : sd[sl].has(iy))) continue;  // mirror empty unless 0 < c < Nx/2
+          const double wy = o.lk * (k.y - (double)iy * o.sy);
+          const float2 e = expi_reduced(chi_eval(ch, wy) - kch);
+          const float2 gq = side ? cconj(v[i]) : v[i];
+          const float2 z = make_float2(gq.x * e.x - gq.y * e.y, gq.x * e.y + gq.y * e.x);
+          // Tbar at this pair's frequency (read when needed: kept in registers for every frequency
+          // of the lane, it costs occupancy)
+          const float2 tb = side ? a.Tbt[(int64_t)(nx - c) * NY + ((NY - m) & (NY - 1))] : a.Tbt[(int64_t)c * NY + m];
+          const double w = (double)(tb.x * (-z.y) + tb.y * z.x);
+          any = true;
+          double t = w;
+          M0 += t;
+          t *= wy;
+          M1 += t;
+          t *= wy;
+          M2 += t;
+          t *= wy;
+          M3 += t;
+          t *= wy;
+          M4 += t;
         }
-        const double qx = (double)ix * o.sx, qy = (double)iy * o.sy;
-        double bm[8];
-        chi_basis(k.x - qx, k.y - qy, o, bm);
-        double chim = 0.0;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) chim += o.c[j] * bm[j];
-        const float2 e = expi_reduced(chim - kch);
-        const float2 gq = side ? cconj(v[i]) : v[i];
-        const float2 z = make_float2(gq.x * e.x - gq.y * e.y, gq.x * e.y + gq.y * e.x);
-        const float2 tb = side ? tbm[i] : tbd[i];
-        const float w = tb.x * (-z.y) + tb.y * z.x;
-        wsum += w;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) dc[j] += (double)w * (bm[j] - bk[j]);
+        if (any) {
+          // sum over the column's pairs of w B_j(K - Q), B_j as polynomials in wy
+          const double x2 = wx * wx, x3 = x2 * wx, x4 = x2 * x2;
+          dc[0] += 0.5 * s2pi * (x2 * M0 + M2);
+          dc[1] += 0.5 * s2pi * (x2 * M0 - M2);
+          dc[2] += s2pi * (wx * M1);
+          dc[3] += (s2pi / 3.0) * (x3 * M0 + wx * M2);
+          dc[4] += (s2pi / 3.0) * (x2 * M1 + M3);
+          dc[5] += (s2pi / 3.0) * (x3 * M0 - 3.0 * wx * M2);
+          dc[6] += (s2pi / 3.0) * (3.0 * x2 * M1 - M3);
+          dc[7] += 0.25 * s2pi * (x4 * M0 + 2.0 * x2 * M2 + M4);
+          wl += M0;
+        }
       }
     }
+    if (wl != 0.0) {
+      double bk[8];
+      chi_basis(k.x, k.y, o, bk);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) dc[j] -= bk[j] * wl;
+    }
+    float wsum = (float)wl;
     for (int off = 32; off > 0; off >>= 1) wsum += __shfl_xor(wsum, off);
-    if (lane == 0) pdth[(int64_t)cs * n_k + kd] = -wsum;
+    if (lane == 0) pth[kd] = -wsum;
+    done = kd + 1;
+    kd = kdn;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = vn[i];
   }
+  if (lane == 0)
+    for (int z = done; z < kd_b; ++z) pth[z] = 0.f;
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
-    double v = dc[j];
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    if (lane == 0) pdc[wid * 8 + j] = v;
+    double t = dc[j];
+    for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
+    if (lane == 0) a.pdc[wid * 8 + j] = a.accumulate ? a.pdc[wid * 8 + j] + t : t;
   }
 }
 
@@ -661,22 +799,37 @@ int launch_xstage_p(int nx, const DT* D, int ny, int ry0, int nr, int64_t nrows,
   return STEM_OK;
 }
 
-template <int PREC>
-int launch_yreduce_p(int ny, float2* X, const double2* kc, const double* kchi, const int4* cst,
-                     const uint64_t* cmask, int nmw, int n_k, int nx, int ngroups, const Optics& o,
-                     int store_g, int chi0, float2* part, unsigned long long* wcnt, hipStream_t s) {
+// grid of the fused column kernels: column sets in fours (one per wave) times pixel groups
+inline dim3 ygrid(int ny, int nx, int ngroups) {
   const int B = 1024 / ny;
   const int ncs = (nx / 2 + 1 + B - 1) / B;
-  const dim3 grid((unsigned)(((ncs + 3) / 4) * ngroups)), blk(kYThreads);
-  STEM_TRACE(PREC == STEM_FFT_FP32 ? "ssb_yreduce" : "ssb_yreduce_mfma", s);
+  return dim3((unsigned)(((ncs + 3) / 4) * ngroups));
+}
+
+// the fused sum over pixels [a.k0, a.k1): transform policy of precision PREC, or the pruned G
+// (PREC < 0); pwrite: also write the pruned G
+template <int PREC>
+int launch_yreduce_p(int ny, const YArgs& a, const Optics& o, int chi0, int pwrite, hipStream_t s) {
+  const dim3 grid = ygrid(ny, a.nx, a.ngroups), blk(kYThreads);
+  STEM_TRACE(PREC < 0 ? "ssb_reduce" : PREC == STEM_FFT_FP32 ? "ssb_yreduce" : "ssb_yreduce_mfma", s);
   const int st = with_n(ny, [&](auto nc) {
-    using XF = typename XfSel<decltype(nc)::value, PREC>::type;
-    if (chi0)
-      hipLaunchKernelGGL((k_yreduce<XF, true>), grid, blk, 0, s, X, kc, kchi, cst, cmask, nmw, n_k, nx, ngroups, o,
-                         store_g, part, wcnt);
-    else
-      hipLaunchKernelGGL((k_yreduce<XF, false>), grid, blk, 0, s, X, kc, kchi, cst, cmask, nmw, n_k, nx, ngroups, o,
-                         store_g, part, wcnt);
+    constexpr int N = decltype(nc)::value;
+    using XF = std::conditional_t<(PREC < 0), XfPruned<N>, typename XfSel<N, (PREC < 0 ? 0 : PREC)>::type>;
+    if constexpr (PREC < 0) {
+      if (chi0)
+        hipLaunchKernelGGL((k_yreduce<XF, true, false>), grid, blk, 0, s, a, o);
+      else
+        hipLaunchKernelGGL((k_yreduce<XF, false, false>), grid, blk, 0, s, a, o);
+    } else {
+      if (chi0 && pwrite)
+        hipLaunchKernelGGL((k_yreduce<XF, true, true>), grid, blk, 0, s, a, o);
+      else if (chi0)
+        hipLaunchKernelGGL((k_yreduce<XF, true, false>), grid, blk, 0, s, a, o);
+      else if (pwrite)
+        hipLaunchKernelGGL((k_yreduce<XF, false, true>), grid, blk, 0, s, a, o);
+      else
+        hipLaunchKernelGGL((k_yreduce<XF, false, false>), grid, blk, 0, s, a, o);
+    }
   });
   if (st) return st;
   STEM_LAUNCH_CHECK();
@@ -684,17 +837,13 @@ int launch_yreduce_p(int ny, float2* X, const double2* kc, const double* kchi, c
 }
 
 template <int PREC>
-int launch_yadjoint_p(int ny, const float2* X, const double2* kc, const double* kchi, const int4* cst, int n_k,
-                      int nx, int ngroups,
-                      const Optics& o, int g_stored, const float2* Tbt, double* pdc, float* pdth, hipStream_t s) {
-  const int B = 1024 / ny;
-  const int ncs = (nx / 2 + 1 + B - 1) / B;
-  const dim3 grid((unsigned)(((ncs + 3) / 4) * ngroups)), blk(kYThreads);
-  STEM_TRACE(PREC == STEM_FFT_FP32 ? "ssb_yadjoint" : "ssb_yadjoint_mfma", s);
+int launch_yadjoint_p(int ny, const YArgs& a, const Optics& o, hipStream_t s) {
+  const dim3 grid = ygrid(ny, a.nx, a.ngroups), blk(kYThreads);
+  STEM_TRACE(PREC < 0 ? "ssb_adjoint_pruned" : PREC == STEM_FFT_FP32 ? "ssb_yadjoint" : "ssb_yadjoint_mfma", s);
   const int st = with_n(ny, [&](auto nc) {
-    using XF = typename XfSel<decltype(nc)::value, PREC>::type;
-    hipLaunchKernelGGL((k_yadjoint<XF>), grid, blk, 0, s, X, kc, kchi, cst, n_k, nx, ngroups, o, g_stored, Tbt,
-                       pdc, pdth);
+    constexpr int N = decltype(nc)::value;
+    using XF = std::conditional_t<(PREC < 0), XfPruned<N>, typename XfSel<N, (PREC < 0 ? 0 : PREC)>::type>;
+    hipLaunchKernelGGL((k_yadjoint<XF>), grid, blk, 0, s, a, o);
   });
   if (st) return st;
   STEM_LAUNCH_CHECK();
@@ -703,15 +852,11 @@ int launch_yadjoint_p(int ny, const float2* X, const double2* kc, const double* 
 
 extern template int launch_xstage_p<STEM_DFT_BF16_SPLIT, uint8_t>(int, const uint8_t*, int, int, int, int64_t, float2*, hipStream_t);
 extern template int launch_xstage_p<STEM_DFT_BF16_SPLIT, uint16_t>(int, const uint16_t*, int, int, int, int64_t, float2*, hipStream_t);
-extern template int launch_yreduce_p<STEM_DFT_BF16_SPLIT>(int, float2*, const double2*, const double*, const int4*, const uint64_t*, int, int, int, int,
-                                            const Optics&, int, int, float2*, unsigned long long*, hipStream_t);
-extern template int launch_yadjoint_p<STEM_DFT_BF16_SPLIT>(int, const float2*, const double2*, const double*, const int4*, int, int, int,
-                                             const Optics&, int, const float2*, double*, float*, hipStream_t);
+extern template int launch_yreduce_p<STEM_DFT_BF16_SPLIT>(int, const YArgs&, const Optics&, int, int, hipStream_t);
+extern template int launch_yadjoint_p<STEM_DFT_BF16_SPLIT>(int, const YArgs&, const Optics&, hipStream_t);
 extern template int launch_xstage_p<STEM_DFT_FP16_SPLIT, uint8_t>(int, const uint8_t*, int, int, int, int64_t, float2*, hipStream_t);
 extern template int launch_xstage_p<STEM_DFT_FP16_SPLIT, uint16_t>(int, const uint16_t*, int, int, int, int64_t, float2*, hipStream_t);
-extern template int launch_yreduce_p<STEM_DFT_FP16_SPLIT>(int, float2*, const double2*, const double*, const int4*, const uint64_t*, int, int, int, int,
-                                            const Optics&, int, int, float2*, unsigned long long*, hipStream_t);
-extern template int launch_yadjoint_p<STEM_DFT_FP16_SPLIT>(int, const float2*, const double2*, const double*, const int4*, int, int, int,
-                                             const Optics&, int, const float2*, double*, float*, hipStream_t);
+extern template int launch_yreduce_p<STEM_DFT_FP16_SPLIT>(int, const YArgs&, const Optics&, int, int, hipStream_t);
+extern template int launch_yadjoint_p<STEM_DFT_FP16_SPLIT>(int, const YArgs&, const Optics&, hipStream_t);
 
 }  // namespace stem

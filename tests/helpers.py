@@ -80,9 +80,9 @@ def oracle_ssb(idx, off, wl, c=(0.0,) * 8, theta=None, normalize=False, direct=F
 
 
 def gpu_ssb(d_idx, d_off, wl, c=(0.0,) * 8, theta=None, normalize=0, g_mode=stem.STEM_G_STORE, d_bits=8,
-            chunk_rows=None, precision=stem.STEM_FFT_FP32):
+            chunk_rows=None, precision=stem.STEM_FFT_FP32, scratch_mib=0):
     det, scan, optics = structs(wl, c)
-    ssb = stem.Ssb(precision, normalize, g_mode, d_bits)
+    ssb = stem.Ssb(precision, normalize, g_mode, d_bits, scratch_mib)
     st = stem.SsbState(det, scan, optics, ssb, device=d_idx.device)
     F = wl.n_frames
     ny, nx = wl.scan
@@ -110,12 +110,67 @@ def state_D(st, wl):
     return D.reshape(st.n_k, wl.n_frames).astype(np.int64)
 
 
-def state_G_half(st, wl):
-    """G[kd][mx][my] for mx in [0, Nx/2] -> array [kd][my][mx_half]."""
+def state_X(st, wl):
+    """Row-transformed cube X[kd][mx][ry] (STEM_G_STORE, after ACCUMULATE) -> array [kd][ry][mx_half]."""
     ny, nx = wl.scan
-    raw = st.region(stem.STEM_REGION_G).view(torch.complex64).cpu().numpy()
+    raw = st.region(stem.STEM_REGION_X).view(torch.complex64).cpu().numpy()
     return raw.reshape(st.n_k, nx // 2 + 1, ny).transpose(0, 2, 1)
+
+
+def oracle_row_dft(D, wl):
+    """The DFT along rx of every row of the oracle's cube, first Nx/2 + 1 frequencies: [kd][ry][mx]."""
+    ny, nx = wl.scan
+    D3 = ossb.cube(D, ny, nx).astype(np.complex128)
+    return np.matmul(D3, ossb.dft_matrix(nx).T[None])[:, :, :nx // 2 + 1]
+
+
+def state_pruned(st):
+    """(pruned G values, offsets) of a STEM_G_STORE state after FINALIZE."""
+    poff = st.region(stem.STEM_REGION_POFF).view(torch.int64).cpu().numpy()
+    n = int(poff[-1])
+    pg = st.region(stem.STEM_REGION_PG).view(torch.complex64)[:n].cpu().numpy()
+    return pg, poff
+
+
+def oracle_pruned(G, kc, wl):
+    """G on the double-overlap pairs in the pruned layout, from the oracle's full G[kd][my][mx] and
+    set (ossb.double_overlap): pixel-major, then column mx in [0, Nx), then ascending signed my;
+    and the offsets of every (pixel, column) run."""
+    ny, nx = wl.scan
+    qx, qy = ossb.scan_q_grid(ny, nx, wl.step, wl.dk)
+    order = np.argsort(ossb.signed_freq_index(ny), kind="stable")  # rows by ascending signed my
+    vals, sizes = [], []
+    r2 = float(wl.r_bf) * float(wl.r_bf)
+    for kd in range(len(kc)):
+        m = ossb.double_overlap(float(kc[kd, 0]), float(kc[kd, 1]), qx, qy, r2)[order].T  # [mx][iy]
+        g = G[kd][order].T
+        vals.append(g[m])
+        sizes.append(m.sum(axis=1))
+    sizes = np.concatenate(sizes).astype(np.int64)
+    poff = np.concatenate([[0], np.cumsum(sizes)])
+    return np.concatenate(vals), poff
+
+
+def state_npair(st, wl):
+    """Per-Q pair counts (after a FINALIZE with normalize = 1) as [my][mx]."""
+    ny, nx = wl.scan
+    return st.region(stem.STEM_REGION_NPAIR).view(torch.int32).cpu().numpy().reshape(nx, ny).T
 
 
 def state_kc(st):
     return st.region(stem.STEM_REGION_KC).view(torch.float64).cpu().numpy().reshape(st.n_k, 2)
+
+
+def q_error_scale(G_ref, kc, wl):
+    """Per-Q scale of the error of T: the root sum of squares of its summands |G(K, Q)| over the
+    double-overlap set, plus sqrt(n(Q)) times the rms of G (the floor of a transform's rounding for
+    small elements).  A wrong membership or a wrong term at a single Q moves the error relative to
+    this scale by about 1/sqrt(n(Q))."""
+    s2, npair = ossb.ssb_sum(np.abs(G_ref) ** 2, kc, wl.step, wl.dk, wl.lam, wl.r_bf)
+    g_rms = float(np.sqrt(np.mean(np.abs(G_ref) ** 2)))
+    return np.sqrt(np.abs(s2)) + np.sqrt(npair) * g_rms + 1e-30
+
+
+def per_q_error(T, T_ref, scale):
+    """Largest error of T over the scan frequencies, each relative to its own scale."""
+    return float(np.max(np.abs(np.asarray(T) - T_ref) / scale))

@@ -67,22 +67,64 @@ def test_off_centre_and_fractional_radius():
 def test_state_size_and_regions():
     wl = WORKLOADS["scan1024"]
     det, scan, optics = _geom(wl)
-    ssb = stem.Ssb(stem.STEM_FFT_FP32, 0, stem.STEM_G_STORE, 8)
-    total = stem.ssb_state_bytes(det, scan, optics, ssb)
     n_k = stem.ssb_num_pixels(det, optics)
     F = wl.n_frames
-    regions = {}
-    for r in (stem.STEM_REGION_D, stem.STEM_REGION_G, stem.STEM_REGION_T, stem.STEM_REGION_KC):
-        off, nb = stem.ssb_state_region(det, scan, optics, ssb, r)
-        assert off % 256 == 0 and off + nb <= total
-        regions[r] = (off, nb)
-    assert regions[stem.STEM_REGION_D][1] == n_k * F
-    assert regions[stem.STEM_REGION_G][1] == n_k * (1024 // 2 + 1) * 1024 * 8
-    assert regions[stem.STEM_REGION_KC][1] == n_k * 16
-    # disjoint
-    spans = sorted(regions.values())
-    for (o1, n1), (o2, _) in zip(spans, spans[1:]):
-        assert o1 + n1 <= o2
+    col = (1024 // 2 + 1) * 1024 * 8  # bytes of one pixel's row-transformed columns
+    for g_mode in (stem.STEM_G_STORE, stem.STEM_G_RECOMPUTE):
+        ssb = stem.Ssb(stem.STEM_FFT_FP32, 0, g_mode, 8)
+        total = stem.ssb_state_bytes(det, scan, optics, ssb)
+        regions = {}
+        for r in (stem.STEM_REGION_D, stem.STEM_REGION_X, stem.STEM_REGION_T, stem.STEM_REGION_KC,
+                  stem.STEM_REGION_STATS, stem.STEM_REGION_PG, stem.STEM_REGION_POFF, stem.STEM_REGION_NPAIR):
+            off, nb = stem.ssb_state_region(det, scan, optics, ssb, r)
+            assert off % 256 == 0 and off + nb <= total
+            regions[r] = (off, nb)
+        assert regions[stem.STEM_REGION_D][1] == n_k * F
+        assert regions[stem.STEM_REGION_KC][1] == n_k * 16
+        assert regions[stem.STEM_REGION_NPAIR][1] == 4 * F
+        if g_mode == stem.STEM_G_STORE:
+            assert regions[stem.STEM_REGION_X][1] == n_k * col
+            assert regions[stem.STEM_REGION_POFF][1] == 8 * (n_k * 1024 + 1)
+            # the pruned array's bound: at least the 2.80e7 pairs, well below the whole G
+            assert 28_009_112 * 8 <= regions[stem.STEM_REGION_PG][1] <= 0.5 * n_k * col
+        else:
+            # a bounded scratch of whole pixels (64 MiB by default), no pruned G
+            assert col <= regions[stem.STEM_REGION_X][1] <= 64 << 20
+            assert regions[stem.STEM_REGION_X][1] % col == 0
+            assert regions[stem.STEM_REGION_PG][1] == 0 and regions[stem.STEM_REGION_POFF][1] == 0
+        spans = sorted(v for v in regions.values() if v[1] > 0)
+        for (o1, n1), (o2, _) in zip(spans, spans[1:]):
+            assert o1 + n1 <= o2
+
+
+@pytest.mark.parametrize("name", ["aberrated512", "scan1024"])
+def test_recompute_state_is_a_fraction_of_store(name):
+    """G recomputed in bounded chunks needs well under half the state of the stored-G mode."""
+    wl = WORKLOADS[name]
+    det, scan, optics = _geom(wl)
+    st = stem.ssb_state_bytes(det, scan, optics, stem.Ssb(stem.STEM_FFT_FP32, 0, stem.STEM_G_STORE, 8))
+    rc = stem.ssb_state_bytes(det, scan, optics, stem.Ssb(stem.STEM_FFT_FP32, 0, stem.STEM_G_RECOMPUTE, 8))
+    rc16 = stem.ssb_state_bytes(det, scan, optics, stem.Ssb(stem.STEM_FFT_FP32, 0, stem.STEM_G_RECOMPUTE, 8, 16))
+    assert rc < 0.4 * st
+    assert rc16 < rc
+
+
+def test_pruned_capacity_bounds_the_pair_count():
+    """The pruned array's capacity (a lattice-point bound per pixel) holds every double-overlap pair
+    the oracle counts, for several geometries."""
+    from oracle import ssb as ossb
+    for (ny, nx, step, b, r) in [(32, 32, 0.2, 1, 16.0), (64, 32, 0.25, 2, 16.0), (32, 128, 0.15, 1, 12.5)]:
+        W = H = 64
+        dk = (0.025 / 0.0196875) / r
+        det = stem.Det(W, H, W // 2, H // 2, b)
+        scan = stem.Scan(ny, nx, step)
+        optics = stem.Optics.from_values(0.0196875, r, dk)
+        ssb = stem.Ssb(stem.STEM_FFT_FP32, 0, stem.STEM_G_STORE, 8)
+        _, nb = stem.ssb_state_region(det, scan, optics, ssb, stem.STEM_REGION_PG)
+        kc, _ = oeer.bin_geometry(W, H, b, r)
+        qx, qy = ossb.scan_q_grid(ny, nx, step, dk)
+        P = sum(int(ossb.double_overlap(kx, ky, qx, qy, r * r).sum()) for kx, ky in kc)
+        assert P * 8 <= nb <= 3 * P * 8
 
 
 def test_host_argument_errors_return_einval_without_device_work():
@@ -116,11 +158,10 @@ def test_host_argument_errors_return_einval_without_device_work():
     big = stem.ssb_state_bytes(det, scan, optics, ssb)
     assert L.ssb_reconstruct(fake, fake, 5, 64, ctypes.byref(det), ctypes.byref(scan), ctypes.byref(optics),
                              ctypes.byref(ssb), 0, None, fake, big, None, None, None, None) == 1
-    # refocus needs a stored G
-    rec = stem.Ssb(stem.STEM_FFT_FP32, 0, stem.STEM_G_RECOMPUTE, 8)
-    big_r = stem.ssb_state_bytes(det, scan, optics, rec)
-    assert L.ssb_reconstruct(None, None, 0, 0, ctypes.byref(det), ctypes.byref(scan), ctypes.byref(optics),
-                             ctypes.byref(rec), 2, None, fake, big_r, None, None, None, None) == 64
+    # option values outside their range
+    for bad in (stem.Ssb(stem.STEM_FFT_FP32, 2, stem.STEM_G_STORE, 8), stem.Ssb(stem.STEM_FFT_FP32, 0, 2, 8),
+                stem.Ssb(3, 0, stem.STEM_G_STORE, 8), stem.Ssb(stem.STEM_FFT_FP32, 0, stem.STEM_G_RECOMPUTE, 8, -1)):
+        assert L.ssb_state_bytes(ctypes.byref(det), ctypes.byref(scan), ctypes.byref(optics), ctypes.byref(bad)) == 0
     # the fused centre of mass: only ACCUMULATE / ONESHOT, at least one output, detectors < 65536
     com = lambda mode, c64=fake, d=det: L.ssb_reconstruct_com(fake, fake, 0, 1024, ctypes.byref(d),
                                                               ctypes.byref(scan), ctypes.byref(optics),

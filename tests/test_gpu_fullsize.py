@@ -20,7 +20,8 @@ from oracle import dpc as odpc
 from oracle import eer as oeer
 from oracle import ssb as ossb
 
-from helpers import gpu_ssb, rel_l2, state_D, state_G_half, structs
+from helpers import (gpu_ssb, oracle_pruned, per_q_error, q_error_scale, rel_l2, state_D, state_npair,
+                     state_pruned, state_X, structs)
 
 pytestmark = pytest.mark.gpu
 
@@ -71,6 +72,10 @@ def oracle(name, key):
         ref[key] = ossb.ssb_sum(oracle(name, "G"), kc, wl.step, wl.dk, wl.lam, wl.r_bf, wl.aberr)
     elif key == "phi":
         ref[key] = ossb.phase_from_T(oracle(name, "T")[0])
+    elif key == "pruned":
+        ref[key] = oracle_pruned(oracle(name, "G"), oracle(name, "geom")[0], wl)
+    elif key == "qscale":
+        ref[key] = q_error_scale(oracle(name, "G"), oracle(name, "geom")[0], wl)
     log(f"{name}: oracle {key} in {time.time() - t0:.1f} s")
     return ref[key]
 
@@ -80,16 +85,31 @@ def _announce(request):
     print(f"\n[gpu] {request.node.name}", flush=True)
 
 
-def g_half_error(st, wl, G):
-    """rel L2 of the stored half spectrum against the oracle's, one pixel at a time."""
-    nh = wl.scan[1] // 2 + 1
-    Gg = state_G_half(st, wl)
+def x_error(st, wl, D):
+    """rel L2 of the stored row transform against numpy's FP64 row FFT of the oracle's cube, one
+    pixel at a time; also whether the zero-frequency column equals the row sums exactly."""
+    ny, nx = wl.scan
+    nh = nx // 2 + 1
+    X = state_X(st, wl)
     num = den = 0.0
-    for kd in range(G.shape[0]):
-        r = G[kd, :, :nh]
-        num += float(np.sum(np.abs(Gg[kd] - r) ** 2))
+    dc_exact = True
+    for kd in range(D.shape[0]):
+        d = D[kd].reshape(ny, nx)
+        r = np.fft.fft(d.astype(np.float64), axis=1)[:, :nh]
+        num += float(np.sum(np.abs(X[kd] - r) ** 2))
         den += float(np.sum(np.abs(r) ** 2))
-    return np.sqrt(num / den), Gg
+        dc_exact &= bool(np.array_equal(X[kd, :, 0].real.astype(np.float64), d.sum(axis=1).astype(np.float64))
+                         and np.all(X[kd, :, 0].imag == 0))
+    return np.sqrt(num / den), dc_exact
+
+
+def pruned_error(st, name):
+    """Offsets of the stored double-overlap values equal the oracle's run lengths (the sets agree
+    pair by pair); rel L2 of the values against the oracle's G on those pairs."""
+    wl = case(name)[0]
+    pg, poff = state_pruned(st)
+    ref, poff_ref = oracle(name, "pruned")
+    return bool(np.array_equal(poff, poff_ref)), rel_l2(pg, ref)
 
 
 @pytest.mark.parametrize("name", ["scan256", "scan1024", "aberrated512"])
@@ -148,30 +168,56 @@ def test_full_com_from_binning_pass(gpu, name):
 
 @pytest.mark.parametrize("name", ["scan256", "scan1024", "aberrated512"])
 def test_full_binning_transform_and_sum(gpu, name):
-    """Stored-G mode: binned cube bit-exact, G, T and phi against the oracle."""
+    """Stored-G mode: binned cube bit-exact; the row transform (its zero-frequency column exactly
+    the row sums); G on every double-overlap pair (the sets equal pair by pair); T per Q and phi
+    against the oracle."""
     wl, d_idx, d_off, idx, off, _ = case(name)
     st, out = gpu_ssb(d_idx, d_off, wl, c=wl.aberr)
     assert out["status"] == 0
     assert np.array_equal(state_D(st, wl), oracle(name, "D"))
-    G = oracle(name, "G")
-    eg, Gg = g_half_error(st, wl, G)
-    assert np.array_equal(Gg[:, 0, 0].real.astype(np.float64), oracle(name, "D").sum(axis=1).astype(np.float64))
+    ex, dc_exact = x_error(st, wl, oracle(name, "D"))
+    assert dc_exact
+    same_sets, eg = pruned_error(st, name)
+    assert same_sets
     T, npair = oracle(name, "T")
     et, ep = rel_l2(out["T"], T), rel_l2(out["phi"], oracle(name, "phi"))
-    log(f"{name}: FP32 rel L2 G {eg:.2e} T {et:.2e} phi {ep:.2e}")
-    assert eg <= TOL and et <= TOL and ep <= TOL
+    eq = per_q_error(out["T"], T, oracle(name, "qscale"))
+    emax = float(np.max(np.abs(out["phi"] - oracle(name, "phi"))) / np.max(np.abs(oracle(name, "phi"))))
+    log(f"{name}: FP32 rel L2 X {ex:.2e} G {eg:.2e} T {et:.2e} phi {ep:.2e}; worst Q {eq:.2e}, max|dphi| {emax:.2e}")
+    assert ex <= TOL and eg <= TOL and et <= TOL and ep <= TOL
+    assert eq <= 1e-4 and emax <= 1e-4
     assert st.pair_count() == int(npair.sum())
 
 
 @pytest.mark.parametrize("name", ["scan256", "scan1024", "aberrated512"])
 def test_full_recompute_mode(gpu, name):
-    """The benchmark's mode: G recomputed in the fused column kernel, never stored."""
+    """G recomputed chunk by chunk (bounded scratch) from the binned counts, never stored."""
     wl, d_idx, d_off, idx, off, _ = case(name)
     st, out = gpu_ssb(d_idx, d_off, wl, c=wl.aberr, g_mode=stem.STEM_G_RECOMPUTE)
     assert out["status"] == 0
-    et, ep = rel_l2(out["T"], oracle(name, "T")[0]), rel_l2(out["phi"], oracle(name, "phi"))
-    log(f"{name}: recompute rel L2 T {et:.2e} phi {ep:.2e}")
-    assert et <= TOL and ep <= TOL
+    T = oracle(name, "T")[0]
+    et, ep = rel_l2(out["T"], T), rel_l2(out["phi"], oracle(name, "phi"))
+    eq = per_q_error(out["T"], T, oracle(name, "qscale"))
+    log(f"{name}: recompute ({st.stats()[3]} chunks) rel L2 T {et:.2e} phi {ep:.2e}; worst Q {eq:.2e}")
+    assert et <= TOL and ep <= TOL and eq <= 1e-4
+    assert st.stats()[3] >= 1 and st.pair_count() == int(oracle(name, "T")[1].sum())
+
+
+def test_full_normalised_per_q_counts_scan1024(gpu):
+    """The normalised sum at 1024x1024: the number of double-overlap pixels of every Q equals the
+    oracle's, frequency by frequency, and T / n is right element by element."""
+    name = "scan1024"
+    wl, d_idx, d_off, idx, off, _ = case(name)
+    st, out = gpu_ssb(d_idx, d_off, wl, c=wl.aberr, normalize=1, g_mode=stem.STEM_G_RECOMPUTE)
+    assert out["status"] == 0
+    T, npair = oracle(name, "T")
+    assert np.array_equal(state_npair(st, wl), npair)
+    Tn = np.where(npair > 0, T / np.maximum(npair, 1), 0.0)
+    scale = np.maximum(npair, 1)
+    eq = per_q_error(out["T"] * scale, Tn * scale, oracle(name, "qscale"))
+    log(f"{name}: normalised worst Q {eq:.2e}, rel L2 {rel_l2(out['T'], Tn):.2e}")
+    assert eq <= 1e-4 and rel_l2(out["T"], Tn) <= TOL
+    assert np.all(out["T"][npair == 0] == 0)
 
 
 @pytest.mark.parametrize("prec", [stem.STEM_DFT_BF16_SPLIT, stem.STEM_DFT_FP16_SPLIT], ids=["bf16", "fp16"])
@@ -181,14 +227,44 @@ def test_full_split_precision(gpu, prec):
     wl, d_idx, d_off, idx, off, _ = case(name)
     st, out = gpu_ssb(d_idx, d_off, wl, c=wl.aberr, precision=prec)
     assert out["status"] == 0
-    eg, Gg = g_half_error(st, wl, oracle(name, "G"))
-    assert np.array_equal(Gg[:, 0, 0].real.astype(np.float64), oracle(name, "D").sum(axis=1).astype(np.float64))
+    ex, dc_exact = x_error(st, wl, oracle(name, "D"))
+    assert dc_exact
+    same_sets, eg = pruned_error(st, name)
+    assert same_sets
     et, ep = rel_l2(out["T"], oracle(name, "T")[0]), rel_l2(out["phi"], oracle(name, "phi"))
-    log(f"{name}: split prec={prec} rel L2 G {eg:.2e} T {et:.2e} phi {ep:.2e}")
-    assert eg <= TOL_SPLIT and et <= TOL_SPLIT and ep <= TOL_SPLIT
+    log(f"{name}: split prec={prec} rel L2 X {ex:.2e} G {eg:.2e} T {et:.2e} phi {ep:.2e}")
+    assert ex <= TOL_SPLIT and eg <= TOL_SPLIT and et <= TOL_SPLIT and ep <= TOL_SPLIT
     del st
     _, out2 = gpu_ssb(d_idx, d_off, wl, c=wl.aberr, g_mode=stem.STEM_G_RECOMPUTE, precision=prec)
     assert rel_l2(out2["phi"], oracle(name, "phi")) <= TOL_SPLIT
+
+
+@pytest.mark.parametrize("g_mode", [stem.STEM_G_RECOMPUTE, stem.STEM_G_STORE], ids=["recompute", "store"])
+def test_full_adjoint_with_probe_phase(gpu, g_mode):
+    """The adjoint at 512x512 with a per-pixel probe phase theta: dL/dc component by component
+    and dL/dtheta against the oracle gradient, G recomputed in chunks or read from the stored
+    double-overlap values."""
+    name = "aberrated512"
+    wl, d_idx, d_off, idx, off, _ = case(name)
+    rng = np.random.default_rng(12)
+    c0 = np.array(wl.aberr) * (1 + rng.uniform(-0.5, 0.5, size=8))
+    kc = oracle(name, "geom")[0]
+    theta = rng.uniform(-0.2, 0.2, size=len(kc)).astype(np.float32)
+    st, out = gpu_ssb(d_idx, d_off, wl, c=c0, theta=theta, g_mode=g_mode)
+    assert out["status"] == 0
+    phi = torch.from_numpy(out["phi"]).cuda().view(-1)
+    gbar = (-(2.0 / phi.numel()) * (phi - phi.mean())).contiguous()
+    dc, dth = st.backward(gbar, c=c0, theta=torch.from_numpy(theta).cuda())
+    G = oracle(name, "G")
+    T, _ = ossb.ssb_sum(G, kc, wl.step, wl.dk, wl.lam, wl.r_bf, c0, theta)
+    phio = ossb.phase_from_T(T)
+    assert rel_l2(out["phi"], phio) <= TOL
+    dco, dtho = ossb.ssb_adjoint(G, kc, ossb.neg_var_grad(phio), wl.step, wl.dk, wl.lam, wl.r_bf, c0, theta)
+    dc, dth = dc.cpu().numpy(), dth.cpu().numpy()
+    log(f"{name} ({g_mode}): dL/dc rel per component {np.abs(dc - dco) / np.abs(dco)}, "
+        f"dL/dtheta rel L2 {rel_l2(dth, dtho):.2e}")
+    assert np.all(np.abs(dc - dco) <= 1e-4 * np.abs(dco) + 1e-6 * np.max(np.abs(dco)))
+    assert rel_l2(dth, dtho) <= 1e-4
 
 
 def test_full_adjoint(gpu):

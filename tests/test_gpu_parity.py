@@ -12,8 +12,8 @@ from gen import C4_TRUE_ABERRATIONS, WORKLOADS, random_csr, shuffle_within_frame
 from oracle import eer as oeer
 from oracle import ssb as ossb
 
-from helpers import (gpu_com, gpu_ssb, oracle_dpc, oracle_ssb, rel_l2, state_D, state_G_half, state_kc,
-                     structs, to_device)
+from helpers import (gpu_com, gpu_ssb, oracle_dpc, oracle_pruned, oracle_row_dft, oracle_ssb, per_q_error,
+                     q_error_scale, rel_l2, state_D, state_kc, state_npair, state_pruned, state_X, structs, to_device)
 
 pytestmark = pytest.mark.gpu
 
@@ -119,13 +119,18 @@ def test_binning_and_scan_transform(gpu, name):
     assert out["status"] == 0
     assert np.array_equal(state_kc(st), ref["kc"])
     assert np.array_equal(state_D(st, wl), ref["D"])
-    nh = wl.scan[1] // 2 + 1
-    G = state_G_half(st, wl)
-    Gr = ref["G"][:, :, :nh]
-    assert rel_l2(G, Gr) <= TOL
-    # G(K, Q=0) is the summed pattern, exactly (P6)
-    assert np.array_equal(G[:, 0, 0].real.astype(np.float64), ref["D"].sum(axis=1).astype(np.float64))
-    assert np.all(G[:, 0, 0].imag == 0)
+    # the row transform of every pixel, and its zero-frequency column: the row sums, exactly
+    X = state_X(st, wl)
+    assert rel_l2(X, oracle_row_dft(ref["D"], wl)) <= TOL
+    rows = ossb.cube(ref["D"], *wl.scan).sum(axis=2)
+    assert np.array_equal(X[:, :, 0].real.astype(np.float64), rows.astype(np.float64))
+    assert np.all(X[:, :, 0].imag == 0)
+    # G on the double-overlap pairs: every (pixel, column) run has the oracle's length (the sets
+    # are equal pair by pair) and the values match
+    pg, poff = state_pruned(st)
+    pg_ref, poff_ref = oracle_pruned(ref["G"], ref["kc"], wl)
+    assert np.array_equal(poff, poff_ref)
+    assert rel_l2(pg, pg_ref) <= TOL
 
 
 @pytest.mark.parametrize("name", ["small", "mid", "rect", "aberr", "n128", "n512", "n1024"])
@@ -143,15 +148,25 @@ def test_ssb_phase_parity(gpu, name):
     assert rel_l2(out["T"], ref["T"]) <= TOL
     assert rel_l2(out["phi"], ref["phi"]) <= TOL
     assert out["T"][0, 0] == 0
+    # every Q, relative to its own summands
+    assert per_q_error(out["T"], ref["T"], q_error_scale(ref["G"], ref["kc"], wl)) <= 1e-4
 
 
 def test_ssb_normalized_parity(gpu):
     wl, idx, off = data("small")
     d_idx, d_off = to_device(idx, off)
-    st, out = gpu_ssb(d_idx, d_off, wl, normalize=1)
-    ref = oracle_ssb(idx, off, wl, normalize=True)
-    assert rel_l2(out["T"], ref["T"]) <= TOL
-    assert rel_l2(out["phi"], ref["phi"]) <= TOL
+    for g_mode in (stem.STEM_G_STORE, stem.STEM_G_RECOMPUTE):
+        st, out = gpu_ssb(d_idx, d_off, wl, normalize=1, g_mode=g_mode, c=wl.aberr)
+        ref = oracle_ssb(idx, off, wl, normalize=True, c=wl.aberr)
+        assert out["status"] == 0
+        assert rel_l2(out["T"], ref["T"]) <= TOL
+        assert rel_l2(out["phi"], ref["phi"]) <= TOL
+        # element by element, relative to each Q's own size (the division by the pair count)
+        assert np.max(np.abs(out["T"] - ref["T"])) <= 1e-5 * np.max(np.abs(ref["T"]))
+        # a second FINALIZE (the per-Q counts are rebuilt, G recomputed or from the stored values)
+        phase = torch.zeros(wl.n_frames, dtype=torch.float32, device="cuda")
+        st.finalize(c=wl.aberr, phase=phase)
+        assert rel_l2(phase.cpu().numpy().reshape(wl.scan), ref["phi"]) <= TOL
 
 
 @pytest.mark.parametrize("name", ["small", "mid", "rect", "aberr", "n512", "n1024", "wide"])
@@ -170,12 +185,24 @@ def test_pair_count_matches_oracle(gpu, name):
     st, out = gpu_ssb(d_idx, d_off, wl, c=wl.aberr, g_mode=stem.STEM_G_STORE)
     s = st.stats()
     assert out["status"] == 0
-    assert s[0] == P and s[1] >= 1 and s[2] == 0 and s[3] == 0
+    assert s[0] == P and s[1] >= 1 and s[2] > 0 and s[3] == 1
     st.refocus(c=wl.aberr)
     torch.cuda.synchronize()
+    s = st.stats()
+    assert s[0] == P and 0 < s[2] <= 8 * P  # the refocus reads stored pairs only
+    # the adjoint leaves the counters of the last sum
+    phase = torch.zeros(wl.n_frames, dtype=torch.float32, device="cuda")
+    st.refocus(c=wl.aberr, phase=phase)
+    st.backward((-(2.0 / phase.numel()) * (phase - phase.mean())).contiguous(), c=wl.aberr)
+    torch.cuda.synchronize()
     assert st.stats()[0] == P
+    # per Q: the normalised sum's pair counts equal the oracle's, frequency by frequency
     stn, outn = gpu_ssb(d_idx, d_off, wl, c=wl.aberr, normalize=1)
-    assert outn["status"] == 0 and stn.stats()[:2] == [P, 1]
+    assert outn["status"] == 0 and stn.stats()[0] == P
+    assert np.array_equal(state_npair(stn, wl), npair)
+    # G recomputed in several chunks of pixels: the same count
+    str_, outr = gpu_ssb(d_idx, d_off, wl, c=wl.aberr, g_mode=stem.STEM_G_RECOMPUTE, scratch_mib=1)
+    assert outr["status"] == 0 and str_.stats()[0] == P
 
 
 def test_refocus_matches_fresh_reconstruction(gpu):
@@ -192,14 +219,18 @@ def test_refocus_matches_fresh_reconstruction(gpu):
     assert rel_l2(phase.cpu().numpy().reshape(wl.scan), ref["phi"]) <= TOL
 
 
+@pytest.mark.parametrize("scratch_mib", [0, 1])
 @pytest.mark.parametrize("name", ["small", "mid", "aberr"])
-def test_recompute_mode_matches_oracle(gpu, name):
-    """G-recompute mode: the fused column transform + sum never stores G; the row-transformed
-    cube stays, so a second FINALIZE with other coefficients works and the adjoint recomputes G."""
+def test_recompute_mode_matches_oracle(gpu, name, scratch_mib):
+    """G-recompute mode: the state keeps the binned counts only; every sum transforms chunks of
+    pixels in a bounded scratch (1 MiB: several chunks), so a second FINALIZE with other
+    coefficients works, and the adjoint recomputes G the same way."""
     wl, idx, off = data(name)
     d_idx, d_off = to_device(idx, off)
     c = wl.aberr
-    st, out = gpu_ssb(d_idx, d_off, wl, c=c, g_mode=stem.STEM_G_RECOMPUTE)
+    st, out = gpu_ssb(d_idx, d_off, wl, c=c, g_mode=stem.STEM_G_RECOMPUTE, scratch_mib=scratch_mib)
+    if scratch_mib:
+        assert st.stats()[3] > 1
     ref = oracle_ssb(idx, off, wl, c=c)
     assert out["status"] == 0
     assert rel_l2(out["T"], ref["T"]) <= TOL
@@ -221,6 +252,9 @@ def test_recompute_mode_matches_oracle(gpu, name):
     dc = dc.cpu().numpy()
     assert np.all(np.abs(dc - dco) <= 1e-4 * np.abs(dco) + 1e-6 * np.max(np.abs(dco)))
     assert rel_l2(dth.cpu().numpy(), dtho) <= 1e-4
+    # REFOCUS in this mode runs the recomputed sum again
+    st.refocus(c=c, phase=phase)
+    assert rel_l2(phase.cpu().numpy().reshape(wl.scan), ref["phi"]) <= TOL
 
 
 @pytest.mark.parametrize("prec", [stem.STEM_FFT_FP32, stem.STEM_DFT_BF16_SPLIT, stem.STEM_DFT_FP16_SPLIT],

@@ -13,7 +13,8 @@ import paper_2104_06336_amd as stem
 from gen import C4_TRUE_ABERRATIONS, with_pileup
 from oracle import ssb as ossb
 
-from helpers import gpu_ssb, oracle_ssb, rel_l2, state_D, state_G_half, structs, to_device
+from helpers import (gpu_ssb, oracle_pruned, oracle_row_dft, oracle_ssb, rel_l2, state_D, state_pruned, state_X,
+                     structs, to_device)
 from test_gpu_parity import data
 
 pytestmark = pytest.mark.gpu
@@ -37,16 +38,19 @@ def test_split_transform_per_output(gpu, name, prec):
     ref = oracle_ssb(idx, off, wl, c=wl.aberr)
     assert out["status"] == 0
     assert np.array_equal(state_D(st, wl), ref["D"])
-    nh = wl.scan[1] // 2 + 1
-    G = state_G_half(st, wl)
-    errs = {"G": rel_l2(G, ref["G"][:, :, :nh]), "T": rel_l2(out["T"], ref["T"]),
+    X = state_X(st, wl)
+    pg, poff = state_pruned(st)
+    pg_ref, poff_ref = oracle_pruned(ref["G"], ref["kc"], wl)
+    assert np.array_equal(poff, poff_ref)
+    errs = {"X": rel_l2(X, oracle_row_dft(ref["D"], wl)), "G": rel_l2(pg, pg_ref), "T": rel_l2(out["T"], ref["T"]),
             "phi": rel_l2(out["phi"], ref["phi"])}
     print(f"[split] {name} prec={prec} rel_l2 {errs}", flush=True)
     for k, e in errs.items():
         assert e <= TOL_SPLIT, k
-    # G(K, 0) is the summed pattern, exactly (P6)
-    assert np.array_equal(G[:, 0, 0].real.astype(np.float64), ref["D"].sum(axis=1).astype(np.float64))
-    assert np.all(G[:, 0, 0].imag == 0)
+    # the zero-frequency column of the row transform is the row sums, exactly (its DFT weights are 1)
+    rows = ossb.cube(ref["D"], *wl.scan).sum(axis=2)
+    assert np.array_equal(X[:, :, 0].real.astype(np.float64), rows.astype(np.float64))
+    assert np.all(X[:, :, 0].imag == 0)
     assert out["T"][0, 0] == 0
 
 
@@ -92,8 +96,8 @@ def test_split_uint16_cube(gpu, prec):
     assert out["status"] == 0
     ref = oracle_ssb(idx2, off2, wl)
     assert np.array_equal(state_D(st, wl), ref["D"])
-    G = state_G_half(st, wl)
-    assert rel_l2(G, ref["G"][:, :, :wl.scan[1] // 2 + 1]) <= TOL_SPLIT
+    assert rel_l2(state_X(st, wl), oracle_row_dft(ref["D"], wl)) <= TOL_SPLIT
+    assert rel_l2(state_pruned(st)[0], oracle_pruned(ref["G"], ref["kc"], wl)[0]) <= TOL_SPLIT
     assert rel_l2(out["phi"], ref["phi"]) <= TOL_SPLIT
 
 
@@ -101,12 +105,14 @@ def test_split_uint16_cube(gpu, prec):
 def test_split_normalized(gpu, prec):
     wl, idx, off = data("small")
     d_idx, d_off = to_device(idx, off)
-    st, out = gpu_ssb(d_idx, d_off, wl, normalize=1, precision=prec)
     ref = oracle_ssb(idx, off, wl, normalize=True)
-    assert rel_l2(out["T"], ref["T"]) <= TOL_SPLIT
-    assert rel_l2(out["phi"], ref["phi"]) <= TOL_SPLIT
     npair = int(ossb.ssb_sum(ref["G"], ref["kc"], wl.step, wl.dk, wl.lam, wl.r_bf, (0.0,) * 8)[1].sum())
-    assert st.pair_count() == npair
+    for g_mode in (stem.STEM_G_STORE, stem.STEM_G_RECOMPUTE):
+        st, out = gpu_ssb(d_idx, d_off, wl, normalize=1, precision=prec, g_mode=g_mode)
+        assert out["status"] == 0
+        assert rel_l2(out["T"], ref["T"]) <= TOL_SPLIT
+        assert rel_l2(out["phi"], ref["phi"]) <= TOL_SPLIT
+        assert st.pair_count() == npair
 
 
 @pytest.mark.parametrize("prec", SPLIT, ids=IDS)
@@ -121,11 +127,13 @@ def test_split_chunked_accumulate(gpu, prec):
 @pytest.mark.parametrize("prec", SPLIT, ids=IDS)
 @pytest.mark.parametrize("g_mode", [stem.STEM_G_RECOMPUTE, stem.STEM_G_STORE], ids=["recompute", "store"])
 def test_split_adjoint(gpu, g_mode, prec):
+    """Every component of dL/dc within 1e-4 of its own size (plus 1e-6 of the largest), and
+    dL/dtheta by rel-L2, against the oracle gradient."""
     wl, idx, off = data("aberr")
     d_idx, d_off = to_device(idx, off)
     rng = np.random.default_rng(7)
     c = np.array(C4_TRUE_ABERRATIONS) * (1 + rng.uniform(-0.5, 0.5, size=8))
-    st, out = gpu_ssb(d_idx, d_off, wl, c=c, g_mode=g_mode, precision=prec)
+    st, out = gpu_ssb(d_idx, d_off, wl, c=c, g_mode=g_mode, precision=prec, scratch_mib=1)
     phi = torch.from_numpy(out["phi"]).cuda()
     gbar = (-(2.0 / phi.numel()) * (phi - phi.mean())).contiguous().view(-1)
     dc, dth = st.backward(gbar, c=c)
@@ -134,5 +142,5 @@ def test_split_adjoint(gpu, g_mode, prec):
                                  wl.r_bf, c)
     dc = dc.cpu().numpy()
     print(f"[split] adjoint prec={prec} rel per comp {np.abs(dc - dco) / np.abs(dco)}", flush=True)
-    assert rel_l2(dc, dco) <= TOL_SPLIT
+    assert np.all(np.abs(dc - dco) <= TOL_SPLIT * np.abs(dco) + 1e-6 * np.max(np.abs(dco)))
     assert rel_l2(dth.cpu().numpy(), dtho) <= TOL_SPLIT
