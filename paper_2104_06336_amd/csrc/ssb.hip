@@ -16,6 +16,7 @@
 #include "common.h"
 #include "fft_wave.h"
 #include "ssb_fused.h"
+#include "ssb_pruned.h"
 #include "kernels.h"
 #include "optics.h"
 #include "trace.h"
@@ -32,11 +33,14 @@ struct SsbLayout {
   int xpix;       // pixels whose row-transformed columns the X region holds (n_k, or one chunk)
   int nchunks;    // pixel chunks of a sum
   int64_t pcap;   // entries of the pruned G array (0 without STEM_G_STORE)
-  size_t rows, kc, kchi, cst, cmask, lut, stats, npq, D, X, poff, pg, T, A, Tb, pdc, pdth, part, wcnt, total;
+  size_t rows, kc, kchi, cst, cmask, lut, stats, npq, D, X, poff, ptot, pg, T, A, Tb, pdc, pdth, part, wcnt, total;
   int nmw;      // 64-bit words per column set of the active-pixel mask
   int groups;   // pixel groups of the fused column kernels (the same for every chunk)
+  int pgroups;  // pixel groups of the kernels over the stored double-overlap values
   int ncs;      // column sets (B = 1024/Ny half-spectrum columns each)
   int64_t nwy;  // waves of the fused kernels
+  int64_t nwp;  // waves of the refocus sum over the stored values
+  int64_t nwa;  // waves of the adjoint over the stored values
 };
 
 static int yreduce_groups(int ny, int nx, int n_k);
@@ -115,6 +119,7 @@ static size_t make_layout(const stem_det& det, const stem_scan& scan, const stem
   L->D = o;     o = align256(o + (size_t)n_k * L->F * (ssb.d_bits / 8));
   L->X = o;     o = align256(o + (size_t)L->xpix * per_pixel);
   L->poff = o;  o = align256(o + (L->store ? sizeof(int64_t) * ((size_t)n_k * scan.nx + 1) : 0));
+  L->ptot = o;  o = align256(o + (L->store ? sizeof(int64_t) * (size_t)n_k : 0));
   L->pg = o;    o = align256(o + sizeof(float2) * (size_t)L->pcap);
   L->T = o;     o = align256(o + (size_t)L->F * sizeof(float2));
   L->A = o;     o = align256(o + (size_t)L->F * sizeof(float2));
@@ -126,10 +131,25 @@ static size_t make_layout(const stem_det& det, const stem_scan& scan, const stem
   if (g > smallest) g = smallest;
   L->groups = g < 1 ? 1 : g;
   L->nwy = (int64_t)((L->ncs + 3) / 4) * 4 * L->groups;
-  L->pdc = o;   o = align256(o + (size_t)L->nwy * 8 * sizeof(double));
-  L->pdth = o;  o = align256(o + (size_t)L->ncs * n_k * sizeof(float));
-  L->part = o;  o = align256(o + (size_t)L->groups * L->F * sizeof(float2));
-  L->wcnt = o;  o = align256(o + (size_t)L->nwy * sizeof(unsigned long long));
+  // the kernels over the stored values: one wave per column of the whole plane and pixel group,
+  // about 3072 waves, at most the fused kernels' partial sums
+  {
+    int pg = (3072 + scan.nx - 1) / scan.nx;
+    const int gmax = yreduce_groups(scan.ny, scan.nx, n_k);
+    pg = pg > n_k ? n_k : pg;
+    pg = pg > gmax ? gmax : pg;
+    L->pgroups = pg < 1 ? 1 : pg;
+    L->nwp = pruned_launch_waves(scan.ny, scan.nx, L->pgroups, false);
+    L->nwa = pruned_launch_waves(scan.ny, scan.nx, L->pgroups, true);
+  }
+  int64_t nw = L->nwy > L->nwp ? L->nwy : L->nwp;
+  nw = nw > L->nwa ? nw : L->nwa;
+  const int rows = L->ncs > scan.nx ? L->ncs : scan.nx;
+  const int parts = L->groups > L->pgroups ? L->groups : L->pgroups;
+  L->pdc = o;   o = align256(o + (size_t)nw * 8 * sizeof(double));
+  L->pdth = o;  o = align256(o + (size_t)rows * n_k * sizeof(float));
+  L->part = o;  o = align256(o + (size_t)parts * L->F * sizeof(float2));
+  L->wcnt = o;  o = align256(o + (size_t)nw * sizeof(unsigned long long));
   L->total = o;
   return o;
 }
@@ -195,7 +215,6 @@ static int chi_is_zero(const Optics& o, const float* theta) {
 // the fused sum with the transform of precision prec (prec < 0: from the pruned G)
 static int launch_yreduce(int prec, int ny, const YArgs& a, const Optics& o, int chi0, int pwrite, hipStream_t s) {
   switch (prec) {
-    case -1: return launch_yreduce_p<-1>(ny, a, o, chi0, 0, s);
     case STEM_DFT_BF16_SPLIT: return launch_yreduce_p<STEM_DFT_BF16_SPLIT>(ny, a, o, chi0, pwrite, s);
     case STEM_DFT_FP16_SPLIT: return launch_yreduce_p<STEM_DFT_FP16_SPLIT>(ny, a, o, chi0, pwrite, s);
     default: return launch_yreduce_p<STEM_FFT_FP32>(ny, a, o, chi0, pwrite, s);
@@ -204,7 +223,6 @@ static int launch_yreduce(int prec, int ny, const YArgs& a, const Optics& o, int
 
 static int launch_yadjoint(int prec, int ny, const YArgs& a, const Optics& o, hipStream_t s) {
   switch (prec) {
-    case -1: return launch_yadjoint_p<-1>(ny, a, o, s);
     case STEM_DFT_BF16_SPLIT: return launch_yadjoint_p<STEM_DFT_BF16_SPLIT>(ny, a, o, s);
     case STEM_DFT_FP16_SPLIT: return launch_yadjoint_p<STEM_DFT_FP16_SPLIT>(ny, a, o, s);
     default: return launch_yadjoint_p<STEM_FFT_FP32>(ny, a, o, s);
@@ -255,44 +273,75 @@ __global__ void __launch_bounds__(256) k_pair_count(const int4* __restrict__ cst
 }
 
 // Offsets of the pruned double-overlap array: poff[kd * Nx + mx] = number of values of the (pixel,
-// column) pairs before it in pixel-major, column-minor order; poff[n_k * Nx] = the total.  One
-// workgroup: every thread sums a contiguous segment, a scan of the segment sums gives its base.
-__global__ void __launch_bounds__(1024) k_prune_offsets(const int4* __restrict__ cst, int n_k, int nx,
-                                                        int64_t* __restrict__ poff, int64_t pcap,
-                                                        int32_t* __restrict__ status) {
-  __shared__ int64_t s_sum[1024];
-  const int64_t n = (int64_t)n_k * nx;
-  const int t = threadIdx.x;
-  const int64_t seg = (n + 1023) / 1024;
-  const int64_t e0 = (int64_t)t * seg < n ? (int64_t)t * seg : n;
-  const int64_t e1 = e0 + seg < n ? e0 + seg : n;
+// column) pairs before it in pixel-major, column-minor order; poff[n_k * Nx] = the total.  Three
+// passes: the runs of each pixel scanned by its own workgroup (offsets relative to the pixel,
+// pixel totals to ptot), the pixel totals scanned by one workgroup, then each pixel's base added.
+
+__device__ __forceinline__ int64_t pruned_size(const int4* __restrict__ cst, int kd, int mx, int nx) {
   const int nc = nx / 2 + 1;
-  auto size_of = [&](int64_t e) -> int64_t {
-    const int kd = (int)(e / nx), mx = (int)(e % nx);
-    const bool mir = 2 * mx > nx;
-    ColSet d, m;
-    load_colsets(cst, (int64_t)kd * nc + (mir ? nx - mx : mx), d, m);
-    return set_size(mir ? m : d);
-  };
-  int64_t sum = 0;
-  for (int64_t e = e0; e < e1; ++e) sum += size_of(e);
-  s_sum[t] = sum;
+  const bool mir = 2 * mx > nx;
+  ColSet d, m;
+  load_colsets(cst, (int64_t)kd * nc + (mir ? nx - mx : mx), d, m);
+  return set_size(mir ? m : d);
+}
+
+// inclusive scan of one value per thread over a 256-thread workgroup (s: 256 entries)
+__device__ __forceinline__ int64_t block_scan256(int64_t v, int64_t* s) {
+  const int t = threadIdx.x;
+  s[t] = v;
   __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {  // inclusive scan of the segment sums
-    const int64_t v = t >= o ? s_sum[t - o] : 0;
+  for (int o = 1; o < 256; o <<= 1) {
+    const int64_t u = t >= o ? s[t - o] : 0;
     __syncthreads();
-    s_sum[t] += v;
+    s[t] += u;
     __syncthreads();
   }
-  int64_t base = t ? s_sum[t - 1] : 0;
-  for (int64_t e = e0; e < e1; ++e) {
-    poff[e] = base;
-    base += size_of(e);
+  const int64_t r = s[t];
+  __syncthreads();
+  return r;
+}
+
+__global__ void __launch_bounds__(256) k_prune_runs(const int4* __restrict__ cst, int nx, int64_t* __restrict__ poff,
+                                                    int64_t* __restrict__ ptot) {
+  __shared__ int64_t s[256];
+  const int kd = blockIdx.x;
+  const int per = (nx + 255) / 256;  // consecutive columns per thread
+  const int m0 = threadIdx.x * per;
+  int64_t sum = 0;
+  for (int mx = m0; mx < m0 + per && mx < nx; ++mx) sum += pruned_size(cst, kd, mx, nx);
+  int64_t base = block_scan256(sum, s) - sum;
+  for (int mx = m0; mx < m0 + per && mx < nx; ++mx) {
+    poff[(int64_t)kd * nx + mx] = base;
+    base += pruned_size(cst, kd, mx, nx);
   }
-  if (t == 1023) {
-    poff[n] = s_sum[1023];
-    if (s_sum[1023] > pcap) report(status, STEM_EWORKSPACE);  // never with the layout's bound
+  if (threadIdx.x == 255) ptot[kd] = base;
+}
+
+__global__ void __launch_bounds__(256) k_prune_bases(int n_k, int nx, int64_t* __restrict__ poff,
+                                                     int64_t* __restrict__ ptot, int64_t pcap,
+                                                     int32_t* __restrict__ status) {
+  __shared__ int64_t s[256];
+  const int per = (n_k + 255) / 256;
+  const int k0 = threadIdx.x * per;
+  int64_t sum = 0;
+  for (int kd = k0; kd < k0 + per && kd < n_k; ++kd) sum += ptot[kd];
+  int64_t base = block_scan256(sum, s) - sum;
+  for (int kd = k0; kd < k0 + per && kd < n_k; ++kd) {
+    const int64_t t = ptot[kd];
+    ptot[kd] = base;  // now the pixel's first entry
+    base += t;
   }
+  if (threadIdx.x == 255) {
+    poff[(int64_t)n_k * nx] = base;
+    if (base > pcap) report(status, STEM_EWORKSPACE);  // never with the layout's bound
+  }
+}
+
+__global__ void __launch_bounds__(256) k_prune_add(int nx, int64_t* __restrict__ poff,
+                                                   const int64_t* __restrict__ ptot) {
+  const int kd = blockIdx.x;
+  const int64_t b = ptot[kd];
+  for (int mx = threadIdx.x; mx < nx; mx += 256) poff[(int64_t)kd * nx + mx] += b;
 }
 
 // number of pixel groups of the fused sum: about 4096 waves, at most n_k, partial sums <= 64 MB
@@ -393,6 +442,7 @@ struct Bufs {
   void* D;
   float2* X;
   int64_t* poff;
+  int64_t* ptot;
   float2* pg;
   float2* T;
   float2* A;
@@ -408,7 +458,7 @@ static Bufs carve(void* state, const SsbLayout& L) {
   return Bufs{(RowRun*)(p + L.rows), (double2*)(p + L.kc), (double*)(p + L.kchi), (int4*)(p + L.cst),
               (uint64_t*)(p + L.cmask), (int16_t*)(p + L.lut), (unsigned long long*)(p + L.stats),
               (int32_t*)(p + L.npq), (void*)(p + L.D), (float2*)(p + L.X), (int64_t*)(p + L.poff),
-              (float2*)(p + L.pg), (float2*)(p + L.T), (float2*)(p + L.A), (float2*)(p + L.Tb),
+              (int64_t*)(p + L.ptot), (float2*)(p + L.pg), (float2*)(p + L.T), (float2*)(p + L.A), (float2*)(p + L.Tb),
               (double*)(p + L.pdc), (float*)(p + L.pdth), (float2*)(p + L.part),
               (unsigned long long*)(p + L.wcnt)};
 }
@@ -478,14 +528,14 @@ static int xstage_pixels(const SsbLayout& L, const Bufs& b, const stem_ssb& ssb,
 // T = sum of the partial sums (column-major [mx][my]), divided by the pair count of each Q when
 // npq is given; phi = Im IFFT2(T); d_T row-major.  The fused kernels' per-wave counters become the
 // state's counters.
-static int run_phase(const SsbLayout& L, const Bufs& b, const stem_scan& sc, const int32_t* npq, float* d_phase,
-                     float* d_T, hipStream_t s) {
+static int run_phase(const SsbLayout& L, const Bufs& b, const stem_scan& sc, int nparts, int64_t nwaves,
+                     const int32_t* npq, float* d_phase, float* d_T, hipStream_t s) {
   const int ny = sc.ny, nx = sc.nx;
   RowFftArgs a{};
   // inverse along my of each mx row of T -> A[ry][mx]; the summed T is kept in the state
   a.nrows = nx;
   a.in_c = b.part;
-  a.nparts = L.groups;
+  a.nparts = nparts;
   a.part_stride = L.F;
   a.sum_out = b.T;
   a.norm_cnt = npq;
@@ -494,9 +544,9 @@ static int run_phase(const SsbLayout& L, const Bufs& b, const stem_scan& sc, con
   a.osc = make_float2(1.f, 0.f);
   a.tag = "phase_fft";
   a.wcnt = b.wcnt;
-  a.nwcnt = L.nwy;
+  a.nwcnt = nwaves;
   a.stats = b.stats;
-  a.stats_groups = L.groups;
+  a.stats_groups = nparts;
   a.stats_chunks = L.store ? 1 : L.nchunks;
   int st = launch_row_fft(ny, true, IN_C64_SUM, OUT_T_C64, a, s);
   if (st) return st;
@@ -535,7 +585,11 @@ static int run_pair_count(const SsbLayout& L, const Bufs& b, int ny, int nx, hip
 
 static int run_prune_offsets(const SsbLayout& L, const Bufs& b, int nx, int32_t* d_status, hipStream_t s) {
   STEM_TRACE("prune_offsets", s);
-  hipLaunchKernelGGL(k_prune_offsets, dim3(1), dim3(1024), 0, s, b.cst, L.n_k, nx, b.poff, L.pcap, d_status);
+  hipLaunchKernelGGL(k_prune_runs, dim3((unsigned)L.n_k), dim3(256), 0, s, b.cst, nx, b.poff, b.ptot);
+  STEM_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_prune_bases, dim3(1), dim3(256), 0, s, L.n_k, nx, b.poff, b.ptot, L.pcap, d_status);
+  STEM_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_prune_add, dim3((unsigned)L.n_k), dim3(256), 0, s, nx, b.poff, b.ptot);
   STEM_LAUNCH_CHECK();
   return STEM_OK;
 }
@@ -639,7 +693,9 @@ static int reconstruct(const int32_t* d_idx, const int64_t* d_off, int64_t frame
   YArgs a = yargs(L, b, nx);
   if (L.store && refocus) {
     // Eq. 3 again from the stored double-overlap values
-    if ((st = launch_yreduce(-1, ny, a, o, chi0, 0, s))) return st;
+    a.ngroups = L.pgroups;
+    if ((st = launch_psum(ny, a, o, chi0, s))) return st;
+    return run_phase(L, b, *scan, L.pgroups, L.nwp, ssb->normalize ? b.npq : nullptr, d_phase, d_T, s);
   } else if (L.store) {
     if ((st = run_prune_offsets(L, b, nx, d_status, s))) return st;
     if ((st = launch_yreduce(ssb->precision, ny, a, o, chi0, 1, s))) return st;
@@ -656,7 +712,7 @@ static int reconstruct(const int32_t* d_idx, const int64_t* d_off, int64_t frame
       if ((st = launch_yreduce(ssb->precision, ny, a, o, chi0, 0, s))) return st;
     }
   }
-  return run_phase(L, b, *scan, ssb->normalize ? b.npq : nullptr, d_phase, d_T, s);
+  return run_phase(L, b, *scan, L.groups, L.nwy, ssb->normalize ? b.npq : nullptr, d_phase, d_T, s);
 }
 
 extern "C" int ssb_reconstruct(const int32_t* d_idx, const int64_t* d_off, int64_t frame0, int64_t n_frames,
@@ -874,8 +930,12 @@ extern "C" int ssb_backward(const float* d_dLdphi, const stem_det* det, const st
   // chi(Kc) + theta for these coefficients; the interval table and mask are the last sum's
   if ((st = run_chi_table(b, d_theta, n_k, o, s))) return st;
   YArgs y = yargs(L, b, nx);
+  int64_t npdc = L.nwy, npdth = L.ncs;
   if (L.store) {
-    if ((st = launch_yadjoint(-1, ny, y, o, s))) return st;
+    y.ngroups = L.pgroups;
+    if ((st = launch_padj(ny, y, o, s))) return st;
+    npdc = L.nwa;
+    npdth = nx;
   } else {
     for (int ch = 0; ch < L.nchunks; ++ch) {
       int k0, k1;
@@ -890,8 +950,8 @@ extern "C" int ssb_backward(const float* d_dLdphi, const stem_det* det, const st
   }
   {
     STEM_TRACE("ssb_adjoint_final", s);
-    hipLaunchKernelGGL(k_adjoint_final, dim3(1 + (n_k + 255) / 256), dim3(256), 0, s, b.pdc, L.nwy, b.pdth,
-                       (int64_t)L.ncs, n_k, d_dLdc, d_dLdtheta);
+    hipLaunchKernelGGL(k_adjoint_final, dim3(1 + (n_k + 255) / 256), dim3(256), 0, s, b.pdc, npdc, b.pdth, npdth,
+                       n_k, d_dLdc, d_dLdtheta);
   }
   STEM_LAUNCH_CHECK();
   return STEM_OK;

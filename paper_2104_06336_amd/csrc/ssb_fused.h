@@ -28,7 +28,6 @@ template <int N_>
 struct XfFft {
   static constexpr int N = N_;
   static constexpr bool kMfma = false;
-  static constexpr bool kPruned = false;
   static constexpr int RL = fft_last_radix<N>();
   static constexpr int NB = N / RL;
   static constexpr bool kUniformCol = NB >= kWave;
@@ -52,7 +51,6 @@ template <int N_, int PREC>
 struct XfMfma {
   static constexpr int N = N_;
   static constexpr bool kMfma = true;
-  static constexpr bool kPruned = false;
   static constexpr int slot_of(int) { return 0; }  // all 16 registers of a lane share its column
   static constexpr int kSlots = 1;
   static constexpr bool kUniformCol = false;        // (the lanes of a wave do not)
@@ -71,17 +69,6 @@ struct XfMfma {
   static __device__ __forceinline__ void run(float2* v, float2*, const float2* tw, const uint4* tab, int lane) {
     mfma_dft<N, PREC, EXACT>(v, tab, tw, lane);
   }
-};
-
-// No transform: the registers hold G read from the pruned double-overlap array in the FFT's output
-// layout, so the fused sum's slots and membership masks apply unchanged (Eq. 3 again from the
-// stored values, and the adjoint from them).
-template <int N_>
-struct XfPruned : XfFft<N_> {
-  static constexpr bool kPruned = true;
-  static __device__ __forceinline__ void in(int lane, int i, int& b, int& n) { fft_out_index<N_>(lane, i, b, n); }
-  template <bool EXACT>
-  static __device__ __forceinline__ void run(float2*, float2*, const float2*, const uint4*, int) {}
 };
 
 template <int N, int PREC>
@@ -236,7 +223,7 @@ __global__ void __launch_bounds__(64 * XF::kXWaves) k_xstage(const DT* __restric
 // that column, ascending iy with the hole [b0, b1] skipped, start at poff[kd * Nx + mx].  Column
 // mx <= Nx/2 is half-spectrum column c = mx (direct set); mx > Nx/2 is the mirror of c = Nx - mx,
 // whose values are conj G(kd, (-iy, c)).  PWRITE: the fused sum writes them (FINALIZE that keeps
-// G); XfPruned: the sum reads them instead of transforming X (refocus).
+// G); the refocus sum and the adjoint read them (ssb_pruned.h).
 
 // The sets of one pixel for a half-spectrum column c (direct) and for -c (mirror) depend only on
 // the geometry; they are tabulated once per reconstruction (k_colsets), 16 bytes per (pixel,
@@ -259,7 +246,7 @@ struct YArgs {
   int k0, k1;               // pixels of this launch
   int ngroups;              // pixel groups of [k0, k1)
   int accumulate;           // add to part / wcnt / pdc (a later chunk of pixels)
-  const float2* pg;         // XfPruned: pruned G read
+  const float2* pg;         // pruned G read (refocus, adjoint)
   float2* pgw;              // PWRITE: pruned G written
   const int64_t* poff;      // pruned offsets [n_k][Nx]
   int64_t pcap;             // capacity of the pruned array (entries)
@@ -284,59 +271,36 @@ __device__ __forceinline__ int set_size(const ColSet& s) {
   return (s.a1 - s.a0 + 1) - (h0 <= h1 ? h1 - h0 + 1 : 0);
 }
 
-// Registers of pixel kd for the wave's columns: the row-transformed input (transform policies) or
-// G itself from the pruned array (XfPruned).  Returns the number of 8-byte loads of this lane.
+// Where the registers of a pixel come from.
+struct PixSrc {
+  const float2* X;
+  int xk0, nx;
+  const int4* cst;
+  const int64_t* poff;
+  const float2* pg;
+  int64_t pcap;
+};
+
+__device__ __forceinline__ PixSrc pix_src(const YArgs& a) {
+  return PixSrc{a.X, a.xk0, a.nx, a.cst, a.poff, a.pg, a.pcap};
+}
+
+// Registers of pixel kd for the wave's columns: the row-transformed input in the transform's input
+// layout.  Returns the number of 8-byte loads of this lane.
 template <typename XF>
-__device__ __forceinline__ unsigned load_pixel(const YArgs& a, int kd, int c0, int lane, float2* v) {
+__device__ __forceinline__ unsigned load_pixel(const PixSrc a, int kd, int c0, int lane, float2* v) {
   constexpr int NY = XF::N;
   const int nc = a.nx / 2 + 1;
   unsigned n = 0;
-  if constexpr (XF::kPruned) {
-    constexpr int kSlotStride = 16 / XF::kSlots;
+  const int64_t kstride = (int64_t)nc * NY;
+  const float2* xcol = a.X + (int64_t)(kd - a.xk0) * kstride + (int64_t)c0 * NY;
 #pragma unroll
-    for (int sl = 0; sl < XF::kSlots; ++sl) {
-      int b0, m0;
-      XF::out(lane, sl * kSlotStride, b0, m0);
-      const int c = c0 + b0;
-      ColSet sd{1, 0, 1, 0}, sm{1, 0, 1, 0};
-      int64_t pd = 0, pm = 0;
-      if (c < nc) {
-        load_colsets(a.cst, (int64_t)kd * nc + c, sd, sm);
-        pd = a.poff[(int64_t)kd * a.nx + c];
-        if (c > 0 && 2 * c < a.nx) pm = a.poff[(int64_t)kd * a.nx + (a.nx - c)];
-      }
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        if (XF::slot_of(i) != sl) continue;
-        int b, m;
-        XF::out(lane, i, b, m);
-        const int iy = signed_index(m, NY), jy = signed_index((NY - m) & (NY - 1), NY);
-        // entries are read only inside the array (a state whose FINALIZE never ran reads nothing
-        // out of bounds)
-        float2 x = make_float2(0.f, 0.f);
-        if (c < nc && sd.has(iy)) {
-          const int64_t e = pd + set_rank(sd, iy);
-          if (e >= 0 && e < a.pcap) x = a.pg[e];
-          ++n;
-        } else if (c < nc && sm.has(jy)) {
-          const int64_t e = pm + set_rank(sm, jy);
-          if (e >= 0 && e < a.pcap) x = cconj(a.pg[e]);
-          ++n;
-        }
-        v[i] = x;
-      }
-    }
-  } else {
-    const int64_t kstride = (int64_t)nc * NY;
-    const float2* xcol = a.X + (int64_t)(kd - a.xk0) * kstride + (int64_t)c0 * NY;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      int b, n_;
-      XF::in(lane, i, b, n_);
-      const bool in = c0 + b < nc;
-      v[i] = in ? xcol[(int64_t)b * NY + n_] : make_float2(0.f, 0.f);
-      n += in ? 1u : 0u;
-    }
+  for (int i = 0; i < 16; ++i) {
+    int b, n_;
+    XF::in(lane, i, b, n_);
+    const bool in = c0 + b < nc;
+    v[i] = in ? xcol[(int64_t)b * NY + n_] : make_float2(0.f, 0.f);
+    n += in ? 1u : 0u;
   }
   return n;
 }
@@ -373,8 +337,8 @@ struct MaskScan {
 template <typename XF, bool CHI0, bool PWRITE>
 __global__ void __launch_bounds__(kYThreads, 2) k_yreduce(YArgs a, Optics o) {
   constexpr int NY = XF::N;
-  __shared__ float2 s_tw[XF::kPruned ? 1 : 1024];
-  __shared__ float2 s_buf[(XF::kMfma || XF::kPruned) ? 1 : 4 * kXWaveStride];
+  __shared__ float2 s_tw[1024];
+  __shared__ float2 s_buf[XF::kMfma ? 1 : 4 * kXWaveStride];
   __shared__ uint4 s_tab[XF::kMfma ? kMfmaTab : 1];
   constexpr int B = 1024 / NY;
   using SL = XF;
@@ -386,12 +350,11 @@ __global__ void __launch_bounds__(kYThreads, 2) k_yreduce(YArgs a, Optics o) {
   const int g = blockIdx.x % a.ngroups;
   const int cs = (blockIdx.x / a.ngroups) * 4 + wave;     // this wave's column set
   const int64_t wid = (int64_t)blockIdx.x * 4 + wave;
-  if constexpr (!XF::kPruned) {
-    fill_twiddles(s_tw, threadIdx.x, kYThreads);
-    __syncthreads();
-    XF::fill(s_tab, s_tw, threadIdx.x, kYThreads);
-    if (XF::kMfma) __syncthreads();
-  }
+  const PixSrc src = pix_src(a);
+  fill_twiddles(s_tw, threadIdx.x, kYThreads);
+  __syncthreads();
+  XF::fill(s_tab, s_tw, threadIdx.x, kYThreads);
+  if (XF::kMfma) __syncthreads();
   if (cs >= ncs) {
     if (lane == 0 && !a.accumulate) a.wcnt[wid] = 0ull;
     return;
@@ -411,9 +374,9 @@ __global__ void __launch_bounds__(kYThreads, 2) k_yreduce(YArgs a, Optics o) {
   int kd = ms.next(kd_a);
   int kd1 = kAhead == 2 && kd < kd_b ? ms.next(kd + 1) : kd_b;
   float2 v[16], v1[kAhead == 2 ? 16 : 1];
-  if (kd < kd_b) nld += load_pixel<XF>(a, kd, c0, lane, v);
+  if (kd < kd_b) nld += load_pixel<XF>(src, kd, c0, lane, v);
   if constexpr (kAhead == 2) {
-    if (kd1 < kd_b) nld += load_pixel<XF>(a, kd1, c0, lane, v1);
+    if (kd1 < kd_b) nld += load_pixel<XF>(src, kd1, c0, lane, v1);
   }
   while (kd < kd_b) {
     int kdn;
@@ -421,10 +384,10 @@ __global__ void __launch_bounds__(kYThreads, 2) k_yreduce(YArgs a, Optics o) {
     if constexpr (kAhead == 2) {
       kdn = kd1;
       kd1 = kd1 < kd_b ? ms.next(kd1 + 1) : kd_b;
-      if (kd1 < kd_b) nld += load_pixel<XF>(a, kd1, c0, lane, vn);
+      if (kd1 < kd_b) nld += load_pixel<XF>(src, kd1, c0, lane, vn);
     } else {
       kdn = ms.next(kd + 1);
-      if (kdn < kd_b) nld += load_pixel<XF>(a, kdn, c0, lane, vn);
+      if (kdn < kd_b) nld += load_pixel<XF>(src, kdn, c0, lane, vn);
     }
     const double2 k = a.kc[kd];
     // double-overlap sets of this pixel for the lane's columns (direct and mirrored)
@@ -627,6 +590,13 @@ __global__ void __launch_bounds__(kYThreads, 2) k_yreduce(YArgs a, Optics o) {
   if (lane == 0) a.wcnt[wid] = a.accumulate ? a.wcnt[wid] + cc : cc;
 }
 
+template <typename XF>
+constexpr bool slots_consecutive() {
+  for (int i = 0; i < 16; ++i)
+    if (XF::slot_of(i) != i / (16 / XF::kSlots)) return false;
+  return true;
+}
+
 // Fused column transform + adjoint of Eq. 3.  Same work split as k_yreduce (also over chunks of
 // pixels, with `accumulate`).  For every double-overlap pair, z = G e^{i psi} (conj G for mirrored
 // frequencies), w = Re(conj(Tbar(Q)) i z); dL/dc_j gains w (B_j(K - Q) - B_j(K)) and
@@ -637,9 +607,10 @@ __global__ void __launch_bounds__(kYThreads, 2) k_yreduce(YArgs a, Optics o) {
 // pixel's sum of w.  Partials: pdc[wave][8] (FP64), pdth[column set][kd] (FP32; one writer).
 template <typename XF>
 __global__ void __launch_bounds__(kYThreads, 2) k_yadjoint(YArgs a, Optics o) {
+  static_assert(slots_consecutive<XF>(), "the registers of a slot are consecutive");
   constexpr int NY = XF::N;
-  __shared__ float2 s_tw[XF::kPruned ? 1 : 1024];
-  __shared__ float2 s_buf[(XF::kMfma || XF::kPruned) ? 1 : 4 * kXWaveStride];
+  __shared__ float2 s_tw[1024];
+  __shared__ float2 s_buf[XF::kMfma ? 1 : 4 * kXWaveStride];
   __shared__ uint4 s_tab[XF::kMfma ? kMfmaTab : 1];
   constexpr int B = 1024 / NY;
   constexpr int kSlotStride = 16 / XF::kSlots;
@@ -650,12 +621,11 @@ __global__ void __launch_bounds__(kYThreads, 2) k_yadjoint(YArgs a, Optics o) {
   const int g = blockIdx.x % a.ngroups;
   const int cs = (blockIdx.x / a.ngroups) * 4 + wave;
   const int64_t wid = (int64_t)blockIdx.x * 4 + wave;
-  if constexpr (!XF::kPruned) {
-    fill_twiddles(s_tw, threadIdx.x, kYThreads);
-    __syncthreads();
-    XF::fill(s_tab, s_tw, threadIdx.x, kYThreads);
-    if (XF::kMfma) __syncthreads();
-  }
+  const PixSrc src = pix_src(a);
+  fill_twiddles(s_tw, threadIdx.x, kYThreads);
+  __syncthreads();
+  XF::fill(s_tab, s_tw, threadIdx.x, kYThreads);
+  if (XF::kMfma) __syncthreads();
   if (cs >= ncs) {
     if (lane < 8 && !a.accumulate) a.pdc[wid * 8 + lane] = 0.0;
     return;
@@ -673,11 +643,11 @@ __global__ void __launch_bounds__(kYThreads, 2) k_yadjoint(YArgs a, Optics o) {
   int done = kd_a;  // pixels below `done` have their dL/dtheta partial written
   int kd = ms.next(kd_a);
   float2 v[16];
-  if (kd < kd_b) load_pixel<XF>(a, kd, c0, lane, v);
+  if (kd < kd_b) load_pixel<XF>(src, kd, c0, lane, v);
   while (kd < kd_b) {
     const int kdn = ms.next(kd + 1);
     float2 vn[16];
-    if (kdn < kd_b) load_pixel<XF>(a, kdn, c0, lane, vn);
+    if (kdn < kd_b) load_pixel<XF>(src, kdn, c0, lane, vn);
     if (lane == 0)
       for (int z = done; z < kd; ++z) pth[z] = 0.f;  // pixels without pairs in these columns
     const double2 k = a.kc[kd];
@@ -705,21 +675,12 @@ __global__ void __launch_bounds__(kYThreads, 2) k_yadjoint(YArgs a, Optics o) {
         const ChiCol ch = chi_column(wx, o);
         double M0 = 0.0, M1 = 0.0, M2 = 0.0, M3 = 0.0, M4 = 0.0;
         bool any = false;
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          if (XF::slot_of(i) != sl) continue;
-          int b, m;
-          XF::out(lane, i, b, m);
-          asm volatile("" : "+v"(m));  // see k_yreduce
-          const int iy = side ? signed_index((NY - m) & (NY - 1), NY) : signed_index(m, NY);
-          if (c >= nc || !(side ? sm[sl].has(iy) : sd[sl].has(iy))) continue;  // mirror empty unless 0 < c < Nx/2
+        // the pairs of register i: w = Re(conj(Tbar) i z) into the moments
+        auto pair = [&](int i, int m, int iy, float2 tb) {
           const double wy = o.lk * (k.y - (double)iy * o.sy);
           const float2 e = expi_reduced(chi_eval(ch, wy) - kch);
           const float2 gq = side ? cconj(v[i]) : v[i];
           const float2 z = make_float2(gq.x * e.x - gq.y * e.y, gq.x * e.y + gq.y * e.x);
-          // Tbar at this pair's frequency (read when needed: kept in registers for every frequency
-          // of the lane, it costs occupancy)
-          const float2 tb = side ? a.Tbt[(int64_t)(nx - c) * NY + ((NY - m) & (NY - 1))] : a.Tbt[(int64_t)c * NY + m];
           const double w = (double)(tb.x * (-z.y) + tb.y * z.x);
           any = true;
           double t = w;
@@ -732,6 +693,53 @@ __global__ void __launch_bounds__(kYThreads, 2) k_yadjoint(YArgs a, Optics o) {
           M3 += t;
           t *= wy;
           M4 += t;
+          (void)m;
+        };
+        if constexpr (XF::kSlots == 1) {
+          // Tbar at the pairs' frequencies: first the loads of every register holding a pair in some
+          // lane of the wave (one uniform branch each, so that they issue together), then the
+          // pairs; kept in registers for every frequency of the lane across the pixel loop, Tbar
+          // would cost occupancy
+          float2 tbv[16];
+          uint32_t hasp = 0;  // registers with a pair in this lane
+#pragma unroll
+          for (int i = 0; i < 16; ++i) {
+            int b, m;
+            XF::out(lane, i, b, m);
+            const int iy = side ? signed_index((NY - m) & (NY - 1), NY) : signed_index(m, NY);
+            const bool ok = c < nc && (side ? sm[sl].has(iy) : sd[sl].has(iy));  // mirror empty unless 0 < c < Nx/2
+            hasp |= ok ? 1u << i : 0u;
+            tbv[i] = make_float2(0.f, 0.f);
+            if (__ballot(ok)) {
+              const int cq = c < nc ? c : nc - 1;
+              const int col = side ? (nx - cq) % nx : cq;
+              tbv[i] = a.Tbt[(int64_t)col * NY + (side ? ((NY - m) & (NY - 1)) : m)];
+            }
+          }
+#pragma unroll
+          for (int i = 0; i < 16; ++i) {
+            if (!((hasp >> i) & 1u)) continue;
+            int b, m;
+            XF::out(lane, i, b, m);
+            asm volatile("" : "+v"(m));  // see k_yreduce
+            pair(i, m, side ? signed_index((NY - m) & (NY - 1), NY) : signed_index(m, NY), tbv[i]);
+          }
+        } else {
+          // several columns per wave: each lane reads Tbar at its register's frequency (a clamped
+          // address past the half spectrum), then the pair
+#pragma unroll
+          for (int i = 0; i < 16; ++i) {
+            if (XF::slot_of(i) != sl) continue;
+            int b, m;
+            XF::out(lane, i, b, m);
+            asm volatile("" : "+v"(m));  // see k_yreduce
+            const int iy = side ? signed_index((NY - m) & (NY - 1), NY) : signed_index(m, NY);
+            const int cq = c < nc ? c : nc - 1;
+            const int col = side ? (nx - cq) % nx : cq;
+            const float2 tb = a.Tbt[(int64_t)col * NY + (side ? ((NY - m) & (NY - 1)) : m)];
+            if (c >= nc || !(side ? sm[sl].has(iy) : sd[sl].has(iy))) continue;  // mirror empty unless 0 < c < Nx/2
+            pair(i, m, iy, tb);
+          }
         }
         if (any) {
           // sum over the column's pairs of w B_j(K - Q), B_j as polynomials in wy
@@ -806,30 +814,22 @@ inline dim3 ygrid(int ny, int nx, int ngroups) {
   return dim3((unsigned)(((ncs + 3) / 4) * ngroups));
 }
 
-// the fused sum over pixels [a.k0, a.k1): transform policy of precision PREC, or the pruned G
-// (PREC < 0); pwrite: also write the pruned G
+// the fused sum over pixels [a.k0, a.k1) with the transform policy of precision PREC; pwrite: also
+// write the pruned G
 template <int PREC>
 int launch_yreduce_p(int ny, const YArgs& a, const Optics& o, int chi0, int pwrite, hipStream_t s) {
   const dim3 grid = ygrid(ny, a.nx, a.ngroups), blk(kYThreads);
-  STEM_TRACE(PREC < 0 ? "ssb_reduce" : PREC == STEM_FFT_FP32 ? "ssb_yreduce" : "ssb_yreduce_mfma", s);
+  STEM_TRACE(PREC == STEM_FFT_FP32 ? "ssb_yreduce" : "ssb_yreduce_mfma", s);
   const int st = with_n(ny, [&](auto nc) {
-    constexpr int N = decltype(nc)::value;
-    using XF = std::conditional_t<(PREC < 0), XfPruned<N>, typename XfSel<N, (PREC < 0 ? 0 : PREC)>::type>;
-    if constexpr (PREC < 0) {
-      if (chi0)
-        hipLaunchKernelGGL((k_yreduce<XF, true, false>), grid, blk, 0, s, a, o);
-      else
-        hipLaunchKernelGGL((k_yreduce<XF, false, false>), grid, blk, 0, s, a, o);
-    } else {
-      if (chi0 && pwrite)
-        hipLaunchKernelGGL((k_yreduce<XF, true, true>), grid, blk, 0, s, a, o);
-      else if (chi0)
-        hipLaunchKernelGGL((k_yreduce<XF, true, false>), grid, blk, 0, s, a, o);
-      else if (pwrite)
-        hipLaunchKernelGGL((k_yreduce<XF, false, true>), grid, blk, 0, s, a, o);
-      else
-        hipLaunchKernelGGL((k_yreduce<XF, false, false>), grid, blk, 0, s, a, o);
-    }
+    using XF = typename XfSel<decltype(nc)::value, PREC>::type;
+    if (chi0 && pwrite)
+      hipLaunchKernelGGL((k_yreduce<XF, true, true>), grid, blk, 0, s, a, o);
+    else if (chi0)
+      hipLaunchKernelGGL((k_yreduce<XF, true, false>), grid, blk, 0, s, a, o);
+    else if (pwrite)
+      hipLaunchKernelGGL((k_yreduce<XF, false, true>), grid, blk, 0, s, a, o);
+    else
+      hipLaunchKernelGGL((k_yreduce<XF, false, false>), grid, blk, 0, s, a, o);
   });
   if (st) return st;
   STEM_LAUNCH_CHECK();
@@ -839,10 +839,9 @@ int launch_yreduce_p(int ny, const YArgs& a, const Optics& o, int chi0, int pwri
 template <int PREC>
 int launch_yadjoint_p(int ny, const YArgs& a, const Optics& o, hipStream_t s) {
   const dim3 grid = ygrid(ny, a.nx, a.ngroups), blk(kYThreads);
-  STEM_TRACE(PREC < 0 ? "ssb_adjoint_pruned" : PREC == STEM_FFT_FP32 ? "ssb_yadjoint" : "ssb_yadjoint_mfma", s);
+  STEM_TRACE(PREC == STEM_FFT_FP32 ? "ssb_yadjoint" : "ssb_yadjoint_mfma", s);
   const int st = with_n(ny, [&](auto nc) {
-    constexpr int N = decltype(nc)::value;
-    using XF = std::conditional_t<(PREC < 0), XfPruned<N>, typename XfSel<N, (PREC < 0 ? 0 : PREC)>::type>;
+    using XF = typename XfSel<decltype(nc)::value, PREC>::type;
     hipLaunchKernelGGL((k_yadjoint<XF>), grid, blk, 0, s, a, o);
   });
   if (st) return st;
