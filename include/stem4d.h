@@ -69,8 +69,10 @@ typedef struct {
   int32_t bin;
 } stem_det;
 
-/* Scan grid: Ny x Nx probe positions, spacing `step` angstrom.  The transforms need
- * Ny and Nx to be powers of two in [32, 1024]; centre of mass alone takes any size. */
+/* Scan grid: Ny x Nx probe positions, spacing `step` angstrom.  The transforms take Ny and Nx
+ * of the form 2^a 3^b 5^c, even, in [16, 4096] (the fused single-wave kernels serve powers of
+ * two in [32, 1024]; the other lengths run a mixed-radix LDS FFT and separate sum kernels);
+ * centre of mass alone takes any size. */
 typedef struct {
   int32_t ny, nx;
   double step;
@@ -171,7 +173,7 @@ size_t com_dpc_workspace_bytes(const stem_scan* scan);
  * d_phase[F] = Re IFFT2(Phi) in row-major (ry, rx) order.  ws must hold
  * com_dpc_workspace_bytes(scan) bytes (256-byte aligned) when d_phase != NULL.
  * Errors: STEM_EINVAL (NULL idx/off, no COM output when integrating, frame range outside
- * [0, F), scan not a power of two in [32, 1024] when integrating), STEM_EWORKSPACE. */
+ * [0, F), a scan length the transforms do not take when integrating), STEM_EWORKSPACE. */
 int com_dpc(const int32_t* d_idx, const int64_t* d_off, int64_t frame0, int64_t n_frames,
             const stem_det* det, const stem_scan* scan, const stem_optics* optics,
             const stem_dpc* dpc, double* d_com64, float* d_com32, int32_t* d_counts,
@@ -268,8 +270,9 @@ size_t ssb_state_bytes(const stem_det* det, const stem_scan* scan, const stem_op
  * mode ONESHOT: ACCUMULATE of all F frames then FINALIZE.
  * d_theta[n_K] (FP32, may be NULL = 0) is the per-pixel probe phase.  det, scan, optics
  * r_bf/dk/lam and ssb must stay the same across the calls sharing a state.
- * Errors: STEM_EINVAL (geometry, sizes, non-row chunks, scan not a power of two in
- * [32, 1024], n_K = 0 or > 4096), STEM_EWORKSPACE, STEM_ESTATE; device bits ERANGE/EOVERFLOW. */
+ * Errors: STEM_EINVAL (geometry, sizes, non-row chunks, a scan length the transforms do not
+ * take, a split precision with a length other than a power of two in [32, 1024], n_K = 0 or
+ * > 4096), STEM_EWORKSPACE, STEM_ESTATE; device bits ERANGE/EOVERFLOW. */
 int ssb_reconstruct(const int32_t* d_idx, const int64_t* d_off, int64_t frame0, int64_t n_frames,
                     const stem_det* det, const stem_scan* scan, const stem_optics* optics,
                     const stem_ssb* ssb, int mode, const float* d_theta, void* state,

@@ -9,6 +9,7 @@
 #include <mutex>
 
 #include "common.h"
+#include "fft_generic.h"
 #include "fft_wave.h"
 #include "kernels.h"
 #include "trace.h"
@@ -210,9 +211,135 @@ static void launch_n(bool inv, const RowFftArgs& a, int in, int out, hipStream_t
     launch_nw<N, 8>(inv, a, in, out, s);
 }
 
+// ---------------------------------------------------------------------------------------------
+// Batched row FFTs of the lengths the wavefront FFT does not take (fft_generic.h): a workgroup
+// loads RB rows into LDS (the input modes of k_row_fft, and real rows of counts), transforms them
+// and writes them (the output modes of k_row_fft, and the row-transformed cube's transposed
+// layout), grid-stride over batches of rows, its twiddle table filled once.  Transposed outputs
+// are written rows-fastest (runs of RB consecutive rows per frequency).
+
+bool scan_length_ok(int n) {
+  if (fast_length(n)) return true;
+  GPlan p;
+  return n >= 16 && n % 2 == 0 && gen_plan(n, p);
+}
+
+__global__ void __launch_bounds__(kGenThreads) k_grow_fft(RowFftArgs a, GPlan p, int inv, int in_mode, int out_mode) {
+  extern __shared__ float2 s_g[];  // twiddles [n], then rb rows of n
+  const int n = p.n, rb = gen_rows_per_block(n);
+  float2* tw = s_g;
+  float2* buf = s_g + n;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (in_mode == IN_C64_SUM && a.stats && blockIdx.x == 0) {
+    // the fused sums' per-wave counters: pair count below bit 40, 8-byte loads above
+    __shared__ unsigned long long s_red[2][kGenThreads / 64];
+    unsigned long long c = 0, l = 0;
+    for (int64_t i = threadIdx.x; i < a.nwcnt; i += blockDim.x) {
+      c += a.wcnt[i] & ((1ull << 40) - 1);
+      l += a.wcnt[i] >> 40;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      c += __shfl_xor(c, off);
+      l += __shfl_xor(l, off);
+    }
+    if (lane == 0) {
+      s_red[0][wave] = c;
+      s_red[1][wave] = l;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+      unsigned long long t = 0, u = 0;
+      for (int w = 0; w < kGenThreads / 64; ++w) {
+        t += s_red[0][w];
+        u += s_red[1][w];
+      }
+      a.stats[threadIdx.x] = threadIdx.x == 0   ? t
+                             : threadIdx.x == 1 ? (unsigned long long)a.stats_groups
+                             : threadIdx.x == 2 ? 8ull * u
+                                                : (unsigned long long)a.stats_chunks;
+    }
+  }
+  gen_twiddles(tw, n);
+  __syncthreads();
+  const int64_t nbatch = (a.nrows + rb - 1) / rb;
+  const bool transposed = out_mode == OUT_T_C64 || out_mode == OUT_T_RE || out_mode == OUT_T_IM || out_mode == OUT_X;
+  const int nh = n / 2 + 1;
+  for (int64_t bt = blockIdx.x; bt < nbatch; bt += gridDim.x) {
+    const int64_t r0 = bt * rb;
+    for (int e = threadIdx.x; e < rb * n; e += blockDim.x) {
+      const int rl = e / n, i = e % n;
+      const int64_t r = r0 + rl;
+      float2 x = make_float2(0.f, 0.f);
+      if (r < a.nrows) {
+        const int64_t el = r * n + i;
+        if (in_mode == IN_C64) {
+          x = a.in_c[el];
+        } else if (in_mode == IN_C64_SUM) {
+          for (int q = 0; q < a.nparts; ++q) x = cadd(x, a.in_c[(int64_t)q * a.part_stride + el]);
+          if (a.norm_cnt) {
+            const int32_t cnt = a.norm_cnt[el];
+            x = cnt > 0 ? make_float2(x.x / (float)cnt, x.y / (float)cnt) : make_float2(0.f, 0.f);
+          }
+          if (a.sum_out) a.sum_out[el] = x;
+        } else if (in_mode == IN_HALF_C64) {
+          const float2* hr = a.in_c + r * nh;
+          x = 2 * i <= n ? hr[i] : cconj(hr[n - i]);
+        } else if (in_mode == IN_F32_PAIR) {
+          x.x = a.in_f0[el] * a.s0;
+          x.y = a.in_f1 ? a.in_f1[el] * a.s1 : 0.f;
+        } else if (in_mode == IN_F64_PAIR) {
+          x.x = (float)(a.in_d0[el] * (double)a.s0);
+          x.y = a.in_d1 ? (float)(a.in_d1[el] * (double)a.s1) : 0.f;
+        } else if (in_mode == IN_U8) {
+          x.x = (float)((const uint8_t*)a.in_u)[el];
+        } else {
+          x.x = (float)((const uint16_t*)a.in_u)[el];
+        }
+      }
+      buf[e] = inv ? cconj(x) : x;
+    }
+    __syncthreads();
+    gen_fft(buf, tw, p, rb);
+    for (int e = threadIdx.x; e < rb * n; e += blockDim.x) {
+      // transposed outputs rows-fastest, the others along the row
+      const int rl = transposed ? e % rb : e / n, m = transposed ? e / rb : e % n;
+      const int64_t r = r0 + rl;
+      if (r >= a.nrows) continue;
+      const float2 y = buf[rl * n + m];
+      const float2 v = cmul(inv ? cconj(y) : y, a.osc);
+      if (out_mode == OUT_ROW_C64) a.out_c[r * n + m] = v;
+      else if (out_mode == OUT_ROW_RE) a.out_f[r * n + m] = v.x;
+      else if (out_mode == OUT_ROW_IM) a.out_f[r * n + m] = v.y;
+      else if (out_mode == OUT_T_C64) a.out_c[(int64_t)m * a.out_stride + r] = v;
+      else if (out_mode == OUT_T_RE) a.out_f[(int64_t)m * a.out_stride + r] = v.x;
+      else if (out_mode == OUT_T_IM) a.out_f[(int64_t)m * a.out_stride + r] = v.y;
+      else if (m < nh) {
+        const int64_t kd = r / a.xrows, y_ = r % a.xrows;
+        a.out_c[(kd * nh + m) * a.xrows + y_] = v;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+static int launch_generic(int n, bool inverse, RowIn in, RowOut out, const RowFftArgs& a, hipStream_t stream) {
+  GPlan p;
+  if (!gen_plan(n, p)) return STEM_EINVAL;
+  const int rb = gen_rows_per_block(n);
+  const int64_t batches = (a.nrows + rb - 1) / rb;
+  const size_t lds = (size_t)(n + rb * n) * sizeof(float2);
+  const int res = resident_blocks((const void*)k_grow_fft, kGenThreads, lds);
+  const int64_t cap = res > 0 ? res : 1024;
+  hipLaunchKernelGGL(k_grow_fft, dim3((unsigned)(batches < cap ? batches : cap)), dim3(kGenThreads), lds, stream, a,
+                     p, inverse ? 1 : 0, (int)in, (int)out);
+  STEM_LAUNCH_CHECK();
+  return STEM_OK;
+}
+
 int launch_row_fft(int n, bool inverse, RowIn in, RowOut out, const RowFftArgs& a, hipStream_t stream) {
   if (a.nrows <= 0) return STEM_OK;
   STEM_TRACE(a.tag ? a.tag : "row_fft", stream);
+  if (!fast_length(n) || in == IN_U8 || in == IN_U16 || out == OUT_X) return launch_generic(n, inverse, in, out, a, stream);
   switch (n) {
     case 32: launch_n<32>(inverse, a, in, out, stream); break;
     case 64: launch_n<64>(inverse, a, in, out, stream); break;
@@ -435,6 +562,96 @@ static int launch_dpc(const double* c64, const float* c32, int64_t F, int ny, in
   return launch_row_fft(nx, true, IN_HALF_C64, OUT_ROW_RE, a, s);
 }
 
+// ---------------------------------------------------------------------------------------------
+// DPC for the other scan lengths, in five passes of the generic FFT and one per-frequency pass:
+// rows ry of z = g (COM_x + i COM_y) transformed along rx and written transposed [mx][ry]; rows mx
+// transformed along ry in place (C = FFT2 z, column-major [mx][my]); the descent per frequency from
+// Gx = (C(q) + conj C(-q))/2 and Gy = (C(q) - conj C(-q))/(2i) into Phi; the inverse along my,
+// written transposed [ry][mx]; the inverse along mx, real part / F.
+
+__global__ void __launch_bounds__(256) k_dpc_descent(const float2* __restrict__ C, int ny, int nx, double step,
+                                                     double mu, double lam1, double lam2, int n_iter,
+                                                     float2* __restrict__ Phi) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= (int64_t)ny * nx) return;
+  const int mx = (int)(q / ny), my = (int)(q % ny);
+  const float2 c = C[q];
+  const float2 cm = cconj(C[(int64_t)((nx - mx) % nx) * ny + (ny - my) % ny]);
+  const double two_pi = 6.283185307179586476925286766559;
+  const int sy = my < (ny + 1) / 2 ? my : my - ny;
+  const int sx = mx < (nx + 1) / 2 ? mx : mx - nx;
+  const double qy = two_pi * ((double)sy / ((double)ny * step));
+  const double qx = two_pi * ((double)sx / ((double)nx * step));
+  const double q2 = qx * qx + qy * qy;
+  const double d = lam1 + q2 + lam2 * q2 * q2;
+  const bool live = d != 0.0 && !(my == 0 && mx == 0) && 2 * my != ny && 2 * mx != nx;
+  double pr = 0.0, pi = 0.0;
+  if (live) {
+    // Gx = (c + cm)/2, Gy = (c - cm)/(2i)
+    const float2 gx = make_float2(0.5f * (c.x + cm.x), 0.5f * (c.y + cm.y));
+    const float2 gy = make_float2(0.5f * (c.y - cm.y), -0.5f * (c.x - cm.x));
+    const double gxr = gx.x, gxi = gx.y, gyr = gy.x, gyi = gy.y;
+    const double md = mu / d;
+    for (int l = 0; l < n_iter; ++l) {
+      // residuals G - D Phi with D = i q, then conj(D) r = -i q r
+      const double rxr = gxr + qx * pi, rxi = gxi - qx * pr;
+      const double ryr = gyr + qy * pi, ryi = gyi - qy * pr;
+      const double ur = qx * rxi + qy * ryi, ui = -(qx * rxr + qy * ryr);
+      pr += md * ur;
+      pi += md * ui;
+    }
+  }
+  Phi[q] = make_float2((float)pr, (float)pi);
+}
+
+static int launch_dpc_generic(const double* c64, const float* c32, int64_t F, int ny, int nx, float g, double step,
+                              const stem_dpc& p, float2* A, float2* B, float* phase, hipStream_t s) {
+  RowFftArgs a{};
+  a.nrows = ny;
+  if (c64) {
+    a.in_d0 = c64;
+    a.in_d1 = c64 + F;
+  } else {
+    a.in_f0 = c32;
+    a.in_f1 = c32 + F;
+  }
+  a.s0 = a.s1 = g;
+  a.out_c = A;
+  a.out_stride = ny;
+  a.osc = make_float2(1.f, 0.f);
+  a.tag = "dpc_fft";
+  int st = launch_row_fft(nx, false, c64 ? IN_F64_PAIR : IN_F32_PAIR, OUT_T_C64, a, s);
+  if (st) return st;
+  a = RowFftArgs{};
+  a.nrows = nx;
+  a.in_c = A;
+  a.out_c = A;
+  a.osc = make_float2(1.f, 0.f);
+  a.tag = "dpc_fft";
+  if ((st = launch_row_fft(ny, false, IN_C64, OUT_ROW_C64, a, s))) return st;
+  {
+    STEM_TRACE("dpc_descent", s);
+    hipLaunchKernelGGL(k_dpc_descent, dim3((unsigned)((F + 255) / 256)), dim3(256), 0, s, A, ny, nx, step, p.mu,
+                       p.lam1, p.lam2, p.n_iter, B);
+    STEM_LAUNCH_CHECK();
+  }
+  a = RowFftArgs{};
+  a.nrows = nx;
+  a.in_c = B;
+  a.out_c = A;
+  a.out_stride = nx;
+  a.osc = make_float2(1.f, 0.f);
+  a.tag = "dpc_fft";
+  if ((st = launch_row_fft(ny, true, IN_C64, OUT_T_C64, a, s))) return st;
+  a = RowFftArgs{};
+  a.nrows = ny;
+  a.in_c = A;
+  a.out_f = phase;
+  a.osc = make_float2((float)(1.0 / (double)F), 0.f);
+  a.tag = "dpc_fft";
+  return launch_row_fft(nx, true, IN_C64, OUT_ROW_RE, a, s);
+}
+
 }  // namespace stem
 
 // ---------------------------------------------------------------------------------------------
@@ -444,8 +661,11 @@ using namespace stem;
 
 extern "C" size_t com_dpc_workspace_bytes(const stem_scan* scan) {
   if (!scan || scan->ny <= 0 || scan->nx <= 0) return 0;
-  // the half spectra Gx, Gy along x and the half-spectrum result, (Nx/2+1) Ny complex64 each
-  return 3 * align256((size_t)scan->ny * (scan->nx / 2 + 1) * sizeof(float2));
+  if (fast_length(scan->ny) && fast_length(scan->nx))
+    // the half spectra Gx, Gy along x and the half-spectrum result, (Nx/2+1) Ny complex64 each
+    return 3 * align256((size_t)scan->ny * (scan->nx / 2 + 1) * sizeof(float2));
+  // the other lengths: the full transform of z and the descent's result, F complex64 each
+  return 2 * align256((size_t)scan->ny * scan->nx * sizeof(float2));
 }
 
 static int run_com_dpc(const int32_t* d_idx, const int64_t* d_off, int64_t frame0, int64_t n_frames,
@@ -460,7 +680,7 @@ static int run_com_dpc(const int32_t* d_idx, const int64_t* d_off, int64_t frame
   hipStream_t stream = (hipStream_t)stream_;
   if (d_phase) {
     if (!optics || !dpc || (!d_com64 && !d_com32)) return STEM_EINVAL;
-    if (!is_pow2_in(scan->ny, 32, 1024) || !is_pow2_in(scan->nx, 32, 1024)) return STEM_EINVAL;
+    if (!scan_length_ok(scan->ny) || !scan_length_ok(scan->nx)) return STEM_EINVAL;
     if (!(scan->step > 0) || !(optics->dk > 0) || dpc->n_iter < 0) return STEM_EINVAL;
     if (!ws || ws_bytes < com_dpc_workspace_bytes(scan) || ((uintptr_t)ws & 255)) return STEM_EWORKSPACE;
   }
@@ -468,11 +688,17 @@ static int run_com_dpc(const int32_t* d_idx, const int64_t* d_off, int64_t frame
   if (st != STEM_OK || !d_phase) return st;
 
   const int ny = scan->ny, nx = scan->nx;
+  const float g = (float)(2.0 * 3.14159265358979323846 * optics->dk);
+  if (!fast_length(ny) || !fast_length(nx)) {
+    float2* A = (float2*)ws;
+    float2* B = (float2*)((char*)ws + align256((size_t)F * sizeof(float2)));
+    return launch_dpc_generic(d_com64, d_com64 ? nullptr : d_com32, F, ny, nx, g, scan->step, *dpc, A, B, d_phase,
+                              stream);
+  }
   const size_t half = align256((size_t)ny * (nx / 2 + 1) * sizeof(float2));
   float2* Ax = (float2*)ws;
   float2* Ay = (float2*)((char*)ws + half);
   float2* Q = (float2*)((char*)ws + 2 * half);
-  const float g = (float)(2.0 * 3.14159265358979323846 * optics->dk);
   return launch_dpc(d_com64, d_com64 ? nullptr : d_com32, F, ny, nx, g, scan->step, *dpc, Ax, Ay, Q, d_phase, stream);
 }
 

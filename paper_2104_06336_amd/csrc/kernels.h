@@ -33,8 +33,8 @@ int launch_bin(const int32_t* idx, const int64_t* off, int64_t frame0, int64_t n
 bool bin_builds_sets(const stem_det& det, double r2);
 
 // ---- fft2.hip: batched row FFTs of length n (power of two, 32..1024) --------------------------
-enum RowIn { IN_C64 = 0, IN_C64_SUM = 1, IN_F32_PAIR = 2, IN_F64_PAIR = 3, IN_HALF_C64 = 4 };
-enum RowOut { OUT_T_C64 = 0, OUT_ROW_C64 = 1, OUT_ROW_RE = 2, OUT_ROW_IM = 3, OUT_T_RE = 4, OUT_T_IM = 5 };
+enum RowIn { IN_C64 = 0, IN_C64_SUM = 1, IN_F32_PAIR = 2, IN_F64_PAIR = 3, IN_HALF_C64 = 4, IN_U8 = 5, IN_U16 = 6 };
+enum RowOut { OUT_T_C64 = 0, OUT_ROW_C64 = 1, OUT_ROW_RE = 2, OUT_ROW_IM = 3, OUT_T_RE = 4, OUT_T_IM = 5, OUT_X = 6 };
 
 struct RowFftArgs {
   int64_t nrows;
@@ -48,9 +48,13 @@ struct RowFftArgs {
   const float* in_f1;
   const double* in_d0;     // IN_F64_PAIR
   const double* in_d1;
+  const void* in_u;        // IN_U8 / IN_U16 (generic lengths only): real row r at in_u + r*n
   float s0, s1;
   // outputs
-  float2* out_c;           // OUT_T_*: element (r, m) at out[m*out_stride + r]; OUT_ROW_*: out[r*n + m]
+  float2* out_c;           // OUT_T_*: element (r, m) at out[m*out_stride + r]; OUT_ROW_*: out[r*n + m];
+                           // OUT_X (generic lengths only): m <= n/2 of row r = kd*xrows + y at
+                           // out[(kd*(n/2+1) + m)*xrows + y]
+  int32_t xrows;
   float* out_f;
   int64_t out_stride;
   float2 osc;              // complex factor applied to every output value
@@ -69,6 +73,11 @@ struct RowFftArgs {
 };
 
 int launch_row_fft(int n, bool inverse, RowIn in, RowOut out, const RowFftArgs& a, hipStream_t stream);
+
+// lengths the wavefront FFT takes (powers of two in [32, 1024]); the others go to the generic FFT
+inline bool fast_length(int n) { return is_pow2_in(n, 32, 1024); }
+// lengths the library transforms: the fast ones, and even N = 2^a 3^b 5^c in [16, 4096]
+bool scan_length_ok(int n);
 
 // ---- ssb.hip ---------------------------------------------------------------------------------
 size_t ssb_layout(const stem_det& det, const stem_scan& scan, const stem_optics& optics,

@@ -236,7 +236,7 @@ __device__ __forceinline__ ColSet col_set(double kx, double ky, int ix, int ny, 
 }
 
 // The double-overlap interval table of the fused column sum and its active-pixel mask: for
-// column set cs (B = 1024/ny consecutive half-spectrum columns) and mask word w, lane j takes
+// column set cs (B consecutive half-spectrum columns, colset_width) and mask word w, lane j takes
 // pixel kd = 64 w + j; cst[kd * nc + c] packs its direct and mirrored sets of every column c of
 // the set, and bit j of mask[cs * nmw + w] says whether any of them is non-empty.
 struct SetsJob {
@@ -244,11 +244,16 @@ struct SetsJob {
   int n_k, nx, ny, ncs, nmw;
   int4* cst;          // nullptr: nothing to do
   uint64_t* mask;
+  int B;              // half-spectrum columns per column set
 };
+
+// Half-spectrum columns per column set: the B = 1024/Ny columns one wave of the fused kernels takes
+// (one column for the lengths those kernels do not take).
+__host__ __device__ inline int colset_width(int ny) { return (ny >= 32 && ny <= 1024 && (ny & (ny - 1)) == 0) ? 1024 / ny : 1; }
 
 // One mask word (one wave, every lane active); k = Kc of the lane's pixel when kd < n_k.
 __device__ __forceinline__ void sets_word(const SetsJob& j, int64_t word, int lane, double2 k) {
-  const int nc = j.nx / 2 + 1, B = 1024 / j.ny;
+  const int nc = j.nx / 2 + 1, B = j.B;
   const int cs = (int)(word / j.nmw), w = (int)(word % j.nmw);
   const int kd = 64 * w + lane;
   auto pk = [](int lo, int hi) { return (int)(((uint32_t)lo & 0xffffu) | ((uint32_t)hi << 16)); };

@@ -14,6 +14,7 @@
 // transform for a chunk of pixels at a time into a bounded scratch and fuses the column
 // transform and the sum on it.
 #include "common.h"
+#include "fft_generic.h"
 #include "fft_wave.h"
 #include "ssb_fused.h"
 #include "ssb_pruned.h"
@@ -31,13 +32,15 @@ struct SsbLayout {
   int64_t F;
   bool store;     // STEM_G_STORE
   int xpix;       // pixels whose row-transformed columns the X region holds (n_k, or one chunk)
+  int ypix;       // pixels of the column-transform scratch (stored G of the other lengths), or 0
   int nchunks;    // pixel chunks of a sum
   int64_t pcap;   // entries of the pruned G array (0 without STEM_G_STORE)
-  size_t rows, kc, kchi, cst, cmask, lut, stats, npq, D, X, poff, ptot, pg, T, A, Tb, pdc, pdth, part, wcnt, total;
+  size_t rows, kc, kchi, cst, cmask, lut, stats, npq, D, X, Y, poff, ptot, pg, T, A, Tb, pdc, pdth, part, wcnt, total;
   int nmw;      // 64-bit words per column set of the active-pixel mask
   int groups;   // pixel groups of the fused column kernels (the same for every chunk)
   int pgroups;  // pixel groups of the kernels over the stored double-overlap values
-  int ncs;      // column sets (B = 1024/Ny half-spectrum columns each)
+  int ncs;      // column sets (colset_width(Ny) half-spectrum columns each)
+  bool fast;    // both scan lengths taken by the fused kernels (powers of two in [32, 1024])
   int64_t nwy;  // waves of the fused kernels
   int64_t nwp;  // waves of the refocus sum over the stored values
   int64_t nwa;  // waves of the adjoint over the stored values
@@ -89,17 +92,27 @@ static size_t make_layout(const stem_det& det, const stem_scan& scan, const stem
   L->nh = scan.nx / 2 + 1;
   L->F = (int64_t)scan.ny * scan.nx;
   L->store = ssb.g_mode == STEM_G_STORE;
+  L->fast = fast_length(scan.ny) && fast_length(scan.nx);
   const size_t per_pixel = (size_t)L->nh * scan.ny * sizeof(float2);
-  if (L->store) {
-    L->xpix = n_k;
-    L->nchunks = 1;
-    L->pcap = pruned_bound(scan, op, n_k);
-  } else {
+  // chunks of pixels whose columns fit the scratch: balanced, of xpix or xpix - 1 pixels
+  int chunk;
+  {
     const size_t cap = (size_t)(ssb.scratch_mib > 0 ? ssb.scratch_mib : kDefaultScratchMib) << 20;
     int nc = (int)(cap / per_pixel);
     nc = nc < 1 ? 1 : nc > n_k ? n_k : nc;
     L->nchunks = (n_k + nc - 1) / nc;
-    L->xpix = (n_k + L->nchunks - 1) / L->nchunks;  // balanced chunks of xpix or xpix - 1 pixels
+    chunk = (n_k + L->nchunks - 1) / L->nchunks;
+  }
+  L->ypix = 0;
+  if (L->store) {
+    // every pixel's row transform; the other lengths also transform the columns in chunks into a
+    // scratch of their own (the row transform stays for the panel of G)
+    L->xpix = n_k;
+    if (L->fast) L->nchunks = 1;
+    else L->ypix = chunk;
+    L->pcap = pruned_bound(scan, op, n_k);
+  } else {
+    L->xpix = chunk;
     L->pcap = 0;
   }
   size_t o = 0;
@@ -109,7 +122,7 @@ static size_t make_layout(const stem_det& det, const stem_scan& scan, const stem
   L->cst = o;   o = align256(o + sizeof(int4) * n_k * L->nh);
   L->nmw = (n_k + 63) / 64;
   {
-    const int B = 1024 / scan.ny;
+    const int B = colset_width(scan.ny);
     L->ncs = (L->nh + B - 1) / B;
   }
   L->cmask = o; o = align256(o + sizeof(uint64_t) * (size_t)L->nmw * L->ncs);
@@ -118,6 +131,7 @@ static size_t make_layout(const stem_det& det, const stem_scan& scan, const stem
   L->npq = o;   o = align256(o + sizeof(int32_t) * (size_t)L->F);
   L->D = o;     o = align256(o + (size_t)n_k * L->F * (ssb.d_bits / 8));
   L->X = o;     o = align256(o + (size_t)L->xpix * per_pixel);
+  L->Y = o;     o = align256(o + (size_t)L->ypix * per_pixel);
   L->poff = o;  o = align256(o + (L->store ? sizeof(int64_t) * ((size_t)n_k * scan.nx + 1) : 0));
   L->ptot = o;  o = align256(o + (L->store ? sizeof(int64_t) * (size_t)n_k : 0));
   L->pg = o;    o = align256(o + sizeof(float2) * (size_t)L->pcap);
@@ -187,7 +201,7 @@ __global__ void __launch_bounds__(256) k_colsets(const double2* __restrict__ kc,
   const int64_t word = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (word >= (int64_t)ncs * nmw) return;  // uniform across the wave
   const int lane = (int)(threadIdx.x & 63), kd = 64 * (int)(word % nmw) + lane;
-  const SetsJob j{o, n_k, nx, ny, ncs, nmw, cst, mask};
+  const SetsJob j{o, n_k, nx, ny, ncs, nmw, cst, mask, B};
   sets_word(j, word, lane, kd < n_k ? kc[kd] : make_double2(0.0, 0.0));
 }
 
@@ -195,7 +209,7 @@ __global__ void __launch_bounds__(256) k_colsets(const double2* __restrict__ kc,
 static int launch_colsets(const double2* kc, int n_k, int nx, int ny, const Optics& o, int4* cst, uint64_t* cmask,
                           int nmw, hipStream_t s, const float* theta, double* kchi) {
   STEM_TRACE("ssb_colsets", s);
-  const int B = 1024 / ny, ncs = (nx / 2 + 1 + B - 1) / B;
+  const int B = colset_width(ny), ncs = (nx / 2 + 1 + B - 1) / B;
   const int64_t words = (int64_t)ncs * nmw;
   const int mask_blocks = (int)((words + 3) / 4);
   const int chi_blocks = kchi ? (n_k + 255) / 256 : 0;
@@ -346,7 +360,7 @@ __global__ void __launch_bounds__(256) k_prune_add(int nx, int64_t* __restrict__
 
 // number of pixel groups of the fused sum: about 4096 waves, at most n_k, partial sums <= 64 MB
 static int yreduce_groups(int ny, int nx, int n_k) {
-  const int B = 1024 / ny;
+  const int B = colset_width(ny);
   const int ncs = (nx / 2 + 1 + B - 1) / B;
   // about 2560 waves: 1.25 times the waves the GPU holds at once (256 CUs x 8 at this kernel's
   // register use), so that waves of cheap columns (few pixels with a non-empty set) free their
@@ -441,6 +455,7 @@ struct Bufs {
   int32_t* npq;
   void* D;
   float2* X;
+  float2* Y;
   int64_t* poff;
   int64_t* ptot;
   float2* pg;
@@ -457,7 +472,7 @@ static Bufs carve(void* state, const SsbLayout& L) {
   char* p = (char*)state;
   return Bufs{(RowRun*)(p + L.rows), (double2*)(p + L.kc), (double*)(p + L.kchi), (int4*)(p + L.cst),
               (uint64_t*)(p + L.cmask), (int16_t*)(p + L.lut), (unsigned long long*)(p + L.stats),
-              (int32_t*)(p + L.npq), (void*)(p + L.D), (float2*)(p + L.X), (int64_t*)(p + L.poff),
+              (int32_t*)(p + L.npq), (void*)(p + L.D), (float2*)(p + L.X), (float2*)(p + L.Y), (int64_t*)(p + L.poff),
               (int64_t*)(p + L.ptot), (float2*)(p + L.pg), (float2*)(p + L.T), (float2*)(p + L.A), (float2*)(p + L.Tb),
               (double*)(p + L.pdc), (float*)(p + L.pdth), (float2*)(p + L.part),
               (unsigned long long*)(p + L.wcnt)};
@@ -466,13 +481,14 @@ static Bufs carve(void* state, const SsbLayout& L) {
 static int check_common(const stem_det* det, const stem_scan* scan, const stem_optics* optics,
                         const stem_ssb* ssb, int* n_k) {
   if (!det_ok(det) || !scan || !optics_ok(optics) || !ssb) return STEM_EINVAL;
-  if (!is_pow2_in(scan->ny, 32, 1024) || !is_pow2_in(scan->nx, 32, 1024) || !(scan->step > 0))
-    return STEM_EINVAL;
+  if (!scan_length_ok(scan->ny) || !scan_length_ok(scan->nx) || !(scan->step > 0)) return STEM_EINVAL;
   if (ssb->d_bits != 8 && ssb->d_bits != 16) return STEM_EINVAL;
   if (ssb->precision != STEM_FFT_FP32 && ssb->precision != STEM_DFT_BF16_SPLIT &&
       ssb->precision != STEM_DFT_FP16_SPLIT)
     return STEM_EINVAL;
   if (ssb->g_mode != STEM_G_STORE && ssb->g_mode != STEM_G_RECOMPUTE) return STEM_EINVAL;
+  // the split-precision matrix-core transforms exist for the fused kernels' lengths only
+  if (ssb->precision != STEM_FFT_FP32 && !(fast_length(scan->ny) && fast_length(scan->nx))) return STEM_EINVAL;
   if (ssb->normalize != 0 && ssb->normalize != 1) return STEM_EINVAL;
   if (ssb->scratch_mib < 0 || ssb->scratch_mib > (1 << 20)) return STEM_EINVAL;
   const int n = count_pixels(*det, optics->r_bf * optics->r_bf);
@@ -498,7 +514,7 @@ static YArgs yargs(const SsbLayout& L, const Bufs& b, int nx) {
   a.accumulate = 0;
   a.pg = b.pg;
   a.pgw = b.pg;
-  a.poff = b.poff;
+  a.poff = L.store ? b.poff : nullptr;
   a.pcap = L.pcap;
   a.part = b.part;
   a.wcnt = b.wcnt;
@@ -525,10 +541,36 @@ static int xstage_pixels(const SsbLayout& L, const Bufs& b, const stem_ssb& ssb,
                                    s);
 }
 
+// The other scan lengths: row transform of the pixels [k0, k1) (all rows) into X by the generic
+// FFT (one real row per transform), then the column transforms of those pixels, from src into dst
+// (in place when equal).
+static int xstage_generic(const SsbLayout& L, const Bufs& b, const stem_ssb& ssb, int ny, int nx, int k0, int k1,
+                          hipStream_t s) {
+  RowFftArgs a{};
+  a.nrows = (int64_t)(k1 - k0) * ny;
+  a.in_u = ssb.d_bits == 8 ? (const void*)((const uint8_t*)b.D + (size_t)k0 * L.F)
+                           : (const void*)((const uint16_t*)b.D + (size_t)k0 * L.F);
+  a.out_c = b.X;
+  a.xrows = ny;
+  a.osc = make_float2(1.f, 0.f);
+  a.tag = "xstage_fft";
+  return launch_row_fft(nx, false, ssb.d_bits == 8 ? IN_U8 : IN_U16, OUT_X, a, s);
+}
+
+static int colfft_generic(const SsbLayout& L, int ny, int k0, int k1, const float2* src, float2* dst, hipStream_t s) {
+  RowFftArgs a{};
+  a.nrows = (int64_t)(k1 - k0) * L.nh;
+  a.in_c = src;
+  a.out_c = dst;
+  a.osc = make_float2(1.f, 0.f);
+  a.tag = "ystage_fft";
+  return launch_row_fft(ny, false, IN_C64, OUT_ROW_C64, a, s);
+}
+
 // T = sum of the partial sums (column-major [mx][my]), divided by the pair count of each Q when
 // npq is given; phi = Im IFFT2(T); d_T row-major.  The fused kernels' per-wave counters become the
 // state's counters.
-static int run_phase(const SsbLayout& L, const Bufs& b, const stem_scan& sc, int nparts, int64_t nwaves,
+static int run_phase(const SsbLayout& L, const Bufs& b, const stem_scan& sc, int nparts, int64_t nwaves, int nchunks,
                      const int32_t* npq, float* d_phase, float* d_T, hipStream_t s) {
   const int ny = sc.ny, nx = sc.nx;
   RowFftArgs a{};
@@ -547,7 +589,7 @@ static int run_phase(const SsbLayout& L, const Bufs& b, const stem_scan& sc, int
   a.nwcnt = nwaves;
   a.stats = b.stats;
   a.stats_groups = nparts;
-  a.stats_chunks = L.store ? 1 : L.nchunks;
+  a.stats_chunks = nchunks;
   int st = launch_row_fft(ny, true, IN_C64_SUM, OUT_T_C64, a, s);
   if (st) return st;
   if (d_phase) {
@@ -662,11 +704,11 @@ static int reconstruct(const int32_t* d_idx, const int64_t* d_off, int64_t frame
     if (frame0 < 0 || n_frames <= 0 || frame0 % nx || n_frames % nx || frame0 + n_frames > L.F)
       return STEM_EINVAL;
     // the binning also builds the interval table and the active-pixel mask when it can (geometry only)
-    const SetsJob job{o, n_k, nx, ny, L.ncs, L.nmw, b.cst, b.cmask};
+    const SetsJob job{o, n_k, nx, ny, L.ncs, L.nmw, b.cst, b.cmask, colset_width(ny)};
     if ((st = launch_bin(d_idx, d_off, frame0, n_frames, *det, o.r2, b.rows, b.kc, b.lut, n_k, L.F, b.D,
                           ssb->d_bits, d_status, s, com, &job)))
       return st;
-    if (L.store) {
+    if (L.store && L.fast) {
       // STEM_G_STORE keeps the row transform of every pixel: transform this chunk's rows now
       const int ry0 = (int)(frame0 / nx), nr = (int)(n_frames / nx);
       const int64_t nrows = (int64_t)n_k * nr;
@@ -694,8 +736,33 @@ static int reconstruct(const int32_t* d_idx, const int64_t* d_off, int64_t frame
   if (L.store && refocus) {
     // Eq. 3 again from the stored double-overlap values
     a.ngroups = L.pgroups;
-    if ((st = launch_psum(ny, a, o, chi0, s))) return st;
-    return run_phase(L, b, *scan, L.pgroups, L.nwp, ssb->normalize ? b.npq : nullptr, d_phase, d_T, s);
+    if ((st = launch_psum(ny, a, o, chi0, false, false, s))) return st;
+    return run_phase(L, b, *scan, L.pgroups, L.nwp, 1, ssb->normalize ? b.npq : nullptr, d_phase, d_T, s);
+  } else if (!L.fast) {
+    // the other scan lengths: row and column transforms by the generic FFT, then Eq. 3 per
+    // (pixel, column) run over the full columns of G, chunk by chunk
+    a.ngroups = L.pgroups;
+    if (L.store) {
+      if ((st = xstage_generic(L, b, *ssb, ny, nx, 0, n_k, s))) return st;
+      if ((st = run_prune_offsets(L, b, nx, d_status, s))) return st;
+    }
+    for (int ch = 0; ch < L.nchunks; ++ch) {
+      int k0, k1;
+      chunk_range(L, ch, k0, k1);
+      if (L.store) {
+        if ((st = colfft_generic(L, ny, k0, k1, b.X + (size_t)k0 * L.nh * ny, b.Y, s))) return st;
+        a.X = b.Y;
+      } else {
+        if ((st = xstage_generic(L, b, *ssb, ny, nx, k0, k1, s))) return st;
+        if ((st = colfft_generic(L, ny, k0, k1, b.X, b.X, s))) return st;
+      }
+      a.xk0 = k0;
+      a.k0 = k0;
+      a.k1 = k1;
+      a.accumulate = ch > 0;
+      if ((st = launch_psum(ny, a, o, chi0, true, L.store, s))) return st;
+    }
+    return run_phase(L, b, *scan, L.pgroups, L.nwp, L.nchunks, ssb->normalize ? b.npq : nullptr, d_phase, d_T, s);
   } else if (L.store) {
     if ((st = run_prune_offsets(L, b, nx, d_status, s))) return st;
     if ((st = launch_yreduce(ssb->precision, ny, a, o, chi0, 1, s))) return st;
@@ -712,7 +779,8 @@ static int reconstruct(const int32_t* d_idx, const int64_t* d_off, int64_t frame
       if ((st = launch_yreduce(ssb->precision, ny, a, o, chi0, 0, s))) return st;
     }
   }
-  return run_phase(L, b, *scan, L.groups, L.nwy, ssb->normalize ? b.npq : nullptr, d_phase, d_T, s);
+  return run_phase(L, b, *scan, L.groups, L.nwy, L.store ? 1 : L.nchunks, ssb->normalize ? b.npq : nullptr, d_phase,
+                   d_T, s);
 }
 
 extern "C" int ssb_reconstruct(const int32_t* d_idx, const int64_t* d_off, int64_t frame0, int64_t n_frames,
@@ -792,7 +860,7 @@ __global__ void __launch_bounds__(64) k_g_panel(const float2* __restrict__ X, co
 // From the binned cube (STEM_G_RECOMPUTE keeps no row-transformed cube): one workgroup per bin, the
 // 2D DFT over (ry, rx) at every Q_j, FP64 accumulation; twiddles W_N^t for exact integer t (FP64
 // sincospi rounded to FP32) in LDS.
-constexpr int kPanelTw = 1024;
+constexpr int kPanelTw = kGenMax;
 
 template <typename DT>
 __global__ void __launch_bounds__(256) k_g_panel_d(const DT* __restrict__ D, const RowRun* __restrict__ rows,
@@ -933,7 +1001,22 @@ extern "C" int ssb_backward(const float* d_dLdphi, const stem_det* det, const st
   int64_t npdc = L.nwy, npdth = L.ncs;
   if (L.store) {
     y.ngroups = L.pgroups;
-    if ((st = launch_padj(ny, y, o, s))) return st;
+    if ((st = launch_padj(ny, y, o, false, s))) return st;
+    npdc = L.nwa;
+    npdth = nx;
+  } else if (!L.fast) {
+    y.ngroups = L.pgroups;
+    for (int ch = 0; ch < L.nchunks; ++ch) {
+      int k0, k1;
+      chunk_range(L, ch, k0, k1);
+      if ((st = xstage_generic(L, b, *ssb, ny, nx, k0, k1, s))) return st;
+      if ((st = colfft_generic(L, ny, k0, k1, b.X, b.X, s))) return st;
+      y.xk0 = k0;
+      y.k0 = k0;
+      y.k1 = k1;
+      y.accumulate = ch > 0;
+      if ((st = launch_padj(ny, y, o, true, s))) return st;
+    }
     npdc = L.nwa;
     npdth = nx;
   } else {

@@ -10,6 +10,12 @@
 // into the column's T kept in LDS (one slot per row frequency my: the entries of a run have
 // distinct my, so no two lanes touch one slot).  The partial T of the group goes to part[g]
 // (column-major [mx][my], summed by the phase pass like the fused sum's).
+//
+// FULLG: the runs are read from a block of full half-spectrum columns of G instead (pixel kd's
+// column c at X + ((kd - xk0) (Nx/2+1) + c) Ny; a column mx > Nx/2 is the conjugate of column
+// Nx - mx at -my): the sums of the scan lengths the fused kernels do not take, whose G comes from
+// separate row and column transforms.  With PWRITE the values read are also stored as the pruned
+// array.
 #pragma once
 
 #include "ssb_fused.h"
@@ -31,25 +37,31 @@ __host__ __device__ inline size_t pruned_wave_lds(int ny, bool adjoint) {
   return (size_t)ny * sizeof(float2) + 64 * sizeof(RunDesc) + (adjoint ? 64 * sizeof(float) : 0);
 }
 
-// descriptors of pixels [kb, kb + 64) for column mx (lane j takes pixel kb + j)
+// descriptors of pixels [kb, kb + 64) for column mx (lane j takes pixel kb + j); fullg: run lengths
+// from the sets (e0 = the pruned array's offset when it exists)
 __device__ __forceinline__ void gather_runs(const YArgs& a, const Optics& o, int kb, int kd_b, int mx, int lane,
-                                            bool general, RunDesc* rd) {
+                                            bool general, bool fullg, RunDesc* rd) {
   const int nx = a.nx, nc = nx / 2 + 1;
   const bool mir = 2 * mx > nx;
   const int c = mir ? nx - mx : mx;
   const int kd = kb + lane;
   RunDesc d{0, 0, 0, 0, 0, 0.0, 0.0, 0.0};
   if (kd < kd_b) {
-    const int64_t e0 = a.poff[(int64_t)kd * nx + mx], e1 = a.poff[(int64_t)kd * nx + mx + 1];
     ColSet sd, sm;
     load_colsets(a.cst, (int64_t)kd * nc + c, sd, sm);
     const ColSet s = mir ? sm : sd;
     const int h0 = max(s.a0, s.b0), h1 = min(s.a1, s.b1);
-    // entries are read only inside the array (a state whose FINALIZE never ran reads nothing
-    // out of bounds)
-    const bool ok = e0 >= 0 && e1 >= e0 && e1 <= a.pcap;
-    d.e0 = ok ? e0 : 0;
-    d.len = ok ? (int)(e1 - e0) : 0;
+    if (fullg) {
+      d.e0 = a.poff ? a.poff[(int64_t)kd * nx + mx] : 0;
+      d.len = set_size(s);
+    } else {
+      const int64_t e0 = a.poff[(int64_t)kd * nx + mx], e1 = a.poff[(int64_t)kd * nx + mx + 1];
+      // entries are read only inside the array (a state whose FINALIZE never ran reads nothing
+      // out of bounds)
+      const bool ok = e0 >= 0 && e1 >= e0 && e1 <= a.pcap;
+      d.e0 = ok ? e0 : 0;
+      d.len = ok ? (int)(e1 - e0) : 0;
+    }
     d.a0 = s.a0;
     d.hl = h0 <= h1 ? h1 - h0 + 1 : 0;
     d.split = h0 - s.a0;
@@ -64,13 +76,32 @@ __device__ __forceinline__ void gather_runs(const YArgs& a, const Optics& o, int
   (void)o;
 }
 
-// One round of a run: entries u0 + lane + 64 q (q < 4) of run r (0 past its end).
-__device__ __forceinline__ void load_round(const float2* __restrict__ pg, const RunDesc& r, int u0, int lane,
+// Signed row frequency of entry u of run r.
+__device__ __forceinline__ int run_iy(const RunDesc& r, int u) { return r.a0 + u + ((r.hl && u >= r.split) ? r.hl : 0); }
+
+// One round of a run: entries u0 + lane + 64 q (q < 4) of run r of pixel kd, column mx (0 past its
+// end), from the pruned array or (FULLG) from the full columns of G.
+template <bool FULLG>
+__device__ __forceinline__ void load_round(const YArgs& a, const RunDesc& r, int kd, int mx, int ny, int u0, int lane,
                                            float2* gv) {
+  const int nx = a.nx, nh = nx / 2 + 1;
+  const bool mir = 2 * mx > nx;
+  const float2* col =
+      FULLG ? a.X + ((int64_t)(kd - a.xk0) * nh + (mir ? nx - mx : mx)) * ny : nullptr;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int u = u0 + lane + 64 * q;
-    gv[q] = u < r.len ? pg[r.e0 + u] : make_float2(0.f, 0.f);
+    float2 x = make_float2(0.f, 0.f);
+    if (u < r.len) {
+      if constexpr (FULLG) {
+        const int iy = run_iy(r, u);
+        const int my = iy < 0 ? iy + ny : iy;
+        x = mir ? cconj(col[(ny - my) % ny]) : col[my];
+      } else {
+        x = a.pg[r.e0 + u];
+      }
+    }
+    gv[q] = x;
   }
 }
 
@@ -83,7 +114,7 @@ __device__ __forceinline__ int next_run(const RunDesc* rd, int j, int nb) {
 
 // T of column mx over the pixels [kd_a, kd_b) of group g from the stored values.  CHI0: every phase
 // factor is exactly 1.  The first rounds of the next two runs are loaded while a run is summed.
-template <bool CHI0>
+template <bool CHI0, bool FULLG, bool PWRITE>
 __global__ void __launch_bounds__(256) k_psum(YArgs a, Optics o, int ny) {
   extern __shared__ __align__(16) unsigned char s_dyn[];
   const int W = blockDim.x >> 6;
@@ -105,19 +136,19 @@ __global__ void __launch_bounds__(256) k_psum(YArgs a, Optics o, int ny) {
   const int kd_b = a.k0 + (int)((int64_t)(a.k1 - a.k0) * (g + 1) / a.ngroups);
   unsigned long long cnt = 0;
   for (int kb = kd_a; kb < kd_b; kb += 64) {
-    gather_runs(a, o, kb, kd_b, mx, lane, !CHI0, rd);
+    gather_runs(a, o, kb, kd_b, mx, lane, !CHI0, FULLG, rd);
     wave_lds_sync();
     const int nb = min(64, kd_b - kb);
     int j = next_run(rd, -1, nb);
     int j1 = j < nb ? next_run(rd, j, nb) : nb;
     float2 g0[4], g1[4];
-    if (j < nb) load_round(a.pg, rd[j], 0, lane, g0);
-    if (j1 < nb) load_round(a.pg, rd[j1], 0, lane, g1);
+    if (j < nb) load_round<FULLG>(a, rd[j], kb + j, mx, ny, 0, lane, g0);
+    if (j1 < nb) load_round<FULLG>(a, rd[j1], kb + j1, mx, ny, 0, lane, g1);
     while (j < nb) {
       const RunDesc r = rd[j];
       const int j2 = j1 < nb ? next_run(rd, j1, nb) : nb;
       float2 g2[4];
-      if (j2 < nb) load_round(a.pg, rd[j2], 0, lane, g2);
+      if (j2 < nb) load_round<FULLG>(a, rd[j2], kb + j2, mx, ny, 0, lane, g2);
       cnt += (unsigned long long)r.len;
       ChiCol ch{};
       if constexpr (!CHI0) ch = chi_column(o.lk * (r.kx - qx), o);
@@ -127,15 +158,18 @@ __global__ void __launch_bounds__(256) k_psum(YArgs a, Optics o, int ny) {
 #pragma unroll
           for (int q = 0; q < 4; ++q) gv[q] = g0[q];
         } else {
-          load_round(a.pg, r, u0, lane, gv);
+          load_round<FULLG>(a, r, kb + j, mx, ny, u0, lane, gv);
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int u = u0 + lane + 64 * q;
           if (u >= r.len) continue;
-          const int iy = r.a0 + u + ((r.hl && u >= r.split) ? r.hl : 0);
+          const int iy = run_iy(r, u);
           const int my = iy < 0 ? iy + ny : iy;
           float2 val = gv[q];
+          if constexpr (PWRITE) {
+            if (r.e0 + u < a.pcap) a.pgw[r.e0 + u] = val;
+          }
           if constexpr (!CHI0) {
             const double wy = o.lk * (r.ky - (double)iy * o.sy);
             const float2 e = expi_reduced(chi_eval(ch, wy) - r.kch);
@@ -170,6 +204,7 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
 // per (pixel, column) run the moments M_n = sum w wy^n (n = 0..4) give the eight dL/dc terms (the
 // B_j(K - Q) are polynomials in wy along a column, see k_yadjoint); dL/dtheta[kd] = -sum w.
 // Partials: pdc[wave][8] (FP64), pdth[mx][kd] (FP32; one writer per entry).
+template <bool FULLG>
 __global__ void __launch_bounds__(256) k_padj(YArgs a, Optics o, int ny) {
   extern __shared__ __align__(16) unsigned char s_dyn[];
   const int W = blockDim.x >> 6;
@@ -196,20 +231,20 @@ __global__ void __launch_bounds__(256) k_padj(YArgs a, Optics o, int ny) {
   for (int j = 0; j < 8; ++j) dc[j] = 0.0;
   float* pth = a.pdth + (int64_t)mx * a.n_k;
   for (int kb = kd_a; kb < kd_b; kb += 64) {
-    gather_runs(a, o, kb, kd_b, mx, lane, true, rd);
+    gather_runs(a, o, kb, kd_b, mx, lane, true, FULLG, rd);
     wave_lds_sync();
     const int nb = min(64, kd_b - kb);
     if (lane < nb) wth[lane] = 0.f;  // pixels without pairs in this column
     int j = next_run(rd, -1, nb);
     int j1 = j < nb ? next_run(rd, j, nb) : nb;
     float2 g0[4], g1[4];
-    if (j < nb) load_round(a.pg, rd[j], 0, lane, g0);
-    if (j1 < nb) load_round(a.pg, rd[j1], 0, lane, g1);
+    if (j < nb) load_round<FULLG>(a, rd[j], kb + j, mx, ny, 0, lane, g0);
+    if (j1 < nb) load_round<FULLG>(a, rd[j1], kb + j1, mx, ny, 0, lane, g1);
     while (j < nb) {
       const RunDesc r = rd[j];
       const int j2 = j1 < nb ? next_run(rd, j1, nb) : nb;
       float2 g2[4];
-      if (j2 < nb) load_round(a.pg, rd[j2], 0, lane, g2);
+      if (j2 < nb) load_round<FULLG>(a, rd[j2], kb + j2, mx, ny, 0, lane, g2);
       const double wx = o.lk * (r.kx - qx);
       const ChiCol ch = chi_column(wx, o);
       double M0 = 0.0, M1 = 0.0, M2 = 0.0, M3 = 0.0, M4 = 0.0;
@@ -219,13 +254,13 @@ __global__ void __launch_bounds__(256) k_padj(YArgs a, Optics o, int ny) {
 #pragma unroll
           for (int q = 0; q < 4; ++q) gv[q] = g0[q];
         } else {
-          load_round(a.pg, r, u0, lane, gv);
+          load_round<FULLG>(a, r, kb + j, mx, ny, u0, lane, gv);
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int u = u0 + lane + 64 * q;
           if (u >= r.len) continue;
-          const int iy = r.a0 + u + ((r.hl && u >= r.split) ? r.hl : 0);
+          const int iy = run_iy(r, u);
           const int my = iy < 0 ? iy + ny : iy;
           const double wy = o.lk * (r.ky - (double)iy * o.sy);
           const float2 e = expi_reduced(chi_eval(ch, wy) - r.kch);
@@ -296,23 +331,39 @@ inline int64_t pruned_launch_waves(int ny, int nx, int ngroups, bool adjoint) {
   return (int64_t)((nx + w - 1) / w) * ngroups * w;
 }
 
-inline int launch_psum(int ny, const YArgs& a, const Optics& o, int chi0, hipStream_t s) {
+// fullg: the runs from full columns of G at a.X (pixels from a.xk0); pwrite: also store the values
+// as the pruned array
+inline int launch_psum(int ny, const YArgs& a, const Optics& o, int chi0, bool fullg, bool pwrite, hipStream_t s) {
   const int w = pruned_waves(ny, false);
   const size_t lds = (size_t)w * pruned_wave_lds(ny, false);
-  STEM_TRACE("ssb_reduce", s);
-  if (chi0)
-    hipLaunchKernelGGL(k_psum<true>, pruned_grid(a.nx, a.ngroups, w), dim3(64 * w), lds, s, a, o, ny);
-  else
-    hipLaunchKernelGGL(k_psum<false>, pruned_grid(a.nx, a.ngroups, w), dim3(64 * w), lds, s, a, o, ny);
+  const dim3 grid = pruned_grid(a.nx, a.ngroups, w), blk(64 * w);
+  STEM_TRACE(fullg ? "ssb_gsum" : "ssb_reduce", s);
+  auto go = [&](auto c0, auto fg, auto pw) {
+    hipLaunchKernelGGL((k_psum<decltype(c0)::value, decltype(fg)::value, decltype(pw)::value>), grid, blk, lds, s, a,
+                       o, ny);
+  };
+  using T_ = std::true_type;
+  using F_ = std::false_type;
+  if (!fullg) {
+    chi0 ? go(T_{}, F_{}, F_{}) : go(F_{}, F_{}, F_{});
+  } else if (pwrite) {
+    chi0 ? go(T_{}, T_{}, T_{}) : go(F_{}, T_{}, T_{});
+  } else {
+    chi0 ? go(T_{}, T_{}, F_{}) : go(F_{}, T_{}, F_{});
+  }
   STEM_LAUNCH_CHECK();
   return STEM_OK;
 }
 
-inline int launch_padj(int ny, const YArgs& a, const Optics& o, hipStream_t s) {
+inline int launch_padj(int ny, const YArgs& a, const Optics& o, bool fullg, hipStream_t s) {
   const int w = pruned_waves(ny, true);
   const size_t lds = (size_t)w * pruned_wave_lds(ny, true);
-  STEM_TRACE("ssb_adjoint_pruned", s);
-  hipLaunchKernelGGL(k_padj, pruned_grid(a.nx, a.ngroups, w), dim3(64 * w), lds, s, a, o, ny);
+  const dim3 grid = pruned_grid(a.nx, a.ngroups, w), blk(64 * w);
+  STEM_TRACE(fullg ? "ssb_gadjoint" : "ssb_adjoint_pruned", s);
+  if (fullg)
+    hipLaunchKernelGGL(k_padj<true>, grid, blk, lds, s, a, o, ny);
+  else
+    hipLaunchKernelGGL(k_padj<false>, grid, blk, lds, s, a, o, ny);
   STEM_LAUNCH_CHECK();
   return STEM_OK;
 }

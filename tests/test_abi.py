@@ -132,11 +132,21 @@ def test_host_argument_errors_return_einval_without_device_work():
     det, scan, optics = _geom(wl)
     L = stem.lib()
     ssb = stem.Ssb(stem.STEM_FFT_FP32, 0, stem.STEM_G_STORE, 8)
-    # bad binning, non power-of-two scan, bad optics, bad d_bits
+    # bad binning, scan lengths the transforms do not take, bad optics, bad d_bits
     bad_det = stem.Det(64, 64, 32, 32, 3)
     assert L.ssb_state_bytes(ctypes.byref(bad_det), ctypes.byref(scan), ctypes.byref(optics), ctypes.byref(ssb)) == 0
-    bad_scan = stem.Scan(48, 32, 0.2)
-    assert L.ssb_state_bytes(ctypes.byref(det), ctypes.byref(bad_scan), ctypes.byref(optics), ctypes.byref(ssb)) == 0
+    for ny, nx in [(49, 32), (56, 32), (32, 45), (8, 32), (32, 4608), (6, 32)]:
+        bad_scan = stem.Scan(ny, nx, 0.2)
+        assert L.ssb_state_bytes(ctypes.byref(det), ctypes.byref(bad_scan), ctypes.byref(optics),
+                                 ctypes.byref(ssb)) == 0, (ny, nx)
+    # the mixed-radix lengths are taken in FP32, the split precisions only at the fused lengths
+    for ny, nx in [(48, 32), (96, 160), (1000, 1000), (2048, 2048), (16, 4096)]:
+        ok_scan = stem.Scan(ny, nx, 0.2)
+        assert L.ssb_state_bytes(ctypes.byref(det), ctypes.byref(ok_scan), ctypes.byref(optics),
+                                 ctypes.byref(ssb)) > 0, (ny, nx)
+        split = stem.Ssb(stem.STEM_DFT_BF16_SPLIT, 0, stem.STEM_G_STORE, 8)
+        assert L.ssb_state_bytes(ctypes.byref(det), ctypes.byref(ok_scan), ctypes.byref(optics),
+                                 ctypes.byref(split)) == 0, (ny, nx)
     bad_optics = stem.Optics.from_values(wl.lam, -1.0, wl.dk)
     assert L.ssb_num_pixels(ctypes.byref(det), ctypes.byref(bad_optics)) < 0
     nan_optics = stem.Optics.from_values(wl.lam, wl.r_bf, wl.dk, [float("nan")] + [0.0] * 7)

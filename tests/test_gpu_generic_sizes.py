@@ -1,0 +1,181 @@
+"""GPU parity at scan lengths other than the fused kernels' powers of two in [32, 1024].
+
+Lengths 2^a 3^b 5^c (even, 16 to 4096) run the mixed-radix LDS FFT for the row, column and phase
+transforms and the DPC integration, and Eq. 3 per (pixel, column) run over full columns of G:
+
+g96x160    96 x 160 scan (radices 4.4.2.3 and 4.4.2.5), 64x64 detector unbinned (793 pixels)
+g48x80ab   48 x 80, aberrated, per-pixel probe phase: adjoint in both G modes
+g16x4096   16 x 4096 and 4096 x 16: the shortest and the longest transform
+g1000      1000 x 1000 (4.2.5.5.5), 64x64 detector binned 4x (52 pixels)
+g2048      2048 x 2048, binned 8x (12 pixels): lengths beyond the single-wave FFT
+
+Every output is compared element by element with the FP64 oracle: counts and the binned cube bit
+for bit, the row transform, pruned G, T, phi and the DPC phase by relative L2 (1e-5), the
+per-Q pair counts exactly, the adjoint against the oracle gradient.
+"""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2104_06336_amd as stem
+from gen import C4_TRUE_ABERRATIONS, WORKLOADS, simulate
+from oracle import eer as oeer
+from oracle import ssb as ossb
+
+from helpers import (gpu_com, gpu_ssb, oracle_dpc, oracle_pruned, oracle_row_dft, oracle_ssb, per_q_error,
+                     q_error_scale, rel_l2, state_D, state_npair, state_pruned, state_X, structs)
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+SMALL = WORKLOADS["small"]
+CASES = {
+    "g96x160": SMALL.replace(name="scan 96x160, detector 64x64 unbinned", scan=(96, 160)),
+    "g48x80ab": SMALL.replace(name="scan 48x80 aberrated", scan=(48, 80), aberr=C4_TRUE_ABERRATIONS),
+    "g16x4096": SMALL.replace(name="scan 16x4096, binned 4x", scan=(16, 4096), bin=4, mean_e=10.0),
+    "g4096x16": SMALL.replace(name="scan 4096x16, binned 4x", scan=(4096, 16), bin=4, mean_e=10.0),
+    "g1000": SMALL.replace(name="scan 1000x1000, binned 4x", scan=(1000, 1000), bin=4, mean_e=10.0),
+    "g2048": SMALL.replace(name="scan 2048x2048, binned 8x", scan=(2048, 2048), bin=8, mean_e=5.0),
+}
+_DATA = {}
+
+
+def log(msg):
+    print(f"[generic] {msg}", flush=True)
+
+
+def data(name):
+    """(wl, device CSR, host CSR, oracle cache) of one case, generated once per session."""
+    if name not in _DATA:
+        wl = CASES[name]
+        t0 = time.time()
+        d = simulate(wl, device="cuda")
+        torch.cuda.synchronize()
+        d_idx, d_off = d.idx.contiguous(), d.off.contiguous()
+        idx, off = d_idx.cpu().numpy(), d_off.cpu().numpy()
+        log(f"{name}: {wl.n_frames} frames, {len(idx)} events in {time.time() - t0:.1f} s")
+        _DATA[name] = (wl, d_idx, d_off, idx, off, {})
+    return _DATA[name]
+
+
+def oracle(name, c=None, theta=None, normalize=False):
+    wl, _, _, idx, off, cache = data(name)
+    c = wl.aberr if c is None else tuple(c)
+    key = (c, None if theta is None else theta.tobytes(), normalize)
+    if key not in cache:
+        t0 = time.time()
+        cache[key] = oracle_ssb(idx, off, wl, c=c, theta=theta, normalize=normalize)
+        log(f"{name}: oracle in {time.time() - t0:.1f} s")
+    return cache[key]
+
+
+def npair_ref(name):
+    """The oracle's per-Q pair counts [my][mx]."""
+    wl, _, _, _, _, cache = data(name)
+    if "npair" not in cache:
+        kc = oracle(name)["kc"]
+        cache["npair"] = ossb.ssb_sum(np.zeros((len(kc),) + wl.scan), kc, wl.step, wl.dk, wl.lam, wl.r_bf)[1]
+    return cache["npair"]
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    print(f"\n[gpu] {request.node.name}", flush=True)
+
+
+@pytest.mark.parametrize("name", ["g96x160", "g16x4096", "g4096x16", "g1000", "g2048"])
+def test_com_and_dpc_phase(gpu, name):
+    wl, d_idx, d_off, idx, off, _ = data(name)
+    for lam1, lam2, L in [(0.0, 0.0, 10), (1.0, 0.05, 25)]:
+        g = gpu_com(d_idx, d_off, wl, phase=True, dpc_params=stem.Dpc(0.5, lam1, lam2, L))
+        assert g["status"] == 0
+        if L == 10:
+            H, W = wl.det
+            cx, cy, _, _, n = oeer.com(idx, off, W, H)
+            assert np.array_equal(g["counts"], n)
+            assert np.array_equal(g["com64"][0], cx) and np.array_equal(g["com64"][1], cy)
+        ref = oracle_dpc(idx, off, wl, lam1=lam1, lam2=lam2, n_iter=L)
+        assert rel_l2(g["phase"], ref) <= TOL, (lam1, lam2, L)
+
+
+@pytest.mark.parametrize("name", ["g96x160", "g16x4096", "g4096x16", "g1000", "g2048"])
+def test_binning_transform_and_pruned_values(gpu, name):
+    wl, d_idx, d_off, idx, off, _ = data(name)
+    st, out = gpu_ssb(d_idx, d_off, wl, c=wl.aberr)
+    ref = oracle(name)
+    assert out["status"] == 0
+    assert np.array_equal(state_D(st, wl), ref["D"])
+    X = state_X(st, wl)
+    assert rel_l2(X, oracle_row_dft(ref["D"], wl)) <= TOL
+    rows = ossb.cube(ref["D"], *wl.scan).sum(axis=2)
+    assert np.array_equal(X[:, :, 0].real.astype(np.float64), rows.astype(np.float64))
+    assert np.all(X[:, :, 0].imag == 0)
+    pg, poff = state_pruned(st)
+    pg_ref, poff_ref = oracle_pruned(ref["G"], ref["kc"], wl)
+    assert np.array_equal(poff, poff_ref)
+    assert rel_l2(pg, pg_ref) <= TOL
+
+
+@pytest.mark.parametrize("g_mode", [stem.STEM_G_STORE, stem.STEM_G_RECOMPUTE], ids=["store", "recompute"])
+@pytest.mark.parametrize("name", ["g96x160", "g16x4096", "g4096x16", "g1000", "g2048"])
+def test_ssb_phase(gpu, name, g_mode):
+    wl, d_idx, d_off, idx, off, _ = data(name)
+    st, out = gpu_ssb(d_idx, d_off, wl, c=wl.aberr, g_mode=g_mode)
+    ref = oracle(name)
+    assert out["status"] == 0
+    assert rel_l2(out["T"], ref["T"]) <= TOL
+    assert rel_l2(out["phi"], ref["phi"]) <= TOL
+    assert out["T"][0, 0] == 0
+    assert per_q_error(out["T"], ref["T"], q_error_scale(ref["G"], ref["kc"], wl)) <= 1e-4
+    assert st.stats()[0] == int(npair_ref(name).sum())
+
+
+@pytest.mark.parametrize("g_mode", [stem.STEM_G_STORE, stem.STEM_G_RECOMPUTE], ids=["store", "recompute"])
+def test_chunks_normalise_and_refocus(gpu, g_mode):
+    """96 x 160 with a 1 MiB scratch (16 pixels per chunk, 51 chunks): chunked binning equals one
+    call, the normalised sum divides by the oracle's per-Q pair counts, and a refocus with other
+    coefficients equals a fresh reconstruction."""
+    name = "g96x160"
+    wl, d_idx, d_off, idx, off, _ = data(name)
+    st, out = gpu_ssb(d_idx, d_off, wl, normalize=1, g_mode=g_mode, scratch_mib=1, chunk_rows=7)
+    ref = oracle(name, normalize=True)
+    assert out["status"] == 0
+    assert st.stats()[3] > 1
+    assert rel_l2(out["T"], ref["T"]) <= TOL
+    assert rel_l2(out["phi"], ref["phi"]) <= TOL
+    assert np.max(np.abs(out["T"] - ref["T"])) <= 1e-5 * np.max(np.abs(ref["T"]))
+    assert np.array_equal(state_npair(st, wl), npair_ref(name))
+    # refocus: the sum again with aberrations, from the stored values or recomputed
+    F = wl.n_frames
+    phase = torch.zeros(F, dtype=torch.float32, device="cuda")
+    T = torch.zeros(F, dtype=torch.complex64, device="cuda")
+    st.refocus(c=C4_TRUE_ABERRATIONS, phase=phase, T=T)
+    ref2 = oracle(name, c=C4_TRUE_ABERRATIONS, normalize=True)
+    assert rel_l2(T.cpu().numpy().reshape(wl.scan), ref2["T"]) <= TOL
+    assert rel_l2(phase.cpu().numpy().reshape(wl.scan), ref2["phi"]) <= TOL
+
+
+@pytest.mark.parametrize("scratch_mib", [0, 1])
+@pytest.mark.parametrize("g_mode", [stem.STEM_G_STORE, stem.STEM_G_RECOMPUTE], ids=["store", "recompute"])
+def test_adjoint_matches_oracle_gradient(gpu, g_mode, scratch_mib):
+    name = "g48x80ab"
+    wl, d_idx, d_off, idx, off, _ = data(name)
+    det, _, optics = structs(wl)
+    theta = np.random.default_rng(3).uniform(-0.3, 0.3, size=stem.ssb_num_pixels(det, optics)).astype(np.float32)
+    rng = np.random.default_rng(7)
+    c = tuple(np.array(C4_TRUE_ABERRATIONS) * (1 + rng.uniform(-0.5, 0.5, size=8)))
+    st, out = gpu_ssb(d_idx, d_off, wl, c=c, theta=theta, g_mode=g_mode, scratch_mib=scratch_mib)
+    ref = oracle(name, c=c, theta=theta)
+    assert out["status"] == 0
+    assert rel_l2(out["phi"], ref["phi"]) <= TOL
+    phi = torch.from_numpy(out["phi"]).cuda()
+    gbar = (-(2.0 / phi.numel()) * (phi - phi.mean())).contiguous().view(-1)
+    dc, dth = st.backward(gbar, c=c, theta=torch.from_numpy(theta).cuda())
+    dco, dtho = ossb.ssb_adjoint(ref["G"], ref["kc"], ossb.neg_var_grad(ref["phi"]), wl.step, wl.dk, wl.lam,
+                                 wl.r_bf, c, theta)
+    dc = dc.cpu().numpy()
+    assert np.all(np.abs(dc - dco) <= 1e-4 * np.abs(dco) + 1e-6 * np.max(np.abs(dco)))
+    assert rel_l2(dth.cpu().numpy(), dtho) <= 1e-4
