@@ -191,28 +191,37 @@ __device__ __forceinline__ double chi_eval(const ChiCol& c, double wy) {
   return c.h0 + wy * (c.h1 + wy * (c.h2 + wy * (c.h3 + wy * c.h4)));
 }
 
-// exp(i psi): psi is reduced in double to r in [-pi/4, pi/4] plus a quadrant (r = psi - q pi/2,
-// q an integer), then sin r and cos r are the Taylor polynomials to degree 9 and 10 evaluated in
-// float (truncation below 2e-9 on that interval, under float rounding), and the quadrant
-// rotates the pair.
+// chi(K - Q) - chi(Kc) - theta along one column as a polynomial in the signed row index iy:
+// with wy = A + B iy (A = lam dk Ky, B = -lam dk sy), the quartic of chi_column expanded in powers
+// of iy, the constant term less kch.  psi = p0 + iy (p1 + iy (p2 + iy (p3 + iy p4))).
+struct ChiRow {
+  double p0, p1, p2, p3, p4;
+};
+
+__device__ __forceinline__ ChiRow chi_row(const ChiCol& c, double A, double B, double kch) {
+  const double A2 = A * A, A3 = A2 * A, A4 = A2 * A2;
+  const double B2 = B * B, B3 = B2 * B, B4 = B2 * B2;
+  ChiRow r;
+  r.p0 = (c.h0 + A * c.h1 + A2 * c.h2 + A3 * c.h3 + A4 * c.h4) - kch;
+  r.p1 = B * (c.h1 + 2.0 * A * c.h2 + 3.0 * A2 * c.h3 + 4.0 * A3 * c.h4);
+  r.p2 = B2 * (c.h2 + 3.0 * A * c.h3 + 6.0 * A2 * c.h4);
+  r.p3 = B3 * (c.h3 + 4.0 * A * c.h4);
+  r.p4 = B4 * c.h4;
+  return r;
+}
+
+__device__ __forceinline__ double chi_row_eval(const ChiRow& r, double t) {
+  return r.p0 + t * (r.p1 + t * (r.p2 + t * (r.p3 + t * r.p4)));
+}
+
+// exp(i psi): psi in revolutions, r = psi / (2 pi), is reduced in FP64 to f = r - rint(r) in
+// [-1/2, 1/2] (error below |r| ulp(1/(2 pi)) + ulp(r)), rounded to float; the hardware sine and
+// cosine of 2 pi f (v_sin_f32 / v_cos_f32, whose argument is in revolutions) give the pair.
 __device__ __forceinline__ float2 expi_reduced(double psi) {
-  const double two_pi = 6.283185307179586476925286766559;
   const double inv_two_pi = 0.15915494309189533576888376337251;
-  const double half_pi = 1.5707963267948966192313216916398;
-  const double two_over_pi = 0.63661977236758134307553505349006;
-  const double red = psi - two_pi * rint(psi * inv_two_pi);  // [-pi, pi]
-  const double qd = rint(red * two_over_pi);                  // -2 .. 2
-  const float x = (float)(red - qd * half_pi);
-  const float x2 = x * x;
-  const float sn = x * (1.f + x2 * (-1.f / 6.f + x2 * (1.f / 120.f + x2 * (-1.f / 5040.f + x2 * (1.f / 362880.f)))));
-  const float cs = 1.f + x2 * (-0.5f + x2 * (1.f / 24.f + x2 * (-1.f / 720.f + x2 * (1.f / 40320.f +
-                                                                               x2 * (-1.f / 3628800.f)))));
-  switch ((int)qd & 3) {
-    case 0: return make_float2(cs, sn);
-    case 1: return make_float2(-sn, cs);
-    case 2: return make_float2(-cs, -sn);
-    default: return make_float2(sn, -cs);
-  }
+  const double r = psi * inv_two_pi;
+  const float f = (float)(r - rint(r));
+  return make_float2(__builtin_amdgcn_cosf(f), __builtin_amdgcn_sinf(f));
 }
 
 // Double-overlap sets of pixel K along column ix: iy in [a0, a1] but not in [b0, b1].

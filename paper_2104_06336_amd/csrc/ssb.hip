@@ -26,6 +26,10 @@ namespace stem {
 
 constexpr int kMaxPixels = 4096;
 constexpr int kDefaultScratchMib = 64;  // row-transformed columns held at once in STEM_G_RECOMPUTE
+#ifndef STEM_PRUNED_BLOCKS
+#define STEM_PRUNED_BLOCKS 3072
+#endif
+constexpr int kPrunedBlocks = STEM_PRUNED_BLOCKS;  // (column, pixel group) items without a schedule
 
 struct SsbLayout {
   int n_k, nby, nh;
@@ -145,16 +149,17 @@ static size_t make_layout(const stem_det& det, const stem_scan& scan, const stem
   if (g > smallest) g = smallest;
   L->groups = g < 1 ? 1 : g;
   L->nwy = (int64_t)((L->ncs + 3) / 4) * 4 * L->groups;
-  // the kernels over the stored values: one wave per column of the whole plane and pixel group,
-  // about 3072 waves, at most the fused kernels' partial sums
+  // the kernels over the stored values: a wave (refocus) or workgroup (adjoint) per column of the
+  // whole plane and pixel group, about kPrunedBlocks of them, at most the fused kernels' partial
+  // sums
   {
-    int pg = (3072 + scan.nx - 1) / scan.nx;
+    int pg = (kPrunedBlocks + scan.nx - 1) / scan.nx;
     const int gmax = yreduce_groups(scan.ny, scan.nx, n_k);
     pg = pg > n_k ? n_k : pg;
     pg = pg > gmax ? gmax : pg;
     L->pgroups = pg < 1 ? 1 : pg;
-    L->nwp = pruned_launch_waves(scan.ny, scan.nx, L->pgroups, false);
-    L->nwa = pruned_launch_waves(scan.ny, scan.nx, L->pgroups, true);
+    L->nwp = psum_launch_waves(scan.ny, scan.nx, L->pgroups);
+    L->nwa = padj_launch_waves(scan.nx, L->pgroups);
   }
   int64_t nw = L->nwy > L->nwp ? L->nwy : L->nwp;
   nw = nw > L->nwa ? nw : L->nwa;
