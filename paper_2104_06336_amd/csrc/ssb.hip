@@ -397,39 +397,49 @@ __global__ void k_transpose_T(const float2* __restrict__ Tt, int ny, int nx, flo
 }
 
 // ---------------------------------------------------------------------------------------------
-// sums the adjoint partials in a fixed order: dL/dc over waves (workgroup 0), dL/dtheta over
-// column sets (one thread per pixel, eight independent loads in flight)
+// sums the adjoint partials in a fixed order: dL/dc component j over the waves' partials
+// (workgroup j < 8: a strided share per thread with four accumulators, then a tree over the
+// workgroup), dL/dtheta over the npdth rows of partials (one wave per pixel: lane l takes rows
+// l, l + 64, ..., then a fixed tree over the lanes)
+constexpr int kFinalDcBlocks = 8;
 
 __global__ void __launch_bounds__(256) k_adjoint_final(const double* __restrict__ pdc, int64_t npdc,
                                                        const float* __restrict__ pdth, int64_t npdth, int n_k,
                                                        double* __restrict__ dLdc, float* __restrict__ dLdth) {
-  if (blockIdx.x == 0) {
-    __shared__ double s[256][8];
-    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int64_t b = threadIdx.x; b < npdc; b += blockDim.x)
-#pragma unroll
-      for (int j = 0; j < 8; ++j) acc[j] += pdc[b * 8 + j];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) s[threadIdx.x][j] = acc[j];
+  if (blockIdx.x < kFinalDcBlocks) {
+    __shared__ double s[256];
+    const int j = blockIdx.x;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int64_t b = threadIdx.x;
+    for (; b + 768 < npdc; b += 1024) {
+      a0 += pdc[b * 8 + j];
+      a1 += pdc[(b + 256) * 8 + j];
+      a2 += pdc[(b + 512) * 8 + j];
+      a3 += pdc[(b + 768) * 8 + j];
+    }
+    for (; b < npdc; b += 256) a0 += pdc[b * 8 + j];
+    s[threadIdx.x] = (a0 + a1) + (a2 + a3);
     __syncthreads();
     for (int h = 128; h > 0; h >>= 1) {
-      if (threadIdx.x < h)
-#pragma unroll
-        for (int j = 0; j < 8; ++j) s[threadIdx.x][j] += s[threadIdx.x + h][j];
+      if (threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
       __syncthreads();
     }
-    if (threadIdx.x < 8) dLdc[threadIdx.x] = s[0][threadIdx.x];
+    if (threadIdx.x == 0) dLdc[j] = s[0];
     return;
   }
-  const int kd = (blockIdx.x - 1) * blockDim.x + threadIdx.x;
-  if (!dLdth || kd >= n_k) return;
-  double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  int64_t b = 0;
-  for (; b + 8 <= npdth; b += 8)
-#pragma unroll
-    for (int u = 0; u < 8; ++u) a[u] += (double)pdth[(b + u) * n_k + kd];
-  for (; b < npdth; ++b) a[0] += (double)pdth[b * n_k + kd];
-  dLdth[kd] = (float)(((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7])));
+  const int lane = threadIdx.x & 63;
+  const int kd = (blockIdx.x - kFinalDcBlocks) * 4 + (threadIdx.x >> 6);
+  if (!dLdth || kd >= n_k) return;  // uniform per wave
+  double a0 = 0.0, a1 = 0.0;
+  int64_t r = lane;
+  for (; r + 64 < npdth; r += 128) {
+    a0 += (double)pdth[r * n_k + kd];
+    a1 += (double)pdth[(r + 64) * n_k + kd];
+  }
+  for (; r < npdth; r += 64) a0 += (double)pdth[r * n_k + kd];
+  double v = a0 + a1;
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  if (lane == 0) dLdth[kd] = (float)v;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -730,10 +740,11 @@ static int reconstruct(const int32_t* d_idx, const int64_t* d_off, int64_t frame
   // The interval table and mask depend only on the geometry: ACCUMULATE's binning built them when
   // it bins through its LDS table; otherwise the first sum builds them (a refocus finds them from
   // the FINALIZE before it).  chi(Kc) + theta comes with them, or from its own small kernel.
+  // A refocus from the stored values evaluates chi(Kc) + theta per pixel as it gathers the runs.
   if (!refocus && !bin_builds_sets(*det, o.r2)) {
     if ((st = launch_colsets(b.kc, n_k, nx, ny, o, b.cst, b.cmask, L.nmw, s, d_theta, chi0 ? nullptr : b.kchi)))
       return st;
-  } else if (!chi0) {
+  } else if (!chi0 && !(refocus && L.store)) {
     if ((st = run_chi_table(b, d_theta, n_k, o, s))) return st;
   }
   if (ssb->normalize && !refocus && (st = run_pair_count(L, b, ny, nx, s))) return st;
@@ -741,6 +752,8 @@ static int reconstruct(const int32_t* d_idx, const int64_t* d_off, int64_t frame
   if (L.store && refocus) {
     // Eq. 3 again from the stored double-overlap values
     a.ngroups = L.pgroups;
+    a.kch_inline = 1;
+    a.theta = d_theta;
     if ((st = launch_psum(ny, a, o, chi0, false, false, s))) return st;
     return run_phase(L, b, *scan, L.pgroups, L.nwp, 1, ssb->normalize ? b.npq : nullptr, d_phase, d_T, s);
   } else if (!L.fast) {
@@ -1000,12 +1013,15 @@ extern "C" int ssb_backward(const float* d_dLdphi, const stem_det* det, const st
   a.osc = make_float2(0.f, (float)(1.0 / (double)L.F));
   a.tag = "adj_fft";
   if ((st = launch_row_fft(ny, false, IN_C64, OUT_ROW_C64, a, s))) return st;
-  // chi(Kc) + theta for these coefficients; the interval table and mask are the last sum's
-  if ((st = run_chi_table(b, d_theta, n_k, o, s))) return st;
+  // chi(Kc) + theta for these coefficients (evaluated per pixel by the adjoint over the stored
+  // values); the interval table and mask are the last sum's
+  if (!L.store && (st = run_chi_table(b, d_theta, n_k, o, s))) return st;
   YArgs y = yargs(L, b, nx);
   int64_t npdc = L.nwy, npdth = L.ncs;
   if (L.store) {
     y.ngroups = L.pgroups;
+    y.kch_inline = 1;
+    y.theta = d_theta;
     if ((st = launch_padj(ny, y, o, false, s))) return st;
     npdc = L.nwa;
     npdth = nx;
@@ -1038,8 +1054,8 @@ extern "C" int ssb_backward(const float* d_dLdphi, const stem_det* det, const st
   }
   {
     STEM_TRACE("ssb_adjoint_final", s);
-    hipLaunchKernelGGL(k_adjoint_final, dim3(1 + (n_k + 255) / 256), dim3(256), 0, s, b.pdc, npdc, b.pdth, npdth,
-                       n_k, d_dLdc, d_dLdtheta);
+    hipLaunchKernelGGL(k_adjoint_final, dim3(kFinalDcBlocks + (n_k + 3) / 4), dim3(256), 0, s, b.pdc, npdc, b.pdth,
+                       npdth, n_k, d_dLdc, d_dLdtheta);
   }
   STEM_LAUNCH_CHECK();
   return STEM_OK;

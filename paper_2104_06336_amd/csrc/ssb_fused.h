@@ -255,6 +255,10 @@ struct YArgs {
   const float2* Tbt;        // adjoint: Tbar column-major [mx][my]
   double* pdc;              // adjoint: dL/dc partials [wave][8]
   float* pdth;              // adjoint: dL/dtheta partials [column set][n_k]
+  // kernels over the stored values: chi(Kc) + theta evaluated per pixel from kc and theta (may be
+  // null) instead of read from kchi
+  int kch_inline;
+  const float* theta;
 };
 
 constexpr int kLoadShift = 40;  // wcnt packs the pair count below bit 40, the 8-byte loads above

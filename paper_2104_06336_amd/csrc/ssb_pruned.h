@@ -56,8 +56,8 @@ __host__ __device__ inline size_t padj_block_lds(int ny) { return (size_t)ny * s
 
 // descriptors of the pixels kd0 + lane * stride (lane < nb) for column mx; fullg: run lengths from
 // the sets (e0 = the pruned array's offset when it exists)
-__device__ __forceinline__ RunDesc gather_run(const YArgs& a, int kd0, int stride, int nb, int mx, int lane,
-                                              bool general, bool fullg) {
+__device__ __forceinline__ RunDesc gather_run(const YArgs& a, const Optics& o, int kd0, int stride, int nb, int mx,
+                                              int lane, bool general, bool fullg) {
   const int nx = a.nx, nc = nx / 2 + 1;
   const bool mir = 2 * mx > nx;
   const int c = mir ? nx - mx : mx;
@@ -86,7 +86,7 @@ __device__ __forceinline__ RunDesc gather_run(const YArgs& a, int kd0, int strid
       const double2 k = a.kc[kd];
       d.kx = k.x;
       d.ky = k.y;
-      d.kch = a.kchi[kd];
+      d.kch = a.kch_inline ? chi_poly(k.x, k.y, o) + (a.theta ? (double)a.theta[kd] : 0.0) : a.kchi[kd];
     }
   }
   return d;
@@ -241,7 +241,7 @@ __global__ void __launch_bounds__(64 * kPrunedCols) k_psum(YArgs a, Optics o, in
   for (int i0 = 0; i0 < wp.count; i0 += 64) {
     const int kb = wp.kd_a + i0;
     const int nb = min(64, wp.count - i0);
-    const RunBatch rb = make_batch(gather_run(a, kb, 1, nb, mx, lane, !CHI0, FULLG), nb);
+    const RunBatch rb = make_batch(gather_run(a, o, kb, 1, nb, mx, lane, !CHI0, FULLG), nb);
     const int j0 = rb.next(-1);
     if (j0 >= nb) continue;
     Round pos[D];
@@ -339,7 +339,7 @@ __global__ void __launch_bounds__(64 * kAdjWaves) k_padj(YArgs a, Optics o, int 
   for (int i0 = 0; i0 < wp.count; i0 += 64) {
     const int kd0 = wp.kd_a + W * i0;
     const int nb = min(64, wp.count - i0);
-    const RunBatch rb = make_batch(gather_run(a, kd0, W, nb, mx, lane, true, FULLG), nb);
+    const RunBatch rb = make_batch(gather_run(a, o, kd0, W, nb, mx, lane, true, FULLG), nb);
     float wth = 0.f;  // lane j: -(sum of w) of pixel j of the batch (0 without pairs in this column)
     const int j0 = rb.next(-1);
     Round pos[D];
