@@ -113,6 +113,10 @@ PROFILED = {
 }
 
 
+# kernels the benchmark runs on another workload than the timed step's (the adjoint extra)
+PROFILED_WORKLOAD = {"ssb_adjoint_pruned": "aberrated512"}
+
+
 def _pmc_rows(path):
     """Per-dispatch counter sums of a rocprofv3 --pmc CSV: {(dispatch, kernel, grid): {counter: value}}."""
     import csv
@@ -146,13 +150,21 @@ def summarize_profile(d, workload):
         v = [f(c) for (_, k, _), c in rows.items() if k.startswith(("void " + name + "(", name + "("))]
         return (statistics.mean(v), len(v)) if v else (None, 0)
 
-    val = per_kernel(rd, "stem::k_validate", rbytes)[0]
+    # the ingest of the whole event list (the largest k_validate dispatch; a streamed ingest
+    # validates chunks)
+    val = max(rbytes(c) for (_, k, _), c in rd.items() if k.startswith("stem::k_validate("))
     read_factor = val / (4 * C + 8 * (F + 1))
     copies = [c["WRITE_SIZE"] * 1024 for (_, k, g), c in wr.items() if "direct_copy" in k and g == 33546240]
     write_factor = statistics.mean(copies) / (1 << 30)
-    rec = {"_note": summarize_profile.__doc__.split("\n\n")[1].replace("\n    ", " ").strip(),
-           "read_factor": round(read_factor, 5), "write_factor": round(write_factor, 5)}
     sha = source_sha()
+    rec = {}
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(path):
+        # entries of other runs on the same sources are kept
+        with open(path) as fh:
+            rec = {k: v for k, v in json.load(fh).items() if isinstance(v, dict) and v.get("source_sha") == sha}
+    rec.update({"_note": summarize_profile.__doc__.split("\n\n")[1].replace("\n    ", " ").strip(),
+                "read_factor": round(read_factor, 5), "write_factor": round(write_factor, 5)})
     lines = ["| Kernel | Trace name | Dispatches | FETCH_SIZE (MB, raw) | Reads (MB, calibrated) "
              "| Writes (MB, calibrated) |", "|---|---|---:|---:|---:|---:|"]
     for kname, tname in PROFILED.items():
@@ -162,16 +174,38 @@ def summarize_profile(d, workload):
         if r is None or w is None:
             continue
         r, w = r / read_factor, w / write_factor
-        rec[f"{tname}@{workload}"] = {"bytes_per_launch": int(r + w), "read_bytes": int(r), "write_bytes": int(w),
-                                      "source_sha": sha}
-        lines.append(f"| `{kname}` | {tname} | {n} | {fs / 1e6 if fs else float('nan'):.1f} | {r / 1e6:.1f} "
+        wl_k = PROFILED_WORKLOAD.get(tname, workload)
+        rec[f"{tname}@{wl_k}"] = {"bytes_per_launch": int(r + w), "read_bytes": int(r), "write_bytes": int(w),
+                                  "source_sha": sha}
+        lines.append(f"| `{kname}` | {tname}@{wl_k} | {n} | {fs / 1e6 if fs else float('nan'):.1f} | {r / 1e6:.1f} "
                      f"| {w / 1e6:.1f} |")
-    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
+    rec = {k: rec[k] for k in ["_note", "read_factor", "write_factor"] + sorted(k for k in rec if "@" in k)}
+    with open(path, "w") as fh:
         json.dump(rec, fh, indent=1)
         fh.write("\n")
     print(f"C = {C}, F = {F}; read factor {read_factor:.5f} (k_validate), write factor {write_factor:.5f} "
           f"(1 GiB copy, {len(copies)} dispatches); sources sha {sha}\n")
     print("\n".join(lines))
+    sq_path = os.path.join(d, "SQ.csv")
+    if os.path.exists(sq_path):
+        # instruction and wave counters: per launch means, and the derived VALU busy fraction
+        # (SQ_ACTIVE_INST_VALU cycles x 4 / (GRBM_GUI_ACTIVE x the 256 x 4 SIMDs / 8 XCDs))
+        sq = _pmc_rows(sq_path)
+        names = ["SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD", "SQ_ACTIVE_INST_VALU",
+                 "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES", "GRBM_GUI_ACTIVE"]
+        print("\n| Kernel | " + " | ".join(names) + " | VALU busy | mean waves per CU |\n|---|"
+              + "---:|" * (len(names) + 2))
+        for kname, tname in PROFILED.items():
+            vals = {}
+            for c in names:
+                v, _ = per_kernel(sq, kname, lambda r, c=c: r.get(c, float("nan")))
+                vals[c] = v
+            if vals["SQ_WAVES"] is None:
+                continue
+            busy = vals["GRBM_GUI_ACTIVE"] / 8 if vals["GRBM_GUI_ACTIVE"] else float("nan")
+            valu = vals["SQ_ACTIVE_INST_VALU"] * 4 / (busy * 1024) if busy == busy and busy > 0 else float("nan")
+            occ = vals["SQ_WAVE_CYCLES"] / (busy * 256) if busy == busy and busy > 0 else float("nan")
+            print(f"| `{kname}` | " + " | ".join(f"{vals[c]:.4g}" for c in names) + f" | {valu:.3f} | {occ:.1f} |")
     stats = os.path.join(d, "kernel_stats.csv")
     if os.path.exists(stats):
         import csv
@@ -324,6 +358,8 @@ def main():
     ap.add_argument("--fused-com", action="store_true",
                     help="centre of mass formed by the binning pass (ssb_reconstruct_com) instead of its own "
                          "pass over the events on the second stream")
+    ap.add_argument("--no-default-scratch", action="store_true",
+                    help="skip the step timed with the library's default recompute scratch (profiling runs)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run a device copy of this many MiB first (counter calibration)")
     ap.add_argument("--summarize-profile", metavar="DIR",
@@ -473,9 +509,10 @@ def main():
                 f"{r['median_ms']:.4f} ms, min {r['min_ms']:.4f} ms")
     head_key = min(schedules, key=lambda k: schedules[k]["ms"])
     # the library's default recompute scratch (64 MiB: several chunks of pixels), for comparison
-    r = run(stem.STEM_FFT_FP32, stem.STEM_G_RECOMPUTE, args.steps, args.warmup, overlap=False, scratch_mib=0)
-    schedules["recompute(64MiB)/serial"] = r
-    log(f"FP32 recompute with the default 64 MiB scratch, serial: mean {r['ms']:.4f} ms ({r['stats'][3]} chunks)")
+    if not args.no_default_scratch:
+        r = run(stem.STEM_FFT_FP32, stem.STEM_G_RECOMPUTE, args.steps, args.warmup, overlap=False, scratch_mib=0)
+        schedules["recompute(64MiB)/serial"] = r
+        log(f"FP32 recompute with the default 64 MiB scratch, serial: mean {r['ms']:.4f} ms ({r['stats'][3]} chunks)")
     head = schedules[head_key]
     head_mode, head_sched = head_key.split("/")
     head_overlap = head_sched == "overlapped"
