@@ -337,7 +337,7 @@ int ssb_state_region(const stem_det* det, const stem_scan* scan, const stem_opti
  * as complex64 (interleaved re, im).  The state must hold a finished reconstruction with these
  * arguments (ACCUMULATE of every row at least): G is computed with FP64 accumulation as the DFT
  * along ry of the row-transformed cube (g_mode STORE; for mx > Nx/2 as conj G(kd, -Q), D being
- * real) or as the 2D DFT of the binned counts (g_mode RECOMPUTE, scans up to 1024 x 1024).
+ * real) or as the 2D DFT of the binned counts (g_mode RECOMPUTE).
  * Errors: STEM_EINVAL (NULL pointers, n_q outside [1, STEM_MAX_PANEL], an index outside its
  * range), STEM_EWORKSPACE. */
 int ssb_g_panel(const stem_det* det, const stem_scan* scan, const stem_optics* optics, const stem_ssb* ssb,

@@ -47,7 +47,7 @@ struct SsbLayout {
   bool fast;    // both scan lengths taken by the fused kernels (powers of two in [32, 1024])
   int64_t nwy;  // waves of the fused kernels
   int64_t nwp;  // waves of the refocus sum over the stored values
-  int64_t nwa;  // waves of the adjoint over the stored values
+  int64_t nwa;  // dL/dc partials of the adjoint over the stored values (one per workgroup)
 };
 
 static int yreduce_groups(int ny, int nx, int n_k);
@@ -159,7 +159,7 @@ static size_t make_layout(const stem_det& det, const stem_scan& scan, const stem
     pg = pg > gmax ? gmax : pg;
     L->pgroups = pg < 1 ? 1 : pg;
     L->nwp = psum_launch_waves(scan.ny, scan.nx, L->pgroups);
-    L->nwa = padj_launch_waves(scan.nx, L->pgroups);
+    L->nwa = padj_partials(scan.nx, L->pgroups);
   }
   int64_t nw = L->nwy > L->nwp ? L->nwy : L->nwp;
   nw = nw > L->nwa ? nw : L->nwa;
@@ -875,24 +875,29 @@ __global__ void __launch_bounds__(64) k_g_panel(const float2* __restrict__ X, co
   if (lane == 0) *out = v;
 }
 
-// From the binned cube (STEM_G_RECOMPUTE keeps no row-transformed cube): one workgroup per bin, the
-// 2D DFT over (ry, rx) at every Q_j, FP64 accumulation; twiddles W_N^t for exact integer t (FP64
-// sincospi rounded to FP32) in LDS.
+// From the binned cube (STEM_G_RECOMPUTE keeps no row-transformed cube): one workgroup per (bin,
+// group of kPanelGroup frequencies), the 2D DFT over (ry, rx) at those Q_j with FP64
+// accumulation: each thread sums its columns rx of a row with W_Nx^(mx rx) (zero counts skipped),
+// multiplies the row's partial by W_Ny^(my ry) and adds it; twiddles W_N^t for exact integer t
+// (FP64 sincospi rounded to FP32) in LDS, their indices advanced by exact integer steps.
 constexpr int kPanelTw = kGenMax;
+constexpr int kPanelGroup = 8;
 
 template <typename DT>
 __global__ void __launch_bounds__(256) k_g_panel_d(const DT* __restrict__ D, const RowRun* __restrict__ rows,
                                                   int nbx, int n_k, int ny, int nx, PanelQ q, int n_q,
                                                   float2* __restrict__ img) {
   __shared__ float2 s_wx[kPanelTw], s_wy[kPanelTw];
-  __shared__ double s_red[2][4];
+  __shared__ double s_red[2][kPanelGroup][4];
   const int bin = blockIdx.x;
   const int by = bin / nbx, bx = bin % nbx;
   const int nbins = gridDim.x;
+  const int j0 = blockIdx.y * kPanelGroup;
+  const int nj = min(kPanelGroup, n_q - j0);
   const RowRun rr = rows[by];
   const int kd = rr.start + bx - rr.lo;
   if (bx < rr.lo || bx >= rr.hi || kd < 0 || kd >= n_k) {
-    for (int j = threadIdx.x; j < n_q; j += blockDim.x) img[(int64_t)j * nbins + bin] = make_float2(0.f, 0.f);
+    for (int j = threadIdx.x; j < nj; j += blockDim.x) img[(int64_t)(j0 + j) * nbins + bin] = make_float2(0.f, 0.f);
     return;
   }
   for (int t = threadIdx.x; t < nx; t += blockDim.x) {
@@ -908,39 +913,69 @@ __global__ void __launch_bounds__(256) k_g_panel_d(const DT* __restrict__ D, con
   __syncthreads();
   const DT* d = D + (int64_t)kd * ny * nx;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int j = 0; j < n_q; ++j) {
-    const int my = q.my[j], mx = q.mx[j];
-    double re = 0.0, im = 0.0;
-    for (int ry = 0; ry < ny; ++ry) {
-      // row sum along rx, then the factor of ry
-      double rr_ = 0.0, ri = 0.0;
-      for (int rx = threadIdx.x; rx < nx; rx += blockDim.x) {
-        const int c = (int)d[(int64_t)ry * nx + rx];
-        if (c) {
-          const float2 w = s_wx[(int)(((int64_t)mx * rx) % nx)];
-          rr_ += (double)c * (double)w.x;
-          ri += (double)c * (double)w.y;
+  int mx[kPanelGroup], my[kPanelGroup], x0[kPanelGroup], xs[kPanelGroup], yi[kPanelGroup];
+#pragma unroll
+  for (int j = 0; j < kPanelGroup; ++j) {
+    mx[j] = j < nj ? q.mx[j0 + j] : 0;
+    my[j] = j < nj ? q.my[j0 + j] : 0;
+    x0[j] = (int)(((int64_t)mx[j] * threadIdx.x) % nx);        // index of this thread's first rx
+    xs[j] = (int)(((int64_t)mx[j] * blockDim.x) % nx);         // step per blockDim.x columns
+    yi[j] = 0;                                                 // my ry mod Ny
+  }
+  double are[kPanelGroup], aim[kPanelGroup];
+#pragma unroll
+  for (int j = 0; j < kPanelGroup; ++j) are[j] = aim[j] = 0.0;
+  for (int ry = 0; ry < ny; ++ry) {
+    double rre[kPanelGroup], rim[kPanelGroup];
+    int xi[kPanelGroup];
+#pragma unroll
+    for (int j = 0; j < kPanelGroup; ++j) {
+      rre[j] = rim[j] = 0.0;
+      xi[j] = x0[j];
+    }
+    for (int rx = threadIdx.x; rx < nx; rx += blockDim.x) {
+      const int c = (int)d[(int64_t)ry * nx + rx];
+      if (c) {
+#pragma unroll
+        for (int j = 0; j < kPanelGroup; ++j) {
+          const float2 w = s_wx[xi[j]];
+          rre[j] += (double)c * (double)w.x;
+          rim[j] += (double)c * (double)w.y;
         }
       }
-      const float2 w = s_wy[(int)(((int64_t)my * ry) % ny)];
-      re += rr_ * (double)w.x - ri * (double)w.y;
-      im += rr_ * (double)w.y + ri * (double)w.x;
+#pragma unroll
+      for (int j = 0; j < kPanelGroup; ++j) {
+        xi[j] += xs[j];
+        if (xi[j] >= nx) xi[j] -= nx;
+      }
     }
+#pragma unroll
+    for (int j = 0; j < kPanelGroup; ++j) {
+      const float2 w = s_wy[yi[j]];
+      are[j] += rre[j] * (double)w.x - rim[j] * (double)w.y;
+      aim[j] += rre[j] * (double)w.y + rim[j] * (double)w.x;
+      yi[j] += my[j];
+      if (yi[j] >= ny) yi[j] -= ny;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < kPanelGroup; ++j) {
+    double re = are[j], im = aim[j];
     for (int o = 32; o > 0; o >>= 1) {
       re += __shfl_xor(re, o);
       im += __shfl_xor(im, o);
     }
     if (lane == 0) {
-      s_red[0][wave] = re;
-      s_red[1][wave] = im;
+      s_red[0][j][wave] = re;
+      s_red[1][j][wave] = im;
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      const double tr = (s_red[0][0] + s_red[0][1]) + (s_red[0][2] + s_red[0][3]);
-      const double ti = (s_red[1][0] + s_red[1][1]) + (s_red[1][2] + s_red[1][3]);
-      img[(int64_t)j * nbins + bin] = make_float2((float)tr, (float)ti);
-    }
-    __syncthreads();
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < nj) {
+    const int j = threadIdx.x;
+    const double tr = (s_red[0][j][0] + s_red[0][j][1]) + (s_red[0][j][2] + s_red[0][j][3]);
+    const double ti = (s_red[1][j][0] + s_red[1][j][1]) + (s_red[1][j][2] + s_red[1][j][3]);
+    img[(int64_t)(j0 + j) * nbins + bin] = make_float2((float)tr, (float)ti);
   }
 }
 
@@ -969,12 +1004,14 @@ extern "C" int ssb_g_panel(const stem_det* det, const stem_scan* scan, const ste
                        scan->ny, scan->nx, q, (float2*)d_img);
   } else if (scan->nx > kPanelTw || scan->ny > kPanelTw) {
     return STEM_EINVAL;
-  } else if (ssb->d_bits == 8) {
-    hipLaunchKernelGGL(k_g_panel_d<uint8_t>, dim3((unsigned)(nbx * nby)), dim3(256), 0, s, (const uint8_t*)b.D,
-                       b.rows, nbx, n_k, scan->ny, scan->nx, q, n_q, (float2*)d_img);
   } else {
-    hipLaunchKernelGGL(k_g_panel_d<uint16_t>, dim3((unsigned)(nbx * nby)), dim3(256), 0, s, (const uint16_t*)b.D,
-                       b.rows, nbx, n_k, scan->ny, scan->nx, q, n_q, (float2*)d_img);
+    const dim3 grid((unsigned)(nbx * nby), (unsigned)((n_q + kPanelGroup - 1) / kPanelGroup));
+    if (ssb->d_bits == 8)
+      hipLaunchKernelGGL(k_g_panel_d<uint8_t>, grid, dim3(256), 0, s, (const uint8_t*)b.D, b.rows, nbx, n_k,
+                         scan->ny, scan->nx, q, n_q, (float2*)d_img);
+    else
+      hipLaunchKernelGGL(k_g_panel_d<uint16_t>, grid, dim3(256), 0, s, (const uint16_t*)b.D, b.rows, nbx, n_k,
+                         scan->ny, scan->nx, q, n_q, (float2*)d_img);
   }
   STEM_LAUNCH_CHECK();
   return STEM_OK;

@@ -311,8 +311,8 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
 // per (pixel, column) run the moments M_n = sum w wy^n (n = 0..4) give the eight dL/dc terms (the
 // B_j(K - Q) are polynomials in wy along a column, see k_yadjoint); dL/dtheta[kd] = -sum w.
 // Rounds are pipelined through kAdjDepth register slots as in k_psum; the moments of a run carry
-// over its consecutive rounds.  Partials: pdc[wave][8] (FP64), pdth[mx][kd] (FP32; one writer per
-// entry).
+// over its consecutive rounds.  Partials: pdc[workgroup][8] (FP64), pdth[mx][kd] (FP32; one writer per
+// entry), the workgroup's four waves combined into one dL/dc partial.
 template <bool FULLG>
 __global__ void __launch_bounds__(64 * kAdjWaves) k_padj(YArgs a, Optics o, int ny) {
   extern __shared__ __align__(16) unsigned char s_dyn[];
@@ -320,10 +320,9 @@ __global__ void __launch_bounds__(64 * kAdjWaves) k_padj(YArgs a, Optics o, int 
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   float2* tb = (float2*)s_dyn;
   const int nx = a.nx;
-  const int64_t wid = (int64_t)blockIdx.x * W + wave;
   const PrunedItem pi = pruned_item(a, blockIdx.x, 0, 1);
   if (!pi.live) {
-    if (lane < 8 && !a.accumulate) a.pdc[wid * 8 + lane] = 0.0;
+    if (wave == 0 && lane < 8 && !a.accumulate) a.pdc[(int64_t)blockIdx.x * 8 + lane] = 0.0;
     return;
   }
   const int mx = pi.mx;
@@ -419,10 +418,20 @@ __global__ void __launch_bounds__(64 * kAdjWaves) k_padj(YArgs a, Optics o, int 
     }
     if (lane < nb) pth[kd0 + W * lane] = wth;
   }
+  // the workgroup's dL/dc: the waves' sums added in wave order
+  __shared__ double s_dc[kAdjWaves][8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
     const double t = wave_sum_f64(dc[j]);
-    if (lane == 0) a.pdc[wid * 8 + j] = a.accumulate ? a.pdc[wid * 8 + j] + t : t;
+    if (lane == 0) s_dc[wave][j] = t;
+  }
+  __syncthreads();
+  if (wave == 0 && lane < 8) {
+    double t = s_dc[0][lane];
+#pragma unroll
+    for (int w = 1; w < kAdjWaves; ++w) t += s_dc[w][lane];
+    double* p = a.pdc + (int64_t)blockIdx.x * 8 + lane;
+    *p = a.accumulate ? *p + t : t;
   }
 }
 
@@ -438,7 +447,8 @@ inline int64_t psum_launch_waves(int ny, int nx, int ngroups) {
   return (int64_t)((nx + w - 1) / w) * ngroups * w;
 }
 
-inline int64_t padj_launch_waves(int nx, int ngroups) { return (int64_t)nx * ngroups * kAdjWaves; }
+// dL/dc partials of an adjoint launch over the stored values (one per workgroup)
+inline int64_t padj_partials(int nx, int ngroups) { return (int64_t)nx * ngroups; }
 
 // fullg: the runs from full columns of G at a.X (pixels from a.xk0); pwrite: also store the values
 // as the pruned array
@@ -466,7 +476,7 @@ inline int launch_psum(int ny, const YArgs& a, const Optics& o, int chi0, bool f
 
 inline int launch_padj(int ny, const YArgs& a, const Optics& o, bool fullg, hipStream_t s) {
   const size_t lds = padj_block_lds(ny);
-  const dim3 grid((unsigned)(padj_launch_waves(a.nx, a.ngroups) / kAdjWaves)), blk(64 * kAdjWaves);
+  const dim3 grid((unsigned)padj_partials(a.nx, a.ngroups)), blk(64 * kAdjWaves);
   STEM_TRACE(fullg ? "ssb_gadjoint" : "ssb_adjoint_pruned", s);
   if (fullg)
     hipLaunchKernelGGL(k_padj<true>, grid, blk, lds, s, a, o, ny);

@@ -179,3 +179,24 @@ def test_adjoint_matches_oracle_gradient(gpu, g_mode, scratch_mib):
     dc = dc.cpu().numpy()
     assert np.all(np.abs(dc - dco) <= 1e-4 * np.abs(dco) + 1e-6 * np.max(np.abs(dco)))
     assert rel_l2(dth.cpu().numpy(), dtho) <= 1e-4
+
+
+@pytest.mark.parametrize("g_mode", [stem.STEM_G_STORE, stem.STEM_G_RECOMPUTE], ids=["store", "recompute"])
+@pytest.mark.parametrize("name", ["g96x160", "g1000"])
+def test_g_panel(gpu, name, g_mode):
+    """The panel of G at fixed Q (from the row transform, or the 2D DFT of the binned counts in
+    groups of eight frequencies) at the other scan lengths."""
+    wl, d_idx, d_off, idx, off, _ = data(name)
+    st, out = gpu_ssb(d_idx, d_off, wl, c=wl.aberr, g_mode=g_mode)
+    assert out["status"] == 0
+    ny, nx = wl.scan
+    qs = [(0, 0), (3, 2), (ny - 3, nx - 2), (ny // 2, nx // 2), (1, nx - 1), (0, nx // 2 + 1)]
+    qs += [(my, mx) for my in (1, 2, ny - 1) for mx in (0, 1, 2)]
+    img = st.g_panel(qs).cpu().numpy()
+    ref = oracle(name)
+    H, W = wl.det
+    _, lut = oeer.bin_geometry(W, H, wl.bin, wl.r_bf)
+    P = ossb.g_panel(ref["G"], lut, qs)
+    assert rel_l2(img, P) <= TOL
+    assert np.array_equal(img[0].real.astype(np.float64), P[0].real)
+    assert np.all(img[:, lut < 0] == 0)
