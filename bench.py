@@ -651,6 +651,32 @@ def main():
             stg[m] = stem.ssb_state_bytes(det, scan, optics, stem.Ssb(stem.STEM_FFT_FP32, 0, G_MODES[m], 8))
         extras["state_bytes"] = stg
 
+        # Eq. 3 as a batched complex matrix product (the remark after Eq. 3): per column mx,
+        # T(my) = sum_K A(K, my) G(K, my) is the diagonal of A^T G, a (Ny x n_K) by (n_K x Ny)
+        # product per column.  A lower bound on that route: torch's batched complex64 product for a
+        # sample of columns (operands contiguous, their construction not timed), scaled to all
+        # Nx/2 + 1 columns, against the fused column sum that also transforms the columns.
+        ncol = 16
+        ga = torch.randn(ncol, scan.ny, n_k, dtype=torch.complex64, device=dev).contiguous()
+        gb = torch.randn(ncol, n_k, scan.ny, dtype=torch.complex64, device=dev).contiguous()
+        for _ in range(2):
+            torch.bmm(ga, gb)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            torch.bmm(ga, gb)
+        e1.record()
+        torch.cuda.synchronize()
+        bmm_us = e0.elapsed_time(e1) / 5 * 1e3 * (scan.nx // 2 + 1) / ncol
+        flops = 8.0 * (scan.nx // 2 + 1) * scan.ny * scan.ny * n_k
+        extras["eq3_as_gemm"] = {"workload": f"scan1024 geometry: {scan.nx // 2 + 1} columns of a ({scan.ny} x {n_k}) by "
+                                             f"({n_k} x {scan.ny}) complex product, {ncol} timed and scaled",
+                                 "gemm_us": round(bmm_us, 1), "gemm_tflops": round(flops / (bmm_us * 1e-6) / 1e12, 1),
+                                 "fused_sum_us": kernels.get("ssb_yreduce", {}).get("avg_us")}
+        log(f"Eq. 3 as a batched complex product: {bmm_us:.0f} us for all columns ({flops / 1e12:.2f} TFLOP)")
+        del ga, gb
+
         # differentiation workload: forward + adjoint of -Var(phi) w.r.t. the 8 coefficients
         wl4 = WORKLOADS["aberrated512"]
         d4 = simulate(wl4, device=dev)
