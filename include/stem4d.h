@@ -305,10 +305,10 @@ int ssb_reconstruct_com(const int32_t* d_idx, const int64_t* d_off, int64_t fram
  *                    (pixel groups of the fused column kernels); [2] bytes of row-transformed
  *                    columns or stored G values the sum kernels read; [3] pixel chunks.
  *  STEM_REGION_PG    STEM_G_STORE, after FINALIZE: G on the double-overlap pairs, complex64.  For
- *                    pixel kd and scan-frequency column mx in [0, Nx) the values G(kd, (my, mx)),
+ *                    scan-frequency column mx in [0, Nx) and pixel kd the values G(kd, (my, mx)),
  *                    my over the set in ascending signed frequency, start at entry
- *                    POFF[kd*Nx + mx]; the region holds an upper bound of entries.
- *  STEM_REGION_POFF  STEM_G_STORE, after FINALIZE: int64 [n_K*Nx + 1] those offsets, the last
+ *                    POFF[mx*n_K + kd] (column-major); the region holds an upper bound of entries.
+ *  STEM_REGION_POFF  STEM_G_STORE, after FINALIZE: int64 [Nx*n_K + 1] those offsets, the last
  *                    entry the number of pairs.
  *  STEM_REGION_NPAIR int32 [F] number of pixels in the double-overlap set of each Q, column-major
  *                    [mx][my], after a FINALIZE with normalize = 1.

@@ -137,7 +137,7 @@ static size_t make_layout(const stem_det& det, const stem_scan& scan, const stem
   L->X = o;     o = align256(o + (size_t)L->xpix * per_pixel);
   L->Y = o;     o = align256(o + (size_t)L->ypix * per_pixel);
   L->poff = o;  o = align256(o + (L->store ? sizeof(int64_t) * ((size_t)n_k * scan.nx + 1) : 0));
-  L->ptot = o;  o = align256(o + (L->store ? sizeof(int64_t) * (size_t)n_k : 0));
+  L->ptot = o;  o = align256(o + (L->store ? sizeof(int64_t) * (size_t)scan.nx : 0));
   L->pg = o;    o = align256(o + sizeof(float2) * (size_t)L->pcap);
   L->T = o;     o = align256(o + (size_t)L->F * sizeof(float2));
   L->A = o;     o = align256(o + (size_t)L->F * sizeof(float2));
@@ -291,10 +291,11 @@ __global__ void __launch_bounds__(256) k_pair_count(const int4* __restrict__ cst
   npq[q] = cnt;
 }
 
-// Offsets of the pruned double-overlap array: poff[kd * Nx + mx] = number of values of the (pixel,
-// column) pairs before it in pixel-major, column-minor order; poff[n_k * Nx] = the total.  Three
-// passes: the runs of each pixel scanned by its own workgroup (offsets relative to the pixel,
-// pixel totals to ptot), the pixel totals scanned by one workgroup, then each pixel's base added.
+// Offsets of the pruned double-overlap array: poff[mx * n_k + kd] = number of values of the
+// (column, pixel) pairs before it in column-major, pixel-minor order; poff[Nx * n_k] = the total.
+// Three passes: the runs of each column scanned by its own workgroup (offsets relative to the
+// column, column totals to ptot), the column totals scanned by one workgroup, then each column's
+// base added.
 
 __device__ __forceinline__ int64_t pruned_size(const int4* __restrict__ cst, int kd, int mx, int nx) {
   const int nc = nx / 2 + 1;
@@ -320,47 +321,47 @@ __device__ __forceinline__ int64_t block_scan256(int64_t v, int64_t* s) {
   return r;
 }
 
-__global__ void __launch_bounds__(256) k_prune_runs(const int4* __restrict__ cst, int nx, int64_t* __restrict__ poff,
-                                                    int64_t* __restrict__ ptot) {
+__global__ void __launch_bounds__(256) k_prune_runs(const int4* __restrict__ cst, int n_k, int nx,
+                                                    int64_t* __restrict__ poff, int64_t* __restrict__ ptot) {
   __shared__ int64_t s[256];
-  const int kd = blockIdx.x;
-  const int per = (nx + 255) / 256;  // consecutive columns per thread
-  const int m0 = threadIdx.x * per;
+  const int mx = blockIdx.x;
+  const int per = (n_k + 255) / 256;  // consecutive pixels per thread
+  const int k0 = threadIdx.x * per;
   int64_t sum = 0;
-  for (int mx = m0; mx < m0 + per && mx < nx; ++mx) sum += pruned_size(cst, kd, mx, nx);
+  for (int kd = k0; kd < k0 + per && kd < n_k; ++kd) sum += pruned_size(cst, kd, mx, nx);
   int64_t base = block_scan256(sum, s) - sum;
-  for (int mx = m0; mx < m0 + per && mx < nx; ++mx) {
-    poff[(int64_t)kd * nx + mx] = base;
+  for (int kd = k0; kd < k0 + per && kd < n_k; ++kd) {
+    poff[(int64_t)mx * n_k + kd] = base;
     base += pruned_size(cst, kd, mx, nx);
   }
-  if (threadIdx.x == 255) ptot[kd] = base;
+  if (threadIdx.x == 255) ptot[mx] = base;
 }
 
 __global__ void __launch_bounds__(256) k_prune_bases(int n_k, int nx, int64_t* __restrict__ poff,
                                                      int64_t* __restrict__ ptot, int64_t pcap,
                                                      int32_t* __restrict__ status) {
   __shared__ int64_t s[256];
-  const int per = (n_k + 255) / 256;
-  const int k0 = threadIdx.x * per;
+  const int per = (nx + 255) / 256;
+  const int m0 = threadIdx.x * per;
   int64_t sum = 0;
-  for (int kd = k0; kd < k0 + per && kd < n_k; ++kd) sum += ptot[kd];
+  for (int mx = m0; mx < m0 + per && mx < nx; ++mx) sum += ptot[mx];
   int64_t base = block_scan256(sum, s) - sum;
-  for (int kd = k0; kd < k0 + per && kd < n_k; ++kd) {
-    const int64_t t = ptot[kd];
-    ptot[kd] = base;  // now the pixel's first entry
+  for (int mx = m0; mx < m0 + per && mx < nx; ++mx) {
+    const int64_t t = ptot[mx];
+    ptot[mx] = base;  // now the column's first entry
     base += t;
   }
   if (threadIdx.x == 255) {
-    poff[(int64_t)n_k * nx] = base;
+    poff[(int64_t)nx * n_k] = base;
     if (base > pcap) report(status, STEM_EWORKSPACE);  // never with the layout's bound
   }
 }
 
-__global__ void __launch_bounds__(256) k_prune_add(int nx, int64_t* __restrict__ poff,
+__global__ void __launch_bounds__(256) k_prune_add(int n_k, int64_t* __restrict__ poff,
                                                    const int64_t* __restrict__ ptot) {
-  const int kd = blockIdx.x;
-  const int64_t b = ptot[kd];
-  for (int mx = threadIdx.x; mx < nx; mx += 256) poff[(int64_t)kd * nx + mx] += b;
+  const int mx = blockIdx.x;
+  const int64_t b = ptot[mx];
+  for (int kd = threadIdx.x; kd < n_k; kd += 256) poff[(int64_t)mx * n_k + kd] += b;
 }
 
 // number of pixel groups of the fused sum: about 4096 waves, at most n_k, partial sums <= 64 MB
@@ -642,11 +643,11 @@ static int run_pair_count(const SsbLayout& L, const Bufs& b, int ny, int nx, hip
 
 static int run_prune_offsets(const SsbLayout& L, const Bufs& b, int nx, int32_t* d_status, hipStream_t s) {
   STEM_TRACE("prune_offsets", s);
-  hipLaunchKernelGGL(k_prune_runs, dim3((unsigned)L.n_k), dim3(256), 0, s, b.cst, nx, b.poff, b.ptot);
+  hipLaunchKernelGGL(k_prune_runs, dim3((unsigned)nx), dim3(256), 0, s, b.cst, L.n_k, nx, b.poff, b.ptot);
   STEM_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_prune_bases, dim3(1), dim3(256), 0, s, L.n_k, nx, b.poff, b.ptot, L.pcap, d_status);
   STEM_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_prune_add, dim3((unsigned)L.n_k), dim3(256), 0, s, nx, b.poff, b.ptot);
+  hipLaunchKernelGGL(k_prune_add, dim3((unsigned)nx), dim3(256), 0, s, L.n_k, b.poff, b.ptot);
   STEM_LAUNCH_CHECK();
   return STEM_OK;
 }

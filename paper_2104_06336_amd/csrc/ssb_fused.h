@@ -218,9 +218,10 @@ __global__ void __launch_bounds__(64 * XF::kXWaves) k_xstage(const DT* __restric
 // kstride): with `accumulate` a launch adds to the partial sums and counters of the previous
 // chunk's launch (same grid, same wave -> partial mapping) instead of overwriting them.
 //
-// Pruned G: the double-overlap values only, for later sums (refocus) and the adjoint.  For pixel
-// kd and scan-frequency column mx in [0, Nx), the values G(kd, (iy, mx)) for iy in the set of
-// that column, ascending iy with the hole [b0, b1] skipped, start at poff[kd * Nx + mx].  Column
+// Pruned G: the double-overlap values only, for later sums (refocus) and the adjoint.  For
+// scan-frequency column mx in [0, Nx) and pixel kd, the values G(kd, (iy, mx)) for iy in the set of
+// that column, ascending iy with the hole [b0, b1] skipped, start at poff[mx * n_k + kd] (column
+// major: the runs of a column's pixels follow one another).  Column
 // mx <= Nx/2 is half-spectrum column c = mx (direct set); mx > Nx/2 is the mirror of c = Nx - mx,
 // whose values are conj G(kd, (-iy, c)).  PWRITE: the fused sum writes them (FINALIZE that keeps
 // G); the refocus sum and the adjoint read them (ssb_pruned.h).
@@ -248,7 +249,7 @@ struct YArgs {
   int accumulate;           // add to part / wcnt / pdc (a later chunk of pixels)
   const float2* pg;         // pruned G read (refocus, adjoint)
   float2* pgw;              // PWRITE: pruned G written
-  const int64_t* poff;      // pruned offsets [n_k][Nx]
+  const int64_t* poff;      // pruned offsets [Nx][n_k]
   int64_t pcap;             // capacity of the pruned array (entries)
   float2* part;             // partial sums of T [groups][F]
   unsigned long long* wcnt; // per wave: pairs | (8-byte loads << 40)
@@ -415,8 +416,8 @@ __global__ void __launch_bounds__(kYThreads, 2) k_yreduce(YArgs a, Optics o) {
         const int c = c0 + b0;
         int64_t pd = 0, pm = 0;
         if (c < nc) {
-          pd = a.poff[(int64_t)kd * nx + c];
-          if (c > 0 && 2 * c < nx) pm = a.poff[(int64_t)kd * nx + (nx - c)];
+          pd = a.poff[(int64_t)c * a.n_k + kd];
+          if (c > 0 && 2 * c < nx) pm = a.poff[(int64_t)(nx - c) * a.n_k + kd];
         }
 #pragma unroll
         for (int i = 0; i < 16; ++i) {

@@ -69,10 +69,10 @@ __device__ __forceinline__ RunDesc gather_run(const YArgs& a, const Optics& o, i
     const ColSet s = mir ? sm : sd;
     const int h0 = max(s.a0, s.b0), h1 = min(s.a1, s.b1);
     if (fullg) {
-      d.e0 = a.poff ? a.poff[(int64_t)kd * nx + mx] : 0;
+      d.e0 = a.poff ? a.poff[(int64_t)mx * a.n_k + kd] : 0;
       d.len = set_size(s);
     } else {
-      const int64_t e0 = a.poff[(int64_t)kd * nx + mx], e1 = a.poff[(int64_t)kd * nx + mx + 1];
+      const int64_t e0 = a.poff[(int64_t)mx * a.n_k + kd], e1 = a.poff[(int64_t)mx * a.n_k + kd + 1];
       // entries are read only inside the array (a state whose FINALIZE never ran reads nothing
       // out of bounds)
       const bool ok = e0 >= 0 && e1 >= e0 && e1 <= a.pcap;
@@ -192,9 +192,9 @@ struct PrunedItem {
 };
 
 // The work of wave w of workgroup blk: the pixels [kd_a, kd_b) of group g = blk % ngroups of
-// ngroups equal shares of [k0, k1), and column mx = (blk / ngroups) W + w: W adjacent columns of
-// the same pixels, which are adjacent in the pruned array (W = 1 for the adjoint, whose workgroup
-// takes one column).
+// ngroups equal shares of [k0, k1), and column mx = (blk / ngroups) W + w (W = 1 for the adjoint,
+// whose workgroup takes one column).  In the column-major pruned array the runs of a column's
+// pixels follow one another, so each item reads one contiguous stretch.
 __device__ __forceinline__ PrunedItem pruned_item(const YArgs& a, int64_t blk, int w, int W) {
   PrunedItem it{0, 0, 0, 0, false};
   it.g = (int)(blk % a.ngroups);

@@ -134,20 +134,22 @@ def state_pruned(st):
 
 def oracle_pruned(G, kc, wl):
     """G on the double-overlap pairs in the pruned layout, from the oracle's full G[kd][my][mx] and
-    set (ossb.double_overlap): pixel-major, then column mx in [0, Nx), then ascending signed my;
-    and the offsets of every (pixel, column) run."""
+    set (ossb.double_overlap): column mx in [0, Nx) major, then pixel, then ascending signed my;
+    and the offsets of every (column, pixel) run."""
     ny, nx = wl.scan
     qx, qy = ossb.scan_q_grid(ny, nx, wl.step, wl.dk)
     order = np.argsort(ossb.signed_freq_index(ny), kind="stable")  # rows by ascending signed my
-    vals, sizes = [], []
+    masks, gs = [], []
     r2 = float(wl.r_bf) * float(wl.r_bf)
     for kd in range(len(kc)):
-        m = ossb.double_overlap(float(kc[kd, 0]), float(kc[kd, 1]), qx, qy, r2)[order].T  # [mx][iy]
-        g = G[kd][order].T
-        vals.append(g[m])
-        sizes.append(m.sum(axis=1))
-    sizes = np.concatenate(sizes).astype(np.int64)
-    poff = np.concatenate([[0], np.cumsum(sizes)])
+        masks.append(ossb.double_overlap(float(kc[kd, 0]), float(kc[kd, 1]), qx, qy, r2)[order].T)  # [mx][iy]
+        gs.append(G[kd][order].T)
+    vals, sizes = [], []
+    for mx in range(nx):
+        for kd in range(len(kc)):
+            vals.append(gs[kd][mx][masks[kd][mx]])
+            sizes.append(int(masks[kd][mx].sum()))
+    poff = np.concatenate([[0], np.cumsum(np.asarray(sizes, dtype=np.int64))])
     return np.concatenate(vals), poff
 
 
