@@ -8,6 +8,8 @@ g48x80ab   48 x 80, aberrated, per-pixel probe phase: adjoint in both G modes
 g16x4096   16 x 4096 and 4096 x 16: the shortest and the longest transform
 g1000      1000 x 1000 (4.2.5.5.5), 64x64 detector binned 4x (52 pixels)
 g2048      2048 x 2048, binned 8x (12 pixels): lengths beyond the single-wave FFT
+g4096      4096 x 4096, binned 8x (12 pixels), 2 e-/frame: the longest transforms both ways
+g16x16     16 x 16, the shortest
 
 Every output is compared element by element with the FP64 oracle: counts and the binned cube bit
 for bit, the row transform, pruned G, T, phi and the DPC phase by relative L2 (1e-5), the
@@ -39,6 +41,9 @@ CASES = {
     "g4096x16": SMALL.replace(name="scan 4096x16, binned 4x", scan=(4096, 16), bin=4, mean_e=10.0),
     "g1000": SMALL.replace(name="scan 1000x1000, binned 4x", scan=(1000, 1000), bin=4, mean_e=10.0),
     "g2048": SMALL.replace(name="scan 2048x2048, binned 8x", scan=(2048, 2048), bin=8, mean_e=5.0),
+    # the largest transforms in both directions, and the smallest
+    "g4096": SMALL.replace(name="scan 4096x4096, binned 8x", scan=(4096, 4096), bin=8, mean_e=2.0),
+    "g16x16": SMALL.replace(name="scan 16x16", scan=(16, 16)),
 }
 _DATA = {}
 
@@ -86,7 +91,7 @@ def _announce(request):
     print(f"\n[gpu] {request.node.name}", flush=True)
 
 
-@pytest.mark.parametrize("name", ["g96x160", "g16x4096", "g4096x16", "g1000", "g2048"])
+@pytest.mark.parametrize("name", ["g96x160", "g16x4096", "g4096x16", "g1000", "g2048", "g4096", "g16x16"])
 def test_com_and_dpc_phase(gpu, name):
     wl, d_idx, d_off, idx, off, _ = data(name)
     for lam1, lam2, L in [(0.0, 0.0, 10), (1.0, 0.05, 25)]:
@@ -120,7 +125,7 @@ def test_binning_transform_and_pruned_values(gpu, name):
 
 
 @pytest.mark.parametrize("g_mode", [stem.STEM_G_STORE, stem.STEM_G_RECOMPUTE], ids=["store", "recompute"])
-@pytest.mark.parametrize("name", ["g96x160", "g16x4096", "g4096x16", "g1000", "g2048"])
+@pytest.mark.parametrize("name", ["g96x160", "g16x4096", "g4096x16", "g1000", "g2048", "g4096", "g16x16"])
 def test_ssb_phase(gpu, name, g_mode):
     wl, d_idx, d_off, idx, off, _ = data(name)
     st, out = gpu_ssb(d_idx, d_off, wl, c=wl.aberr, g_mode=g_mode)
