@@ -191,22 +191,24 @@ __device__ __forceinline__ double chi_eval(const ChiCol& c, double wy) {
   return c.h0 + wy * (c.h1 + wy * (c.h2 + wy * (c.h3 + wy * c.h4)));
 }
 
-// chi(K - Q) - chi(Kc) - theta along one column as a polynomial in the signed row index iy:
-// with wy = A + B iy (A = lam dk Ky, B = -lam dk sy), the quartic of chi_column expanded in powers
-// of iy, the constant term less kch.  psi = p0 + iy (p1 + iy (p2 + iy (p3 + iy p4))).
+// chi(K - Q) - chi(Kc) - theta along one column as a polynomial in the signed row index iy, in
+// revolutions (divided by 2 pi): with wy = A + B iy (A = lam dk Ky, B = -lam dk sy), the quartic of
+// chi_column expanded in powers of iy, the constant term less kch.
+// psi / (2 pi) = p0 + iy (p1 + iy (p2 + iy (p3 + iy p4))).
 struct ChiRow {
   double p0, p1, p2, p3, p4;
 };
 
 __device__ __forceinline__ ChiRow chi_row(const ChiCol& c, double A, double B, double kch) {
+  const double inv_two_pi = 0.15915494309189533576888376337251;
   const double A2 = A * A, A3 = A2 * A, A4 = A2 * A2;
   const double B2 = B * B, B3 = B2 * B, B4 = B2 * B2;
   ChiRow r;
-  r.p0 = (c.h0 + A * c.h1 + A2 * c.h2 + A3 * c.h3 + A4 * c.h4) - kch;
-  r.p1 = B * (c.h1 + 2.0 * A * c.h2 + 3.0 * A2 * c.h3 + 4.0 * A3 * c.h4);
-  r.p2 = B2 * (c.h2 + 3.0 * A * c.h3 + 6.0 * A2 * c.h4);
-  r.p3 = B3 * (c.h3 + 4.0 * A * c.h4);
-  r.p4 = B4 * c.h4;
+  r.p0 = ((c.h0 + A * c.h1 + A2 * c.h2 + A3 * c.h3 + A4 * c.h4) - kch) * inv_two_pi;
+  r.p1 = B * (c.h1 + 2.0 * A * c.h2 + 3.0 * A2 * c.h3 + 4.0 * A3 * c.h4) * inv_two_pi;
+  r.p2 = B2 * (c.h2 + 3.0 * A * c.h3 + 6.0 * A2 * c.h4) * inv_two_pi;
+  r.p3 = B3 * (c.h3 + 4.0 * A * c.h4) * inv_two_pi;
+  r.p4 = B4 * c.h4 * inv_two_pi;
   return r;
 }
 
@@ -214,14 +216,18 @@ __device__ __forceinline__ double chi_row_eval(const ChiRow& r, double t) {
   return r.p0 + t * (r.p1 + t * (r.p2 + t * (r.p3 + t * r.p4)));
 }
 
-// exp(i psi): psi in revolutions, r = psi / (2 pi), is reduced in FP64 to f = r - rint(r) in
-// [-1/2, 1/2] (error below |r| ulp(1/(2 pi)) + ulp(r)), rounded to float; the hardware sine and
-// cosine of 2 pi f (v_sin_f32 / v_cos_f32, whose argument is in revolutions) give the pair.
-__device__ __forceinline__ float2 expi_reduced(double psi) {
-  const double inv_two_pi = 0.15915494309189533576888376337251;
-  const double r = psi * inv_two_pi;
+// exp(2 pi i r) for a phase r in revolutions: r is reduced in FP64 to f = r - rint(r) in
+// [-1/2, 1/2], rounded to float; the hardware sine and cosine of 2 pi f (v_sin_f32 / v_cos_f32,
+// whose argument is in revolutions) give the pair.
+__device__ __forceinline__ float2 expi_rev(double r) {
   const float f = (float)(r - rint(r));
   return make_float2(__builtin_amdgcn_cosf(f), __builtin_amdgcn_sinf(f));
+}
+
+// exp(i psi): psi / (2 pi) (error below |psi / 2 pi| ulp(1/(2 pi)) + ulp) through expi_rev.
+__device__ __forceinline__ float2 expi_reduced(double psi) {
+  const double inv_two_pi = 0.15915494309189533576888376337251;
+  return expi_rev(psi * inv_two_pi);
 }
 
 // Double-overlap sets of pixel K along column ix: iy in [a0, a1] but not in [b0, b1].

@@ -32,7 +32,8 @@ struct RunDesc {
   int32_t a0;     // signed row frequency of the first entry
   int32_t split;  // entries before the hole of the set
   int32_t hl;     // hole length (0: none)
-  double kx, ky, kch;
+  double kx, ky;  // Kc
+  ChiRow ch;      // the phase of the pixel's pairs in this column, in revolutions, by row index
 };
 
 // columns (waves) per workgroup of the refocus sum (fewer while its LDS would pass 64 KB), and
@@ -48,20 +49,22 @@ constexpr int kAdjWaves = 4;
 constexpr int kSumDepth = STEM_SUM_DEPTH;  // rounds in flight per wave, refocus sum
 constexpr int kAdjDepth = 3;     // rounds in flight per wave, adjoint
 
-// LDS bytes of one refocus wave: its column of T
-__host__ __device__ inline size_t pruned_wave_lds(int ny) { return (size_t)ny * sizeof(float2); }
+// LDS bytes of one refocus wave: its column of T and a spare slot (the target of the lanes past a
+// run's end), padded to 16 bytes
+__host__ __device__ inline size_t pruned_wave_lds(int ny) { return (size_t)(ny + 2) * sizeof(float2); }
 
 // LDS bytes of an adjoint workgroup: its column of Tbar
 __host__ __device__ inline size_t padj_block_lds(int ny) { return (size_t)ny * sizeof(float2); }
 
 // descriptors of the pixels kd0 + lane * stride (lane < nb) for column mx; fullg: run lengths from
-// the sets (e0 = the pruned array's offset when it exists)
+// the sets (e0 = the pruned array's offset when it exists); general: Kc and the phase polynomial
+// of the column (chi(Kc) + theta evaluated from Kc and theta when a.kch_inline)
 __device__ __forceinline__ RunDesc gather_run(const YArgs& a, const Optics& o, int kd0, int stride, int nb, int mx,
                                               int lane, bool general, bool fullg) {
   const int nx = a.nx, nc = nx / 2 + 1;
   const bool mir = 2 * mx > nx;
   const int c = mir ? nx - mx : mx;
-  RunDesc d{0, 0, 0, 0, 0, 0.0, 0.0, 0.0};
+  RunDesc d{0, 0, 0, 0, 0, 0.0, 0.0, ChiRow{0.0, 0.0, 0.0, 0.0, 0.0}};
   if (lane < nb) {
     const int kd = kd0 + lane * stride;
     ColSet sd, sm;
@@ -86,7 +89,10 @@ __device__ __forceinline__ RunDesc gather_run(const YArgs& a, const Optics& o, i
       const double2 k = a.kc[kd];
       d.kx = k.x;
       d.ky = k.y;
-      d.kch = a.kch_inline ? chi_poly(k.x, k.y, o) + (a.theta ? (double)a.theta[kd] : 0.0) : a.kchi[kd];
+      const double kch =
+          a.kch_inline ? chi_poly(k.x, k.y, o) + (a.theta ? (double)a.theta[kd] : 0.0) : a.kchi[kd];
+      const double qx = (double)signed_index(mx, nx) * o.sx;
+      d.ch = chi_row(chi_column(o.lk * (k.x - qx), o), o.lk * k.y, -o.lk * o.sy, kch);
     }
   }
   return d;
@@ -107,18 +113,20 @@ struct RunBatch {
   __device__ __forceinline__ static double rld(double v, int j) { return __longlong_as_double(rl64(__double_as_longlong(v), j)); }
 
   __device__ __forceinline__ int len(int j) const { return rl(d.len, j); }
-  __device__ __forceinline__ RunDesc at(int j, bool general) const {
+  // run j's extent (the entries and their row frequencies)
+  __device__ __forceinline__ RunDesc at(int j) const {
     RunDesc r;
     r.e0 = rl64(d.e0, j);
     r.len = rl(d.len, j);
     r.a0 = rl(d.a0, j);
     r.split = rl(d.split, j);
     r.hl = rl(d.hl, j);
-    r.kx = general ? rld(d.kx, j) : 0.0;
-    r.ky = general ? rld(d.ky, j) : 0.0;
-    r.kch = general ? rld(d.kch, j) : 0.0;
     return r;
   }
+  __device__ __forceinline__ ChiRow chi(int j) const {
+    return ChiRow{rld(d.ch.p0, j), rld(d.ch.p1, j), rld(d.ch.p2, j), rld(d.ch.p3, j), rld(d.ch.p4, j)};
+  }
+  __device__ __forceinline__ double2 kc(int j) const { return make_double2(rld(d.kx, j), rld(d.ky, j)); }
   // the first run with entries after slot j (nb if none)
   __device__ __forceinline__ int next(int j) const {
     const uint64_t m = j >= 63 ? 0ull : mask & (~0ull << (j + 1));
@@ -218,7 +226,10 @@ __device__ __forceinline__ WavePixels wave_pixels(int kd_a, int kd_b, int w, int
 
 // T of column mx over the pixels of group g from the stored values.  CHI0: every phase factor is
 // exactly 1.  The rounds go through kSumDepth register slots: slot d is summed, then refilled
-// with the next round's loads, so kSumDepth - 1 rounds are in flight while one is summed.
+// with the next round's loads, so kSumDepth - 1 rounds are in flight while one is summed.  A
+// round's slices of 64 entries with no entry of the run are skipped (a wave-uniform test); inside
+// a slice every lane works, and the lanes past the run's end read and write the wave's spare LDS
+// slot, so the LDS accesses of a round issue back to back with no divergent branch between them.
 template <bool CHI0, bool FULLG, bool PWRITE>
 __global__ void __launch_bounds__(64 * kPrunedCols) k_psum(YArgs a, Optics o, int ny) {
   extern __shared__ __align__(16) unsigned char s_dyn[];
@@ -235,7 +246,6 @@ __global__ void __launch_bounds__(64 * kPrunedCols) k_psum(YArgs a, Optics o, in
   }
   const int mx = pi.mx, g = pi.g;
   for (int i = lane; i < ny; i += 64) t[i] = make_float2(0.f, 0.f);
-  const double qx = (double)signed_index(mx, nx) * o.sx;
   const WavePixels wp = wave_pixels(pi.kd_a, pi.kd_b, 0, 1);
   unsigned long long cnt = 0;
   for (int i0 = 0; i0 < wp.count; i0 += 64) {
@@ -250,47 +260,45 @@ __global__ void __launch_bounds__(64 * kPrunedCols) k_psum(YArgs a, Optics o, in
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       const Round l = it.load_target(nb);
-      load_round<FULLG>(a, rb.at(l.j, false), kb + l.j, mx, ny, l.u0, lane, buf[d]);
+      load_round<FULLG>(a, rb.at(l.j), kb + l.j, mx, ny, l.u0, lane, buf[d]);
       pos[d] = it.take(rb);
     }
     while (pos[0].j < nb) {
 #pragma unroll
       for (int d = 0; d < D; ++d) {
         if (pos[d].j < nb) {
-          const RunDesc r = rb.at(pos[d].j, !CHI0);
+          const RunDesc r = rb.at(pos[d].j);
           const int u0 = pos[d].u0;
           if (u0 == 0) cnt += (unsigned long long)r.len;
           ChiRow ch{};
-          if constexpr (!CHI0) ch = chi_row(chi_column(o.lk * (r.kx - qx), o), o.lk * r.ky, -o.lk * o.sy, r.kch);
-          int my[4];
+          if constexpr (!CHI0) ch = rb.chi(pos[d].j);
+          int ad[4];
           float2 val[4], tv[4];
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const int u = u0 + lane + 64 * q;
             const int iy = run_iy(r, u);
-            my[q] = iy < 0 ? iy + ny : iy;
+            ad[q] = u < r.len ? (iy < 0 ? iy + ny : iy) : ny;
             val[q] = buf[d][q];
-            if (u < r.len) {
+            if (u0 + 64 * q < r.len) {
               if constexpr (PWRITE) {
-                if (r.e0 + u < a.pcap) a.pgw[r.e0 + u] = val[q];
+                if (u < r.len && r.e0 + u < a.pcap) a.pgw[r.e0 + u] = val[q];
               }
               if constexpr (!CHI0) {
-                const float2 e = expi_reduced(chi_row_eval(ch, (double)iy));
+                const float2 e = expi_rev(chi_row_eval(ch, (double)iy));
                 const float2 x = val[q];
                 val[q] = make_float2(x.x * e.x - x.y * e.y, x.x * e.y + x.y * e.x);
               }
             }
           }
-          // the four entries of a lane are distinct row frequencies of one run: read all, then write
+          // the entries of a round are distinct row frequencies of one run: read all, then write
 #pragma unroll
-          for (int q = 0; q < 4; ++q)
-            if (u0 + lane + 64 * q < r.len) tv[q] = t[my[q]];
+          for (int q = 0; q < 4; ++q) tv[q] = t[ad[q]];
 #pragma unroll
-          for (int q = 0; q < 4; ++q)
-            if (u0 + lane + 64 * q < r.len) t[my[q]] = cadd(tv[q], val[q]);
+          for (int q = 0; q < 4; ++q) t[ad[q]] = cadd(tv[q], val[q]);
         }
         const Round l = it.load_target(nb);
-        load_round<FULLG>(a, rb.at(l.j, false), kb + l.j, mx, ny, l.u0, lane, buf[d]);
+        load_round<FULLG>(a, rb.at(l.j), kb + l.j, mx, ny, l.u0, lane, buf[d]);
         pos[d] = it.take(rb);
       }
     }
@@ -348,7 +356,7 @@ __global__ void __launch_bounds__(64 * kAdjWaves) k_padj(YArgs a, Optics o, int 
 #pragma unroll
       for (int d = 0; d < D; ++d) {
         const Round l = it.load_target(nb);
-        load_round<FULLG>(a, rb.at(l.j, false), kd0 + W * l.j, mx, ny, l.u0, lane, buf[d]);
+        load_round<FULLG>(a, rb.at(l.j), kd0 + W * l.j, mx, ny, l.u0, lane, buf[d]);
         pos[d] = it.take(rb);
       }
     } else {
@@ -359,24 +367,26 @@ __global__ void __launch_bounds__(64 * kAdjWaves) k_padj(YArgs a, Optics o, int 
 #pragma unroll
       for (int d = 0; d < D; ++d) {
         if (pos[d].j < nb) {
-          const RunDesc r = rb.at(pos[d].j, true);
+          const RunDesc r = rb.at(pos[d].j);
+          const double2 kc = rb.kc(pos[d].j);
+          const ChiRow ch = rb.chi(pos[d].j);
           const int u0 = pos[d].u0;
-          const double wx = o.lk * (r.kx - qx);
-          const double A = o.lk * r.ky, B = -o.lk * o.sy;
-          const ChiRow ch = chi_row(chi_column(wx, o), A, B, r.kch);
+          const double wx = o.lk * (kc.x - qx);
+          const double A = o.lk * kc.y, B = -o.lk * o.sy;
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
+            if (u0 + 64 * q >= r.len) continue;  // wave-uniform: no entry of the run in this slice
             const int u = u0 + lane + 64 * q;
-            if (u >= r.len) continue;
+            const bool in = u < r.len;
             const int iy = run_iy(r, u);
-            const int my = iy < 0 ? iy + ny : iy;
+            const int my = in ? (iy < 0 ? iy + ny : iy) : 0;
             const double ty = (double)iy;
             const double wy = fma(B, ty, A);
-            const float2 e = expi_reduced(chi_row_eval(ch, ty));
+            const float2 e = expi_rev(chi_row_eval(ch, ty));
             const float2 gq = buf[d][q];
             const float2 z = make_float2(gq.x * e.x - gq.y * e.y, gq.x * e.y + gq.y * e.x);
             const float2 tq = tb[my];
-            double t = (double)(tq.x * (-z.y) + tq.y * z.x);
+            double t = in ? (double)(tq.x * (-z.y) + tq.y * z.x) : 0.0;
             M0 += t;
             t *= wy;
             M1 += t;
@@ -403,7 +413,7 @@ __global__ void __launch_bounds__(64 * kAdjWaves) k_padj(YArgs a, Optics o, int 
             const double wsum = wave_sum_f64(M0);
             if (lane == 0) {
               double bk[8];
-              chi_basis(r.kx, r.ky, o, bk);
+              chi_basis(kc.x, kc.y, o, bk);
 #pragma unroll
               for (int q = 0; q < 8; ++q) dc[q] -= bk[q] * wsum;
             }
@@ -412,7 +422,7 @@ __global__ void __launch_bounds__(64 * kAdjWaves) k_padj(YArgs a, Optics o, int 
           }
         }
         const Round l = it.load_target(nb);
-        load_round<FULLG>(a, rb.at(l.j, false), kd0 + W * l.j, mx, ny, l.u0, lane, buf[d]);
+        load_round<FULLG>(a, rb.at(l.j), kd0 + W * l.j, mx, ny, l.u0, lane, buf[d]);
         pos[d] = it.take(rb);
       }
     }
