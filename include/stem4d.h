@@ -302,7 +302,8 @@ int ssb_reconstruct_com(const int32_t* d_idx, const int64_t* d_off, int64_t fram
  *  STEM_REGION_KC    double2 Kc[kd] (x, y) bin centres in unbinned pixels, after ACCUMULATE.
  *  STEM_REGION_STATS uint64 [4] about the last sum (FINALIZE / REFOCUS): [0] number of (pixel, Q)
  *                    pairs in the double-overlap sets; [1] number of partial sums of T combined
- *                    (pixel groups of the fused column kernels); [2] bytes of row-transformed
+ *                    (pixel groups of the fused column kernels; after a REFOCUS from the stored
+ *                    values, the pieces that sum was cut into, all columns); [2] bytes of row-transformed
  *                    columns or stored G values the sum kernels read; [3] pixel chunks.
  *  STEM_REGION_PG    STEM_G_STORE, after FINALIZE: G on the double-overlap pairs, complex64.  For
  *                    scan-frequency column mx in [0, Nx) and pixel kd the values G(kd, (my, mx)),

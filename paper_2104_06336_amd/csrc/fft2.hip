@@ -19,8 +19,9 @@ namespace stem {
 constexpr int kWaveStride = kFftLds + 4;  // float2 per wave buffer; the +4 staggers LDS banks
 
 // SUM: the input is the sum of a.nparts partial planes (in_mode IN_C64_SUM), read four at a time;
-// a separate instantiation, so that the other input modes keep their lower register count.
-template <int N, bool INV, int W, bool SUM>
+// a separate instantiation, so that the other input modes keep their lower register count.  SEG
+// (with SUM): the partials are segments, row r adding rows a.part_seg[r] .. a.part_seg[r+1]-1.
+template <int N, bool INV, int W, bool SUM, bool SEG = false>
 __global__ void __launch_bounds__(64 * W) k_row_fft(RowFftArgs a, int in_mode, int out_mode) {
   constexpr int kRowThreads = 64 * W;
   __shared__ float2 s_tw[1024];
@@ -62,7 +63,8 @@ __global__ void __launch_bounds__(64 * W) k_row_fft(RowFftArgs a, int in_mode, i
           u += s_red[1][w];
         }
         a.stats[threadIdx.x] = threadIdx.x == 0   ? t
-                               : threadIdx.x == 1 ? (unsigned long long)a.stats_groups
+                               : threadIdx.x == 1 ? (a.part_seg ? (unsigned long long)a.part_seg[a.nrows]
+                                                                : (unsigned long long)a.stats_groups)
                                : threadIdx.x == 2 ? 8ull * u
                                                   : (unsigned long long)a.stats_chunks;
       }
@@ -90,21 +92,43 @@ __global__ void __launch_bounds__(64 * W) k_row_fft(RowFftArgs a, int in_mode, i
           t[i] = r < a.nrows ? src[r * N + n] : make_float2(0.f, 0.f);
         }
       };
-      int p = 0;
-      for (; p + 4 <= a.nparts; p += 4) {
-        float2 t[4][16];
+      if constexpr (SEG) {
+        // segments: row r adds rows part_seg[r] .. part_seg[r + 1] - 1, in order (a lane's 16
+        // elements are of one row); the wave runs to the largest count among its rows
+        int b, n;
+        fft_in_index<N>(lane, 0, b, n);
+        const int64_t r = r0 + b;
+        const int64_t s0 = r < a.nrows ? a.part_seg[r] : 0;
+        const int sn = r < a.nrows ? (int)(a.part_seg[r + 1] - s0) : 0;
+        int most = sn;
+        for (int off = 32; off > 0; off >>= 1) most = max(most, __shfl_xor(most, off));
+        for (int q = 0; q < most; ++q) {
+          float2 t[16];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) load_part(p + k, t[k]);
+          for (int i = 0; i < 16; ++i) {
+            fft_in_index<N>(lane, i, b, n);
+            t[i] = q < sn ? a.in_c[(int64_t)(s0 + q) * N + n] : make_float2(0.f, 0.f);
+          }
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
+          for (int i = 0; i < 16; ++i) v[i] = cadd(v[i], t[i]);
+        }
+      } else {
+        int p = 0;
+        for (; p + 4 <= a.nparts; p += 4) {
+          float2 t[4][16];
 #pragma unroll
-          for (int i = 0; i < 16; ++i) v[i] = cadd(v[i], t[k][i]);
-      }
-      for (; p < a.nparts; ++p) {
-        float2 t[16];
-        load_part(p, t);
+          for (int k = 0; k < 4; ++k) load_part(p + k, t[k]);
 #pragma unroll
-        for (int i = 0; i < 16; ++i) v[i] = cadd(v[i], t[i]);
+          for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) v[i] = cadd(v[i], t[k][i]);
+        }
+        for (; p < a.nparts; ++p) {
+          float2 t[16];
+          load_part(p, t);
+#pragma unroll
+          for (int i = 0; i < 16; ++i) v[i] = cadd(v[i], t[i]);
+        }
       }
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
@@ -190,7 +214,12 @@ static void launch_nw(bool inv, const RowFftArgs& a, int in, int out, hipStream_
   const int64_t tr = W * (1024 / N);
   const int64_t tiles = (a.nrows + tr - 1) / tr;
   const dim3 grid((unsigned)(tiles < 2048 ? tiles : 2048));
-  if (in == IN_C64_SUM) {
+  if (in == IN_C64_SUM && a.part_seg) {
+    if (inv)
+      hipLaunchKernelGGL((k_row_fft<N, true, W, true, true>), grid, dim3(64 * W), 0, s, a, in, out);
+    else
+      hipLaunchKernelGGL((k_row_fft<N, false, W, true, true>), grid, dim3(64 * W), 0, s, a, in, out);
+  } else if (in == IN_C64_SUM) {
     if (inv)
       hipLaunchKernelGGL((k_row_fft<N, true, W, true>), grid, dim3(64 * W), 0, s, a, in, out);
     else
@@ -254,7 +283,8 @@ __global__ void __launch_bounds__(kGenThreads) k_grow_fft(RowFftArgs a, GPlan p,
         u += s_red[1][w];
       }
       a.stats[threadIdx.x] = threadIdx.x == 0   ? t
-                             : threadIdx.x == 1 ? (unsigned long long)a.stats_groups
+                             : threadIdx.x == 1 ? (a.part_seg ? (unsigned long long)a.part_seg[a.nrows]
+                                                              : (unsigned long long)a.stats_groups)
                              : threadIdx.x == 2 ? 8ull * u
                                                 : (unsigned long long)a.stats_chunks;
     }
@@ -275,7 +305,11 @@ __global__ void __launch_bounds__(kGenThreads) k_grow_fft(RowFftArgs a, GPlan p,
         if (in_mode == IN_C64) {
           x = a.in_c[el];
         } else if (in_mode == IN_C64_SUM) {
-          for (int q = 0; q < a.nparts; ++q) x = cadd(x, a.in_c[(int64_t)q * a.part_stride + el]);
+          if (a.part_seg) {
+            for (int64_t q = a.part_seg[r]; q < a.part_seg[r + 1]; ++q) x = cadd(x, a.in_c[q * n + i]);
+          } else {
+            for (int q = 0; q < a.nparts; ++q) x = cadd(x, a.in_c[(int64_t)q * a.part_stride + el]);
+          }
           if (a.norm_cnt) {
             const int32_t cnt = a.norm_cnt[el];
             x = cnt > 0 ? make_float2(x.x / (float)cnt, x.y / (float)cnt) : make_float2(0.f, 0.f);

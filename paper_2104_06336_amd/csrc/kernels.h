@@ -43,6 +43,8 @@ struct RowFftArgs {
                            // IN_HALF_C64: entries 0..n/2 of a Hermitian row at in_c + r*(n/2+1)
   int64_t part_stride;
   int32_t nparts;
+  const int64_t* part_seg; // IN_C64_SUM: if set, row r adds rows part_seg[r] .. part_seg[r+1]-1 of in_c
+                           // (n values each) instead of the nparts planes
   float2* sum_out;         // IN_C64_SUM: if set, the summed input is also stored here (row-major)
   const float* in_f0;      // IN_F32_PAIR: re = in_f0[r*n + j]*s0, im = in_f1[...]*s1 (in_f1 may be null)
   const float* in_f1;

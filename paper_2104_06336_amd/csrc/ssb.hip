@@ -39,14 +39,17 @@ struct SsbLayout {
   int ypix;       // pixels of the column-transform scratch (stored G of the other lengths), or 0
   int nchunks;    // pixel chunks of a sum
   int64_t pcap;   // entries of the pruned G array (0 without STEM_G_STORE)
-  size_t rows, kc, kchi, cst, cmask, lut, stats, npq, D, X, Y, poff, ptot, pg, T, A, Tb, pdc, pdth, part, wcnt, total;
+  size_t rows, kc, kchi, cst, cmask, lut, stats, npq, D, X, Y, poff, ptot, pg, T, A, Tb, pdc, pdth, part, wcnt, pws, pcs,
+      total;
   int nmw;      // 64-bit words per column set of the active-pixel mask
   int groups;   // pixel groups of the fused column kernels (the same for every chunk)
   int pgroups;  // pixel groups of the kernels over the stored double-overlap values
   int ncs;      // column sets (colset_width(Ny) half-spectrum columns each)
   bool fast;    // both scan lengths taken by the fused kernels (powers of two in [32, 1024])
   int64_t nwy;  // waves of the fused kernels
-  int64_t nwp;  // waves of the refocus sum over the stored values
+  int64_t nwp;  // waves of the refocus sum over the full columns of G (other scan lengths)
+  int64_t nws;  // pieces the refocus sum over the stored values aims at
+  int64_t nwq;  // STEM_G_STORE: waves (at most) of the refocus sum over the stored values
   int64_t nwa;  // dL/dc partials of the adjoint over the stored values (one per workgroup)
 };
 
@@ -160,15 +163,29 @@ static size_t make_layout(const stem_det& det, const stem_scan& scan, const stem
     L->pgroups = pg < 1 ? 1 : pg;
     L->nwp = psum_launch_waves(scan.ny, scan.nx, L->pgroups);
     L->nwa = padj_partials(scan.nx, L->pgroups);
+    // the balanced pieces: as many as the GPU holds waves at once (more, one per column with
+    // pairs, when the columns outnumber them)
+    const int w = psum_waves(scan.ny);
+    const int64_t nws = psum_stream_waves(scan.ny);
+    L->nws = nws;
+    L->nwq = L->store ? ((nws > scan.nx ? nws : scan.nx) + w - 1) / w * w : 0;
   }
   int64_t nw = L->nwy > L->nwp ? L->nwy : L->nwp;
+  nw = nw > L->nwq ? nw : L->nwq;
   nw = nw > L->nwa ? nw : L->nwa;
   const int rows = L->ncs > scan.nx ? L->ncs : scan.nx;
   const int parts = L->groups > L->pgroups ? L->groups : L->pgroups;
   L->pdc = o;   o = align256(o + (size_t)nw * 8 * sizeof(double));
   L->pdth = o;  o = align256(o + (size_t)rows * n_k * sizeof(float));
-  L->part = o;  o = align256(o + (size_t)parts * L->F * sizeof(float2));
+  // partials: the fused kernels' and the adjoint's planes, or one row of ny values per piece of
+  // the refocus sum
+  size_t part_rows = (size_t)parts * scan.nx;
+  if (part_rows < (size_t)L->nwq) part_rows = (size_t)L->nwq;
+  L->part = o;  o = align256(o + part_rows * scan.ny * sizeof(float2));
   L->wcnt = o;  o = align256(o + (size_t)nw * sizeof(unsigned long long));
+  // the refocus sum's tables (STEM_G_STORE): per piece its first run and entries, per column
+  L->pws = o;   o = align256(o + (size_t)L->nwq * sizeof(PieceTab));
+  L->pcs = o;   o = align256(o + (L->store ? sizeof(int64_t) * stream_ctab_words(scan.nx) : 0));
   L->total = o;
   return o;
 }
@@ -482,6 +499,8 @@ struct Bufs {
   float* pdth;
   float2* part;
   unsigned long long* wcnt;  // pair counts and loads per wave of the fused kernels
+  PieceTab* pws;             // refocus sum: per piece its first run and entries
+  int64_t* pcs;              // refocus sum: per column its first piece, cost and span of runs
 };
 
 static Bufs carve(void* state, const SsbLayout& L) {
@@ -491,7 +510,7 @@ static Bufs carve(void* state, const SsbLayout& L) {
               (int32_t*)(p + L.npq), (void*)(p + L.D), (float2*)(p + L.X), (float2*)(p + L.Y), (int64_t*)(p + L.poff),
               (int64_t*)(p + L.ptot), (float2*)(p + L.pg), (float2*)(p + L.T), (float2*)(p + L.A), (float2*)(p + L.Tb),
               (double*)(p + L.pdc), (float*)(p + L.pdth), (float2*)(p + L.part),
-              (unsigned long long*)(p + L.wcnt)};
+              (unsigned long long*)(p + L.wcnt), (PieceTab*)(p + L.pws), (int64_t*)(p + L.pcs)};
 }
 
 static int check_common(const stem_det* det, const stem_scan* scan, const stem_optics* optics,
@@ -586,8 +605,11 @@ static int colfft_generic(const SsbLayout& L, int ny, int k0, int k1, const floa
 // T = sum of the partial sums (column-major [mx][my]), divided by the pair count of each Q when
 // npq is given; phi = Im IFFT2(T); d_T row-major.  The fused kernels' per-wave counters become the
 // state's counters.
+// part_seg: the partials are the rows of the refocus sum's pieces (row mx of T adds rows
+// part_seg[mx] .. part_seg[mx + 1] - 1 of b.part) instead of nparts planes
 static int run_phase(const SsbLayout& L, const Bufs& b, const stem_scan& sc, int nparts, int64_t nwaves, int nchunks,
-                     const int32_t* npq, float* d_phase, float* d_T, hipStream_t s) {
+                     const int32_t* npq, float* d_phase, float* d_T, hipStream_t s,
+                     const int64_t* part_seg = nullptr) {
   const int ny = sc.ny, nx = sc.nx;
   RowFftArgs a{};
   // inverse along my of each mx row of T -> A[ry][mx]; the summed T is kept in the state
@@ -595,6 +617,7 @@ static int run_phase(const SsbLayout& L, const Bufs& b, const stem_scan& sc, int
   a.in_c = b.part;
   a.nparts = nparts;
   a.part_stride = L.F;
+  a.part_seg = part_seg;
   a.sum_out = b.T;
   a.norm_cnt = npq;
   a.out_c = b.A;
@@ -648,6 +671,13 @@ static int run_prune_offsets(const SsbLayout& L, const Bufs& b, int nx, int32_t*
   hipLaunchKernelGGL(k_prune_bases, dim3(1), dim3(256), 0, s, L.n_k, nx, b.poff, b.ptot, L.pcap, d_status);
   STEM_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_prune_add, dim3((unsigned)nx), dim3(256), 0, s, L.n_k, b.poff, b.ptot);
+  STEM_LAUNCH_CHECK();
+  // the tables of the refocus sum in balanced pieces
+  hipLaunchKernelGGL(k_stream_cols, dim3((unsigned)nx), dim3(256), 0, s, L.n_k, b.poff, nx, b.pcs);
+  STEM_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_stream_colseg, dim3(1), dim3(256), 0, s, nx, (int)L.nws, b.pcs);
+  STEM_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_stream_waves, dim3((unsigned)nx), dim3(256), 0, s, L.n_k, b.poff, nx, b.pcs, b.pws);
   STEM_LAUNCH_CHECK();
   return STEM_OK;
 }
@@ -755,8 +785,8 @@ static int reconstruct(const int32_t* d_idx, const int64_t* d_off, int64_t frame
     a.ngroups = L.pgroups;
     a.kch_inline = 1;
     a.theta = d_theta;
-    if ((st = launch_psum(ny, a, o, chi0, false, false, s))) return st;
-    return run_phase(L, b, *scan, L.pgroups, L.nwp, 1, ssb->normalize ? b.npq : nullptr, d_phase, d_T, s);
+    if ((st = launch_psum_stream(ny, a, o, chi0, (int)L.nwq, b.pws, b.pcs, s))) return st;
+    return run_phase(L, b, *scan, L.pgroups, L.nwq, 1, ssb->normalize ? b.npq : nullptr, d_phase, d_T, s, b.pcs);
   } else if (!L.fast) {
     // the other scan lengths: row and column transforms by the generic FFT, then Eq. 3 per
     // (pixel, column) run over the full columns of G, chunk by chunk

@@ -32,6 +32,7 @@ struct RunDesc {
   int32_t a0;     // signed row frequency of the first entry
   int32_t split;  // entries before the hole of the set
   int32_t hl;     // hole length (0: none)
+  int32_t lo;     // first entry of the run taken (entries [lo, len) are summed)
   double kx, ky;  // Kc
   ChiRow ch;      // the phase of the pixel's pairs in this column, in revolutions, by row index
 };
@@ -64,7 +65,7 @@ __device__ __forceinline__ RunDesc gather_run(const YArgs& a, const Optics& o, i
   const int nx = a.nx, nc = nx / 2 + 1;
   const bool mir = 2 * mx > nx;
   const int c = mir ? nx - mx : mx;
-  RunDesc d{0, 0, 0, 0, 0, 0.0, 0.0, ChiRow{0.0, 0.0, 0.0, 0.0, 0.0}};
+  RunDesc d{0, 0, 0, 0, 0, 0, 0.0, 0.0, ChiRow{0.0, 0.0, 0.0, 0.0, 0.0}};
   if (lane < nb) {
     const int kd = kd0 + lane * stride;
     ColSet sd, sm;
@@ -121,8 +122,10 @@ struct RunBatch {
     r.a0 = rl(d.a0, j);
     r.split = rl(d.split, j);
     r.hl = rl(d.hl, j);
+    r.lo = rl(d.lo, j);
     return r;
   }
+  __device__ __forceinline__ int lo(int j) const { return rl(d.lo, j); }
   __device__ __forceinline__ ChiRow chi(int j) const {
     return ChiRow{rld(d.ch.p0, j), rld(d.ch.p1, j), rld(d.ch.p2, j), rld(d.ch.p3, j), rld(d.ch.p4, j)};
   }
@@ -135,7 +138,7 @@ struct RunBatch {
 };
 
 __device__ __forceinline__ RunBatch make_batch(const RunDesc& d, int nb) {
-  return RunBatch{d, (uint64_t)__ballot(d.len > 0), nb};
+  return RunBatch{d, (uint64_t)__ballot(d.len > d.lo), nb};
 }
 
 // Signed row frequency of entry u of run r.
@@ -176,7 +179,8 @@ struct Round {
 __device__ __forceinline__ Round next_round(const RunBatch& rb, Round r) {
   if (r.j >= rb.nb) return r;
   if (r.u0 + 256 < rb.len(r.j)) return Round{r.j, r.u0 + 256};
-  return Round{rb.next(r.j), 0};
+  const int j = rb.next(r.j);
+  return Round{j, j < rb.nb ? rb.lo(j) : 0};
 }
 
 // The rounds of a batch in order.  `at` is the next round to load; `safe` the last real one, whose
@@ -224,16 +228,79 @@ __device__ __forceinline__ WavePixels wave_pixels(int kd_a, int kd_b, int w, int
   return WavePixels{kd_a + w, n > 0 ? (n + W - 1) / W : 0};
 }
 
-// T of column mx over the pixels of group g from the stored values.  CHI0: every phase factor is
-// exactly 1.  The rounds go through kSumDepth register slots: slot d is summed, then refilled
-// with the next round's loads, so kSumDepth - 1 rounds are in flight while one is summed.  A
-// round's slices of 64 entries with no entry of the run are skipped (a wave-uniform test); inside
-// a slice every lane works, and the lanes past the run's end read and write the wave's spare LDS
-// slot, so the LDS accesses of a round issue back to back with no divergent branch between them.
+// Adds the runs of a batch (pixels kb + j, column mx), times their phase factors, into the wave's
+// column t of T.  CHI0: every phase factor is exactly 1.  The rounds go through kSumDepth register
+// slots: slot d is summed, then refilled with the next round's loads, so kSumDepth - 1 rounds are
+// in flight while one is summed.  A round's slices of 64 entries with no entry of the run are
+// skipped (a wave-uniform test); inside a slice every lane works, and the lanes past the run's end
+// read and write the wave's spare LDS slot t[ny], so the LDS accesses of a round issue back to back
+// with no divergent branch between them.  Returns the pairs added.
+template <bool CHI0, bool FULLG, bool PWRITE>
+__device__ __forceinline__ unsigned long long sum_batch(const YArgs& a, const RunBatch& rb, int kb, int mx, int ny,
+                                                        int lane, float2* t) {
+  constexpr int D = kSumDepth;
+  const int nb = rb.nb;
+  unsigned long long cnt = 0;
+  const int j0 = rb.next(-1);
+  if (j0 >= nb) return 0;
+  Round pos[D];
+  float2 buf[D][4];
+  const Round r0{j0, rb.lo(j0)};
+  RoundCursor it{r0, r0};
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    const Round l = it.load_target(nb);
+    load_round<FULLG>(a, rb.at(l.j), kb + l.j, mx, ny, l.u0, lane, buf[d]);
+    pos[d] = it.take(rb);
+  }
+  while (pos[0].j < nb) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      if (pos[d].j < nb) {
+        const RunDesc r = rb.at(pos[d].j);
+        const int u0 = pos[d].u0;
+        if (u0 == r.lo) cnt += (unsigned long long)(r.len - r.lo);
+        ChiRow ch{};
+        if constexpr (!CHI0) ch = rb.chi(pos[d].j);
+        int ad[4];
+        float2 val[4], tv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int u = u0 + lane + 64 * q;
+          const int iy = run_iy(r, u);
+          ad[q] = u < r.len ? (iy < 0 ? iy + ny : iy) : ny;
+          val[q] = buf[d][q];
+          if (u0 + 64 * q < r.len) {
+            if constexpr (PWRITE) {
+              if (u < r.len && r.e0 + u < a.pcap) a.pgw[r.e0 + u] = val[q];
+            }
+            if constexpr (!CHI0) {
+              const float2 e = expi_rev(chi_row_eval(ch, (double)iy));
+              const float2 x = val[q];
+              val[q] = make_float2(x.x * e.x - x.y * e.y, x.x * e.y + x.y * e.x);
+            }
+          }
+        }
+        // the entries of a round are distinct row frequencies of one run: read all, then write
+#pragma unroll
+        for (int q = 0; q < 4; ++q) tv[q] = t[ad[q]];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) t[ad[q]] = cadd(tv[q], val[q]);
+      }
+      const Round l = it.load_target(nb);
+      load_round<FULLG>(a, rb.at(l.j), kb + l.j, mx, ny, l.u0, lane, buf[d]);
+      pos[d] = it.take(rb);
+    }
+  }
+  return cnt;
+}
+
+// T of column mx over the pixels of group g (the sums of the scan lengths the fused kernels do not
+// take, from full columns of G, chunk by chunk): the partial T of the group goes to part[g]
+// (column-major [mx][my], summed by the phase pass like the fused sum's).
 template <bool CHI0, bool FULLG, bool PWRITE>
 __global__ void __launch_bounds__(64 * kPrunedCols) k_psum(YArgs a, Optics o, int ny) {
   extern __shared__ __align__(16) unsigned char s_dyn[];
-  constexpr int D = kSumDepth;
   const int W = blockDim.x >> 6;
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   float2* t = (float2*)(s_dyn + (size_t)wave * pruned_wave_lds(ny));
@@ -252,61 +319,242 @@ __global__ void __launch_bounds__(64 * kPrunedCols) k_psum(YArgs a, Optics o, in
     const int kb = wp.kd_a + i0;
     const int nb = min(64, wp.count - i0);
     const RunBatch rb = make_batch(gather_run(a, o, kb, 1, nb, mx, lane, !CHI0, FULLG), nb);
-    const int j0 = rb.next(-1);
-    if (j0 >= nb) continue;
-    Round pos[D];
-    float2 buf[D][4];
-    RoundCursor it{Round{j0, 0}, Round{j0, 0}};
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-      const Round l = it.load_target(nb);
-      load_round<FULLG>(a, rb.at(l.j), kb + l.j, mx, ny, l.u0, lane, buf[d]);
-      pos[d] = it.take(rb);
-    }
-    while (pos[0].j < nb) {
-#pragma unroll
-      for (int d = 0; d < D; ++d) {
-        if (pos[d].j < nb) {
-          const RunDesc r = rb.at(pos[d].j);
-          const int u0 = pos[d].u0;
-          if (u0 == 0) cnt += (unsigned long long)r.len;
-          ChiRow ch{};
-          if constexpr (!CHI0) ch = rb.chi(pos[d].j);
-          int ad[4];
-          float2 val[4], tv[4];
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int u = u0 + lane + 64 * q;
-            const int iy = run_iy(r, u);
-            ad[q] = u < r.len ? (iy < 0 ? iy + ny : iy) : ny;
-            val[q] = buf[d][q];
-            if (u0 + 64 * q < r.len) {
-              if constexpr (PWRITE) {
-                if (u < r.len && r.e0 + u < a.pcap) a.pgw[r.e0 + u] = val[q];
-              }
-              if constexpr (!CHI0) {
-                const float2 e = expi_rev(chi_row_eval(ch, (double)iy));
-                const float2 x = val[q];
-                val[q] = make_float2(x.x * e.x - x.y * e.y, x.x * e.y + x.y * e.x);
-              }
-            }
-          }
-          // the entries of a round are distinct row frequencies of one run: read all, then write
-#pragma unroll
-          for (int q = 0; q < 4; ++q) tv[q] = t[ad[q]];
-#pragma unroll
-          for (int q = 0; q < 4; ++q) t[ad[q]] = cadd(tv[q], val[q]);
-        }
-        const Round l = it.load_target(nb);
-        load_round<FULLG>(a, rb.at(l.j), kb + l.j, mx, ny, l.u0, lane, buf[d]);
-        pos[d] = it.take(rb);
-      }
-    }
+    cnt += sum_batch<CHI0, FULLG, PWRITE>(a, rb, kb, mx, ny, lane, t);
   }
   float2* pgp = a.part + (int64_t)g * nx * ny + (int64_t)mx * ny;
   for (int i = lane; i < ny; i += 64) pgp[i] = a.accumulate ? cadd(pgp[i], t[i]) : t[i];
   unsigned long long cc = cnt + (cnt << kLoadShift);  // one 8-byte load per pair
   if (lane == 0) a.wcnt[wid] = a.accumulate ? a.wcnt[wid] + cc : cc;
+}
+
+// Refocus sum in balanced pieces.  The pruned array is column-major (the runs of a column's pixels
+// follow one another), so a column's values are one contiguous stretch.  Each column is cut into
+// pieces of equal cost, cost = entries + kRunCost per run with entries (a run costs at least one
+// round whatever its length), the cost per piece Cc the same for every column (about total cost /
+// nws, see k_stream_colseg); one wave sums one piece.  Every wave thus does about the same work (a column of few
+// pairs is one short piece), and no wave leaves its column: its partial T is one row of ny values
+// at part + w ny, the pieces of column mx being the waves colseg[mx] .. colseg[mx + 1] - 1, which
+// the phase pass adds in order.
+constexpr int64_t kRunCost = 192;
+
+// Per wave (tables from k_stream_*): the run (mx n_k + kd) holding its first entry, then its
+// entries [E0, E1) of the array.
+struct PieceTab {
+  int64_t run, e0, e1;
+};
+
+// Table of the columns, ctab (int64): colseg [nx + 1], then the cost per piece, then per column
+// its cost and the span [first, last + 1) of its runs with entries (run indices), [nx][3].
+__host__ __device__ inline size_t stream_ctab_words(int nx) { return (size_t)(nx + 1) + 1 + 3 * (size_t)nx; }
+
+template <bool CHI0>
+__global__ void __launch_bounds__(64 * kPrunedCols) k_psum_stream(YArgs a, Optics o, int ny, int nwmax,
+                                                                  const PieceTab* __restrict__ wtab,
+                                                                  const int64_t* __restrict__ ctab) {
+  extern __shared__ __align__(16) unsigned char s_dyn[];
+  const int W = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  float2* t = (float2*)(s_dyn + (size_t)wave * pruned_wave_lds(ny));
+  const int nx = a.nx, n_k = a.n_k, nc = nx / 2 + 1;
+  const int64_t wid = (int64_t)blockIdx.x * W + wave;
+  if (wid >= nwmax || wid >= ctab[nx]) {
+    if (lane == 0 && wid < nwmax) a.wcnt[wid] = 0ull;
+    return;
+  }
+  const PieceTab pc = wtab[wid];
+  const int64_t E0 = pc.e0, E1 = pc.e1;
+  int64_t i = pc.run;
+  const int mx = (int)(i / n_k);
+  const int64_t cend = ctab[(nx + 2) + 3 * (int64_t)mx + 2];
+  const bool mir = 2 * mx > nx;
+  const int c = mir ? nx - mx : mx;
+  double qx = 0.0;
+  if (!CHI0) qx = (double)signed_index(mx, nx) * o.sx;
+  for (int k = lane; k < ny; k += 64) t[k] = make_float2(0.f, 0.f);
+  unsigned long long cnt = 0;
+  while (true) {
+    // runs [i, i + nb) of column mx, clipped to the piece
+    const int nb = (int)min((int64_t)64, cend - i);
+    RunDesc d{0, 0, 0, 0, 0, 0, 0.0, 0.0, ChiRow{0.0, 0.0, 0.0, 0.0, 0.0}};
+    int64_t e1raw = 0;
+    if (lane < nb) {
+      const int kd = (int)(i + lane - (int64_t)mx * n_k);
+      ColSet sd, sm;
+      load_colsets(a.cst, (int64_t)kd * nc + c, sd, sm);
+      const ColSet st = mir ? sm : sd;
+      const int h0 = max(st.a0, st.b0), h1 = min(st.a1, st.b1);
+      const int64_t e0 = a.poff[i + lane], e1 = a.poff[i + lane + 1];
+      e1raw = e1;
+      if (e0 >= 0 && e1 >= e0 && e1 <= a.pcap) {
+        d.e0 = e0;
+        d.lo = (int)(max(e0, E0) - e0);
+        d.len = max(d.lo, (int)(min(e1, E1) - e0));
+      }
+      d.a0 = st.a0;
+      d.hl = h0 <= h1 ? h1 - h0 + 1 : 0;
+      d.split = h0 - st.a0;
+      if (!CHI0) {
+        const double2 k = a.kc[kd];
+        const double kch = chi_poly(k.x, k.y, o) + (a.theta ? (double)a.theta[kd] : 0.0);
+        d.ch = chi_row(chi_column(o.lk * (k.x - qx), o), o.lk * k.y, -o.lk * o.sy, kch);
+      }
+    }
+    const RunBatch rb = make_batch(d, nb);
+    cnt += sum_batch<CHI0, false, false>(a, rb, 0, mx, ny, lane, t);
+    i += nb;
+    if (RunBatch::rl64(e1raw, nb - 1) >= E1 || i >= cend) break;
+  }
+  float2* dst = a.part + wid * ny;
+  for (int k = lane; k < ny; k += 64) dst[k] = t[k];
+  unsigned long long cc = cnt + (cnt << kLoadShift);  // one 8-byte load per pair
+  if (lane == 0) a.wcnt[wid] = cc;
+}
+
+// The cost of the runs [r0, r0 + n) of the array (offsets poff): entries + kRunCost per non-empty run.
+__device__ __forceinline__ int64_t runs_cost(const int64_t* __restrict__ poff, int64_t r0, int n) {
+  int64_t c = 0;
+  for (int k = 0; k < n; ++k) {
+    const int64_t len = poff[r0 + k + 1] - poff[r0 + k];
+    c += len > 0 ? len + kRunCost : 0;
+  }
+  return c;
+}
+
+// Per column (workgroup; thread j takes the pixels [j q, (j + 1) q), q = ceil(n_k / 256)): its cost
+// and the span of its runs with entries.
+__global__ void __launch_bounds__(256) k_stream_cols(int n_k, const int64_t* __restrict__ poff, int nx,
+                                                     int64_t* __restrict__ ctab) {
+  __shared__ int64_t s_cost[256];
+  __shared__ int s_lo, s_hi;
+  const int mx = blockIdx.x;
+  if (threadIdx.x == 0) {
+    s_lo = n_k;
+    s_hi = -1;
+  }
+  const int q = (n_k + 255) / 256, k0 = min((int)threadIdx.x * q, n_k), k1 = min(k0 + q, n_k);
+  const int64_t r0 = (int64_t)mx * n_k;
+  int lo = n_k, hi = -1;
+  for (int kd = k0; kd < k1; ++kd)
+    if (poff[r0 + kd + 1] > poff[r0 + kd]) {
+      lo = min(lo, kd);
+      hi = max(hi, kd);
+    }
+  s_cost[threadIdx.x] = runs_cost(poff, r0 + k0, k1 - k0);
+  __syncthreads();
+  atomicMin(&s_lo, lo);
+  atomicMax(&s_hi, hi);
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) s_cost[threadIdx.x] += s_cost[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    int64_t* col = ctab + (nx + 2) + 3 * (int64_t)mx;
+    col[0] = s_cost[0];
+    col[1] = s_hi >= 0 ? r0 + s_lo : 0;
+    col[2] = s_hi >= 0 ? r0 + s_hi + 1 : 0;
+  }
+}
+
+// One workgroup: the cost per piece Cc and colseg, the exclusive scan of the pieces per column
+// ceil(cost / Cc).  Cc is the smallest of 256 candidates spread over [total / nws, total /
+// (nws - nx)] (the second always gives at most nws pieces, as the pieces number at most
+// total / Cc + nx) for which the pieces number at most nws, so that the launch's nws waves (the
+// waves the GPU holds at once) each sum one piece and every compute unit gets the same work.
+__global__ void __launch_bounds__(256) k_stream_colseg(int nx, int nws, int64_t* __restrict__ ctab) {
+  __shared__ int64_t s_sum[256];
+  __shared__ int64_t s_cost[4096];
+  const int64_t* col = ctab + (nx + 2);
+  for (int mx = threadIdx.x; mx < nx; mx += 256) s_cost[mx] = col[3 * mx];
+  int64_t tot = 0;
+  for (int mx = threadIdx.x; mx < nx; mx += 256) tot += col[3 * mx];
+  s_sum[threadIdx.x] = tot;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) s_sum[threadIdx.x] += s_sum[threadIdx.x + off];
+    __syncthreads();
+  }
+  const int64_t total = s_sum[0];
+  __syncthreads();
+  int64_t Cc = 1;
+  if (total > 0) {
+    const int64_t lo = (total + nws - 1) / nws;
+    const int64_t hi = nws > nx ? (total + (nws - nx) - 1) / (nws - nx) : total;
+    // candidate t: lo + t (hi - lo) / 255; feasible when its pieces number at most nws
+    const int64_t c = hi > lo ? lo + (int64_t)threadIdx.x * (hi - lo) / 255 : hi;
+    int64_t n = 0;
+    for (int mx = 0; mx < nx; ++mx) n += (s_cost[mx] + c - 1) / c;
+    s_sum[threadIdx.x] = n <= nws || threadIdx.x == 255 ? c : INT64_MAX;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+      if (threadIdx.x < off) s_sum[threadIdx.x] = min(s_sum[threadIdx.x], s_sum[threadIdx.x + off]);
+      __syncthreads();
+    }
+    Cc = s_sum[0];
+    __syncthreads();
+  }
+  const int per = (nx + 255) / 256, m0 = threadIdx.x * per;
+  int64_t n = 0;
+  for (int mx = m0; mx < m0 + per && mx < nx; ++mx) n += (s_cost[mx] + Cc - 1) / Cc;
+  s_sum[threadIdx.x] = n;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const int64_t v = threadIdx.x >= off ? s_sum[threadIdx.x - off] : 0;
+    __syncthreads();
+    s_sum[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int64_t base = s_sum[threadIdx.x] - n;
+  for (int mx = m0; mx < m0 + per && mx < nx; ++mx) {
+    ctab[mx] = base;
+    base += (s_cost[mx] + Cc - 1) / Cc;
+  }
+  if (threadIdx.x == 255) {
+    ctab[nx] = s_sum[255];
+    ctab[nx + 1] = Cc;
+  }
+}
+
+// Per column (workgroup): the pieces' first runs and entry ranges.  Piece p of column mx starts at
+// cost p Cc of the column; inside run r (cost [c_r, c_r + kRunCost + len)) that is entry
+// max(0, p Cc - c_r - kRunCost) of the run.  Piece p ends where piece p + 1 starts, the last at
+// the column's end.
+__global__ void __launch_bounds__(256) k_stream_waves(int n_k, const int64_t* __restrict__ poff, int nx,
+                                                      const int64_t* __restrict__ ctab, PieceTab* __restrict__ wtab) {
+  __shared__ int64_t s_pre[256];
+  const int mx = blockIdx.x;
+  const int64_t* col = ctab + (nx + 2) + 3 * (int64_t)mx;
+  const int64_t ccost = col[0], Cc = ctab[nx + 1], seg0 = ctab[mx];
+  if (ccost == 0) return;
+  const int64_t npieces = (ccost + Cc - 1) / Cc;
+  const int q = (n_k + 255) / 256, k0 = min((int)threadIdx.x * q, n_k), k1 = min(k0 + q, n_k);
+  const int64_t r0 = (int64_t)mx * n_k;
+  const int64_t mine = runs_cost(poff, r0 + k0, k1 - k0);
+  s_pre[threadIdx.x] = mine;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const int64_t v = threadIdx.x >= off ? s_pre[threadIdx.x - off] : 0;
+    __syncthreads();
+    s_pre[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int64_t cr = s_pre[threadIdx.x] - mine;  // cost before this thread's first run
+  for (int kd = k0; kd < k1; ++kd) {
+    const int64_t e0 = poff[r0 + kd], len = poff[r0 + kd + 1] - e0;
+    if (len <= 0) continue;
+    const int64_t c1 = cr + kRunCost + len;
+    // the pieces starting inside this run's cost range [cr, c1)
+    for (int64_t p = (cr + Cc - 1) / Cc; p < npieces && p * Cc < c1; ++p) {
+      const int64_t e = e0 + max((int64_t)0, p * Cc - cr - kRunCost);
+      wtab[seg0 + p].run = r0 + kd;
+      wtab[seg0 + p].e0 = e;
+      if (p > 0) wtab[seg0 + p - 1].e1 = e;
+    }
+    cr = c1;
+  }
+  if (threadIdx.x == 255) {
+    const int64_t ce = mx + 1 < nx ? poff[r0 + n_k] : poff[(int64_t)nx * n_k];
+    wtab[seg0 + npieces - 1].e1 = ce;
+  }
 }
 
 // FP64 sum over the 64 lanes of a wave (every lane active), returned to every lane
@@ -480,6 +728,30 @@ inline int launch_psum(int ny, const YArgs& a, const Optics& o, int chi0, bool f
   } else {
     chi0 ? go(T_{}, T_{}, F_{}) : go(F_{}, T_{}, F_{});
   }
+  STEM_LAUNCH_CHECK();
+  return STEM_OK;
+}
+
+// Waves of the refocus sum in balanced pieces: the waves MI355X holds at once (256 compute units;
+// per unit the workgroups its 160 KB of LDS holds, at most 5 waves per SIMD by registers), so
+// that all of them run together and every unit gets the same number of pieces.
+inline int64_t psum_stream_waves(int ny) {
+  const int w = psum_waves(ny);
+  const int64_t per_cu = (int64_t)((160u << 10) / ((size_t)w * pruned_wave_lds(ny))) * w;
+  return 256 * (per_cu < 20 ? per_cu : 20);
+}
+
+// the refocus sum over the stored values in balanced pieces: nwmax waves at most
+inline int launch_psum_stream(int ny, const YArgs& a, const Optics& o, int chi0, int nwmax, const PieceTab* wtab,
+                              const int64_t* ctab, hipStream_t s) {
+  const int w = psum_waves(ny);
+  const size_t lds = (size_t)w * pruned_wave_lds(ny);
+  const dim3 grid((unsigned)((nwmax + w - 1) / w)), blk(64 * w);
+  STEM_TRACE("ssb_reduce", s);
+  if (chi0)
+    hipLaunchKernelGGL(k_psum_stream<true>, grid, blk, lds, s, a, o, ny, nwmax, wtab, ctab);
+  else
+    hipLaunchKernelGGL(k_psum_stream<false>, grid, blk, lds, s, a, o, ny, nwmax, wtab, ctab);
   STEM_LAUNCH_CHECK();
   return STEM_OK;
 }

@@ -190,6 +190,8 @@ def test_pair_count_matches_oracle(gpu, name):
     torch.cuda.synchronize()
     s = st.stats()
     assert s[0] == P and 0 < s[2] <= 8 * P  # the refocus reads stored pairs only
+    # the refocus sum's pieces: at least one per column with pairs, at most the waves the GPU holds
+    assert (npair.sum(axis=0) > 0).sum() <= s[1] <= max(256 * 20, nx)
     # the adjoint leaves the counters of the last sum
     phase = torch.zeros(wl.n_frames, dtype=torch.float32, device="cuda")
     st.refocus(c=wl.aberr, phase=phase)
