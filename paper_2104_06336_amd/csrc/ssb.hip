@@ -423,6 +423,7 @@ constexpr int kFinalDcBlocks = 8;
 
 __global__ void __launch_bounds__(256) k_adjoint_final(const double* __restrict__ pdc, int64_t npdc,
                                                        const float* __restrict__ pdth, int64_t npdth, int n_k,
+                                                       const int64_t* __restrict__ pieces,
                                                        double* __restrict__ dLdc, float* __restrict__ dLdth) {
   if (blockIdx.x < kFinalDcBlocks) {
     __shared__ double s[256];
@@ -450,11 +451,16 @@ __global__ void __launch_bounds__(256) k_adjoint_final(const double* __restrict_
   if (!dLdth || kd >= n_k) return;  // uniform per wave
   double a0 = 0.0, a1 = 0.0;
   int64_t r = lane;
+  // with pieces (the adjoint over the stored values): a column without pieces has no pairs and
+  // its row of pdth is not written, it adds 0
+  auto row = [&](int64_t q) -> double {
+    return pieces && pieces[q + 1] == pieces[q] ? 0.0 : (double)pdth[q * n_k + kd];
+  };
   for (; r + 64 < npdth; r += 128) {
-    a0 += (double)pdth[r * n_k + kd];
-    a1 += (double)pdth[(r + 64) * n_k + kd];
+    a0 += row(r);
+    a1 += row(r + 64);
   }
-  for (; r < npdth; r += 64) a0 += (double)pdth[r * n_k + kd];
+  for (; r < npdth; r += 64) a0 += row(r);
   double v = a0 + a1;
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
   if (lane == 0) dLdth[kd] = (float)v;
@@ -678,6 +684,9 @@ static int run_prune_offsets(const SsbLayout& L, const Bufs& b, int nx, int32_t*
   hipLaunchKernelGGL(k_stream_colseg, dim3(1), dim3(256), 0, s, nx, (int)L.nws, b.pcs);
   STEM_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_stream_waves, dim3((unsigned)nx), dim3(256), 0, s, L.n_k, b.poff, nx, b.pcs, b.pws);
+  STEM_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_stream_runs, dim3((unsigned)((L.nwq + 255) / 256)), dim3(256), 0, s, L.n_k, b.poff, nx, b.pcs,
+                     b.pws);
   STEM_LAUNCH_CHECK();
   return STEM_OK;
 }
@@ -1086,13 +1095,14 @@ extern "C" int ssb_backward(const float* d_dLdphi, const stem_det* det, const st
   if (!L.store && (st = run_chi_table(b, d_theta, n_k, o, s))) return st;
   YArgs y = yargs(L, b, nx);
   int64_t npdc = L.nwy, npdth = L.ncs;
+  const int64_t* pieces = nullptr;
   if (L.store) {
-    y.ngroups = L.pgroups;
     y.kch_inline = 1;
     y.theta = d_theta;
-    if ((st = launch_padj(ny, y, o, false, s))) return st;
-    npdc = L.nwa;
+    if ((st = launch_padj_stream(ny, y, o, (int)L.nwq, b.pws, b.pcs, s))) return st;
+    npdc = L.nwq;
     npdth = nx;
+    pieces = b.pcs;
   } else if (!L.fast) {
     y.ngroups = L.pgroups;
     for (int ch = 0; ch < L.nchunks; ++ch) {
@@ -1123,7 +1133,7 @@ extern "C" int ssb_backward(const float* d_dLdphi, const stem_det* det, const st
   {
     STEM_TRACE("ssb_adjoint_final", s);
     hipLaunchKernelGGL(k_adjoint_final, dim3(kFinalDcBlocks + (n_k + 3) / 4), dim3(256), 0, s, b.pdc, npdc, b.pdth,
-                       npdth, n_k, d_dLdc, d_dLdtheta);
+                       npdth, n_k, pieces, d_dLdc, d_dLdtheta);
   }
   STEM_LAUNCH_CHECK();
   return STEM_OK;

@@ -48,7 +48,10 @@ constexpr int kAdjWaves = 4;
 #define STEM_SUM_DEPTH 4
 #endif
 constexpr int kSumDepth = STEM_SUM_DEPTH;  // rounds in flight per wave, refocus sum
-constexpr int kAdjDepth = 3;     // rounds in flight per wave, adjoint
+#ifndef STEM_ADJ_DEPTH
+#define STEM_ADJ_DEPTH 3
+#endif
+constexpr int kAdjDepth = STEM_ADJ_DEPTH;  // rounds in flight per wave, adjoint
 
 // LDS bytes of one refocus wave: its column of T and a spare slot (the target of the lanes past a
 // run's end), padded to 16 bytes
@@ -337,10 +340,12 @@ __global__ void __launch_bounds__(64 * kPrunedCols) k_psum(YArgs a, Optics o, in
 // the phase pass adds in order.
 constexpr int64_t kRunCost = 192;
 
-// Per wave (tables from k_stream_*): the run (mx n_k + kd) holding its first entry, then its
-// entries [E0, E1) of the array.
+// Per piece (tables from k_stream_*): the run (mx n_k + kd) holding its first entry, its entries
+// [E0, E1) of the array, and for the adjoint the whole runs [ra, rb) whose first entry lies in
+// [E0, E1) (the column's first piece from the column's first run, the last to its last, so that
+// the pieces of a column take each of its runs once, empty ones included).
 struct PieceTab {
-  int64_t run, e0, e1;
+  int64_t run, e0, e1, ra, rb;
 };
 
 // Table of the columns, ctab (int64): colseg [nx + 1], then the cost per piece, then per column
@@ -563,6 +568,98 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
   return v;
 }
 
+// Adds the adjoint terms of a batch's runs (pixels kd0 + stride j, column mx) to dc and returns
+// on lane j -(sum of w) of run j (0 without pairs).  tb: the column of Tbar in LDS.  Rounds are
+// pipelined through kAdjDepth register slots as in sum_batch; the moments of a run carry over its
+// consecutive rounds.
+template <bool FULLG>
+__device__ __forceinline__ float adj_batch(const YArgs& a, const Optics& o, const RunBatch& rb, int kd0, int stride,
+                                           int mx, int ny, int lane, const float2* tb, double qx, double s2pi,
+                                           double* dc) {
+  constexpr int D = kAdjDepth;
+  const int nb = rb.nb;
+  float wth = 0.f;
+  const int j0 = rb.next(-1);
+  Round pos[D];
+  float2 buf[D][4];
+  RoundCursor it{Round{j0, 0}, Round{j0, 0}};
+  if (j0 < nb) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const Round l = it.load_target(nb);
+      load_round<FULLG>(a, rb.at(l.j), kd0 + stride * l.j, mx, ny, l.u0, lane, buf[d]);
+      pos[d] = it.take(rb);
+    }
+  } else {
+    pos[0] = Round{nb, 0};
+  }
+  double M0 = 0.0, M1 = 0.0, M2 = 0.0, M3 = 0.0, M4 = 0.0;
+  while (pos[0].j < nb) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      if (pos[d].j < nb) {
+        const RunDesc r = rb.at(pos[d].j);
+        const double2 kc = rb.kc(pos[d].j);
+        const ChiRow ch = rb.chi(pos[d].j);
+        const int u0 = pos[d].u0;
+        const double wx = o.lk * (kc.x - qx);
+        const double A = o.lk * kc.y, B = -o.lk * o.sy;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (u0 + 64 * q >= r.len) continue;  // wave-uniform: no entry of the run in this slice
+          const int u = u0 + lane + 64 * q;
+          const bool in = u < r.len;
+          const int iy = run_iy(r, u);
+          const int my = in ? (iy < 0 ? iy + ny : iy) : 0;
+          const double ty = (double)iy;
+          const double wy = fma(B, ty, A);
+          const float2 e = expi_rev(chi_row_eval(ch, ty));
+          const float2 gq = buf[d][q];
+          const float2 z = make_float2(gq.x * e.x - gq.y * e.y, gq.x * e.y + gq.y * e.x);
+          const float2 tq = tb[my];
+          double t = in ? (double)(tq.x * (-z.y) + tq.y * z.x) : 0.0;
+          M0 += t;
+          t *= wy;
+          M1 += t;
+          t *= wy;
+          M2 += t;
+          t *= wy;
+          M3 += t;
+          t *= wy;
+          M4 += t;
+        }
+        if (u0 + 256 >= r.len) {
+          // last round of the run: this lane's sum over its pairs of w B_j(K - Q), B_j as
+          // polynomials in wy
+          const double x2 = wx * wx, x3 = x2 * wx, x4 = x2 * x2;
+          dc[0] += 0.5 * s2pi * (x2 * M0 + M2);
+          dc[1] += 0.5 * s2pi * (x2 * M0 - M2);
+          dc[2] += s2pi * (wx * M1);
+          dc[3] += (s2pi / 3.0) * (x3 * M0 + wx * M2);
+          dc[4] += (s2pi / 3.0) * (x2 * M1 + M3);
+          dc[5] += (s2pi / 3.0) * (x3 * M0 - 3.0 * wx * M2);
+          dc[6] += (s2pi / 3.0) * (3.0 * x2 * M1 - M3);
+          dc[7] += 0.25 * s2pi * (x4 * M0 + 2.0 * x2 * M2 + M4);
+          // sum over the run of w B_j(K): B_j(K) times the run's sum of w, on lane 0
+          const double wsum = wave_sum_f64(M0);
+          if (lane == 0) {
+            double bk[8];
+            chi_basis(kc.x, kc.y, o, bk);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) dc[q] -= bk[q] * wsum;
+          }
+          if (lane == pos[d].j) wth = (float)-wsum;
+          M0 = M1 = M2 = M3 = M4 = 0.0;
+        }
+      }
+      const Round l = it.load_target(nb);
+      load_round<FULLG>(a, rb.at(l.j), kd0 + stride * l.j, mx, ny, l.u0, lane, buf[d]);
+      pos[d] = it.take(rb);
+    }
+  }
+  return wth;
+}
+
 // Adjoint of Eq. 3 from the stored values: for every pair, z = G e^{i psi}, w = Re(conj(Tbar(Q)) i z);
 // per (pixel, column) run the moments M_n = sum w wy^n (n = 0..4) give the eight dL/dc terms (the
 // B_j(K - Q) are polynomials in wy along a column, see k_yadjoint); dL/dtheta[kd] = -sum w.
@@ -572,7 +669,7 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
 template <bool FULLG>
 __global__ void __launch_bounds__(64 * kAdjWaves) k_padj(YArgs a, Optics o, int ny) {
   extern __shared__ __align__(16) unsigned char s_dyn[];
-  constexpr int D = kAdjDepth, W = kAdjWaves;
+  constexpr int W = kAdjWaves;
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   float2* tb = (float2*)s_dyn;
   const int nx = a.nx;
@@ -595,85 +692,7 @@ __global__ void __launch_bounds__(64 * kAdjWaves) k_padj(YArgs a, Optics o, int 
     const int kd0 = wp.kd_a + W * i0;
     const int nb = min(64, wp.count - i0);
     const RunBatch rb = make_batch(gather_run(a, o, kd0, W, nb, mx, lane, true, FULLG), nb);
-    float wth = 0.f;  // lane j: -(sum of w) of pixel j of the batch (0 without pairs in this column)
-    const int j0 = rb.next(-1);
-    Round pos[D];
-    float2 buf[D][4];
-    RoundCursor it{Round{j0, 0}, Round{j0, 0}};
-    if (j0 < nb) {
-#pragma unroll
-      for (int d = 0; d < D; ++d) {
-        const Round l = it.load_target(nb);
-        load_round<FULLG>(a, rb.at(l.j), kd0 + W * l.j, mx, ny, l.u0, lane, buf[d]);
-        pos[d] = it.take(rb);
-      }
-    } else {
-      pos[0] = Round{nb, 0};
-    }
-    double M0 = 0.0, M1 = 0.0, M2 = 0.0, M3 = 0.0, M4 = 0.0;
-    while (pos[0].j < nb) {
-#pragma unroll
-      for (int d = 0; d < D; ++d) {
-        if (pos[d].j < nb) {
-          const RunDesc r = rb.at(pos[d].j);
-          const double2 kc = rb.kc(pos[d].j);
-          const ChiRow ch = rb.chi(pos[d].j);
-          const int u0 = pos[d].u0;
-          const double wx = o.lk * (kc.x - qx);
-          const double A = o.lk * kc.y, B = -o.lk * o.sy;
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            if (u0 + 64 * q >= r.len) continue;  // wave-uniform: no entry of the run in this slice
-            const int u = u0 + lane + 64 * q;
-            const bool in = u < r.len;
-            const int iy = run_iy(r, u);
-            const int my = in ? (iy < 0 ? iy + ny : iy) : 0;
-            const double ty = (double)iy;
-            const double wy = fma(B, ty, A);
-            const float2 e = expi_rev(chi_row_eval(ch, ty));
-            const float2 gq = buf[d][q];
-            const float2 z = make_float2(gq.x * e.x - gq.y * e.y, gq.x * e.y + gq.y * e.x);
-            const float2 tq = tb[my];
-            double t = in ? (double)(tq.x * (-z.y) + tq.y * z.x) : 0.0;
-            M0 += t;
-            t *= wy;
-            M1 += t;
-            t *= wy;
-            M2 += t;
-            t *= wy;
-            M3 += t;
-            t *= wy;
-            M4 += t;
-          }
-          if (u0 + 256 >= r.len) {
-            // last round of the run: this lane's sum over its pairs of w B_j(K - Q), B_j as
-            // polynomials in wy
-            const double x2 = wx * wx, x3 = x2 * wx, x4 = x2 * x2;
-            dc[0] += 0.5 * s2pi * (x2 * M0 + M2);
-            dc[1] += 0.5 * s2pi * (x2 * M0 - M2);
-            dc[2] += s2pi * (wx * M1);
-            dc[3] += (s2pi / 3.0) * (x3 * M0 + wx * M2);
-            dc[4] += (s2pi / 3.0) * (x2 * M1 + M3);
-            dc[5] += (s2pi / 3.0) * (x3 * M0 - 3.0 * wx * M2);
-            dc[6] += (s2pi / 3.0) * (3.0 * x2 * M1 - M3);
-            dc[7] += 0.25 * s2pi * (x4 * M0 + 2.0 * x2 * M2 + M4);
-            // sum over the run of w B_j(K): B_j(K) times the run's sum of w, on lane 0
-            const double wsum = wave_sum_f64(M0);
-            if (lane == 0) {
-              double bk[8];
-              chi_basis(kc.x, kc.y, o, bk);
-#pragma unroll
-              for (int q = 0; q < 8; ++q) dc[q] -= bk[q] * wsum;
-            }
-            if (lane == pos[d].j) wth = (float)-wsum;
-            M0 = M1 = M2 = M3 = M4 = 0.0;
-          }
-        }
-        const Round l = it.load_target(nb);
-        load_round<FULLG>(a, rb.at(l.j), kd0 + W * l.j, mx, ny, l.u0, lane, buf[d]);
-        pos[d] = it.take(rb);
-      }
-    }
+    const float wth = adj_batch<FULLG>(a, o, rb, kd0, W, mx, ny, lane, tb, qx, s2pi, dc);
     if (lane < nb) pth[kd0 + W * lane] = wth;
   }
   // the workgroup's dL/dc: the waves' sums added in wave order
@@ -690,6 +709,52 @@ __global__ void __launch_bounds__(64 * kAdjWaves) k_padj(YArgs a, Optics o, int 
     for (int w = 1; w < kAdjWaves; ++w) t += s_dc[w][lane];
     double* p = a.pdc + (int64_t)blockIdx.x * 8 + lane;
     *p = a.accumulate ? *p + t : t;
+  }
+}
+
+// Adjoint over the stored values in the refocus sum's pieces: the wave of piece w takes the whole
+// runs [ra, rb) of its column (no run is split, so dL/dtheta[mx][kd] keeps one writer; runs
+// outside the column's span of runs with pairs get 0 without a gather), with its own copy of the
+// column of Tbar in LDS; dL/dc: one partial per wave, pdc[w][8].
+__global__ void __launch_bounds__(64 * kPrunedCols) k_padj_stream(YArgs a, Optics o, int ny, int nwmax,
+                                                                  const PieceTab* __restrict__ wtab,
+                                                                  const int64_t* __restrict__ ctab) {
+  extern __shared__ __align__(16) unsigned char s_dyn[];
+  const int W = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  float2* tb = (float2*)(s_dyn + (size_t)wave * padj_block_lds(ny));
+  const int nx = a.nx, n_k = a.n_k;
+  const int64_t wid = (int64_t)blockIdx.x * W + wave;
+  if (wid >= nwmax) return;
+  if (wid >= ctab[nx]) {
+    if (lane < 8) a.pdc[wid * 8 + lane] = 0.0;
+    return;
+  }
+  const PieceTab pc = wtab[wid];
+  const int mx = (int)(pc.run / n_k);
+  const int64_t c0 = (int64_t)mx * n_k;
+  const int64_t* col = ctab + (nx + 2) + 3 * (int64_t)mx;
+  const int64_t ga = max(pc.ra, col[1]), gb = min(pc.rb, col[2]);
+  float* pth = a.pdth + c0;
+  for (int64_t r = pc.ra + lane; r < pc.rb; r += 64)
+    if (r < ga || r >= gb) pth[r - c0] = 0.f;
+  for (int i = lane; i < ny; i += 64) tb[i] = a.Tbt[(int64_t)mx * ny + i];
+  const double qx = (double)signed_index(mx, nx) * o.sx;
+  const double s2pi = 6.283185307179586476925286766559 / o.lam;
+  double dc[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) dc[j] = 0.0;
+  for (int64_t i = ga; i < gb; i += 64) {
+    const int kd0 = (int)(i - c0);
+    const int nb = (int)min((int64_t)64, gb - i);
+    const RunBatch rb = make_batch(gather_run(a, o, kd0, 1, nb, mx, lane, true, false), nb);
+    const float wth = adj_batch<false>(a, o, rb, kd0, 1, mx, ny, lane, tb, qx, s2pi, dc);
+    if (lane < nb) pth[kd0 + lane] = wth;
+  }
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const double t = wave_sum_f64(dc[j]);
+    if (lane == 0) a.pdc[wid * 8 + j] = t;
   }
 }
 
@@ -741,6 +806,20 @@ inline int64_t psum_stream_waves(int ny) {
   return 256 * (per_cu < 20 ? per_cu : 20);
 }
 
+// Per piece (thread): the adjoint's run range from the piece's entries.
+__global__ void __launch_bounds__(256) k_stream_runs(int n_k, const int64_t* __restrict__ poff, int nx,
+                                                     const int64_t* __restrict__ ctab, PieceTab* __restrict__ wtab) {
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= ctab[nx]) return;
+  const PieceTab pc = wtab[p];
+  const int mx = (int)(pc.run / n_k);
+  auto first_run = [&](const PieceTab& q) { return q.e0 == poff[q.run] ? q.run : q.run + 1; };
+  const int64_t ra = p == ctab[mx] ? (int64_t)mx * n_k : first_run(pc);
+  const int64_t rb = p + 1 == ctab[mx + 1] ? (int64_t)(mx + 1) * n_k : first_run(wtab[p + 1]);
+  wtab[p].ra = ra;
+  wtab[p].rb = rb;
+}
+
 // the refocus sum over the stored values in balanced pieces: nwmax waves at most
 inline int launch_psum_stream(int ny, const YArgs& a, const Optics& o, int chi0, int nwmax, const PieceTab* wtab,
                               const int64_t* ctab, hipStream_t s) {
@@ -752,6 +831,18 @@ inline int launch_psum_stream(int ny, const YArgs& a, const Optics& o, int chi0,
     hipLaunchKernelGGL(k_psum_stream<true>, grid, blk, lds, s, a, o, ny, nwmax, wtab, ctab);
   else
     hipLaunchKernelGGL(k_psum_stream<false>, grid, blk, lds, s, a, o, ny, nwmax, wtab, ctab);
+  STEM_LAUNCH_CHECK();
+  return STEM_OK;
+}
+
+// the adjoint over the stored values in the refocus sum's pieces
+inline int launch_padj_stream(int ny, const YArgs& a, const Optics& o, int nwmax, const PieceTab* wtab,
+                              const int64_t* ctab, hipStream_t s) {
+  const int w = psum_waves(ny);
+  const size_t lds = (size_t)w * padj_block_lds(ny);
+  const dim3 grid((unsigned)((nwmax + w - 1) / w)), blk(64 * w);
+  STEM_TRACE("ssb_adjoint_pruned", s);
+  hipLaunchKernelGGL(k_padj_stream, grid, blk, lds, s, a, o, ny, nwmax, wtab, ctab);
   STEM_LAUNCH_CHECK();
   return STEM_OK;
 }
