@@ -108,7 +108,7 @@ PROFILED = {
     "stem::k_xstage<stem::XfFft<1024>, unsigned char>": "xstage_fft",
     "stem::k_yreduce<stem::XfFft<1024>, true, false>": "ssb_yreduce",
     "stem::k_psum_stream<false>": "ssb_reduce",
-    "stem::k_padj<false>": "ssb_adjoint_pruned",
+    "stem::k_padj_stream": "ssb_adjoint_pruned",
     "stem::k_dpc_cols<1024, 4>": "dpc_cols",
 }
 

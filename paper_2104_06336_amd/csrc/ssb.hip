@@ -818,7 +818,7 @@ static int reconstruct(const int32_t* d_idx, const int64_t* d_off, int64_t frame
       a.k0 = k0;
       a.k1 = k1;
       a.accumulate = ch > 0;
-      if ((st = launch_psum(ny, a, o, chi0, true, L.store, s))) return st;
+      if ((st = launch_psum(ny, a, o, chi0, L.store, s))) return st;
     }
     return run_phase(L, b, *scan, L.pgroups, L.nwp, L.nchunks, ssb->normalize ? b.npq : nullptr, d_phase, d_T, s);
   } else if (L.store) {
@@ -1114,7 +1114,7 @@ extern "C" int ssb_backward(const float* d_dLdphi, const stem_det* det, const st
       y.k0 = k0;
       y.k1 = k1;
       y.accumulate = ch > 0;
-      if ((st = launch_padj(ny, y, o, true, s))) return st;
+      if ((st = launch_padj(ny, y, o, s))) return st;
     }
     npdc = L.nwa;
     npdth = nx;

@@ -2,24 +2,24 @@
 // ssb_fused.h describes): the refocus sum of Sec. IV (only the summation runs again) and the
 // adjoint without any transform.
 //
-// Refocus sum: a wave owns one scan-frequency column mx of the whole plane (Qx = ix(mx) sx, mx in
-// [0, Nx)) and a group of pixels, and keeps the column's T in LDS.  The lanes first gather the
-// descriptors of 64 pixels at a time (start and length of the pixel's run for this column, the
-// set's first row frequency and hole, Kc and chi(Kc) + theta) into LDS; the wave then streams the
-// runs of stored values in rounds of 64 lanes x 4 entries (contiguous, coalesced loads), with the
-// loads of the next rounds in flight while one is summed, and adds every value, times its phase
-// factor, into T (one slot per row frequency my: the entries of a round have distinct my, so no
-// two lanes touch one slot).  The partial T of the group goes to part[g] (column-major [mx][my],
-// summed by the phase pass like the fused sum's).
+// Work unit: the run of one pixel in one scan-frequency column mx (Qx = ix(mx) sx, mx in [0, Nx)),
+// its stored values contiguous.  A wave gathers the descriptors of up to 64 runs at a time into
+// lane registers (start and length, the set's first row frequency and hole, Kc and the phase
+// polynomial of the column), then streams the runs in rounds of 64 lanes x 4 entries (coalesced
+// loads) with the next rounds' loads in flight while one is summed, and adds every value, times
+// its phase factor, into the column's T in LDS (one slot per row frequency my: the entries of a
+// round have distinct my, so no two lanes touch one slot).
 //
-// Adjoint: a workgroup owns a column and a pixel group whose pixels its waves share out (wave w
-// takes every W-th pixel); the column of Tbar is loaded into LDS once per workgroup.
+// Refocus (k_psum_stream) and adjoint (k_padj_stream) over the stored array: the columns are cut
+// into pieces of equal cost, one wave each, as many as the GPU holds at once (tables built at
+// FINALIZE, k_stream_*).  A piece's partial T is one row of the partial buffer; the phase pass
+// adds a column's rows in order.
 //
-// FULLG: the runs are read from a block of full half-spectrum columns of G instead (pixel kd's
-// column c at X + ((kd - xk0) (Nx/2+1) + c) Ny; a column mx > Nx/2 is the conjugate of column
-// Nx - mx at -my): the sums of the scan lengths the fused kernels do not take, whose G comes from
-// separate row and column transforms.  With PWRITE the values read are also stored as the pruned
-// array.
+// The other scan lengths (k_psum, k_padj with FULLG): the runs are read from a block of full
+// half-spectrum columns of G (pixel kd's column c at X + ((kd - xk0) (Nx/2+1) + c) Ny; a column
+// mx > Nx/2 is the conjugate of column Nx - mx at -my), chunk by chunk of pixels; a wave (refocus)
+// or workgroup (adjoint) owns a column and a pixel group, its partial T going to part[g]
+// (column-major [mx][my]).  With PWRITE the values read are also stored as the pruned array.
 #pragma once
 
 #include "ssb_fused.h"
@@ -663,9 +663,10 @@ __device__ __forceinline__ float adj_batch(const YArgs& a, const Optics& o, cons
 // Adjoint of Eq. 3 from the stored values: for every pair, z = G e^{i psi}, w = Re(conj(Tbar(Q)) i z);
 // per (pixel, column) run the moments M_n = sum w wy^n (n = 0..4) give the eight dL/dc terms (the
 // B_j(K - Q) are polynomials in wy along a column, see k_yadjoint); dL/dtheta[kd] = -sum w.
-// Rounds are pipelined through kAdjDepth register slots as in k_psum; the moments of a run carry
-// over its consecutive rounds.  Partials: pdc[workgroup][8] (FP64), pdth[mx][kd] (FP32; one writer per
-// entry), the workgroup's four waves combined into one dL/dc partial.
+// Over full columns of G (the other scan lengths): a workgroup owns a column and a pixel group whose
+// pixels its waves share out (wave w takes every W-th pixel), the column of Tbar loaded into LDS
+// once.  Partials: pdc[workgroup][8] (FP64), pdth[mx][kd] (FP32; one writer per entry), the
+// workgroup's four waves combined into one dL/dc partial.
 template <bool FULLG>
 __global__ void __launch_bounds__(64 * kAdjWaves) k_padj(YArgs a, Optics o, int ny) {
   extern __shared__ __align__(16) unsigned char s_dyn[];
@@ -773,26 +774,22 @@ inline int64_t psum_launch_waves(int ny, int nx, int ngroups) {
 // dL/dc partials of an adjoint launch over the stored values (one per workgroup)
 inline int64_t padj_partials(int nx, int ngroups) { return (int64_t)nx * ngroups; }
 
-// fullg: the runs from full columns of G at a.X (pixels from a.xk0); pwrite: also store the values
-// as the pruned array
-inline int launch_psum(int ny, const YArgs& a, const Optics& o, int chi0, bool fullg, bool pwrite, hipStream_t s) {
+// the sums of the other scan lengths over full columns of G at a.X (pixels from a.xk0), chunk by
+// chunk; pwrite: also store the values as the pruned array
+inline int launch_psum(int ny, const YArgs& a, const Optics& o, int chi0, bool pwrite, hipStream_t s) {
   const int w = psum_waves(ny);
   const size_t lds = (size_t)w * pruned_wave_lds(ny);
   const dim3 grid((unsigned)(psum_launch_waves(ny, a.nx, a.ngroups) / w)), blk(64 * w);
-  STEM_TRACE(fullg ? "ssb_gsum" : "ssb_reduce", s);
-  auto go = [&](auto c0, auto fg, auto pw) {
-    hipLaunchKernelGGL((k_psum<decltype(c0)::value, decltype(fg)::value, decltype(pw)::value>), grid, blk, lds, s, a,
-                       o, ny);
+  STEM_TRACE("ssb_gsum", s);
+  auto go = [&](auto c0, auto pw) {
+    hipLaunchKernelGGL((k_psum<decltype(c0)::value, true, decltype(pw)::value>), grid, blk, lds, s, a, o, ny);
   };
   using T_ = std::true_type;
   using F_ = std::false_type;
-  if (!fullg) {
-    chi0 ? go(T_{}, F_{}, F_{}) : go(F_{}, F_{}, F_{});
-  } else if (pwrite) {
-    chi0 ? go(T_{}, T_{}, T_{}) : go(F_{}, T_{}, T_{});
-  } else {
-    chi0 ? go(T_{}, T_{}, F_{}) : go(F_{}, T_{}, F_{});
-  }
+  if (pwrite)
+    chi0 ? go(T_{}, T_{}) : go(F_{}, T_{});
+  else
+    chi0 ? go(T_{}, F_{}) : go(F_{}, F_{});
   STEM_LAUNCH_CHECK();
   return STEM_OK;
 }
@@ -847,14 +844,12 @@ inline int launch_padj_stream(int ny, const YArgs& a, const Optics& o, int nwmax
   return STEM_OK;
 }
 
-inline int launch_padj(int ny, const YArgs& a, const Optics& o, bool fullg, hipStream_t s) {
+// the adjoint of the other scan lengths over full columns of G at a.X, chunk by chunk
+inline int launch_padj(int ny, const YArgs& a, const Optics& o, hipStream_t s) {
   const size_t lds = padj_block_lds(ny);
   const dim3 grid((unsigned)padj_partials(a.nx, a.ngroups)), blk(64 * kAdjWaves);
-  STEM_TRACE(fullg ? "ssb_gadjoint" : "ssb_adjoint_pruned", s);
-  if (fullg)
-    hipLaunchKernelGGL(k_padj<true>, grid, blk, lds, s, a, o, ny);
-  else
-    hipLaunchKernelGGL(k_padj<false>, grid, blk, lds, s, a, o, ny);
+  STEM_TRACE("ssb_gadjoint", s);
+  hipLaunchKernelGGL(k_padj<true>, grid, blk, lds, s, a, o, ny);
   STEM_LAUNCH_CHECK();
   return STEM_OK;
 }
