@@ -312,8 +312,8 @@ def oracle_parallel(pool, n_workers, idx, off, wl):
 
 
 def oracle_pruned_values(G, kc, wl):
-    """The oracle's G on the double-overlap pairs in the library's stored order (pixel, then
-    scan-frequency column, then ascending signed row frequency), for the error of the stored G."""
+    """The oracle's G on the double-overlap pairs in the library's stored order (scan-frequency
+    column, then pixel, then ascending signed row frequency), for the error of the stored G."""
     import numpy as np
 
     from oracle import ssb as ossb
@@ -321,11 +321,15 @@ def oracle_pruned_values(G, kc, wl):
     qx, qy = ossb.scan_q_grid(ny, nx, wl.step, wl.dk)
     order = np.argsort(ossb.signed_freq_index(ny), kind="stable")
     r2 = float(wl.r_bf) ** 2
-    out = []
-    for kd in range(len(kc)):
-        m = ossb.double_overlap(float(kc[kd, 0]), float(kc[kd, 1]), qx, qy, r2)[order].T
-        out.append(G[kd][order].T[m])
-    return np.concatenate(out)
+    masks = [ossb.double_overlap(float(kc[kd, 0]), float(kc[kd, 1]), qx, qy, r2)[order].T for kd in range(len(kc))]
+    sizes = np.stack([m.sum(axis=1) for m in masks], axis=1)  # [mx][kd]
+    starts = (np.cumsum(sizes.ravel()) - sizes.ravel()).reshape(sizes.shape)
+    out = np.empty(int(sizes.sum()), dtype=np.complex128)
+    for kd, m in enumerate(masks):
+        v = G[kd][order].T[m]  # pixel kd's values, column by column
+        s = sizes[:, kd]
+        out[np.repeat(starts[:, kd] - (np.cumsum(s) - s), s) + np.arange(len(v))] = v
+    return out
 
 
 def rel_l2(a, b):

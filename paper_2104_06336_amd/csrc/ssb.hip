@@ -338,20 +338,56 @@ __device__ __forceinline__ int64_t block_scan256(int64_t v, int64_t* s) {
   return r;
 }
 
+// The first pass also writes the column's entry of the refocus sum's column table (ctab, see
+// ssb_pruned.h): its cost and the span of its runs with entries.
 __global__ void __launch_bounds__(256) k_prune_runs(const int4* __restrict__ cst, int n_k, int nx,
-                                                    int64_t* __restrict__ poff, int64_t* __restrict__ ptot) {
+                                                    int64_t* __restrict__ poff, int64_t* __restrict__ ptot,
+                                                    int64_t* __restrict__ ctab) {
   __shared__ int64_t s[256];
   const int mx = blockIdx.x;
   const int per = (n_k + 255) / 256;  // consecutive pixels per thread
   const int k0 = threadIdx.x * per;
-  int64_t sum = 0;
-  for (int kd = k0; kd < k0 + per && kd < n_k; ++kd) sum += pruned_size(cst, kd, mx, nx);
+  int64_t sum = 0, cost = 0;
+  int lo = n_k, hi = -1;
+  for (int kd = k0; kd < k0 + per && kd < n_k; ++kd) {
+    const int64_t len = pruned_size(cst, kd, mx, nx);
+    sum += len;
+    if (len > 0) {
+      cost += len + kRunCost;
+      lo = min(lo, kd);
+      hi = max(hi, kd);
+    }
+  }
   int64_t base = block_scan256(sum, s) - sum;
   for (int kd = k0; kd < k0 + per && kd < n_k; ++kd) {
     poff[(int64_t)mx * n_k + kd] = base;
     base += pruned_size(cst, kd, mx, nx);
   }
   if (threadIdx.x == 255) ptot[mx] = base;
+  // the column's cost and span: wave reductions, then the four waves' in LDS
+  for (int off = 32; off > 0; off >>= 1) {
+    cost += __shfl_xor(cost, off);
+    lo = min(lo, __shfl_xor(lo, off));
+    hi = max(hi, __shfl_xor(hi, off));
+  }
+  __shared__ int64_t s_cost[4];
+  __shared__ int s_lh[4][2];
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    s_cost[w] = cost;
+    s_lh[w][0] = lo;
+    s_lh[w][1] = hi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int l = min(min(s_lh[0][0], s_lh[1][0]), min(s_lh[2][0], s_lh[3][0]));
+    const int h = max(max(s_lh[0][1], s_lh[1][1]), max(s_lh[2][1], s_lh[3][1]));
+    const int64_t r0 = (int64_t)mx * n_k;
+    int64_t* col = ctab + (nx + 2) + 3 * (int64_t)mx;
+    col[0] = (s_cost[0] + s_cost[1]) + (s_cost[2] + s_cost[3]);
+    col[1] = h >= 0 ? r0 + l : 0;
+    col[2] = h >= 0 ? r0 + h + 1 : 0;
+  }
 }
 
 __global__ void __launch_bounds__(256) k_prune_bases(int n_k, int nx, int64_t* __restrict__ poff,
@@ -672,21 +708,19 @@ static int run_pair_count(const SsbLayout& L, const Bufs& b, int ny, int nx, hip
 
 static int run_prune_offsets(const SsbLayout& L, const Bufs& b, int nx, int32_t* d_status, hipStream_t s) {
   STEM_TRACE("prune_offsets", s);
-  hipLaunchKernelGGL(k_prune_runs, dim3((unsigned)nx), dim3(256), 0, s, b.cst, L.n_k, nx, b.poff, b.ptot);
+  hipLaunchKernelGGL(k_prune_runs, dim3((unsigned)nx), dim3(256), 0, s, b.cst, L.n_k, nx, b.poff, b.ptot, b.pcs);
   STEM_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_prune_bases, dim3(1), dim3(256), 0, s, L.n_k, nx, b.poff, b.ptot, L.pcap, d_status);
   STEM_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_prune_add, dim3((unsigned)nx), dim3(256), 0, s, L.n_k, b.poff, b.ptot);
   STEM_LAUNCH_CHECK();
-  // the tables of the refocus sum in balanced pieces
-  hipLaunchKernelGGL(k_stream_cols, dim3((unsigned)nx), dim3(256), 0, s, L.n_k, b.poff, nx, b.pcs);
+  // the tables of the refocus sum in balanced pieces (the column costs and spans came with the
+  // first pass)
+  hipLaunchKernelGGL(k_stream_cands, dim3(kStreamCands), dim3(256), 0, s, nx, (int)L.nws, b.pcs);
   STEM_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_stream_colseg, dim3(1), dim3(256), 0, s, nx, (int)L.nws, b.pcs);
   STEM_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_stream_waves, dim3((unsigned)nx), dim3(256), 0, s, L.n_k, b.poff, nx, b.pcs, b.pws);
-  STEM_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_stream_runs, dim3((unsigned)((L.nwq + 255) / 256)), dim3(256), 0, s, L.n_k, b.poff, nx, b.pcs,
-                     b.pws);
   STEM_LAUNCH_CHECK();
   return STEM_OK;
 }

@@ -334,7 +334,7 @@ __global__ void __launch_bounds__(64 * kPrunedCols) k_psum(YArgs a, Optics o, in
 // follow one another), so a column's values are one contiguous stretch.  Each column is cut into
 // pieces of equal cost, cost = entries + kRunCost per run with entries (a run costs at least one
 // round whatever its length), the cost per piece Cc the same for every column (about total cost /
-// nws, see k_stream_colseg); one wave sums one piece.  Every wave thus does about the same work (a column of few
+// nws, see k_stream_cands); one wave sums one piece.  Every wave thus does about the same work (a column of few
 // pairs is one short piece), and no wave leaves its column: its partial T is one row of ny values
 // at part + w ny, the pieces of column mx being the waves colseg[mx] .. colseg[mx + 1] - 1, which
 // the phase pass adds in order.
@@ -343,14 +343,20 @@ constexpr int64_t kRunCost = 192;
 // Per piece (tables from k_stream_*): the run (mx n_k + kd) holding its first entry, its entries
 // [E0, E1) of the array, and for the adjoint the whole runs [ra, rb) whose first entry lies in
 // [E0, E1) (the column's first piece from the column's first run, the last to its last, so that
-// the pieces of a column take each of its runs once, empty ones included).
+// the pieces of a column take each of its runs once, empty ones included).  Tables built at
+// FINALIZE: the column costs and spans by k_prune_runs, then k_stream_cands, k_stream_colseg and
+// k_stream_waves.
 struct PieceTab {
   int64_t run, e0, e1, ra, rb;
 };
 
 // Table of the columns, ctab (int64): colseg [nx + 1], then the cost per piece, then per column
-// its cost and the span [first, last + 1) of its runs with entries (run indices), [nx][3].
-__host__ __device__ inline size_t stream_ctab_words(int nx) { return (size_t)(nx + 1) + 1 + 3 * (size_t)nx; }
+// its cost and the span [first, last + 1) of its runs with entries (run indices), [nx][3], then
+// the candidate costs per piece and their piece counts [kStreamCands][2].
+constexpr int kStreamCands = 256;
+__host__ __device__ inline size_t stream_ctab_words(int nx) {
+  return (size_t)(nx + 1) + 1 + 3 * (size_t)nx + 2 * kStreamCands;
+}
 
 template <bool CHI0>
 __global__ void __launch_bounds__(64 * kPrunedCols) k_psum_stream(YArgs a, Optics o, int ny, int nwmax,
@@ -425,51 +431,8 @@ __device__ __forceinline__ int64_t runs_cost(const int64_t* __restrict__ poff, i
   return c;
 }
 
-// Per column (workgroup; thread j takes the pixels [j q, (j + 1) q), q = ceil(n_k / 256)): its cost
-// and the span of its runs with entries.
-__global__ void __launch_bounds__(256) k_stream_cols(int n_k, const int64_t* __restrict__ poff, int nx,
-                                                     int64_t* __restrict__ ctab) {
-  __shared__ int64_t s_cost[256];
-  __shared__ int s_lo, s_hi;
-  const int mx = blockIdx.x;
-  if (threadIdx.x == 0) {
-    s_lo = n_k;
-    s_hi = -1;
-  }
-  const int q = (n_k + 255) / 256, k0 = min((int)threadIdx.x * q, n_k), k1 = min(k0 + q, n_k);
-  const int64_t r0 = (int64_t)mx * n_k;
-  int lo = n_k, hi = -1;
-  for (int kd = k0; kd < k1; ++kd)
-    if (poff[r0 + kd + 1] > poff[r0 + kd]) {
-      lo = min(lo, kd);
-      hi = max(hi, kd);
-    }
-  s_cost[threadIdx.x] = runs_cost(poff, r0 + k0, k1 - k0);
-  __syncthreads();
-  atomicMin(&s_lo, lo);
-  atomicMax(&s_hi, hi);
-  for (int off = 128; off > 0; off >>= 1) {
-    if (threadIdx.x < off) s_cost[threadIdx.x] += s_cost[threadIdx.x + off];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    int64_t* col = ctab + (nx + 2) + 3 * (int64_t)mx;
-    col[0] = s_cost[0];
-    col[1] = s_hi >= 0 ? r0 + s_lo : 0;
-    col[2] = s_hi >= 0 ? r0 + s_hi + 1 : 0;
-  }
-}
-
-// One workgroup: the cost per piece Cc and colseg, the exclusive scan of the pieces per column
-// ceil(cost / Cc).  Cc is the smallest of 256 candidates spread over [total / nws, total /
-// (nws - nx)] (the second always gives at most nws pieces, as the pieces number at most
-// total / Cc + nx) for which the pieces number at most nws, so that the launch's nws waves (the
-// waves the GPU holds at once) each sum one piece and every compute unit gets the same work.
-__global__ void __launch_bounds__(256) k_stream_colseg(int nx, int nws, int64_t* __restrict__ ctab) {
-  __shared__ int64_t s_sum[256];
-  __shared__ int64_t s_cost[4096];
-  const int64_t* col = ctab + (nx + 2);
-  for (int mx = threadIdx.x; mx < nx; mx += 256) s_cost[mx] = col[3 * mx];
+// The sum of the column costs, by every thread of a workgroup.
+__device__ __forceinline__ int64_t stream_total_cost(int nx, const int64_t* __restrict__ col, int64_t* s_sum) {
   int64_t tot = 0;
   for (int mx = threadIdx.x; mx < nx; mx += 256) tot += col[3 * mx];
   s_sum[threadIdx.x] = tot;
@@ -480,46 +443,75 @@ __global__ void __launch_bounds__(256) k_stream_colseg(int nx, int nws, int64_t*
   }
   const int64_t total = s_sum[0];
   __syncthreads();
-  int64_t Cc = 1;
-  if (total > 0) {
-    const int64_t lo = (total + nws - 1) / nws;
-    const int64_t hi = nws > nx ? (total + (nws - nx) - 1) / (nws - nx) : total;
-    // candidate t: lo + t (hi - lo) / 255; feasible when its pieces number at most nws
-    const int64_t c = hi > lo ? lo + (int64_t)threadIdx.x * (hi - lo) / 255 : hi;
-    int64_t n = 0;
-    for (int mx = 0; mx < nx; ++mx) n += (s_cost[mx] + c - 1) / c;
-    s_sum[threadIdx.x] = n <= nws || threadIdx.x == 255 ? c : INT64_MAX;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-      if (threadIdx.x < off) s_sum[threadIdx.x] = min(s_sum[threadIdx.x], s_sum[threadIdx.x + off]);
-      __syncthreads();
-    }
-    Cc = s_sum[0];
-    __syncthreads();
-  }
-  const int per = (nx + 255) / 256, m0 = threadIdx.x * per;
+  return total;
+}
+
+// Candidate t (workgroup t of kStreamCands) for the cost per piece: lo + t (hi - lo) / (kStreamCands
+// - 1) over [lo, hi] = [total / nws, total / (nws - nx)] (the second always gives at most nws
+// pieces, as the pieces number at most total / Cc + nx), and its number of pieces.
+__global__ void __launch_bounds__(256) k_stream_cands(int nx, int nws, int64_t* __restrict__ ctab) {
+  __shared__ int64_t s_sum[256];
+  const int64_t* col = ctab + (nx + 2);
+  const int64_t total = stream_total_cost(nx, col, s_sum);
+  const int64_t lo = total > 0 ? (total + nws - 1) / nws : 1;
+  const int64_t hi = total <= 0 ? 1 : nws > nx ? (total + (nws - nx) - 1) / (nws - nx) : total;
+  const int64_t c = hi > lo ? lo + (int64_t)blockIdx.x * (hi - lo) / (kStreamCands - 1) : hi;
   int64_t n = 0;
-  for (int mx = m0; mx < m0 + per && mx < nx; ++mx) n += (s_cost[mx] + Cc - 1) / Cc;
+  for (int mx = threadIdx.x; mx < nx; mx += 256) n += (col[3 * mx] + c - 1) / c;
   s_sum[threadIdx.x] = n;
   __syncthreads();
-  for (int off = 1; off < 256; off <<= 1) {
-    const int64_t v = threadIdx.x >= off ? s_sum[threadIdx.x - off] : 0;
-    __syncthreads();
-    s_sum[threadIdx.x] += v;
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) s_sum[threadIdx.x] += s_sum[threadIdx.x + off];
     __syncthreads();
   }
-  int64_t base = s_sum[threadIdx.x] - n;
+  if (threadIdx.x == 0) {
+    int64_t* cand = ctab + (nx + 2) + 3 * (int64_t)nx;
+    cand[2 * blockIdx.x] = c;
+    cand[2 * blockIdx.x + 1] = s_sum[0];
+  }
+}
+
+// One workgroup: the cost per piece Cc, the smallest candidate whose pieces number at most nws (the
+// last candidate always does), so that the launch's nws waves (the waves the GPU holds at once)
+// each sum one piece and every compute unit gets the same work; then colseg, the exclusive scan of
+// the pieces per column ceil(cost / Cc).
+__global__ void __launch_bounds__(256) k_stream_colseg(int nx, int nws, int64_t* __restrict__ ctab) {
+  __shared__ int64_t s_sum[256];
+  const int64_t* col = ctab + (nx + 2);
+  const int64_t* cand = col + 3 * (int64_t)nx;
+  static_assert(kStreamCands == 256, "one candidate per thread");
+  const int t = threadIdx.x;
+  s_sum[t] = cand[2 * t + 1] <= nws || t == kStreamCands - 1 ? cand[2 * t] : INT64_MAX;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (t < off) s_sum[t] = min(s_sum[t], s_sum[t + off]);
+    __syncthreads();
+  }
+  const int64_t Cc = s_sum[0];
+  __syncthreads();
+  const int per = (nx + 255) / 256, m0 = t * per;
+  int64_t n = 0;
+  for (int mx = m0; mx < m0 + per && mx < nx; ++mx) n += (col[3 * mx] + Cc - 1) / Cc;
+  s_sum[t] = n;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const int64_t v = t >= off ? s_sum[t - off] : 0;
+    __syncthreads();
+    s_sum[t] += v;
+    __syncthreads();
+  }
+  int64_t base = s_sum[t] - n;
   for (int mx = m0; mx < m0 + per && mx < nx; ++mx) {
     ctab[mx] = base;
-    base += (s_cost[mx] + Cc - 1) / Cc;
+    base += (col[3 * mx] + Cc - 1) / Cc;
   }
-  if (threadIdx.x == 255) {
+  if (t == 255) {
     ctab[nx] = s_sum[255];
     ctab[nx + 1] = Cc;
   }
 }
 
-// Per column (workgroup): the pieces' first runs and entry ranges.  Piece p of column mx starts at
+// Per column (workgroup): the pieces' first runs, entry ranges and (after a barrier) run ranges.  Piece p of column mx starts at
 // cost p Cc of the column; inside run r (cost [c_r, c_r + kRunCost + len)) that is entry
 // max(0, p Cc - c_r - kRunCost) of the run.  Piece p ends where piece p + 1 starts, the last at
 // the column's end.
@@ -559,6 +551,14 @@ __global__ void __launch_bounds__(256) k_stream_waves(int n_k, const int64_t* __
   if (threadIdx.x == 255) {
     const int64_t ce = mx + 1 < nx ? poff[r0 + n_k] : poff[(int64_t)nx * n_k];
     wtab[seg0 + npieces - 1].e1 = ce;
+  }
+  __syncthreads();
+  // the adjoint's run ranges: piece p takes the runs whose first entry lies in its entries (the
+  // first piece from the column's first run, the last to its last run)
+  auto first_run = [&](const PieceTab& q) { return q.e0 == poff[q.run] ? q.run : q.run + 1; };
+  for (int64_t p = threadIdx.x; p < npieces; p += 256) {
+    wtab[seg0 + p].ra = p == 0 ? r0 : first_run(wtab[seg0 + p]);
+    wtab[seg0 + p].rb = p + 1 == npieces ? r0 + n_k : first_run(wtab[seg0 + p + 1]);
   }
 }
 
@@ -801,20 +801,6 @@ inline int64_t psum_stream_waves(int ny) {
   const int w = psum_waves(ny);
   const int64_t per_cu = (int64_t)((160u << 10) / ((size_t)w * pruned_wave_lds(ny))) * w;
   return 256 * (per_cu < 20 ? per_cu : 20);
-}
-
-// Per piece (thread): the adjoint's run range from the piece's entries.
-__global__ void __launch_bounds__(256) k_stream_runs(int n_k, const int64_t* __restrict__ poff, int nx,
-                                                     const int64_t* __restrict__ ctab, PieceTab* __restrict__ wtab) {
-  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (p >= ctab[nx]) return;
-  const PieceTab pc = wtab[p];
-  const int mx = (int)(pc.run / n_k);
-  auto first_run = [&](const PieceTab& q) { return q.e0 == poff[q.run] ? q.run : q.run + 1; };
-  const int64_t ra = p == ctab[mx] ? (int64_t)mx * n_k : first_run(pc);
-  const int64_t rb = p + 1 == ctab[mx + 1] ? (int64_t)(mx + 1) * n_k : first_run(wtab[p + 1]);
-  wtab[p].ra = ra;
-  wtab[p].rb = rb;
 }
 
 // the refocus sum over the stored values in balanced pieces: nwmax waves at most
