@@ -525,37 +525,91 @@ __global__ void __launch_bounds__(kYThreads, 2) k_yreduce(YArgs a, Optics o) {
         }
       }
     } else {
-      const double kch = a.kchi[kd];
+      if constexpr (SL::kSlots > 1) {
+        const double kch = a.kchi[kd];
 #pragma unroll
-      for (int sl = 0; sl < SL::kSlots; ++sl) {
-        int b0, m0;
-        XF::out(lane, sl * kSlotStride, b0, m0);
-        const int c = c0 + b0;
-        const ChiCol chd = chi_column(o.lk * (k.x - (double)signed_index(c, nx) * o.sx), o);
-        const ChiCol chm = chi_column(o.lk * (k.x - (double)signed_index(nx - c, nx) * o.sx), o);
+        for (int sl = 0; sl < SL::kSlots; ++sl) {
+          int b0, m0;
+          XF::out(lane, sl * kSlotStride, b0, m0);
+          // one column polynomial live at a time: the slot's direct frequencies, then its mirrored
+          // ones, each polynomial formed only after the previous pass (formed all at once they stay
+          // live together and spill at N = 512, two slots per lane)
+          asm volatile("" : "+v"(b0));
+          const int c = c0 + b0;
+          {
+            const ChiCol chd = chi_column(o.lk * (k.x - (double)signed_index(c, nx) * o.sx), o);
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          if (SL::slot_of(i) != sl) continue;
-          int b, m;
-          XF::out(lane, i, b, m);
-          // keep the per-register frequency arithmetic inside the pixel loop: hoisted out of it, the
-          // 16 registers' frequencies stay live across the loop and cost occupancy
-          asm volatile("" : "+v"(m));
-          const int iy = signed_index(m, NY);
-          if (sd[sl].has(iy)) {
-            const double wy = o.lk * (k.y - (double)iy * o.sy);
-            const float2 e = expi_reduced(chi_eval(chd, wy) - kch);
-            accd[i].x += v[i].x * e.x - v[i].y * e.y;
-            accd[i].y += v[i].x * e.y + v[i].y * e.x;
-            ++cnt;
+            for (int i = 0; i < 16; ++i) {
+              if (SL::slot_of(i) != sl) continue;
+              int b, m;
+              XF::out(lane, i, b, m);
+              // keep the per-register frequency arithmetic inside the pixel loop: hoisted out of it,
+              // the 16 registers' frequencies stay live across the loop and cost occupancy
+              asm volatile("" : "+v"(m));
+              const int iy = signed_index(m, NY);
+              if (sd[sl].has(iy)) {
+                const double wy = o.lk * (k.y - (double)iy * o.sy);
+                const float2 e = expi_reduced(chi_eval(chd, wy) - kch);
+                accd[i].x += v[i].x * e.x - v[i].y * e.y;
+                accd[i].y += v[i].x * e.y + v[i].y * e.x;
+                ++cnt;
+              }
+            }
           }
-          const int jy = signed_index((NY - m) & (NY - 1), NY);
-          if (sm[sl].has(jy)) {
-            const double wy = o.lk * (k.y - (double)jy * o.sy);
-            const float2 e = expi_reduced(chi_eval(chm, wy) - kch);
-            accm[i].x += v[i].x * e.x + v[i].y * e.y;
-            accm[i].y += v[i].x * e.y - v[i].y * e.x;
-            ++cnt;
+          int cm = c;
+          asm volatile("" : "+v"(cm));
+          {
+            const ChiCol chm = chi_column(o.lk * (k.x - (double)signed_index(nx - cm, nx) * o.sx), o);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+              if (SL::slot_of(i) != sl) continue;
+              int b, m;
+              XF::out(lane, i, b, m);
+              asm volatile("" : "+v"(m));
+              const int jy = signed_index((NY - m) & (NY - 1), NY);
+              if (sm[sl].has(jy)) {
+                const double wy = o.lk * (k.y - (double)jy * o.sy);
+                const float2 e = expi_reduced(chi_eval(chm, wy) - kch);
+                accm[i].x += v[i].x * e.x + v[i].y * e.y;
+                accm[i].y += v[i].x * e.y - v[i].y * e.x;
+                ++cnt;
+              }
+            }
+          }
+        }
+      } else {
+        const double kch = a.kchi[kd];
+#pragma unroll
+        for (int sl = 0; sl < SL::kSlots; ++sl) {
+          int b0, m0;
+          XF::out(lane, sl * kSlotStride, b0, m0);
+          const int c = c0 + b0;
+          const ChiCol chd = chi_column(o.lk * (k.x - (double)signed_index(c, nx) * o.sx), o);
+          const ChiCol chm = chi_column(o.lk * (k.x - (double)signed_index(nx - c, nx) * o.sx), o);
+#pragma unroll
+          for (int i = 0; i < 16; ++i) {
+            if (SL::slot_of(i) != sl) continue;
+            int b, m;
+            XF::out(lane, i, b, m);
+            // keep the per-register frequency arithmetic inside the pixel loop: hoisted out of it, the
+            // 16 registers' frequencies stay live across the loop and cost occupancy
+            asm volatile("" : "+v"(m));
+            const int iy = signed_index(m, NY);
+            if (sd[sl].has(iy)) {
+              const double wy = o.lk * (k.y - (double)iy * o.sy);
+              const float2 e = expi_reduced(chi_eval(chd, wy) - kch);
+              accd[i].x += v[i].x * e.x - v[i].y * e.y;
+              accd[i].y += v[i].x * e.y + v[i].y * e.x;
+              ++cnt;
+            }
+            const int jy = signed_index((NY - m) & (NY - 1), NY);
+            if (sm[sl].has(jy)) {
+              const double wy = o.lk * (k.y - (double)jy * o.sy);
+              const float2 e = expi_reduced(chi_eval(chm, wy) - kch);
+              accm[i].x += v[i].x * e.x + v[i].y * e.y;
+              accm[i].y += v[i].x * e.y - v[i].y * e.x;
+              ++cnt;
+            }
           }
         }
       }
