@@ -34,8 +34,10 @@ struct XfFft {
   static constexpr int slot_of(int i) { return kUniformCol ? (kWave * (i / RL)) / NB : i / RL; }
   static constexpr int kSlots = slot_of(15) + 1;
   // x-stage workgroup: 16 waves (one per CU), each with an LDS buffer for the FFT exchanges; the
-  // tile of 32 rows is written in 256-byte runs (measured 2-4 us faster than 8 waves, 128 bytes)
-  static constexpr int kXWaves = 16;
+  // tile of 32 rows is written in 256-byte runs (measured 2-4 us faster than 8 waves, 128 bytes).
+  // At N = 512 sixteen waves leave 128 registers, which spill 13; eight waves (144 registers, no
+  // spill) measured 96 against 128 us at a 512 x 512 scan with 314 pixels.
+  static constexpr int kXWaves = N == 512 ? 8 : 16;
   static constexpr int kXStride = kXWaveStride;
   static __device__ __forceinline__ int pad(int i) { return fft_pad(i); }
   static __device__ __forceinline__ void in(int lane, int i, int& b, int& n) { fft_in_index<N>(lane, i, b, n); }
