@@ -951,23 +951,31 @@ __global__ void __launch_bounds__(64) k_g_panel(const float2* __restrict__ X, co
 
 // From the binned cube (STEM_G_RECOMPUTE keeps no row-transformed cube): one workgroup per (bin,
 // group of kPanelGroup frequencies), the 2D DFT over (ry, rx) at those Q_j with FP64
-// accumulation: each thread sums its columns rx of a row with W_Nx^(mx rx) (zero counts skipped),
-// multiplies the row's partial by W_Ny^(my ry) and adds it; twiddles W_N^t for exact integer t
-// (FP64 sincospi rounded to FP32) in LDS, their indices advanced by exact integer steps.
+// accumulation of the rows: each thread sums its columns rx of a row with W_Nx^(mx rx) (held in
+// registers for the pass: the same for every row; KC products in FP32), multiplies the row's
+// partial by W_Ny^(my ry) in FP64 and adds it;
+// twiddles W_N^t for exact integer t (FP64 sincospi rounded to FP32) from LDS, their indices
+// advanced by exact integer steps.  The rows' loads are pipelined (kPanelRows in flight), the
+// columns taken in passes of kPanelCols.
 constexpr int kPanelTw = kGenMax;
-constexpr int kPanelGroup = 8;
+#ifndef STEM_PANEL_GROUP
+#define STEM_PANEL_GROUP 2
+#endif
+constexpr int kPanelGroup = STEM_PANEL_GROUP;  // frequencies per workgroup (its unrolled slots)
+constexpr int kPanelCols = 1024;  // columns per pass of the workgroup's 256 threads
+constexpr int kPanelRows = 8;     // rows of counts in flight
 
-template <typename DT>
+template <typename DT, int GQ>
 __global__ void __launch_bounds__(256) k_g_panel_d(const DT* __restrict__ D, const RowRun* __restrict__ rows,
                                                   int nbx, int n_k, int ny, int nx, PanelQ q, int n_q,
                                                   float2* __restrict__ img) {
   __shared__ float2 s_wx[kPanelTw], s_wy[kPanelTw];
-  __shared__ double s_red[2][kPanelGroup][4];
+  __shared__ double s_red[2][GQ][4];
   const int bin = blockIdx.x;
   const int by = bin / nbx, bx = bin % nbx;
   const int nbins = gridDim.x;
-  const int j0 = blockIdx.y * kPanelGroup;
-  const int nj = min(kPanelGroup, n_q - j0);
+  const int j0 = blockIdx.y * GQ;
+  const int nj = min(GQ, n_q - j0);
   const RowRun rr = rows[by];
   const int kd = rr.start + bx - rr.lo;
   if (bx < rr.lo || bx >= rr.hi || kd < 0 || kd >= n_k) {
@@ -987,53 +995,89 @@ __global__ void __launch_bounds__(256) k_g_panel_d(const DT* __restrict__ D, con
   __syncthreads();
   const DT* d = D + (int64_t)kd * ny * nx;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  int mx[kPanelGroup], my[kPanelGroup], x0[kPanelGroup], xs[kPanelGroup], yi[kPanelGroup];
+  // columns in passes of kPanelCols (thread t: rx = cb + t + 256 k, k < kPanelCols / 256); the
+  // counts of kPanelRows rows are in flight (rotating register slots, each refilled with the row
+  // kPanelRows further on once summed), so the row loop does not wait on every row's loads
+  constexpr int KC = kPanelCols / 256, P = kPanelRows;
+  int mx[GQ], my[GQ], xs[GQ];
 #pragma unroll
-  for (int j = 0; j < kPanelGroup; ++j) {
+  for (int j = 0; j < GQ; ++j) {
     mx[j] = j < nj ? q.mx[j0 + j] : 0;
     my[j] = j < nj ? q.my[j0 + j] : 0;
-    x0[j] = (int)(((int64_t)mx[j] * threadIdx.x) % nx);        // index of this thread's first rx
-    xs[j] = (int)(((int64_t)mx[j] * blockDim.x) % nx);         // step per blockDim.x columns
-    yi[j] = 0;                                                 // my ry mod Ny
+    xs[j] = (int)(((int64_t)mx[j] * blockDim.x) % nx);  // index step per blockDim.x columns
   }
-  double are[kPanelGroup], aim[kPanelGroup];
+  double are[GQ], aim[GQ];
 #pragma unroll
-  for (int j = 0; j < kPanelGroup; ++j) are[j] = aim[j] = 0.0;
-  for (int ry = 0; ry < ny; ++ry) {
-    double rre[kPanelGroup], rim[kPanelGroup];
-    int xi[kPanelGroup];
+  for (int j = 0; j < GQ; ++j) are[j] = aim[j] = 0.0;
+  for (int cb = 0; cb < nx; cb += kPanelCols) {
+    // the x twiddles of this thread's columns are the same for every row of the pass
+    float twr[GQ][KC], twi[GQ][KC];
+    int yi[GQ];
 #pragma unroll
-    for (int j = 0; j < kPanelGroup; ++j) {
-      rre[j] = rim[j] = 0.0;
-      xi[j] = x0[j];
+    for (int j = 0; j < GQ; ++j) {
+      int xi = (int)(((int64_t)mx[j] * (cb + (int)threadIdx.x)) % nx);  // this thread's first rx
+#pragma unroll
+      for (int k = 0; k < KC; ++k) {
+        const float2 w = s_wx[xi];
+        twr[j][k] = w.x;
+        twi[j][k] = w.y;
+        xi += xs[j];
+        if (xi >= nx) xi -= nx;
+      }
+      yi[j] = 0;  // my ry mod Ny
     }
-    for (int rx = threadIdx.x; rx < nx; rx += blockDim.x) {
-      const int c = (int)d[(int64_t)ry * nx + rx];
-      if (c) {
+    uint32_t cnt[P][KC];
+    // every load is issued (past the last row or column it reads an in-range count, dropped where
+    // the count is used), so the wait counts of the pipelined loop stay exact
+    bool colok[KC];
 #pragma unroll
-        for (int j = 0; j < kPanelGroup; ++j) {
-          const float2 w = s_wx[xi[j]];
-          rre[j] += (double)c * (double)w.x;
-          rim[j] += (double)c * (double)w.y;
+    for (int k = 0; k < KC; ++k) colok[k] = cb + (int)threadIdx.x + 256 * k < nx;
+    auto load_row = [&](int ry, uint32_t* dst) {
+      const int64_t row = (int64_t)min(ry, ny - 1) * nx;
+#pragma unroll
+      for (int k = 0; k < KC; ++k) dst[k] = (uint32_t)d[row + min(cb + (int)threadIdx.x + 256 * k, nx - 1)];
+    };
+#pragma unroll
+    for (int p = 0; p < P; ++p) load_row(p, cnt[p]);
+    for (int ry0 = 0; ry0 < ny; ry0 += P) {
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        const int ry = ry0 + p;
+        const bool rowok = ry < ny;  // past the last row: counts dropped, the row adds 0
+        // the thread's partial of the row: KC products in FP32 (counts below 2^16 are exact; at
+        // Q = 0 every product and sum is an exact integer), then FP64
+        float fre[GQ], fim[GQ];
+#pragma unroll
+        for (int j = 0; j < GQ; ++j) fre[j] = fim[j] = 0.f;
+#pragma unroll
+        for (int k = 0; k < KC; ++k) {
+          const float c = (float)(rowok && colok[k] ? cnt[p][k] : 0u);
+#pragma unroll
+          for (int j = 0; j < GQ; ++j) {
+            fre[j] = fmaf(c, twr[j][k], fre[j]);
+            fim[j] = fmaf(c, twi[j][k], fim[j]);
+          }
+        }
+        double rre[GQ], rim[GQ];
+#pragma unroll
+        for (int j = 0; j < GQ; ++j) {
+          rre[j] = (double)fre[j];
+          rim[j] = (double)fim[j];
+        }
+        load_row(ry + P, cnt[p]);
+#pragma unroll
+        for (int j = 0; j < GQ; ++j) {
+          const float2 w = s_wy[yi[j]];
+          are[j] += rre[j] * (double)w.x - rim[j] * (double)w.y;
+          aim[j] += rre[j] * (double)w.y + rim[j] * (double)w.x;
+          yi[j] += my[j];
+          if (yi[j] >= ny) yi[j] -= ny;
         }
       }
-#pragma unroll
-      for (int j = 0; j < kPanelGroup; ++j) {
-        xi[j] += xs[j];
-        if (xi[j] >= nx) xi[j] -= nx;
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < kPanelGroup; ++j) {
-      const float2 w = s_wy[yi[j]];
-      are[j] += rre[j] * (double)w.x - rim[j] * (double)w.y;
-      aim[j] += rre[j] * (double)w.y + rim[j] * (double)w.x;
-      yi[j] += my[j];
-      if (yi[j] >= ny) yi[j] -= ny;
     }
   }
 #pragma unroll
-  for (int j = 0; j < kPanelGroup; ++j) {
+  for (int j = 0; j < GQ; ++j) {
     double re = are[j], im = aim[j];
     for (int o = 32; o > 0; o >>= 1) {
       re += __shfl_xor(re, o);
@@ -1081,10 +1125,10 @@ extern "C" int ssb_g_panel(const stem_det* det, const stem_scan* scan, const ste
   } else {
     const dim3 grid((unsigned)(nbx * nby), (unsigned)((n_q + kPanelGroup - 1) / kPanelGroup));
     if (ssb->d_bits == 8)
-      hipLaunchKernelGGL(k_g_panel_d<uint8_t>, grid, dim3(256), 0, s, (const uint8_t*)b.D, b.rows, nbx, n_k,
+      hipLaunchKernelGGL((k_g_panel_d<uint8_t, kPanelGroup>), grid, dim3(256), 0, s, (const uint8_t*)b.D, b.rows, nbx, n_k,
                          scan->ny, scan->nx, q, n_q, (float2*)d_img);
     else
-      hipLaunchKernelGGL(k_g_panel_d<uint16_t>, grid, dim3(256), 0, s, (const uint16_t*)b.D, b.rows, nbx, n_k,
+      hipLaunchKernelGGL((k_g_panel_d<uint16_t, kPanelGroup>), grid, dim3(256), 0, s, (const uint16_t*)b.D, b.rows, nbx, n_k,
                          scan->ny, scan->nx, q, n_q, (float2*)d_img);
   }
   STEM_LAUNCH_CHECK();
