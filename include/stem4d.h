@@ -50,7 +50,7 @@ typedef enum {
   STEM_EOVERFLOW = 8,   /* device: a binned count does not fit the binned-cube element type */
   STEM_EWORKSPACE = 16, /* workspace / state buffer smaller than the size query returns     */
   STEM_EHIP = 32,       /* a HIP runtime call failed (launch, copy)                         */
-  STEM_ESTATE = 64      /* state buffer was not prepared by the mode this call needs        */
+  STEM_ESTATE = 64      /* device: the state holds no FINALIZE (a REFOCUS or backward call)  */
 } stem_status;
 
 const char* stem_strerror(int status);
@@ -264,7 +264,9 @@ size_t ssb_state_bytes(const stem_det* det, const stem_scan* scan, const stem_op
  *   and transforms them along x into the state.  d_phase, d_T unused.
  * mode FINALIZE: needs every row accumulated; writes d_phase[F] (row-major, may be NULL)
  *   and d_T[2F] (interleaved complex64 row-major [my][mx], may be NULL).
- * mode REFOCUS: needs a FINALIZE on this state; the sum and the phase again for the given
+ * mode REFOCUS: needs a FINALIZE on this state (with this layout: same det, scan, optics
+ *   r_bf/dk/lam and ssb), else its sum reads nothing of the state and reports the device bit
+ *   STEM_ESTATE, and d_phase, d_T are undefined; the sum and the phase again for the given
  *   optics.c and theta: from the stored double-overlap values of G (STEM_G_STORE, the paper's
  *   interactive mode), or with G recomputed from the binned counts (STEM_G_RECOMPUTE).
  * mode ONESHOT: ACCUMULATE of all F frames then FINALIZE.
@@ -272,7 +274,7 @@ size_t ssb_state_bytes(const stem_det* det, const stem_scan* scan, const stem_op
  * r_bf/dk/lam and ssb must stay the same across the calls sharing a state.
  * Errors: STEM_EINVAL (geometry, sizes, non-row chunks, a scan length the transforms do not
  * take, a split precision with a length other than a power of two in [32, 1024], n_K = 0 or
- * > 4096), STEM_EWORKSPACE, STEM_ESTATE; device bits ERANGE/EOVERFLOW. */
+ * > 4096), STEM_EWORKSPACE; device bits ERANGE/EOVERFLOW, and STEM_ESTATE (REFOCUS). */
 int ssb_reconstruct(const int32_t* d_idx, const int64_t* d_off, int64_t frame0, int64_t n_frames,
                     const stem_det* det, const stem_scan* scan, const stem_optics* optics,
                     const stem_ssb* ssb, int mode, const float* d_theta, void* state,
@@ -355,8 +357,10 @@ int ssb_g_panel(const stem_det* det, const stem_scan* scan, const stem_optics* o
  *   d_dLdtheta[kd] = -sum over Q of w                                  (FP32, [n_K], may be NULL).
  * G is read from the stored double-overlap values (g_mode STORE) or recomputed chunk by chunk
  * from the binned counts (g_mode RECOMPUTE).  normalize must be 0.  The state's counters
- * (STEM_REGION_STATS) keep describing the last sum.
- * Errors: STEM_EINVAL, STEM_EWORKSPACE, STEM_ESTATE. */
+ * (STEM_REGION_STATS) keep describing the last sum.  On a state that holds no FINALIZE the
+ * adjoint kernels read nothing of it and report the device bit STEM_ESTATE (then d_dLdc and
+ * d_dLdtheta are undefined).
+ * Errors: STEM_EINVAL, STEM_EWORKSPACE; device bit STEM_ESTATE. */
 int ssb_backward(const float* d_dLdphi, const stem_det* det, const stem_scan* scan,
                  const stem_optics* optics, const stem_ssb* ssb, const float* d_theta,
                  void* state, size_t state_bytes, double* d_dLdc, float* d_dLdtheta,

@@ -16,7 +16,8 @@ from ._abi import (Det, Dpc, Optics, Scan, Ssb, StemError, lib, LIB_PATH, STEM_F
                    STEM_DFT_BF16_SPLIT, STEM_DFT_FP16_SPLIT, STEM_G_RECOMPUTE, STEM_G_STORE,
                    STEM_SSB_ACCUMULATE, STEM_SSB_FINALIZE, STEM_SSB_REFOCUS, STEM_SSB_ONESHOT,
                    STEM_REGION_D, STEM_REGION_X, STEM_REGION_T, STEM_REGION_KC, STEM_REGION_STATS, STEM_REGION_PG,
-                   STEM_REGION_POFF, STEM_REGION_NPAIR, STATUS_BITS, strerror, trace_enable,
+                   STEM_REGION_POFF, STEM_REGION_NPAIR, STEM_ERANGE, STEM_EOFFSETS, STEM_EOVERFLOW,
+                   STEM_EWORKSPACE, STEM_EHIP, STEM_ESTATE, STATUS_BITS, strerror, trace_enable,
                    trace_records)
 
 __all__ = [
@@ -27,7 +28,8 @@ __all__ = [
     "STEM_G_STORE", "STEM_SSB_ACCUMULATE", "STEM_SSB_FINALIZE", "STEM_SSB_REFOCUS",
     "STEM_SSB_ONESHOT", "SsbState", "SSBPhase", "ssb_state_region", "STEM_REGION_D", "STEM_REGION_X",
     "STEM_REGION_T", "STEM_REGION_KC", "STEM_REGION_STATS", "STEM_REGION_PG", "STEM_REGION_POFF", "STEM_REGION_NPAIR",
-    "com_dpc_noalloc", "trace_enable", "trace_records",
+    "com_dpc_noalloc", "trace_enable", "trace_records", "STEM_ERANGE", "STEM_EOFFSETS", "STEM_EOVERFLOW",
+    "STEM_EWORKSPACE", "STEM_EHIP", "STEM_ESTATE",
     "virtual_annular", "sum_frames", "eer_decode_rle", "ssb_g_panel", "ssb_reconstruct_com",
 ]
 

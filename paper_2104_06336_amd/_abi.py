@@ -13,6 +13,8 @@ STEM_SSB_ACCUMULATE, STEM_SSB_FINALIZE, STEM_SSB_REFOCUS, STEM_SSB_ONESHOT = 0, 
 STEM_REGION_D, STEM_REGION_X, STEM_REGION_T, STEM_REGION_KC, STEM_REGION_STATS = 0, 1, 2, 3, 4
 STEM_REGION_PG, STEM_REGION_POFF, STEM_REGION_NPAIR = 5, 6, 7
 
+STEM_ERANGE, STEM_EOFFSETS, STEM_EOVERFLOW, STEM_EWORKSPACE, STEM_EHIP, STEM_ESTATE = 2, 4, 8, 16, 32, 64
+
 STATUS_BITS = {1: "EINVAL", 2: "ERANGE", 4: "EOFFSETS", 8: "EOVERFLOW", 16: "EWORKSPACE", 32: "EHIP",
                64: "ESTATE"}
 

@@ -68,6 +68,7 @@ __global__ void __launch_bounds__(64 * W) k_row_fft(RowFftArgs a, int in_mode, i
                                : threadIdx.x == 2 ? 8ull * u
                                                   : (unsigned long long)a.stats_chunks;
       }
+      if (threadIdx.x == 4 && a.ready_out) *a.ready_out = a.ready_val;
     }
   }
   fill_twiddles(s_tw, threadIdx.x, kRowThreads);
@@ -98,8 +99,8 @@ __global__ void __launch_bounds__(64 * W) k_row_fft(RowFftArgs a, int in_mode, i
         int b, n;
         fft_in_index<N>(lane, 0, b, n);
         const int64_t r = r0 + b;
-        const int64_t s0 = r < a.nrows ? a.part_seg[r] : 0;
-        const int sn = r < a.nrows ? (int)(a.part_seg[r + 1] - s0) : 0;
+        const int64_t s0 = r < a.nrows ? min(max(a.part_seg[r], (int64_t)0), a.part_seg_rows) : 0;
+        const int sn = r < a.nrows ? (int)(min(max(a.part_seg[r + 1], s0), a.part_seg_rows) - s0) : 0;
         int most = sn;
         for (int off = 32; off > 0; off >>= 1) most = max(most, __shfl_xor(most, off));
         for (int q = 0; q < most; ++q) {
@@ -288,6 +289,7 @@ __global__ void __launch_bounds__(kGenThreads) k_grow_fft(RowFftArgs a, GPlan p,
                              : threadIdx.x == 2 ? 8ull * u
                                                 : (unsigned long long)a.stats_chunks;
     }
+    if (threadIdx.x == 4 && a.ready_out) *a.ready_out = a.ready_val;
   }
   gen_twiddles(tw, n);
   __syncthreads();
@@ -306,7 +308,9 @@ __global__ void __launch_bounds__(kGenThreads) k_grow_fft(RowFftArgs a, GPlan p,
           x = a.in_c[el];
         } else if (in_mode == IN_C64_SUM) {
           if (a.part_seg) {
-            for (int64_t q = a.part_seg[r]; q < a.part_seg[r + 1]; ++q) x = cadd(x, a.in_c[q * n + i]);
+            const int64_t q0 = min(max(a.part_seg[r], (int64_t)0), a.part_seg_rows);
+            const int64_t q1 = min(max(a.part_seg[r + 1], q0), a.part_seg_rows);
+            for (int64_t q = q0; q < q1; ++q) x = cadd(x, a.in_c[q * n + i]);
           } else {
             for (int q = 0; q < a.nparts; ++q) x = cadd(x, a.in_c[(int64_t)q * a.part_stride + el]);
           }

@@ -44,7 +44,8 @@ struct RowFftArgs {
   int64_t part_stride;
   int32_t nparts;
   const int64_t* part_seg; // IN_C64_SUM: if set, row r adds rows part_seg[r] .. part_seg[r+1]-1 of in_c
-                           // (n values each) instead of the nparts planes
+                           // (n values each) instead of the nparts planes, clamped to
+  int64_t part_seg_rows;   // the rows in_c holds
   float2* sum_out;         // IN_C64_SUM: if set, the summed input is also stored here (row-major)
   const float* in_f0;      // IN_F32_PAIR: re = in_f0[r*n + j]*s0, im = in_f1[...]*s1 (in_f1 may be null)
   const float* in_f1;
@@ -72,6 +73,8 @@ struct RowFftArgs {
   unsigned long long* stats;
   int32_t stats_groups;
   int32_t stats_chunks;
+  unsigned long long* ready_out;  // IN_C64_SUM with stats: if set, the first workgroup also stores
+  unsigned long long ready_val;   // ready_val there (the state's mark of a finished FINALIZE)
 };
 
 int launch_row_fft(int n, bool inverse, RowIn in, RowOut out, const RowFftArgs& a, hipStream_t stream);

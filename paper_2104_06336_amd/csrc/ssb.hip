@@ -50,6 +50,7 @@ struct SsbLayout {
   int64_t nwp;  // waves of the refocus sum over the full columns of G (other scan lengths)
   int64_t nws;  // pieces the refocus sum over the stored values aims at
   int64_t nwq;  // STEM_G_STORE: waves (at most) of the refocus sum over the stored values
+  int64_t part_rows;  // rows of Ny values the partial-sum buffer holds
   int64_t nwa;  // dL/dc partials of the adjoint over the stored values (one per workgroup)
 };
 
@@ -134,7 +135,8 @@ static size_t make_layout(const stem_det& det, const stem_scan& scan, const stem
   }
   L->cmask = o; o = align256(o + sizeof(uint64_t) * (size_t)L->nmw * L->ncs);
   L->lut = o;   o = align256(o + sizeof(int16_t) * (size_t)det.W * det.H);
-  L->stats = o; o = align256(o + sizeof(unsigned long long) * 4);
+  // the counters of the last sum, then the mark a FINALIZE leaves (ready_tag)
+  L->stats = o; o = align256(o + sizeof(unsigned long long) * 5);
   L->npq = o;   o = align256(o + sizeof(int32_t) * (size_t)L->F);
   L->D = o;     o = align256(o + (size_t)n_k * L->F * (ssb.d_bits / 8));
   L->X = o;     o = align256(o + (size_t)L->xpix * per_pixel);
@@ -181,6 +183,7 @@ static size_t make_layout(const stem_det& det, const stem_scan& scan, const stem
   // the refocus sum
   size_t part_rows = (size_t)parts * scan.nx;
   if (part_rows < (size_t)L->nwq) part_rows = (size_t)L->nwq;
+  L->part_rows = (int64_t)part_rows;
   L->part = o;  o = align256(o + part_rows * scan.ny * sizeof(float2));
   L->wcnt = o;  o = align256(o + (size_t)nw * sizeof(unsigned long long));
   // the refocus sum's tables (STEM_G_STORE): per piece its first run and entries, per column
@@ -545,6 +548,12 @@ struct Bufs {
   int64_t* pcs;              // refocus sum: per column its first piece, cost and span of runs
 };
 
+// The value a FINALIZE leaves in the state's mark word: a constant mixed with the layout's size,
+// so that a state prepared for another layout, or never finalized, does not show it by chance.
+static unsigned long long ready_tag(const SsbLayout& L) {
+  return 0x5ab3f1d2c4e5968bull ^ ((unsigned long long)L.total * 0x9e3779b97f4a7c15ull);
+}
+
 static Bufs carve(void* state, const SsbLayout& L) {
   char* p = (char*)state;
   return Bufs{(RowRun*)(p + L.rows), (double2*)(p + L.kc), (double*)(p + L.kchi), (int4*)(p + L.cst),
@@ -601,6 +610,14 @@ static YArgs yargs(const SsbLayout& L, const Bufs& b, int nx) {
   return a;
 }
 
+// the check of refocus and adjoint calls: their sum kernels do nothing, and report STEM_ESTATE,
+// on a state that no FINALIZE has marked
+static void need_finalize(YArgs& a, const SsbLayout& L, const Bufs& b, int32_t* d_status) {
+  a.ready = b.stats + 4;
+  a.ready_tag = ready_tag(L);
+  a.status = d_status;
+}
+
 // pixels [k0, k1) of chunk ch
 static void chunk_range(const SsbLayout& L, int ch, int& k0, int& k1) {
   k0 = (int)((int64_t)L.n_k * ch / L.nchunks);
@@ -649,8 +666,9 @@ static int colfft_generic(const SsbLayout& L, int ny, int k0, int k1, const floa
 // state's counters.
 // part_seg: the partials are the rows of the refocus sum's pieces (row mx of T adds rows
 // part_seg[mx] .. part_seg[mx + 1] - 1 of b.part) instead of nparts planes
+// mark: the call is a FINALIZE, and the first pass leaves ready_tag in the state's mark word
 static int run_phase(const SsbLayout& L, const Bufs& b, const stem_scan& sc, int nparts, int64_t nwaves, int nchunks,
-                     const int32_t* npq, float* d_phase, float* d_T, hipStream_t s,
+                     const int32_t* npq, float* d_phase, float* d_T, hipStream_t s, bool mark,
                      const int64_t* part_seg = nullptr) {
   const int ny = sc.ny, nx = sc.nx;
   RowFftArgs a{};
@@ -660,6 +678,7 @@ static int run_phase(const SsbLayout& L, const Bufs& b, const stem_scan& sc, int
   a.nparts = nparts;
   a.part_stride = L.F;
   a.part_seg = part_seg;
+  a.part_seg_rows = L.part_rows;
   a.sum_out = b.T;
   a.norm_cnt = npq;
   a.out_c = b.A;
@@ -671,6 +690,8 @@ static int run_phase(const SsbLayout& L, const Bufs& b, const stem_scan& sc, int
   a.stats = b.stats;
   a.stats_groups = nparts;
   a.stats_chunks = nchunks;
+  a.ready_out = mark ? b.stats + 4 : nullptr;
+  a.ready_val = ready_tag(L);
   int st = launch_row_fft(ny, true, IN_C64_SUM, OUT_T_C64, a, s);
   if (st) return st;
   if (d_phase) {
@@ -823,13 +844,15 @@ static int reconstruct(const int32_t* d_idx, const int64_t* d_off, int64_t frame
   }
   if (ssb->normalize && !refocus && (st = run_pair_count(L, b, ny, nx, s))) return st;
   YArgs a = yargs(L, b, nx);
+  if (refocus) need_finalize(a, L, b, d_status);
   if (L.store && refocus) {
     // Eq. 3 again from the stored double-overlap values
     a.ngroups = L.pgroups;
     a.kch_inline = 1;
     a.theta = d_theta;
     if ((st = launch_psum_stream(ny, a, o, chi0, (int)L.nwq, b.pws, b.pcs, s))) return st;
-    return run_phase(L, b, *scan, L.pgroups, L.nwq, 1, ssb->normalize ? b.npq : nullptr, d_phase, d_T, s, b.pcs);
+    return run_phase(L, b, *scan, L.pgroups, L.nwq, 1, ssb->normalize ? b.npq : nullptr, d_phase, d_T, s, false,
+                     b.pcs);
   } else if (!L.fast) {
     // the other scan lengths: row and column transforms by the generic FFT, then Eq. 3 per
     // (pixel, column) run over the full columns of G, chunk by chunk
@@ -854,7 +877,8 @@ static int reconstruct(const int32_t* d_idx, const int64_t* d_off, int64_t frame
       a.accumulate = ch > 0;
       if ((st = launch_psum(ny, a, o, chi0, L.store, s))) return st;
     }
-    return run_phase(L, b, *scan, L.pgroups, L.nwp, L.nchunks, ssb->normalize ? b.npq : nullptr, d_phase, d_T, s);
+    return run_phase(L, b, *scan, L.pgroups, L.nwp, L.nchunks, ssb->normalize ? b.npq : nullptr, d_phase, d_T, s,
+                     !refocus);
   } else if (L.store) {
     if ((st = run_prune_offsets(L, b, nx, d_status, s))) return st;
     if ((st = launch_yreduce(ssb->precision, ny, a, o, chi0, 1, s))) return st;
@@ -872,7 +896,7 @@ static int reconstruct(const int32_t* d_idx, const int64_t* d_off, int64_t frame
     }
   }
   return run_phase(L, b, *scan, L.groups, L.nwy, L.store ? 1 : L.nchunks, ssb->normalize ? b.npq : nullptr, d_phase,
-                   d_T, s);
+                   d_T, s, !refocus);
 }
 
 extern "C" int ssb_reconstruct(const int32_t* d_idx, const int64_t* d_off, int64_t frame0, int64_t n_frames,
@@ -1139,7 +1163,6 @@ extern "C" int ssb_backward(const float* d_dLdphi, const stem_det* det, const st
                             const stem_optics* optics, const stem_ssb* ssb, const float* d_theta, void* state,
                             size_t state_bytes, double* d_dLdc, float* d_dLdtheta, int32_t* d_status,
                             void* stream_) {
-  (void)d_status;
   int n_k;
   int st = check_common(det, scan, optics, ssb, &n_k);
   if (st) return st;
@@ -1172,6 +1195,7 @@ extern "C" int ssb_backward(const float* d_dLdphi, const stem_det* det, const st
   // values); the interval table and mask are the last sum's
   if (!L.store && (st = run_chi_table(b, d_theta, n_k, o, s))) return st;
   YArgs y = yargs(L, b, nx);
+  need_finalize(y, L, b, d_status);
   int64_t npdc = L.nwy, npdth = L.ncs;
   const int64_t* pieces = nullptr;
   if (L.store) {

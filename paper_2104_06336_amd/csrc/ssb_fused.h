@@ -262,7 +262,20 @@ struct YArgs {
   // null) instead of read from kchi
   int kch_inline;
   const float* theta;
+  // a call that needs a FINALIZE of the state (refocus, adjoint) passes the state's mark of one and
+  // the value a FINALIZE with this layout leaves there; null: no check
+  const unsigned long long* ready;
+  unsigned long long ready_tag;
+  int32_t* status;
 };
+
+// A kernel of a call that needs a FINALIZE: true when the state holds none (the first thread of the
+// grid reports STEM_ESTATE); the whole workgroup returns then, reading nothing of the state.
+__device__ __forceinline__ bool state_unready(const YArgs& a) {
+  if (a.ready == nullptr || *a.ready == a.ready_tag) return false;
+  if (blockIdx.x == 0 && threadIdx.x == 0) report(a.status, STEM_ESTATE);
+  return true;
+}
 
 constexpr int kLoadShift = 40;  // wcnt packs the pair count below bit 40, the 8-byte loads above
 
@@ -343,6 +356,7 @@ struct MaskScan {
 
 template <typename XF, bool CHI0, bool PWRITE>
 __global__ void __launch_bounds__(kYThreads, 2) k_yreduce(YArgs a, Optics o) {
+  if (state_unready(a)) return;
   constexpr int NY = XF::N;
   __shared__ float2 s_tw[1024];
   __shared__ float2 s_buf[XF::kMfma ? 1 : 4 * kXWaveStride];
@@ -671,6 +685,7 @@ constexpr bool slots_consecutive() {
 // pixel's sum of w.  Partials: pdc[wave][8] (FP64), pdth[column set][kd] (FP32; one writer).
 template <typename XF>
 __global__ void __launch_bounds__(kYThreads, 2) k_yadjoint(YArgs a, Optics o) {
+  if (state_unready(a)) return;
   static_assert(slots_consecutive<XF>(), "the registers of a slot are consecutive");
   constexpr int NY = XF::N;
   __shared__ float2 s_tw[1024];

@@ -303,6 +303,7 @@ __device__ __forceinline__ unsigned long long sum_batch(const YArgs& a, const Ru
 // (column-major [mx][my], summed by the phase pass like the fused sum's).
 template <bool CHI0, bool FULLG, bool PWRITE>
 __global__ void __launch_bounds__(64 * kPrunedCols) k_psum(YArgs a, Optics o, int ny) {
+  if (state_unready(a)) return;
   extern __shared__ __align__(16) unsigned char s_dyn[];
   const int W = blockDim.x >> 6;
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -366,6 +367,7 @@ __global__ void __launch_bounds__(64 * kPrunedCols) k_psum_stream(YArgs a, Optic
   const int W = blockDim.x >> 6;
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   float2* t = (float2*)(s_dyn + (size_t)wave * pruned_wave_lds(ny));
+  if (state_unready(a)) return;
   const int nx = a.nx, n_k = a.n_k, nc = nx / 2 + 1;
   const int64_t wid = (int64_t)blockIdx.x * W + wave;
   if (wid >= nwmax || wid >= ctab[nx]) {
@@ -373,10 +375,17 @@ __global__ void __launch_bounds__(64 * kPrunedCols) k_psum_stream(YArgs a, Optic
     return;
   }
   const PieceTab pc = wtab[wid];
+  // tables outside their ranges read nothing: the piece adds 0
+  if (!(pc.run >= 0 && pc.run < (int64_t)nx * n_k && pc.e0 >= 0 && pc.e0 <= pc.e1 && pc.e1 <= a.pcap)) {
+    for (int k = lane; k < ny; k += 64) a.part[wid * ny + k] = make_float2(0.f, 0.f);
+    if (lane == 0) a.wcnt[wid] = 0ull;
+    return;
+  }
   const int64_t E0 = pc.e0, E1 = pc.e1;
   int64_t i = pc.run;
   const int mx = (int)(i / n_k);
-  const int64_t cend = ctab[(nx + 2) + 3 * (int64_t)mx + 2];
+  const int64_t cend =
+      min(max(ctab[(nx + 2) + 3 * (int64_t)mx + 2], i + 1), (int64_t)(mx + 1) * n_k);  // within the column
   const bool mir = 2 * mx > nx;
   const int c = mir ? nx - mx : mx;
   double qx = 0.0;
@@ -397,9 +406,10 @@ __global__ void __launch_bounds__(64 * kPrunedCols) k_psum_stream(YArgs a, Optic
       const int64_t e0 = a.poff[i + lane], e1 = a.poff[i + lane + 1];
       e1raw = e1;
       if (e0 >= 0 && e1 >= e0 && e1 <= a.pcap) {
+        const int64_t b0 = min(max(e0, E0), e1);  // the run's entries inside the piece: [b0, b1)
         d.e0 = e0;
-        d.lo = (int)(max(e0, E0) - e0);
-        d.len = max(d.lo, (int)(min(e1, E1) - e0));
+        d.lo = (int)(b0 - e0);
+        d.len = (int)(max(min(e1, E1), b0) - e0);
       }
       d.a0 = st.a0;
       d.hl = h0 <= h1 ? h1 - h0 + 1 : 0;
@@ -669,6 +679,7 @@ __device__ __forceinline__ float adj_batch(const YArgs& a, const Optics& o, cons
 // workgroup's four waves combined into one dL/dc partial.
 template <bool FULLG>
 __global__ void __launch_bounds__(64 * kAdjWaves) k_padj(YArgs a, Optics o, int ny) {
+  if (state_unready(a)) return;
   extern __shared__ __align__(16) unsigned char s_dyn[];
   constexpr int W = kAdjWaves;
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -724,6 +735,7 @@ __global__ void __launch_bounds__(64 * kPrunedCols) k_padj_stream(YArgs a, Optic
   const int W = blockDim.x >> 6;
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   float2* tb = (float2*)(s_dyn + (size_t)wave * padj_block_lds(ny));
+  if (state_unready(a)) return;
   const int nx = a.nx, n_k = a.n_k;
   const int64_t wid = (int64_t)blockIdx.x * W + wave;
   if (wid >= nwmax) return;
@@ -732,12 +744,18 @@ __global__ void __launch_bounds__(64 * kPrunedCols) k_padj_stream(YArgs a, Optic
     return;
   }
   const PieceTab pc = wtab[wid];
+  // tables outside their ranges read nothing
+  if (!(pc.run >= 0 && pc.run < (int64_t)nx * n_k)) {
+    if (lane < 8) a.pdc[wid * 8 + lane] = 0.0;
+    return;
+  }
   const int mx = (int)(pc.run / n_k);
   const int64_t c0 = (int64_t)mx * n_k;
   const int64_t* col = ctab + (nx + 2) + 3 * (int64_t)mx;
-  const int64_t ga = max(pc.ra, col[1]), gb = min(pc.rb, col[2]);
+  const int64_t ra = min(max(pc.ra, c0), c0 + n_k), rb = min(max(pc.rb, ra), c0 + n_k);
+  const int64_t ga = min(max(col[1], ra), rb), gb = min(max(col[2], ga), rb);
   float* pth = a.pdth + c0;
-  for (int64_t r = pc.ra + lane; r < pc.rb; r += 64)
+  for (int64_t r = ra + lane; r < rb; r += 64)
     if (r < ga || r >= gb) pth[r - c0] = 0.f;
   for (int i = lane; i < ny; i += 64) tb[i] = a.Tbt[(int64_t)mx * ny + i];
   const double qx = (double)signed_index(mx, nx) * o.sx;

@@ -9,7 +9,9 @@
 - a single event in the whole scan;
 - REFOCUS and the adjoint over the stored values on the irregular data (the balanced pieces of
   those sums over sparse and pile-up columns, other-length and fused scans), and on the
-  degenerate cases (no kept events: T, phi and the gradients 0; no double-overlap pair: the same).
+  degenerate cases (no kept events: T, phi and the gradients 0; no double-overlap pair: the same);
+- REFOCUS and the adjoint on a state that no FINALIZE has marked: STEM_ESTATE, and after a
+  FINALIZE both run clean, REFOCUS at FINALIZE's coefficients giving its phase.
 """
 import numpy as np
 import pytest
@@ -177,3 +179,37 @@ def test_refocus_and_adjoint_without_pairs(gpu):
     st, out = gpu_ssb(d_idx, d_off, wl, g_mode=stem.STEM_G_STORE)
     assert out["status"] == 0 and st.pair_count() == 0
     _zero_refocus_and_adjoint(st, wl)
+
+
+@pytest.mark.parametrize("g_mode", MODES, ids=["store", "recompute"])
+@pytest.mark.parametrize("scan", [(48, 40), (32, 64)], ids=["48x40", "32x64"])
+def test_refocus_and_adjoint_need_a_finalize(gpu, scan, g_mode):
+    wl = SMALL.replace(scan=scan)
+    H, W = wl.det
+    F = wl.n_frames
+    idx, off = random_csr(np.random.default_rng(13), F, W, H, mean=30.0)
+    d_idx, d_off = to_device(idx, off)
+    det, scn, optics = structs(wl)
+    st = stem.SsbState(det, scn, optics, stem.Ssb(stem.STEM_FFT_FP32, 0, g_mode, 8), device="cuda")
+    st.state.zero_()  # a fresh state: no FINALIZE mark
+    st.accumulate(d_idx, d_off, 0, F)
+    torch.cuda.synchronize()
+    assert int(st.status.item()) == 0
+    c = (10.0, 1.0, -1.0, 0, 0, 0, 0, 0)
+    gbar = torch.linspace(-1.0, 1.0, F, dtype=torch.float32, device="cuda")
+    phase = torch.zeros(F, dtype=torch.float32, device="cuda")
+    st.refocus(c=c, phase=phase)
+    torch.cuda.synchronize()
+    assert int(st.status.item()) == stem.STEM_ESTATE
+    st.status.zero_()
+    st.backward(gbar, c=c)
+    torch.cuda.synchronize()
+    assert int(st.status.item()) == stem.STEM_ESTATE
+    st.status.zero_()
+    ref = torch.zeros(F, dtype=torch.float32, device="cuda")
+    st.finalize(c=c, phase=ref)
+    st.refocus(c=c, phase=phase)
+    st.backward(gbar, c=c)
+    torch.cuda.synchronize()
+    assert int(st.status.item()) == 0
+    assert rel_l2(phase.cpu().numpy(), ref.cpu().numpy()) <= TOL
