@@ -421,15 +421,20 @@ __global__ void __launch_bounds__(256) k_prune_add(int n_k, int64_t* __restrict_
 }
 
 // number of pixel groups of the fused sum: about 4096 waves, at most n_k, partial sums <= 64 MB
+#ifndef STEM_YREDUCE_WAVES
+#define STEM_YREDUCE_WAVES 2560
+#endif
+
 static int yreduce_groups(int ny, int nx, int n_k) {
   const int B = colset_width(ny);
   const int ncs = (nx / 2 + 1 + B - 1) / B;
   // about 2560 waves: 1.25 times the waves the GPU holds at once (256 CUs x 8 at this kernel's
   // register use), so that waves of cheap columns (few pixels with a non-empty set) free their
-  // slots for the rest; measured at scan1024 (513 column sets): 5 groups 139 us, 4 groups 145 us,
-  // 8 groups 156 us
+  // slots for the rest; measured at scan1024 (513 column sets, no aberrations, each launch traced):
+  // 3 groups 216-224 us, 4 groups 189-192, 5 groups 170-179, 6 groups 191-193, 7 groups 196-199,
+  // 8 groups 188-191
   const int blocks_per_group = (ncs + 3) / 4;
-  int g = (2560 + 2 * blocks_per_group) / (4 * blocks_per_group);
+  int g = (STEM_YREDUCE_WAVES + 2 * blocks_per_group) / (4 * blocks_per_group);
   const int64_t F = (int64_t)ny * nx;
   const int gmax = (int)((64ll << 20) / (F * 8));
   if (g > gmax) g = gmax;
