@@ -362,6 +362,9 @@ def main():
     ap.add_argument("--fused-com", action="store_true",
                     help="centre of mass formed by the binning pass (ssb_reconstruct_com) instead of its own "
                          "pass over the events on the second stream")
+    ap.add_argument("--schedules", choices=("both", "serial", "overlapped"), default="both",
+                    help="step schedules timed (serial: one stream only, so that a kernel trace of the run "
+                         "holds only dispatches that no other kernel shares the GPU with)")
     ap.add_argument("--no-default-scratch", action="store_true",
                     help="skip the step timed with the library's default recompute scratch (profiling runs)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
@@ -505,8 +508,9 @@ def main():
     # headline (step times from untraced runs)
     modes = [args.g_mode] if args.g_mode != "auto" else ["recompute", "store"]
     schedules = {}
+    ovs = {"both": (False, True), "serial": (False,), "overlapped": (True,)}[args.schedules]
     for m in modes:
-        for ov in (False, True):
+        for ov in ovs:
             r = run(stem.STEM_FFT_FP32, G_MODES[m], args.steps, args.warmup, overlap=ov)
             schedules[f"{m}/{'overlapped' if ov else 'serial'}"] = r
             log(f"FP32 {m:9s} {'overlapped' if ov else 'serial':10s}: mean {r['ms']:.4f} ms, median "
