@@ -265,7 +265,8 @@ size_t ssb_state_bytes(const stem_det* det, const stem_scan* scan, const stem_op
  * mode FINALIZE: needs every row accumulated; writes d_phase[F] (row-major, may be NULL)
  *   and d_T[2F] (interleaved complex64 row-major [my][mx], may be NULL).
  * mode REFOCUS: needs a FINALIZE on this state (with this layout: same det, scan, optics
- *   r_bf/dk/lam and ssb), else its sum reads nothing of the state and reports the device bit
+ *   r_bf/dk/lam and ssb) after its last ACCUMULATE from frame 0 (which voids an earlier
+ *   FINALIZE), else its sum reads nothing of the state and reports the device bit
  *   STEM_ESTATE, and d_phase, d_T are undefined; the sum and the phase again for the given
  *   optics.c and theta: from the stored double-overlap values of G (STEM_G_STORE, the paper's
  *   interactive mode), or with G recomputed from the binned counts (STEM_G_RECOMPUTE).
@@ -357,9 +358,9 @@ int ssb_g_panel(const stem_det* det, const stem_scan* scan, const stem_optics* o
  *   d_dLdtheta[kd] = -sum over Q of w                                  (FP32, [n_K], may be NULL).
  * G is read from the stored double-overlap values (g_mode STORE) or recomputed chunk by chunk
  * from the binned counts (g_mode RECOMPUTE).  normalize must be 0.  The state's counters
- * (STEM_REGION_STATS) keep describing the last sum.  On a state that holds no FINALIZE the
- * adjoint kernels read nothing of it and report the device bit STEM_ESTATE (then d_dLdc and
- * d_dLdtheta are undefined).
+ * (STEM_REGION_STATS) keep describing the last sum.  On a state with no FINALIZE since its
+ * last ACCUMULATE from frame 0, the adjoint kernels read nothing of it and report the device
+ * bit STEM_ESTATE (then d_dLdc and d_dLdtheta are undefined).
  * Errors: STEM_EINVAL, STEM_EWORKSPACE; device bit STEM_ESTATE. */
 int ssb_backward(const float* d_dLdphi, const stem_det* det, const stem_scan* scan,
                  const stem_optics* optics, const stem_ssb* ssb, const float* d_theta,

@@ -513,6 +513,8 @@ struct GeomOut {
   double2* kc;
   int32_t nbx, nby, cx, cy;
   double r2;
+  unsigned long long* mark;  // if set, cleared by the first thread (an accumulation from frame 0
+                             // voids the state's FINALIZE)
 };
 
 // One step of a segmented inclusive scan within rows of 16 lanes: lane i adds the sums of lane
@@ -552,6 +554,7 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(const int32_t* __restrict__
   __shared__ int32_t s_mom[COM ? 2 * kBinFrames : 1];  // [x | y][frame] moment sums of a window
   const int t = threadIdx.x;
   const int lane = t & 63;
+  if (geo.mark && blockIdx.x == 0 && t == 0) *geo.mark = 0ull;
   if (geo.rows && blockIdx.x == 0) {
     // the counters' LDS is free until the first pass clears it
     build_geometry(box.bin, geo.nbx, geo.nby, geo.cx, geo.cy, geo.r2, geo.rows, geo.kc, (int32_t*)s_hist);
@@ -851,7 +854,8 @@ bool bin_builds_sets(const stem_det& det, double r2) {
 
 int launch_bin(const int32_t* idx, const int64_t* off, int64_t frame0, int64_t n_frames,
                const stem_det& det, double r2, RowRun* rows, double2* kc, int16_t* lut, int n_k, int64_t F,
-               void* D, int d_bits, int32_t* status, hipStream_t stream, const ComOut* com, const SetsJob* sets) {
+               void* D, int d_bits, int32_t* status, hipStream_t stream, const ComOut* com, const SetsJob* sets,
+               unsigned long long* mark) {
   if (n_frames == 0) return STEM_OK;
   const int nchunks = (n_k + kBinKd - 1) / kBinKd;
   const int64_t fblocks = (n_frames + kBinFrames - 1) / kBinFrames;
@@ -872,7 +876,7 @@ int launch_bin(const int32_t* idx, const int64_t* off, int64_t frame0, int64_t n
   // per-pixel table needs them first
   GeomOut geo{};
   if (use_box) {
-    geo = GeomOut{rows, kc, nbx, nby, det.cx, det.cy, r2};
+    geo = GeomOut{rows, kc, nbx, nby, det.cx, det.cy, r2, nullptr};
   } else {
     if (int st = launch_geometry(det, r2, rows, kc, stream)) return st;
     // the per-pixel table, read by the binning kernel
@@ -882,6 +886,7 @@ int launch_bin(const int32_t* idx, const int64_t* off, int64_t frame0, int64_t n
                        det.bin, lut);
     STEM_LAUNCH_CHECK();
   }
+  geo.mark = mark;
   STEM_TRACE(com ? "bin_com" : "bin_densify", stream);
   const ComOut co = com ? *com : ComOut{};
   const int npix = det.W * det.H;

@@ -25,11 +25,12 @@ struct ComOut {
 // table lut[W*H] first when the kept bins' box is too large for LDS.  With com, the same pass also
 // writes the frames' centre of mass (as launch_com does).
 // With sets (and the LDS bin table: bin_builds_sets), the binning also builds the interval table
-// and the active-pixel mask of the fused column sum.
+// and the active-pixel mask of the fused column sum.  With mark, its first thread clears that word
+// (the state's FINALIZE mark, at an accumulation from frame 0).
 int launch_bin(const int32_t* idx, const int64_t* off, int64_t frame0, int64_t n_frames,
                const stem_det& det, double r2, RowRun* rows, double2* kc, int16_t* lut, int n_k, int64_t F,
                void* D, int d_bits, int32_t* status, hipStream_t stream, const ComOut* com = nullptr,
-               const SetsJob* sets = nullptr);
+               const SetsJob* sets = nullptr, unsigned long long* mark = nullptr);
 bool bin_builds_sets(const stem_det& det, double r2);
 
 // ---- fft2.hip: batched row FFTs of length n (power of two, 32..1024) --------------------------

@@ -821,7 +821,7 @@ static int reconstruct(const int32_t* d_idx, const int64_t* d_off, int64_t frame
     // the binning also builds the interval table and the active-pixel mask when it can (geometry only)
     const SetsJob job{o, n_k, nx, ny, L.ncs, L.nmw, b.cst, b.cmask, colset_width(ny)};
     if ((st = launch_bin(d_idx, d_off, frame0, n_frames, *det, o.r2, b.rows, b.kc, b.lut, n_k, L.F, b.D,
-                          ssb->d_bits, d_status, s, com, &job)))
+                          ssb->d_bits, d_status, s, com, &job, frame0 == 0 ? b.stats + 4 : nullptr)))
       return st;
     if (L.store && L.fast) {
       // STEM_G_STORE keeps the row transform of every pixel: transform this chunk's rows now

@@ -11,7 +11,8 @@
   those sums over sparse and pile-up columns, other-length and fused scans), and on the
   degenerate cases (no kept events: T, phi and the gradients 0; no double-overlap pair: the same);
 - REFOCUS and the adjoint on a state that no FINALIZE has marked: STEM_ESTATE, and after a
-  FINALIZE both run clean, REFOCUS at FINALIZE's coefficients giving its phase.
+  FINALIZE both run clean, REFOCUS at FINALIZE's coefficients giving its phase; a later
+  accumulation from frame 0 voids the FINALIZE again.
 """
 import numpy as np
 import pytest
@@ -213,3 +214,8 @@ def test_refocus_and_adjoint_need_a_finalize(gpu, scan, g_mode):
     torch.cuda.synchronize()
     assert int(st.status.item()) == 0
     assert rel_l2(phase.cpu().numpy(), ref.cpu().numpy()) <= TOL
+    # a new accumulation from frame 0 voids that FINALIZE
+    st.accumulate(d_idx, d_off, 0, F)
+    st.refocus(c=c, phase=phase)
+    torch.cuda.synchronize()
+    assert int(st.status.item()) == stem.STEM_ESTATE
