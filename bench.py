@@ -109,12 +109,13 @@ PROFILED = {
     "stem::k_yreduce<stem::XfFft<1024>, true, false>": "ssb_yreduce",
     "stem::k_psum_stream<false>": "ssb_reduce",
     "stem::k_padj_stream": "ssb_adjoint_pruned",
+    "stem::k_yadjoint<stem::XfFft<512> >": "ssb_yadjoint",
     "stem::k_dpc_cols<1024, 4>": "dpc_cols",
 }
 
 
 # kernels the benchmark runs on another workload than the timed step's (the adjoint extra)
-PROFILED_WORKLOAD = {"ssb_adjoint_pruned": "aberrated512"}
+PROFILED_WORKLOAD = {"ssb_adjoint_pruned": "aberrated512", "ssb_yadjoint": "aberrated512"}
 
 
 def _pmc_rows(path):
